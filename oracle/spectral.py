@@ -1,0 +1,103 @@
+"""Spectral grid, transforms and the Galilean-PSATD field update (oracle).
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
+
+Conventions (readings of points the paper leaves silent):
+
+* Fourier convention: forward transform with kernel exp(-i k.x), inverse
+  normalised by 1/N (``numpy.fft.fftn`` / ``ifftn``).  With it the spatial
+  derivative with respect to the Galilean coordinates becomes +i k, which is
+  the convention under which the printed theta = exp(i k.v_gal dt / 2) is
+  consistent with the transformed Maxwell equations.
+* k is the exact spectral wavevector 2 pi m / L per axis (pseudo-spectral,
+  no finite-difference modification).
+* Grid quantities are colocated on the nodes x_i = i * d (no staggering).
+* The k = 0 mode and every Nyquist plane (index N_a / 2 on any axis) of the
+  sources and of the fields are held at zero.  On Nyquist planes the update
+  does not map a Hermitian spectrum to a Hermitian spectrum, and the k = 0
+  mode carries the mean current of the electrons, which the co-moving
+  neutralising ion background cancels.
+"""
+
+import numpy as np
+
+C_LIGHT = 1.0
+EPS0 = 1.0
+
+
+def axis_wavenumbers(n, d):
+    """k values of one axis in FFT index order: 2 pi * fftfreq(n, d)."""
+    return 2.0 * np.pi * np.fft.fftfreq(n, d)
+
+
+def wavevectors(shape, spacing):
+    """Full (C2C) wavevector grid, each component shaped like the grid."""
+    kx = axis_wavenumbers(shape[0], spacing[0])
+    ky = axis_wavenumbers(shape[1], spacing[1])
+    kz = axis_wavenumbers(shape[2], spacing[2])
+    return np.meshgrid(kx, ky, kz, indexing="ij")
+
+
+def held_zero_mask(shape):
+    """True on the k = 0 mode and on every Nyquist plane."""
+    mask = np.zeros(shape, dtype=bool)
+    mask[0, 0, 0] = True
+    for axis, n in enumerate(shape):
+        if n % 2 == 0:
+            index = [slice(None)] * 3
+            index[axis] = n // 2
+            mask[tuple(index)] = True
+    return mask
+
+
+def forward(field):
+    """Unnormalised forward DFT, kernel exp(-i k.x)."""
+    return np.fft.fftn(np.asarray(field, dtype=np.float64))
+
+
+def inverse(spectrum):
+    """Inverse DFT normalised by 1/N; the real part of a Hermitian spectrum."""
+    return np.fft.ifftn(spectrum).real
+
+
+def cross(a, b):
+    """Component-wise cross product of two 3-vectors of arrays."""
+    return (a[1] * b[2] - a[2] * b[1],
+            a[2] * b[0] - a[0] * b[2],
+            a[0] * b[1] - a[1] * b[0])
+
+
+def galilean_psatd_update(E, B, J, rho_old, rho_new, k, coef, mask, c=C_LIGHT):
+    """Advance spectral E and B by one step (Galilean-PSATD update).
+
+    Written from the paper's update display for B^{n+1} and E^{n+1}:
+
+      B' = theta^2 C B - (theta^2 S / (c k)) i k x E
+           + theta chi_1 / (eps0 c^2 k^2) i k x J
+      E' = theta^2 C E + (theta^2 S / k) c i k x B
+           + (i nu theta chi_1 - theta^2 S) / (eps0 c k) J
+           - (chi_2 rho^{n+1} - theta^2 chi_3 rho^n) i k / (eps0 k^2)
+
+    ``coef`` holds those products per mode under the names
+    c_EE (= theta^2 C), s (= theta^2 S / (c k)), c_BJ, c_EJ,
+    c_R1 (= -chi_2 / (eps0 k^2)) and c_R0 (= +theta^2 chi_3 / (eps0 k^2)),
+    see ``coefficients.galilean_psatd_coefficients``.  J is taken at
+    (n + 1/2) dt, rho_old at n dt and rho_new at (n + 1) dt.  Modes in
+    ``mask`` are set to zero.  Returns new (E, B) as 3-tuples.
+    """
+    ik = tuple(1j * ka for ka in k)
+    ik_x_E = cross(ik, E)
+    ik_x_B = cross(ik, B)
+    ik_x_J = cross(ik, J)
+    rho_term = coef["c_R1"] * rho_new + coef["c_R0"] * rho_old
+    B_new = []
+    E_new = []
+    for a in range(3):
+        b = coef["c_EE"] * B[a] - coef["s"] * ik_x_E[a] + coef["c_BJ"] * ik_x_J[a]
+        e = (coef["c_EE"] * E[a] + c * c * coef["s"] * ik_x_B[a]
+             + coef["c_EJ"] * J[a] + rho_term * ik[a])
+        b = np.where(mask, 0.0, b)
+        e = np.where(mask, 0.0, e)
+        B_new.append(b)
+        E_new.append(e)
+    return tuple(E_new), tuple(B_new)
