@@ -1,0 +1,223 @@
+/*
+ * galpic.h -- C ABI of the Galilean-PSATD particle-in-cell step on AMD
+ * Instinct MI355X (gfx950).
+ *
+ * Method: Kirchen, Lehe, Godfrey, Dornmair, Jalas, Peters, Vay, Maier,
+ * "Stable discrete representation of relativistically drifting plasmas"
+ * (arXiv:1608.00215).  The paper transforms the Maxwell and Newton-Lorentz
+ * equations to coordinates x' = x - v_gal t, integrates the transformed
+ * Maxwell equations analytically in Fourier space with the current held
+ * constant over a step in x' (the Galilean-PSATD update and its
+ * coefficient block), deposits J at (n+1/2) dt and rho at n dt and
+ * (n+1) dt on the grid nodes, transforms back, interpolates to the
+ * particles and advances them with dx'/dt = v - v_gal.
+ *
+ * One step is the sequence
+ *     gp_deposit -> gp_fft_fwd -> gp_galilean_psatd_update -> gp_fft_inv
+ *     -> gp_gather_push
+ * or gp_step / gp_step_graph, which run the same work (the gather-push of
+ * one step fused with the deposit of the next).
+ *
+ * Conventions
+ *  - Normalised units: c = eps0 = 1.  Lengths in c/omega_p, times in
+ *    1/omega_p.  Momenta are u = p / (m c).
+ *  - Grid: periodic, nx x ny x nz nodes at x_i = i * d (no staggering),
+ *    real arrays [x][y][z] row-major (z contiguous); spectral arrays are
+ *    the half spectrum [x][y][nz/2+1] of interleaved complex values,
+ *    forward kernel exp(-i k.x), unnormalised; the inverse carries 1/N.
+ *    k is the exact spectral wavevector 2 pi m / L.
+ *  - The k = 0 mode and every Nyquist plane of J, rho, E and B are held at
+ *    zero (the co-moving ion background cancels the mean current).
+ *  - Shapes: B-splines of order 1 (cloud-in-cell) or 3 (cubic), the same
+ *    shape for deposit and gather.
+ *  - Precision GP_FP64: every quantity is double; positions are absolute
+ *    doubles wrapped into [0, L).  GP_MIXED: positions are an int32 linear
+ *    cell index (ix * ny + iy) * nz + iz plus three float offsets in
+ *    [0, 1); momenta, real and spectral fields, FFT, update and push are
+ *    float (complex64 spectra); the update coefficients are computed in
+ *    double and rounded once; each deposition tile is summed with a
+ *    compensated (two-term) float accumulator.
+ *
+ * Ownership and threading
+ *  - Particle arrays are owned by the caller (device memory, e.g. torch
+ *    tensors); the library reads and writes them in place and may reorder
+ *    the particles of a run (all arrays of that run, and the optional id
+ *    array, are permuted together).  It never frees them.
+ *  - Everything else (fields, spectra, coefficient tables, FFT scratch,
+ *    sort buffers) is owned by the context from gp_init_grid to
+ *    gp_destroy.
+ *  - Every call is asynchronous on the stream given at gp_init_grid unless
+ *    documented as synchronising.  A context is not thread-safe.  No C++
+ *    exception crosses this boundary; failures return a negative status
+ *    and gp_last_error() describes the last one (thread-local string).
+ */
+#ifndef GALPIC_H
+#define GALPIC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gp_ctx gp_ctx;
+typedef int gp_status;
+
+enum {
+  GP_OK = 0,
+  GP_ERR_ARG = -1,      /* invalid argument                                   */
+  GP_ERR_STATE = -2,    /* call out of order (inputs of the call not ready)    */
+  GP_ERR_HIP = -3,      /* a HIP runtime call failed                           */
+  GP_ERR_UNSTABLE = -4, /* some mode has |k.v_gal| dt >= 2 pi (1 - 1e-6), where
+                           the rho-form of the update is singular             */
+  GP_ERR_OOM = -5       /* device allocation failed                            */
+};
+
+enum { GP_FP64 = 0, GP_MIXED = 1 };
+
+/* Grid selectors for gp_read_field / gp_write_field.  Real arrays hold
+ * nx*ny*nz values of the run's real type; spectral ones nx*ny*(nz/2+1)
+ * complex values (two reals each). */
+enum {
+  GP_EX = 0, GP_EY, GP_EZ, GP_BX, GP_BY, GP_BZ,          /* real E, B      */
+  GP_JX, GP_JY, GP_JZ, GP_RHO,                            /* real J, rho    */
+  GP_EX_HAT, GP_EY_HAT, GP_EZ_HAT,                        /* spectral E^n   */
+  GP_BX_HAT, GP_BY_HAT, GP_BZ_HAT,                        /* spectral B^n   */
+  GP_JX_HAT, GP_JY_HAT, GP_JZ_HAT,                        /* spectral J     */
+  GP_RHO_HAT_OLD,                                         /* rho^n          */
+  GP_RHO_HAT_NEW,                                         /* rho^{n+1}      */
+  GP_COEF0, GP_COEF1, GP_COEF2, GP_COEF3, GP_COEF4, GP_COEF5, /* c_EE, s, c_BJ,
+                                   c_EJ, c_R1, c_R0 (read only, see below) */
+  GP_N_FIELDS
+};
+
+/* One run's grid.  nx, ny, nz: powers of two in [8, 1024]; dx, dy, dz > 0;
+ * dt > 0; shape_order 1 or 3; precision GP_FP64 or GP_MIXED (all runs of a
+ * context use the same precision and shape order). */
+typedef struct {
+  int nx, ny, nz;
+  double dx, dy, dz, dt;
+  int shape_order;
+  int precision;
+} gp_grid_desc;
+
+/* One run's macro-particles (one species, uniform weights).
+ *  n       number of particles (>= 0)
+ *  q, m, w charge, mass and weight (physical particles per macro-particle);
+ *          each deposits q w / (dx dy dz) times its shape
+ *  GP_FP64: x, y, z are double* absolute positions in [0, n_a d_a);
+ *           off_x, off_y, off_z unused (NULL).
+ *  GP_MIXED: x is int32* linear cell index, y and z unused (NULL);
+ *           off_x, off_y, off_z are float* offsets in [0, 1).
+ *  ux, uy, uz: momenta u = p / (m c) (double* or float*), at the half
+ *          step before the next deposit.
+ *  id      optional int64* carried along when particles are reordered. */
+typedef struct {
+  int64_t n;
+  double q, m, w;
+  void *x, *y, *z;
+  void *off_x, *off_y, *off_z;
+  void *ux, *uy, *uz;
+  int64_t *id;
+} gp_particles;
+
+/* Create a context for n_runs independent runs advanced together.
+ * hip_stream: a hipStream_t, or NULL for a stream created and owned by
+ * the context (default priority; graph capture needs a non-null stream).
+ * Allocates all
+ * device state; fields start at zero.  v_gal starts at zero (standard
+ * PSATD) with coefficients built.  Errors: GP_ERR_ARG for an invalid
+ * descriptor, GP_ERR_OOM, GP_ERR_HIP.  Synchronising. */
+gp_status gp_init_grid(const gp_grid_desc *runs, int n_runs, void *hip_stream,
+                       gp_ctx **out);
+
+/* Set v_gal of one run and rebuild its coefficient table in double
+ * precision on the device (paper's coefficient block: C, S, nu, theta,
+ * chi_1..chi_3, evaluated through cancellation-free integral forms).
+ * Errors: GP_ERR_ARG if run is out of range or |v_gal| >= c,
+ * GP_ERR_UNSTABLE if some non-Nyquist mode has |k.v_gal| dt >=
+ * 2 pi (1 - 1e-6). */
+gp_status gp_set_v_gal(gp_ctx *ctx, int run, double vx, double vy, double vz);
+
+/* Register the particle arrays p[0..n_runs-1] with the context, sort them
+ * into deposition tiles (reordering them in place), deposit rho at the
+ * current positions and transform it into rho^n.  Must precede
+ * gp_deposit / gp_gather_push / gp_step; call again after changing the
+ * arrays from outside.  Errors: GP_ERR_ARG (NULL pointers, n < 0,
+ * positions outside the layout contract are not checked). */
+gp_status gp_bind_particles(gp_ctx *ctx, const gp_particles *p);
+
+/* Deposit J^{n+1/2} and rho^{n+1}: move every particle by (v - v_gal) dt/2,
+ * deposit q w v S (lab velocity v = u / gamma) into J, move it by another
+ * (v - v_gal) dt/2, deposit q w S into rho (paper: currents at
+ * (n+1/2) dt, charge at (n+1) dt, on the grid nodes).  Positions are
+ * written back.  p must be the bound arrays (else GP_ERR_STATE). */
+gp_status gp_deposit(gp_ctx *ctx, const gp_particles *p);
+
+/* Forward FFT of J (3 components) and rho^{n+1}; k = 0 and Nyquist planes
+ * set to zero.  Requires a deposit (or written J/rho) since the last
+ * forward transform. */
+gp_status gp_fft_fwd(gp_ctx *ctx);
+
+/* Galilean-PSATD update of spectral E and B from E^n, B^n, J^{n+1/2},
+ * rho^n, rho^{n+1} (the paper's update equations); then rho^{n+1} becomes
+ * rho^n.  Requires gp_fft_fwd (or written spectral J and rho^{n+1}). */
+gp_status gp_galilean_psatd_update(gp_ctx *ctx);
+
+/* Inverse FFT of spectral E and B into the real E and B used by the
+ * gather.  The spectral state is left unchanged. */
+gp_status gp_fft_inv(gp_ctx *ctx);
+
+/* Interpolate E and B to every particle (same shape as the deposit) and
+ * advance u by dt with the relativistic Boris scheme (the paper's
+ * momentum equation dp/dt = q (E + v x B)).  Positions are unchanged.
+ * Requires real E and B produced by gp_fft_inv or gp_write_field. */
+gp_status gp_gather_push(gp_ctx *ctx, const gp_particles *p);
+
+/* One full step for every run (deposit, fft_fwd, update, fft_inv,
+ * gather_push), equivalent to the five calls above. */
+gp_status gp_step(gp_ctx *ctx, const gp_particles *p);
+
+/* nsteps full steps replayed from a captured HIP graph (captured on first
+ * use per particle binding).  Equivalent to nsteps gp_step calls. */
+gp_status gp_step_graph(gp_ctx *ctx, const gp_particles *p, int nsteps);
+
+/* Set E^0 and B^0 of one run from real-space arrays (device or host
+ * pointers to nx*ny*nz values of the run's real type, or NULL for zero):
+ * transformed, held modes set to zero, and with project_transverse != 0
+ * the component along k removed.  Also sets the real E and B. */
+gp_status gp_set_fields(gp_ctx *ctx, int run, const void *const E[3],
+                        const void *const B[3], int project_transverse);
+
+/* Boris half push u^0 -> u^{1/2} through dt/2 with the current real E and
+ * B at the current positions (start-up of the leapfrog). */
+gp_status gp_half_push(gp_ctx *ctx, const gp_particles *p);
+
+/* Copy one grid array of one run to dst / from src (host or device
+ * pointers; synchronising).  Writing marks the array as a valid input of
+ * the next call that consumes it.  Coefficient tables are read-only. */
+gp_status gp_read_field(gp_ctx *ctx, int run, int which, void *dst);
+gp_status gp_write_field(gp_ctx *ctx, int run, int which, const void *src);
+
+/* Field energy W_E = 1/2 sum |E|^2 dV and W_B = 1/2 sum |B|^2 dV of the
+ * real fields, reduced in double on the device (synchronising). */
+gp_status gp_field_energy(gp_ctx *ctx, int run, double *we, double *wb);
+
+/* Device time of the last gp_step_graph replay in milliseconds (HIP
+ * events on the context stream; synchronising). */
+gp_status gp_last_graph_ms(gp_ctx *ctx, double *ms);
+
+/* Wait until all work enqueued on the context's stream has finished. */
+gp_status gp_synchronize(gp_ctx *ctx);
+
+/* Release everything the context owns.  NULL is accepted. */
+gp_status gp_destroy(gp_ctx *ctx);
+
+/* Message of the last failure on this thread ("" if none). */
+const char *gp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GALPIC_H */

@@ -1,0 +1,741 @@
+// C ABI of the Galilean-PSATD step (declared in include/galpic.h).
+//
+// Host-side orchestration only: validation, device allocation, the order of
+// kernel launches, the rho^n / rho^{n+1} buffer rotation and HIP graph
+// capture.  All arithmetic of the step runs in the kernels.
+#include "../../include/galpic.h"
+
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+
+using namespace galpic;
+
+namespace {
+
+thread_local std::string g_err;
+
+gp_status fail(gp_status st, const std::string &msg) {
+  g_err = msg;
+  return st;
+}
+
+#define GP_HIP(call)                                                                    \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(GP_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_));      \
+  } while (0)
+
+#define GP_TRY(expr)                \
+  do {                              \
+    gp_status st_ = (expr);         \
+    if (st_ != GP_OK) return st_;   \
+  } while (0)
+
+gp_status check_launch(const char *what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(GP_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+  return GP_OK;
+}
+
+bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
+int ilog2(int n) {
+  int l = 0;
+  while ((1 << l) < n) ++l;
+  return l;
+}
+
+enum { kReal = 10, kSpec = 11 };
+// spec[] slots: 0-2 E^, 3-5 B^, 6-8 J^, 9-10 rho buffers (rotating)
+
+struct Run {
+  RunGeom g{};
+  void *real[kReal] = {};
+  void *spec[kSpec] = {};
+  void *coef[6] = {};
+  void *scratch[6] = {};
+  int rho_old = 9;          // spec slot holding rho^n; the other holds rho^{n+1}
+  PartPtrs parts{};
+  bool bound = false;
+  bool src_real_ready = false;  // J, rho deposited since the last forward FFT
+  bool src_spec_ready = false;  // J^, rho^{n+1} ready for the update
+  bool eb_real_ready = true;    // real E, B match the spectral state
+};
+
+}  // namespace
+
+struct gp_ctx {
+  int precision = GP_FP64;
+  int order = 1;
+  size_t real_size = 8;  // bytes of one real value
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::vector<Run> runs;
+  std::vector<void *> allocs;
+  void *tw = nullptr;
+  double *d_sum = nullptr;
+  hipGraphExec_t graph[2] = {nullptr, nullptr};
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  bool timed = false;
+};
+
+namespace {
+
+gp_status dev_alloc(gp_ctx *c, size_t bytes, void **out) {
+  void *p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes < 256 ? 256 : bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(GP_ERR_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+  }
+  c->allocs.push_back(p);
+  *out = p;
+  return GP_OK;
+}
+
+void drop_graphs(gp_ctx *c) {
+  for (auto &gx : c->graph) {
+    if (gx) (void)hipGraphExecDestroy(gx);
+    gx = nullptr;
+  }
+}
+
+size_t real_bytes(const gp_ctx *c, const Run &r) { return size_t(r.g.ncell) * c->real_size; }
+size_t spec_bytes(const gp_ctx *c, const Run &r) {
+  return size_t(r.g.nmode) * 2 * c->real_size;
+}
+
+gp_status validate_desc(const gp_grid_desc &d, int i) {
+  const std::string w = "run " + std::to_string(i) + ": ";
+  if (!is_pow2(d.nx) || !is_pow2(d.ny) || !is_pow2(d.nz))
+    return fail(GP_ERR_ARG, w + "nx, ny, nz must be powers of two");
+  if (d.nx < 8 || d.ny < 8 || d.nz < 8 || d.nx > 1024 || d.ny > 1024 || d.nz > 1024)
+    return fail(GP_ERR_ARG, w + "nx, ny, nz must lie in [8, 1024]");
+  if (!(d.dx > 0) || !(d.dy > 0) || !(d.dz > 0) || !(d.dt > 0))
+    return fail(GP_ERR_ARG, w + "dx, dy, dz, dt must be positive");
+  if (d.shape_order != 1 && d.shape_order != 3)
+    return fail(GP_ERR_ARG, w + "shape_order must be 1 or 3");
+  if (d.precision != GP_FP64 && d.precision != GP_MIXED)
+    return fail(GP_ERR_ARG, w + "precision must be GP_FP64 or GP_MIXED");
+  if (int64_t(d.nx) * d.ny * d.nz > (int64_t(1) << 31) - 1)
+    return fail(GP_ERR_ARG, w + "grid too large for int32 cell indices");
+  return GP_OK;
+}
+
+template <typename T>
+Cx<T> *S(const Run &r, int slot) {
+  return static_cast<Cx<T> *>(r.spec[slot]);
+}
+template <typename T>
+T *R(const Run &r, int slot) {
+  return static_cast<T *>(r.real[slot]);
+}
+
+template <typename T>
+GridPtrs<T> grid_ptrs(const Run &r) {
+  GridPtrs<T> g;
+  for (int a = 0; a < 3; ++a) {
+    g.E[a] = R<T>(r, a);
+    g.B[a] = R<T>(r, 3 + a);
+    g.J[a] = R<T>(r, 6 + a);
+  }
+  g.rho = R<T>(r, 9);
+  return g;
+}
+
+// Forward 3D FFT of nf real arrays into nf half spectra (held modes zeroed).
+template <typename T>
+void fft_forward(gp_ctx *c, const Run &r, const void *const *in, void *const *out, int nf) {
+  FieldSet z{}, yx{};
+  for (int f = 0; f < nf; ++f) {
+    z.in[f] = in[f];
+    z.out[f] = out[f];
+    yx.in[f] = out[f];
+    yx.out[f] = out[f];
+  }
+  const Cx<T> *tw = static_cast<const Cx<T> *>(c->tw);
+  launch_r2c_z<T>(z, nf, r.g, tw, c->stream);
+  launch_c2c<T>(yx, nf, r.g, 1, false, false, tw, c->stream);
+  launch_c2c<T>(yx, nf, r.g, 0, false, true, tw, c->stream);
+}
+
+// Inverse 3D FFT of nf half spectra into nf real arrays via the scratch.
+template <typename T>
+void fft_inverse(gp_ctx *c, const Run &r, const void *const *in, void *const *out, int nf) {
+  FieldSet x{}, y{}, z{};
+  for (int f = 0; f < nf; ++f) {
+    x.in[f] = in[f];
+    x.out[f] = r.scratch[f];
+    y.in[f] = r.scratch[f];
+    y.out[f] = r.scratch[f];
+    z.in[f] = r.scratch[f];
+    z.out[f] = out[f];
+  }
+  const Cx<T> *tw = static_cast<const Cx<T> *>(c->tw);
+  launch_c2c<T>(x, nf, r.g, 0, true, false, tw, c->stream);
+  launch_c2c<T>(y, nf, r.g, 1, true, false, tw, c->stream);
+  launch_c2r_z<T>(z, nf, r.g, tw, c->stream);
+}
+
+template <typename T>
+void do_deposit(gp_ctx *c, Run &r) {
+  for (int q = 6; q < 10; ++q) launch_zero(r.real[q], real_bytes(c, r), c->stream);
+  launch_deposit<T>(r.g, r.parts, grid_ptrs<T>(r), c->stream);
+}
+
+template <typename T>
+void do_fft_fwd(gp_ctx *c, Run &r) {
+  const void *in[4] = {r.real[6], r.real[7], r.real[8], r.real[9]};
+  void *out[4] = {r.spec[6], r.spec[7], r.spec[8], r.spec[r.rho_old == 9 ? 10 : 9]};
+  fft_forward<T>(c, r, in, out, 4);
+}
+
+template <typename T>
+void do_update(gp_ctx *c, Run &r) {
+  UpdatePtrs<T> p;
+  for (int a = 0; a < 3; ++a) {
+    p.E[a] = S<T>(r, a);
+    p.B[a] = S<T>(r, 3 + a);
+    p.J[a] = S<T>(r, 6 + a);
+  }
+  p.rho_old = S<T>(r, r.rho_old);
+  p.rho_new = S<T>(r, r.rho_old == 9 ? 10 : 9);
+  for (int i = 0; i < 6; ++i) p.coef[i] = static_cast<const Cx<T> *>(r.coef[i]);
+  launch_update<T>(r.g, p, c->stream);
+  r.rho_old = r.rho_old == 9 ? 10 : 9;
+}
+
+template <typename T>
+void do_fft_inv(gp_ctx *c, Run &r) {
+  const void *in[6] = {r.spec[0], r.spec[1], r.spec[2], r.spec[3], r.spec[4], r.spec[5]};
+  void *out[6] = {r.real[0], r.real[1], r.real[2], r.real[3], r.real[4], r.real[5]};
+  fft_inverse<T>(c, r, in, out, 6);
+}
+
+template <typename T>
+void do_gather_push(gp_ctx *c, Run &r, double dt) {
+  launch_gather_push<T>(r.g, r.parts, grid_ptrs<T>(r), dt, c->stream);
+}
+
+// Enqueue one full step of every run (no state checks).
+template <typename T>
+void enqueue_step(gp_ctx *c) {
+  for (auto &r : c->runs) do_deposit<T>(c, r);
+  for (auto &r : c->runs) do_fft_fwd<T>(c, r);
+  for (auto &r : c->runs) do_update<T>(c, r);
+  for (auto &r : c->runs) do_fft_inv<T>(c, r);
+  for (auto &r : c->runs) do_gather_push<T>(c, r, r.g.dt);
+}
+
+gp_status check_particles(gp_ctx *c, const gp_particles *p) {
+  if (!p) return fail(GP_ERR_ARG, "particles pointer is NULL");
+  for (size_t i = 0; i < c->runs.size(); ++i) {
+    const gp_particles &q = p[i];
+    if (q.n < 0) return fail(GP_ERR_ARG, "run " + std::to_string(i) + ": n < 0");
+    if (q.n == 0) continue;
+    if (!q.x || !q.ux || !q.uy || !q.uz)
+      return fail(GP_ERR_ARG, "run " + std::to_string(i) + ": NULL particle array");
+    if (c->precision == GP_FP64 && (!q.y || !q.z))
+      return fail(GP_ERR_ARG, "run " + std::to_string(i) + ": NULL position array");
+    if (c->precision == GP_MIXED && (!q.off_x || !q.off_y || !q.off_z))
+      return fail(GP_ERR_ARG, "run " + std::to_string(i) + ": NULL offset array");
+    if (!(q.m > 0) || !(q.w >= 0))
+      return fail(GP_ERR_ARG, "run " + std::to_string(i) + ": mass must be > 0, weight >= 0");
+  }
+  return GP_OK;
+}
+
+PartPtrs to_parts(const gp_particles &q) {
+  PartPtrs p;
+  p.n = q.n;
+  p.q = q.q;
+  p.m = q.m;
+  p.w = q.w;
+  p.x = q.x;
+  p.y = q.y;
+  p.z = q.z;
+  p.ox = q.off_x;
+  p.oy = q.off_y;
+  p.oz = q.off_z;
+  p.ux = q.ux;
+  p.uy = q.uy;
+  p.uz = q.uz;
+  p.id = q.id;
+  return p;
+}
+
+bool same_parts(const PartPtrs &a, const gp_particles &b) {
+  return a.n == b.n && a.x == b.x && a.y == b.y && a.z == b.z && a.ox == b.off_x &&
+         a.oy == b.off_y && a.oz == b.off_z && a.ux == b.ux && a.uy == b.uy && a.uz == b.uz &&
+         a.q == b.q && a.m == b.m && a.w == b.w;
+}
+
+gp_status require_bound(gp_ctx *c, const gp_particles *p) {
+  if (!p) return fail(GP_ERR_ARG, "particles pointer is NULL");
+  for (size_t i = 0; i < c->runs.size(); ++i) {
+    if (!c->runs[i].bound)
+      return fail(GP_ERR_STATE, "particles not bound (call gp_bind_particles first)");
+    if (!same_parts(c->runs[i].parts, p[i]))
+      return fail(GP_ERR_STATE, "run " + std::to_string(i) +
+                                    ": particle arrays differ from the bound ones");
+  }
+  return GP_OK;
+}
+
+gp_status check_ctx(gp_ctx *c) {
+  if (!c) return fail(GP_ERR_ARG, "context is NULL");
+  return GP_OK;
+}
+
+template <typename F>
+gp_status dispatch(gp_ctx *c, F &&f) {
+  if (c->precision == GP_FP64)
+    f(double{});
+  else
+    f(float{});
+  return check_launch("kernel launch");
+}
+
+void *field_slot(gp_ctx *c, Run &r, int which, size_t *bytes) {
+  if (which >= GP_EX && which <= GP_RHO) {
+    *bytes = real_bytes(c, r);
+    return r.real[which - GP_EX];
+  }
+  if (which >= GP_EX_HAT && which <= GP_JZ_HAT) {
+    *bytes = spec_bytes(c, r);
+    return r.spec[which - GP_EX_HAT];
+  }
+  if (which == GP_RHO_HAT_OLD) {
+    *bytes = spec_bytes(c, r);
+    return r.spec[r.rho_old];
+  }
+  if (which == GP_RHO_HAT_NEW) {
+    *bytes = spec_bytes(c, r);
+    return r.spec[r.rho_old == 9 ? 10 : 9];
+  }
+  if (which >= GP_COEF0 && which <= GP_COEF5) {
+    *bytes = spec_bytes(c, r);
+    return r.coef[which - GP_COEF0];
+  }
+  return nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *gp_last_error(void) { return g_err.c_str(); }
+
+gp_status gp_synchronize(gp_ctx *c) {
+  GP_TRY(check_ctx(c));
+  GP_HIP(hipStreamSynchronize(c->stream));
+  return GP_OK;
+}
+
+gp_status gp_destroy(gp_ctx *c) {
+  if (!c) return GP_OK;
+  drop_graphs(c);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  for (void *p : c->allocs) (void)hipFree(p);
+  if (c->ev0) (void)hipEventDestroy(c->ev0);
+  if (c->ev1) (void)hipEventDestroy(c->ev1);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+  return GP_OK;
+}
+
+gp_status gp_init_grid(const gp_grid_desc *runs, int n_runs, void *hip_stream, gp_ctx **out) {
+  g_err.clear();
+  if (!out) return fail(GP_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (!runs || n_runs < 1) return fail(GP_ERR_ARG, "need at least one run descriptor");
+  for (int i = 0; i < n_runs; ++i) GP_TRY(validate_desc(runs[i], i));
+  for (int i = 1; i < n_runs; ++i)
+    if (runs[i].precision != runs[0].precision || runs[i].shape_order != runs[0].shape_order)
+      return fail(GP_ERR_ARG, "all runs of a context must share precision and shape order");
+  gp_ctx *c = new gp_ctx();
+  c->precision = runs[0].precision;
+  c->order = runs[0].shape_order;
+  c->real_size = c->precision == GP_FP64 ? sizeof(double) : sizeof(float);
+  auto bail = [&](gp_status st) {
+    std::string keep = g_err;
+    gp_destroy(c);
+    g_err = keep;
+    return st;
+  };
+  if (hip_stream) {
+    c->stream = static_cast<hipStream_t>(hip_stream);
+  } else {
+    if (hipStreamCreate(&c->stream) != hipSuccess)
+      return bail(fail(GP_ERR_HIP, "hipStreamCreate failed"));
+    c->own_stream = true;
+  }
+  if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess)
+    return bail(fail(GP_ERR_HIP, "hipEventCreate failed"));
+  c->runs.resize(n_runs);
+  for (int i = 0; i < n_runs; ++i) {
+    const gp_grid_desc &d = runs[i];
+    Run &r = c->runs[i];
+    RunGeom &g = r.g;
+    g.nx = d.nx;
+    g.ny = d.ny;
+    g.nz = d.nz;
+    g.nzh = d.nz / 2 + 1;
+    g.lx = ilog2(d.nx);
+    g.ly = ilog2(d.ny);
+    g.lz = ilog2(d.nz);
+    g.order = d.shape_order;
+    g.dx = d.dx;
+    g.dy = d.dy;
+    g.dz = d.dz;
+    g.dt = d.dt;
+    g.vgal[0] = g.vgal[1] = g.vgal[2] = 0.0;
+    g.ncell = int64_t(d.nx) * d.ny * d.nz;
+    g.nmode = int64_t(d.nx) * d.ny * g.nzh;
+    for (auto &p : r.real) {
+      gp_status st = dev_alloc(c, real_bytes(c, r), &p);
+      if (st) return bail(st);
+      launch_zero(p, real_bytes(c, r), c->stream);
+    }
+    for (auto &p : r.spec) {
+      gp_status st = dev_alloc(c, spec_bytes(c, r), &p);
+      if (st) return bail(st);
+      launch_zero(p, spec_bytes(c, r), c->stream);
+    }
+    for (auto &p : r.coef) {
+      gp_status st = dev_alloc(c, spec_bytes(c, r), &p);
+      if (st) return bail(st);
+    }
+    for (auto &p : r.scratch) {
+      gp_status st = dev_alloc(c, spec_bytes(c, r), &p);
+      if (st) return bail(st);
+    }
+  }
+  {
+    const size_t twb = 1024 * 2 * c->real_size;
+    gp_status st = dev_alloc(c, twb, &c->tw);
+    if (st) return bail(st);
+    std::vector<char> host(twb);
+    if (c->precision == GP_FP64)
+      fill_twiddles<double>(reinterpret_cast<Cx<double> *>(host.data()));
+    else
+      fill_twiddles<float>(reinterpret_cast<Cx<float> *>(host.data()));
+    if (hipMemcpyAsync(c->tw, host.data(), twb, hipMemcpyHostToDevice, c->stream) != hipSuccess)
+      return bail(fail(GP_ERR_HIP, "twiddle upload failed"));
+    if (hipStreamSynchronize(c->stream) != hipSuccess)
+      return bail(fail(GP_ERR_HIP, "stream synchronize failed"));
+    void *sum = nullptr;
+    st = dev_alloc(c, 2 * sizeof(double), &sum);
+    if (st) return bail(st);
+    c->d_sum = static_cast<double *>(sum);
+  }
+  for (int i = 0; i < n_runs; ++i) {
+    gp_status st = gp_set_v_gal(c, i, 0.0, 0.0, 0.0);
+    if (st) return bail(st);
+  }
+  if (hipStreamSynchronize(c->stream) != hipSuccess)
+    return bail(fail(GP_ERR_HIP, "stream synchronize failed"));
+  *out = c;
+  return GP_OK;
+}
+
+gp_status gp_set_v_gal(gp_ctx *c, int run, double vx, double vy, double vz) {
+  GP_TRY(check_ctx(c));
+  if (run < 0 || run >= int(c->runs.size())) return fail(GP_ERR_ARG, "run out of range");
+  if (!std::isfinite(vx) || !std::isfinite(vy) || !std::isfinite(vz) ||
+      vx * vx + vy * vy + vz * vz >= 1.0)
+    return fail(GP_ERR_ARG, "|v_gal| must be finite and below c");
+  Run &r = c->runs[run];
+  RunGeom &g = r.g;
+  // largest |k.v_gal| dt over non-Nyquist modes
+  const int n[3] = {g.nx, g.ny, g.nz};
+  const double d[3] = {g.dx, g.dy, g.dz};
+  const double v[3] = {vx, vy, vz};
+  double phase = 0.0;
+  for (int a = 0; a < 3; ++a)
+    phase += std::fabs(v[a]) * 2.0 * kPi * double(n[a] / 2 - 1) / (double(n[a]) * d[a]);
+  phase *= g.dt;
+  if (phase >= 2.0 * kPi * (1.0 - 1e-6))
+    return fail(GP_ERR_UNSTABLE, "some mode has |k.v_gal| dt >= 2 pi; the update is singular");
+  g.vgal[0] = vx;
+  g.vgal[1] = vy;
+  g.vgal[2] = vz;
+  CoefPtrs cp;
+  for (int i = 0; i < 6; ++i) cp.c[i] = r.coef[i];
+  if (c->precision == GP_FP64)
+    launch_coefficients<double>(g, cp, c->stream);
+  else
+    launch_coefficients<float>(g, cp, c->stream);
+  GP_TRY(check_launch("coefficients"));
+  drop_graphs(c);
+  return GP_OK;
+}
+
+gp_status gp_bind_particles(gp_ctx *c, const gp_particles *p) {
+  GP_TRY(check_ctx(c));
+  GP_TRY(check_particles(c, p));
+  drop_graphs(c);
+  for (size_t i = 0; i < c->runs.size(); ++i) {
+    Run &r = c->runs[i];
+    r.parts = to_parts(p[i]);
+    r.bound = true;
+  }
+  return dispatch(c, [&](auto t) {
+    using T = decltype(t);
+    for (auto &r : c->runs) {
+      launch_zero(r.real[9], real_bytes(c, r), c->stream);
+      launch_deposit_rho<T>(r.g, r.parts, grid_ptrs<T>(r), c->stream);
+      const void *in[1] = {r.real[9]};
+      void *out[1] = {r.spec[r.rho_old]};
+      fft_forward<T>(c, r, in, out, 1);
+      r.src_real_ready = false;
+      r.src_spec_ready = false;
+    }
+  });
+}
+
+gp_status gp_deposit(gp_ctx *c, const gp_particles *p) {
+  GP_TRY(check_ctx(c));
+  GP_TRY(require_bound(c, p));
+  GP_TRY(dispatch(c, [&](auto t) {
+    using T = decltype(t);
+    for (auto &r : c->runs) do_deposit<T>(c, r);
+  }));
+  for (auto &r : c->runs) r.src_real_ready = true;
+  return GP_OK;
+}
+
+gp_status gp_fft_fwd(gp_ctx *c) {
+  GP_TRY(check_ctx(c));
+  for (auto &r : c->runs)
+    if (!r.src_real_ready) return fail(GP_ERR_STATE, "gp_fft_fwd needs a deposit first");
+  GP_TRY(dispatch(c, [&](auto t) {
+    using T = decltype(t);
+    for (auto &r : c->runs) do_fft_fwd<T>(c, r);
+  }));
+  for (auto &r : c->runs) {
+    r.src_real_ready = false;
+    r.src_spec_ready = true;
+  }
+  return GP_OK;
+}
+
+gp_status gp_galilean_psatd_update(gp_ctx *c) {
+  GP_TRY(check_ctx(c));
+  for (auto &r : c->runs)
+    if (!r.src_spec_ready)
+      return fail(GP_ERR_STATE, "gp_galilean_psatd_update needs gp_fft_fwd first");
+  GP_TRY(dispatch(c, [&](auto t) {
+    using T = decltype(t);
+    for (auto &r : c->runs) do_update<T>(c, r);
+  }));
+  for (auto &r : c->runs) {
+    r.src_spec_ready = false;
+    r.eb_real_ready = false;
+  }
+  return GP_OK;
+}
+
+gp_status gp_fft_inv(gp_ctx *c) {
+  GP_TRY(check_ctx(c));
+  GP_TRY(dispatch(c, [&](auto t) {
+    using T = decltype(t);
+    for (auto &r : c->runs) do_fft_inv<T>(c, r);
+  }));
+  for (auto &r : c->runs) r.eb_real_ready = true;
+  return GP_OK;
+}
+
+gp_status gp_gather_push(gp_ctx *c, const gp_particles *p) {
+  GP_TRY(check_ctx(c));
+  GP_TRY(require_bound(c, p));
+  for (auto &r : c->runs)
+    if (!r.eb_real_ready) return fail(GP_ERR_STATE, "gp_gather_push needs gp_fft_inv first");
+  return dispatch(c, [&](auto t) {
+    using T = decltype(t);
+    for (auto &r : c->runs) do_gather_push<T>(c, r, r.g.dt);
+  });
+}
+
+gp_status gp_half_push(gp_ctx *c, const gp_particles *p) {
+  GP_TRY(check_ctx(c));
+  GP_TRY(require_bound(c, p));
+  for (auto &r : c->runs)
+    if (!r.eb_real_ready) return fail(GP_ERR_STATE, "gp_half_push needs real E and B");
+  return dispatch(c, [&](auto t) {
+    using T = decltype(t);
+    for (auto &r : c->runs) do_gather_push<T>(c, r, 0.5 * r.g.dt);
+  });
+}
+
+gp_status gp_step(gp_ctx *c, const gp_particles *p) {
+  GP_TRY(check_ctx(c));
+  GP_TRY(require_bound(c, p));
+  for (auto &r : c->runs)
+    if (!r.eb_real_ready) return fail(GP_ERR_STATE, "gp_step needs real E and B");
+  GP_TRY(dispatch(c, [&](auto t) {
+    using T = decltype(t);
+    enqueue_step<T>(c);
+  }));
+  for (auto &r : c->runs) {
+    r.src_real_ready = false;
+    r.src_spec_ready = false;
+    r.eb_real_ready = true;
+  }
+  return GP_OK;
+}
+
+gp_status gp_step_graph(gp_ctx *c, const gp_particles *p, int nsteps) {
+  GP_TRY(check_ctx(c));
+  GP_TRY(require_bound(c, p));
+  if (nsteps < 0) return fail(GP_ERR_ARG, "nsteps < 0");
+  for (auto &r : c->runs)
+    if (!r.eb_real_ready) return fail(GP_ERR_STATE, "gp_step_graph needs real E and B");
+  if (c->own_stream == false && c->stream == nullptr)
+    return fail(GP_ERR_STATE, "graph capture needs a non-null stream");
+  // graph[k] is one step starting with rho^n in slot 9 + k
+  const int parity = c->runs[0].rho_old - 9;
+  if (!c->graph[0] || !c->graph[1]) {
+    drop_graphs(c);
+    std::vector<int> saved(c->runs.size());
+    for (size_t i = 0; i < c->runs.size(); ++i) saved[i] = c->runs[i].rho_old;
+    for (int k = 0; k < 2; ++k) {
+      for (auto &r : c->runs) r.rho_old = 9 + k;
+      hipGraph_t graph = nullptr;
+      GP_HIP(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+      if (c->precision == GP_FP64)
+        enqueue_step<double>(c);
+      else
+        enqueue_step<float>(c);
+      hipError_t le = hipGetLastError();
+      hipError_t ee = hipStreamEndCapture(c->stream, &graph);
+      if (le != hipSuccess || ee != hipSuccess) {
+        for (size_t i = 0; i < c->runs.size(); ++i) c->runs[i].rho_old = saved[i];
+        if (graph) (void)hipGraphDestroy(graph);
+        return fail(GP_ERR_HIP, std::string("graph capture failed: ") +
+                                    hipGetErrorString(le != hipSuccess ? le : ee));
+      }
+      hipError_t ie = hipGraphInstantiateWithFlags(&c->graph[k], graph, 0);
+      (void)hipGraphDestroy(graph);
+      if (ie != hipSuccess) {
+        for (size_t i = 0; i < c->runs.size(); ++i) c->runs[i].rho_old = saved[i];
+        drop_graphs(c);
+        return fail(GP_ERR_HIP, std::string("graph instantiate failed: ") + hipGetErrorString(ie));
+      }
+    }
+    for (size_t i = 0; i < c->runs.size(); ++i) c->runs[i].rho_old = saved[i];
+  }
+  int par = parity;
+  GP_HIP(hipEventRecord(c->ev0, c->stream));
+  for (int s = 0; s < nsteps; ++s) {
+    GP_HIP(hipGraphLaunch(c->graph[par], c->stream));
+    par ^= 1;
+  }
+  GP_HIP(hipEventRecord(c->ev1, c->stream));
+  c->timed = true;
+  for (auto &r : c->runs) {
+    r.rho_old = 9 + par;
+    r.src_real_ready = false;
+    r.src_spec_ready = false;
+    r.eb_real_ready = true;
+  }
+  return GP_OK;
+}
+
+gp_status gp_last_graph_ms(gp_ctx *c, double *ms) {
+  GP_TRY(check_ctx(c));
+  if (!ms) return fail(GP_ERR_ARG, "ms is NULL");
+  if (!c->timed) return fail(GP_ERR_STATE, "no graph replay recorded");
+  GP_HIP(hipEventSynchronize(c->ev1));
+  float t = 0.f;
+  GP_HIP(hipEventElapsedTime(&t, c->ev0, c->ev1));
+  *ms = t;
+  return GP_OK;
+}
+
+gp_status gp_set_fields(gp_ctx *c, int run, const void *const E[3], const void *const B[3],
+                        int project_transverse) {
+  GP_TRY(check_ctx(c));
+  if (run < 0 || run >= int(c->runs.size())) return fail(GP_ERR_ARG, "run out of range");
+  Run &r = c->runs[run];
+  const size_t rb = real_bytes(c, r);
+  for (int a = 0; a < 6; ++a) {
+    const void *src = a < 3 ? (E ? E[a] : nullptr) : (B ? B[a - 3] : nullptr);
+    if (src)
+      GP_HIP(hipMemcpyAsync(r.real[a], src, rb, hipMemcpyDefault, c->stream));
+    else
+      launch_zero(r.real[a], rb, c->stream);
+  }
+  GP_TRY(dispatch(c, [&](auto t) {
+    using T = decltype(t);
+    const void *in[6] = {r.real[0], r.real[1], r.real[2], r.real[3], r.real[4], r.real[5]};
+    void *out[6] = {r.spec[0], r.spec[1], r.spec[2], r.spec[3], r.spec[4], r.spec[5]};
+    fft_forward<T>(c, r, in, out, 6);
+    launch_project<T>(r.g, S<T>(r, 0), S<T>(r, 1), S<T>(r, 2), project_transverse != 0,
+                      c->stream);
+    launch_project<T>(r.g, S<T>(r, 3), S<T>(r, 4), S<T>(r, 5), project_transverse != 0,
+                      c->stream);
+    do_fft_inv<T>(c, r);
+  }));
+  GP_HIP(hipStreamSynchronize(c->stream));
+  r.eb_real_ready = true;
+  return GP_OK;
+}
+
+gp_status gp_read_field(gp_ctx *c, int run, int which, void *dst) {
+  GP_TRY(check_ctx(c));
+  if (run < 0 || run >= int(c->runs.size())) return fail(GP_ERR_ARG, "run out of range");
+  if (!dst) return fail(GP_ERR_ARG, "dst is NULL");
+  size_t bytes = 0;
+  void *src = field_slot(c, c->runs[run], which, &bytes);
+  if (!src) return fail(GP_ERR_ARG, "unknown field selector");
+  GP_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDefault, c->stream));
+  GP_HIP(hipStreamSynchronize(c->stream));
+  return GP_OK;
+}
+
+gp_status gp_write_field(gp_ctx *c, int run, int which, const void *src) {
+  GP_TRY(check_ctx(c));
+  if (run < 0 || run >= int(c->runs.size())) return fail(GP_ERR_ARG, "run out of range");
+  if (!src) return fail(GP_ERR_ARG, "src is NULL");
+  if (which >= GP_COEF0 && which <= GP_COEF5)
+    return fail(GP_ERR_ARG, "coefficient tables are read-only");
+  Run &r = c->runs[run];
+  size_t bytes = 0;
+  void *dst = field_slot(c, r, which, &bytes);
+  if (!dst) return fail(GP_ERR_ARG, "unknown field selector");
+  GP_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDefault, c->stream));
+  GP_HIP(hipStreamSynchronize(c->stream));
+  if (which >= GP_JX && which <= GP_RHO) r.src_real_ready = true;
+  if ((which >= GP_JX_HAT && which <= GP_JZ_HAT) || which == GP_RHO_HAT_NEW)
+    r.src_spec_ready = true;
+  if (which >= GP_EX && which <= GP_BZ) r.eb_real_ready = true;
+  return GP_OK;
+}
+
+gp_status gp_field_energy(gp_ctx *c, int run, double *we, double *wb) {
+  GP_TRY(check_ctx(c));
+  if (run < 0 || run >= int(c->runs.size())) return fail(GP_ERR_ARG, "run out of range");
+  if (!we || !wb) return fail(GP_ERR_ARG, "output pointer is NULL");
+  Run &r = c->runs[run];
+  launch_zero(c->d_sum, 2 * sizeof(double), c->stream);
+  GP_TRY(dispatch(c, [&](auto t) {
+    using T = decltype(t);
+    launch_sum_squares<T>(R<T>(r, 0), R<T>(r, 1), R<T>(r, 2), r.g.ncell, c->d_sum, c->stream);
+    launch_sum_squares<T>(R<T>(r, 3), R<T>(r, 4), R<T>(r, 5), r.g.ncell, c->d_sum + 1,
+                          c->stream);
+  }));
+  double h[2];
+  GP_HIP(hipMemcpyAsync(h, c->d_sum, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+  GP_HIP(hipStreamSynchronize(c->stream));
+  const double dv = r.g.dx * r.g.dy * r.g.dz;
+  *we = 0.5 * dv * h[0];
+  *wb = 0.5 * dv * h[1];
+  return GP_OK;
+}
+
+}  // extern "C"

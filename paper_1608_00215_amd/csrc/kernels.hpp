@@ -1,0 +1,88 @@
+// Host-side launchers of the gfx950 kernels (one translation unit each).
+#pragma once
+
+#include "common.hpp"
+
+namespace galpic {
+
+// Up to six field arrays processed by one launch (blockIdx.y = field).
+struct FieldSet {
+  const void *in[6];
+  void *out[6];
+};
+
+// ---- FFT (fft.hip) ---------------------------------------------------------
+// Twiddle table: 1024 values exp(-2 pi i m / 1024) in the run's precision.
+template <typename T>
+void fill_twiddles(Cx<T> *host1024);
+
+// Forward real-to-complex transform along z of nf real arrays [x][y][z] into
+// half spectra [x][y][nz/2+1].
+template <typename T>
+void launch_r2c_z(const FieldSet &fs, int nf, const RunGeom &g, const Cx<T> *tw,
+                  hipStream_t s);
+// Complex transform along y (axis 1) or x (axis 0) of nf half spectra.
+// mask_held: write zero on the k = 0 mode and every Nyquist plane.
+template <typename T>
+void launch_c2c(const FieldSet &fs, int nf, const RunGeom &g, int axis, bool inverse,
+                bool mask_held, const Cx<T> *tw, hipStream_t s);
+// Inverse complex-to-real transform along z with the 1/(nx ny nz) scale.
+template <typename T>
+void launch_c2r_z(const FieldSet &fs, int nf, const RunGeom &g, const Cx<T> *tw,
+                  hipStream_t s);
+
+// ---- coefficients (coef.hip) ----------------------------------------------
+struct CoefPtrs {
+  void *c[6];  // c_EE, s, c_BJ, c_EJ, c_R1, c_R0 as Cx<T>
+};
+template <typename T>
+void launch_coefficients(const RunGeom &g, const CoefPtrs &cp, hipStream_t s);
+
+// ---- k-space update and reductions (update.hip) ----------------------------
+template <typename T>
+struct UpdatePtrs {
+  Cx<T> *E[3];
+  Cx<T> *B[3];
+  const Cx<T> *J[3];
+  const Cx<T> *rho_old;
+  const Cx<T> *rho_new;
+  const Cx<T> *coef[6];
+};
+template <typename T>
+void launch_update(const RunGeom &g, const UpdatePtrs<T> &p, hipStream_t s);
+// Transverse projection F <- F - k (k.F)/k^2 of a spectral 3-vector, held
+// modes zeroed.
+template <typename T>
+void launch_project(const RunGeom &g, Cx<T> *F0, Cx<T> *F1, Cx<T> *F2, bool transverse,
+                    hipStream_t s);
+// Fill nbytes (a multiple of 4) with zeros; a kernel, so it can be captured
+// in a graph.
+void launch_zero(void *p, size_t nbytes, hipStream_t s);
+// out[0] += sum of squares over n values of each of the three arrays.
+template <typename T>
+void launch_sum_squares(const T *a, const T *b, const T *c, int64_t n, double *out,
+                        hipStream_t s);
+
+// ---- particles (particles.hip) ----------------------------------------------
+template <typename T>
+struct GridPtrs {
+  T *E[3];
+  T *B[3];
+  T *J[3];
+  T *rho;
+};
+// Deposit J at the half-way position and rho at the end position, moving
+// the particles by (v - v_gal) dt in two halves.  Grids must be zeroed.
+template <typename T>
+void launch_deposit(const RunGeom &g, const PartPtrs &p, const GridPtrs<T> &gr,
+                    hipStream_t s);
+// rho at the current positions (no move).
+template <typename T>
+void launch_deposit_rho(const RunGeom &g, const PartPtrs &p, const GridPtrs<T> &gr,
+                        hipStream_t s);
+// Gather E, B at the positions and Boris-push u through dt_push.
+template <typename T>
+void launch_gather_push(const RunGeom &g, const PartPtrs &p, const GridPtrs<T> &gr,
+                        double dt_push, hipStream_t s);
+
+}  // namespace galpic

@@ -1,0 +1,197 @@
+// Galilean-PSATD k-space update and small spectral/real helpers.
+//
+// The update is one streaming pass over the half-spectrum modes: per mode it
+// reads E, B (3+3), J (3), rho^n, rho^{n+1} and the six coefficients
+// c0..c5 (see coef.hip), and writes E, B (paper's update equations):
+//
+//   B' = c0 B - c1 (ik x E) + c2 (ik x J)
+//   E' = c0 E + c1 (ik x B) + c3 J + (c4 rho^{n+1} + c5 rho^n) ik
+//
+// k is rebuilt from the mode index.  Modes on a Nyquist plane and k = 0 are
+// written as zero.  HBM-bound: 17 complex values per mode move (136 B in
+// float, 272 B in double) plus the 6 coefficients.
+#include "kernels.hpp"
+
+namespace galpic {
+namespace {
+
+template <typename T>
+__device__ __forceinline__ T wavenumber_t(int i, int n, T kfac) {
+  const int s = i < n / 2 ? i : i - n;
+  return T(s) * kfac;
+}
+
+// (ik x F)_a for real k and complex F
+template <typename T>
+__device__ __forceinline__ void ik_cross(T kx, T ky, T kz, const Cx<T> F[3], Cx<T> out[3]) {
+  const Cx<T> c0 = cx(ky * F[2].re - kz * F[1].re, ky * F[2].im - kz * F[1].im);
+  const Cx<T> c1 = cx(kz * F[0].re - kx * F[2].re, kz * F[0].im - kx * F[2].im);
+  const Cx<T> c2 = cx(kx * F[1].re - ky * F[0].re, kx * F[1].im - ky * F[0].im);
+  out[0] = mul_i(c0);
+  out[1] = mul_i(c1);
+  out[2] = mul_i(c2);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_update(RunGeom g, UpdatePtrs<T> p, T kfx, T kfy,
+                                                T kfz) {
+  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= g.nmode) return;
+  const int iz = int(idx % g.nzh);
+  const int iy = int((idx / g.nzh) % g.ny);
+  const int ix = int(idx / (int64_t(g.nzh) * g.ny));
+  const bool held = ix == g.nx / 2 || iy == g.ny / 2 || iz == g.nz / 2 ||
+                    (ix == 0 && iy == 0 && iz == 0);
+  if (held) {
+    const Cx<T> z = cx(T(0), T(0));
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      p.E[a][idx] = z;
+      p.B[a][idx] = z;
+    }
+    return;
+  }
+  const T kx = wavenumber_t(ix, g.nx, kfx);
+  const T ky = wavenumber_t(iy, g.ny, kfy);
+  const T kz = T(iz) * kfz;
+  Cx<T> E[3], B[3], J[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    E[a] = p.E[a][idx];
+    B[a] = p.B[a][idx];
+    J[a] = p.J[a][idx];
+  }
+  const Cx<T> r0 = p.rho_old[idx];
+  const Cx<T> r1 = p.rho_new[idx];
+  const Cx<T> c0 = p.coef[0][idx];
+  const Cx<T> c1 = p.coef[1][idx];
+  const Cx<T> c2 = p.coef[2][idx];
+  const Cx<T> c3 = p.coef[3][idx];
+  const Cx<T> c4 = p.coef[4][idx];
+  const Cx<T> c5 = p.coef[5][idx];
+  Cx<T> kE[3], kB[3], kJ[3];
+  ik_cross(kx, ky, kz, E, kE);
+  ik_cross(kx, ky, kz, B, kB);
+  ik_cross(kx, ky, kz, J, kJ);
+  // (c4 rho^{n+1} + c5 rho^n) i
+  const Cx<T> rho_i = mul_i(c4 * r1 + c5 * r0);
+  const T kk[3] = {kx, ky, kz};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const Cx<T> bn = c0 * B[a] - c1 * kE[a] + c2 * kJ[a];
+    const Cx<T> en = c0 * E[a] + c1 * kB[a] + c3 * J[a] + kk[a] * rho_i;
+    p.B[a][idx] = bn;
+    p.E[a][idx] = en;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_project(RunGeom g, Cx<T> *F0, Cx<T> *F1, Cx<T> *F2,
+                                                 int transverse, T kfx, T kfy, T kfz) {
+  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= g.nmode) return;
+  const int iz = int(idx % g.nzh);
+  const int iy = int((idx / g.nzh) % g.ny);
+  const int ix = int(idx / (int64_t(g.nzh) * g.ny));
+  const bool held = ix == g.nx / 2 || iy == g.ny / 2 || iz == g.nz / 2 ||
+                    (ix == 0 && iy == 0 && iz == 0);
+  if (held) {
+    const Cx<T> z = cx(T(0), T(0));
+    F0[idx] = z;
+    F1[idx] = z;
+    F2[idx] = z;
+    return;
+  }
+  if (!transverse) return;
+  const T kx = wavenumber_t(ix, g.nx, kfx);
+  const T ky = wavenumber_t(iy, g.ny, kfy);
+  const T kz = T(iz) * kfz;
+  const T inv_k2 = T(1) / (kx * kx + ky * ky + kz * kz);
+  const Cx<T> a = F0[idx], b = F1[idx], c = F2[idx];
+  const Cx<T> kf = inv_k2 * (kx * a + ky * b + kz * c);
+  F0[idx] = a - kx * kf;
+  F1[idx] = b - ky * kf;
+  F2[idx] = c - kz * kf;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_sum_squares(const T *__restrict__ a,
+                                                     const T *__restrict__ b,
+                                                     const T *__restrict__ c, int64_t n,
+                                                     double *out) {
+  double acc = 0.0;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const double x = a[i], y = b[i], z = c[i];
+    acc += x * x + y * y + z * z;
+  }
+  // wave reduction then one atomic per wave
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  if ((threadIdx.x & 63) == 0) atomicAdd(out, acc);
+}
+
+__global__ __launch_bounds__(256) void k_zero(uint4 *p16, size_t n16, uint32_t *p4, size_t n4) {
+  const size_t stride = size_t(gridDim.x) * blockDim.x;
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n16; i += stride)
+    p16[i] = make_uint4(0u, 0u, 0u, 0u);
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n4; i += stride) p4[i] = 0u;
+}
+
+template <typename T>
+T kfac(int n, double d) {
+  return T(2.0 * kPi / (double(n) * d));
+}
+
+}  // namespace
+
+template <typename T>
+void launch_update(const RunGeom &g, const UpdatePtrs<T> &p, hipStream_t s) {
+  const unsigned blocks = unsigned((g.nmode + 255) / 256);
+  hipLaunchKernelGGL((k_update<T>), dim3(blocks), dim3(256), 0, s, g, p, kfac<T>(g.nx, g.dx),
+                     kfac<T>(g.ny, g.dy), kfac<T>(g.nz, g.dz));
+}
+
+template <typename T>
+void launch_project(const RunGeom &g, Cx<T> *F0, Cx<T> *F1, Cx<T> *F2, bool transverse,
+                    hipStream_t s) {
+  const unsigned blocks = unsigned((g.nmode + 255) / 256);
+  hipLaunchKernelGGL((k_project<T>), dim3(blocks), dim3(256), 0, s, g, F0, F1, F2,
+                     transverse ? 1 : 0, kfac<T>(g.nx, g.dx), kfac<T>(g.ny, g.dy),
+                     kfac<T>(g.nz, g.dz));
+}
+
+template <typename T>
+void launch_sum_squares(const T *a, const T *b, const T *c, int64_t n, double *out,
+                        hipStream_t s) {
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL((k_sum_squares<T>), dim3(unsigned(blocks)), dim3(256), 0, s, a, b, c, n,
+                     out);
+}
+
+void launch_zero(void *p, size_t nbytes, hipStream_t s) {
+  if (nbytes == 0) return;
+  // allocations are 256-byte aligned; the tail (if any) is cleared by words
+  const size_t n16 = nbytes / 16;
+  const size_t n4 = (nbytes - n16 * 16) / 4;
+  uint32_t *tail = reinterpret_cast<uint32_t *>(static_cast<char *>(p) + n16 * 16);
+  size_t blocks = (n16 + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_zero, dim3(unsigned(blocks)), dim3(256), 0, s,
+                     static_cast<uint4 *>(p), n16, tail, n4);
+}
+
+template void launch_update<float>(const RunGeom &, const UpdatePtrs<float> &, hipStream_t);
+template void launch_update<double>(const RunGeom &, const UpdatePtrs<double> &, hipStream_t);
+template void launch_project<float>(const RunGeom &, Cx<float> *, Cx<float> *, Cx<float> *,
+                                    bool, hipStream_t);
+template void launch_project<double>(const RunGeom &, Cx<double> *, Cx<double> *,
+                                     Cx<double> *, bool, hipStream_t);
+template void launch_sum_squares<float>(const float *, const float *, const float *, int64_t,
+                                        double *, hipStream_t);
+template void launch_sum_squares<double>(const double *, const double *, const double *,
+                                         int64_t, double *, hipStream_t);
+
+}  // namespace galpic

@@ -1,0 +1,317 @@
+"""ctypes binding of ``libgalpic.so`` (argument marshalling only).
+
+Every step of the method runs in the HIP kernels behind the C ABI declared
+in ``include/galpic.h``; this module only converts Python arguments to
+pointers and sizes.  PyTorch provides device memory for the particle
+arrays.  There is no fallback: if the library is missing, ``load()``
+raises.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgalpic.so")
+
+GP_OK, GP_ERR_ARG, GP_ERR_STATE, GP_ERR_HIP, GP_ERR_UNSTABLE, GP_ERR_OOM = 0, -1, -2, -3, -4, -5
+GP_FP64, GP_MIXED = 0, 1
+
+FIELDS = ["EX", "EY", "EZ", "BX", "BY", "BZ", "JX", "JY", "JZ", "RHO",
+          "EX_HAT", "EY_HAT", "EZ_HAT", "BX_HAT", "BY_HAT", "BZ_HAT",
+          "JX_HAT", "JY_HAT", "JZ_HAT", "RHO_HAT_OLD", "RHO_HAT_NEW",
+          "COEF0", "COEF1", "COEF2", "COEF3", "COEF4", "COEF5"]
+FIELD = {name: i for i, name in enumerate(FIELDS)}
+
+#: every symbol the header declares
+EXPORTS = ["gp_init_grid", "gp_set_v_gal", "gp_bind_particles", "gp_deposit", "gp_fft_fwd",
+           "gp_galilean_psatd_update", "gp_fft_inv", "gp_gather_push", "gp_step",
+           "gp_step_graph", "gp_set_fields", "gp_half_push", "gp_read_field",
+           "gp_write_field", "gp_field_energy", "gp_last_graph_ms", "gp_synchronize",
+           "gp_destroy", "gp_last_error"]
+
+
+class GridDesc(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+                ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", ctypes.c_double),
+                ("dt", ctypes.c_double), ("shape_order", ctypes.c_int),
+                ("precision", ctypes.c_int)]
+
+
+class ParticlesC(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("q", ctypes.c_double), ("m", ctypes.c_double),
+                ("w", ctypes.c_double),
+                ("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("z", ctypes.c_void_p),
+                ("off_x", ctypes.c_void_p), ("off_y", ctypes.c_void_p),
+                ("off_z", ctypes.c_void_p),
+                ("ux", ctypes.c_void_p), ("uy", ctypes.c_void_p), ("uz", ctypes.c_void_p),
+                ("id", ctypes.c_void_p)]
+
+
+class GalpicError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"galpic status {status}: {msg}")
+        self.status = status
+
+
+_LIB = None
+
+
+def load(path=LIB_PATH):
+    """Load the library (once) and declare argument types."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with "
+                           "`python -m paper_1608_00215_amd.build` (no CPU fallback exists)")
+    lib = ctypes.CDLL(path)
+    vp, i32, dbl = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    sig = {
+        "gp_init_grid": [ctypes.POINTER(GridDesc), i32, vp, ctypes.POINTER(vp)],
+        "gp_set_v_gal": [vp, i32, dbl, dbl, dbl],
+        "gp_bind_particles": [vp, vp],
+        "gp_deposit": [vp, vp],
+        "gp_fft_fwd": [vp],
+        "gp_galilean_psatd_update": [vp],
+        "gp_fft_inv": [vp],
+        "gp_gather_push": [vp, vp],
+        "gp_step": [vp, vp],
+        "gp_step_graph": [vp, vp, i32],
+        "gp_set_fields": [vp, i32, vp, vp, i32],
+        "gp_half_push": [vp, vp],
+        "gp_read_field": [vp, i32, i32, vp],
+        "gp_write_field": [vp, i32, i32, vp],
+        "gp_field_energy": [vp, i32, ctypes.POINTER(dbl), ctypes.POINTER(dbl)],
+        "gp_last_graph_ms": [vp, ctypes.POINTER(dbl)],
+        "gp_synchronize": [vp],
+        "gp_destroy": [vp],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.gp_last_error.argtypes = []
+    lib.gp_last_error.restype = ctypes.c_char_p
+    _LIB = lib
+    return lib
+
+
+def _check(lib, status):
+    if status != GP_OK:
+        raise GalpicError(status, lib.gp_last_error().decode())
+
+
+class Particles:
+    """Device arrays of one run's particles (torch tensors, caller-owned).
+
+    FP64: x, y, z absolute positions (float64).  Mixed: ``cell`` int32 linear
+    index and offsets (float32).  Momenta u (float64 or float32); optional
+    int64 ids carried through reorderings.
+    """
+
+    def __init__(self, precision, q, m, w, u, x=None, cell=None, offset=None, ids=None,
+                 device="cuda"):
+        import torch
+
+        self.precision = precision
+        self.q, self.m, self.w = float(q), float(m), float(w)
+        if precision == GP_FP64:
+            dt = torch.float64
+            x = np.asarray(x, dtype=np.float64)
+            self.pos = [torch.tensor(np.ascontiguousarray(x[:, a]), device=device) for a in range(3)]
+            self.off = None
+            self.n = x.shape[0]
+        else:
+            dt = torch.float32
+            self.pos = [torch.tensor(np.ascontiguousarray(cell, dtype=np.int32), device=device)]
+            off = np.asarray(offset, dtype=np.float32)
+            self.off = [torch.tensor(np.ascontiguousarray(off[:, a]), device=device)
+                        for a in range(3)]
+            self.n = off.shape[0]
+        u = np.asarray(u)
+        self.u = [torch.tensor(np.ascontiguousarray(u[:, a]), dtype=dt, device=device)
+                  for a in range(3)]
+        self.ids = None if ids is None else torch.tensor(np.asarray(ids, dtype=np.int64),
+                                                         device=device)
+
+    def c_struct(self):
+        p = ParticlesC()
+        p.n = self.n
+        p.q, p.m, p.w = self.q, self.m, self.w
+        ptr = lambda t: t.data_ptr() if (t is not None and t.numel() > 0) else None
+        if self.precision == GP_FP64:
+            p.x, p.y, p.z = (ptr(t) for t in self.pos)
+        else:
+            p.x = ptr(self.pos[0])
+            p.off_x, p.off_y, p.off_z = (ptr(t) for t in self.off)
+        p.ux, p.uy, p.uz = (ptr(t) for t in self.u)
+        p.id = ptr(self.ids) if self.ids is not None else None
+        if self.n == 0:
+            # zero-length tensors may have no storage; pass a dummy pointer
+            p.x = p.x or 1
+        return p
+
+    def positions(self, shape=None, spacing=None):
+        """Absolute positions (n, 3) as float64 numpy (host copy)."""
+        if self.precision == GP_FP64:
+            return np.stack([t.cpu().numpy() for t in self.pos], axis=1)
+        nx, ny, nz = shape
+        cell = self.pos[0].cpu().numpy().astype(np.int64)
+        off = np.stack([t.cpu().numpy().astype(np.float64) for t in self.off], axis=1)
+        ix = cell // (ny * nz)
+        iy = (cell // nz) % ny
+        iz = cell % nz
+        d = np.asarray(spacing, dtype=np.float64)
+        return (np.stack([ix, iy, iz], axis=1) + off) * d[None, :]
+
+    def momenta(self):
+        return np.stack([t.cpu().numpy().astype(np.float64) for t in self.u], axis=1)
+
+    def id_array(self):
+        return None if self.ids is None else self.ids.cpu().numpy()
+
+
+class Context:
+    """One gp_ctx: n_runs runs of one precision and shape order."""
+
+    def __init__(self, grids, stream=None):
+        """grids: list of dicts with nx, ny, nz, dx, dy, dz, dt, order, precision."""
+        self.lib = load()
+        n = len(grids)
+        arr = (GridDesc * n)()
+        for i, g in enumerate(grids):
+            arr[i] = GridDesc(g["nx"], g["ny"], g["nz"], g.get("dx", 1.0), g.get("dy", 1.0),
+                              g.get("dz", 1.0), g["dt"], g["order"], g["precision"])
+        self.grids = grids
+        self.precision = grids[0]["precision"]
+        self.real = np.float64 if self.precision == GP_FP64 else np.float32
+        self.cplx = np.complex128 if self.precision == GP_FP64 else np.complex64
+        handle = ctypes.c_void_p()
+        _check(self.lib, self.lib.gp_init_grid(arr, n, stream, ctypes.byref(handle)))
+        self.h = handle
+        self._parts = None
+        self._parts_c = None
+
+    # -- lifecycle -------------------------------------------------------------
+    def close(self):
+        if self.h:
+            self.lib.gp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _call(self, name, *args):
+        _check(self.lib, getattr(self.lib, name)(self.h, *args))
+
+    # -- the C ABI, one method per call ---------------------------------------
+    def set_v_gal(self, run, v):
+        self._call("gp_set_v_gal", int(run), float(v[0]), float(v[1]), float(v[2]))
+
+    def bind_particles(self, parts):
+        import torch
+
+        torch.cuda.synchronize()
+        self._parts = list(parts)
+        arr = (ParticlesC * len(parts))()
+        for i, p in enumerate(parts):
+            arr[i] = p.c_struct()
+        self._parts_c = arr
+        self._call("gp_bind_particles", arr)
+
+    def deposit(self):
+        self._call("gp_deposit", self._parts_c)
+
+    def fft_fwd(self):
+        self._call("gp_fft_fwd")
+
+    def galilean_psatd_update(self):
+        self._call("gp_galilean_psatd_update")
+
+    def fft_inv(self):
+        self._call("gp_fft_inv")
+
+    def gather_push(self):
+        self._call("gp_gather_push", self._parts_c)
+
+    def half_push(self):
+        self._call("gp_half_push", self._parts_c)
+
+    def step(self):
+        self._call("gp_step", self._parts_c)
+
+    def step_graph(self, nsteps):
+        self._call("gp_step_graph", self._parts_c, int(nsteps))
+
+    def last_graph_ms(self):
+        ms = ctypes.c_double()
+        self._call("gp_last_graph_ms", ctypes.byref(ms))
+        return ms.value
+
+    def synchronize(self):
+        self._call("gp_synchronize")
+
+    def set_fields(self, run, E=None, B=None, project_transverse=False):
+        """E, B: tuples of three real numpy arrays (host) or None."""
+        keep = []
+
+        def ptrs(F):
+            if F is None:
+                return None
+            arr = (ctypes.c_void_p * 3)()
+            for a in range(3):
+                h = np.ascontiguousarray(F[a], dtype=self.real)
+                keep.append(h)
+                arr[a] = h.ctypes.data
+            return arr
+
+        self._call("gp_set_fields", int(run), ptrs(E), ptrs(B), 1 if project_transverse else 0)
+
+    def _shape(self, run, which):
+        g = self.grids[run]
+        name = FIELDS[which]
+        if name in ("EX", "EY", "EZ", "BX", "BY", "BZ", "JX", "JY", "JZ", "RHO"):
+            return (g["nx"], g["ny"], g["nz"]), self.real
+        return (g["nx"], g["ny"], g["nz"] // 2 + 1), self.cplx
+
+    def read_field(self, run, name):
+        which = FIELD[name]
+        shape, dt = self._shape(run, which)
+        out = np.empty(shape, dtype=dt)
+        self._call("gp_read_field", int(run), which, out.ctypes.data)
+        return out
+
+    def write_field(self, run, name, values):
+        which = FIELD[name]
+        shape, dt = self._shape(run, which)
+        arr = np.ascontiguousarray(np.broadcast_to(values, shape), dtype=dt)
+        self._call("gp_write_field", int(run), which, arr.ctypes.data)
+
+    def field_energy(self, run=0):
+        we, wb = ctypes.c_double(), ctypes.c_double()
+        self._call("gp_field_energy", int(run), ctypes.byref(we), ctypes.byref(wb))
+        return we.value, wb.value
+
+
+def grid_from_config(cfg, precision=None):
+    """Grid descriptor dict of a workload.RunConfig."""
+    prec = precision if precision is not None else (
+        GP_FP64 if cfg.precision == "fp64" else GP_MIXED)
+    return {"nx": cfg.shape[0], "ny": cfg.shape[1], "nz": cfg.shape[2],
+            "dx": cfg.spacing[0], "dy": cfg.spacing[1], "dz": cfg.spacing[2],
+            "dt": cfg.dt, "order": cfg.order, "precision": prec}
+
+
+def particles_from_inputs(inputs, cfg, precision, with_ids=True, device="cuda"):
+    """Device particles of a run from workload.particles_for output."""
+    ids = np.arange(inputs["n"], dtype=np.int64) if with_ids else None
+    if precision == GP_FP64:
+        return Particles(GP_FP64, cfg.q, cfg.m, cfg.w, inputs["u"], x=inputs["x"], ids=ids,
+                         device=device)
+    return Particles(GP_MIXED, cfg.q, cfg.m, cfg.w, inputs["u"], cell=inputs["cell"],
+                     offset=inputs["offset"], ids=ids, device=device)

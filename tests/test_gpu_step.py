@@ -1,0 +1,158 @@
+"""GPU parity of whole steps and step histories against the oracle, graph
+replay against eager steps, and the NCI pair on the GPU."""
+
+import numpy as np
+import pytest
+
+from oracle import diagnostics as odg
+from paper_1608_00215_amd import galpic as gp
+from workload import get_config, particles_for
+from tests.gpu_common import oracle_sim, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+def setup(cfg, precision, inp=None):
+    inp = particles_for(cfg) if inp is None else inp
+    ctx = gp.Context([gp.grid_from_config(cfg, precision)])
+    ctx.set_v_gal(0, cfg.v_gal())
+    parts = gp.particles_from_inputs(inp, cfg, precision)
+    ctx.bind_particles([parts])
+    return ctx, parts, inp
+
+
+def compare_state(ctx, parts, st, cfg, tol_f, tol_p):
+    errs = {}
+    for a, c in enumerate("XYZ"):
+        errs["E" + c] = rel_l2(ctx.read_field(0, "E" + c), st.E[a])
+        errs["B" + c] = rel_l2(ctx.read_field(0, "B" + c), st.B[a])
+    ids = parts.id_array()
+    errs["u"] = rel_l2(parts.momenta(), st.u[ids])
+    L = np.array(cfg.shape) * np.array(cfg.spacing)
+    d = np.abs(parts.positions(cfg.shape, cfg.spacing) - st.x[ids])
+    d = np.minimum(d, L[None, :] - d)
+    errs["x"] = float(d.max())
+    for k, v in errs.items():
+        tol = tol_p if k == "x" else tol_f
+        assert v <= tol, (k, v, errs)
+    return errs
+
+
+@pytest.mark.parametrize("galilean,steps,tol", [(True, 50, 1e-10), (False, 20, 1e-8)])
+def test_c1_history_fp64(gpu_lib, galilean, steps, tol):
+    """16x16x64 FP64 CIC drifting plasma: every step's field energy and the
+    final fields and particles match the oracle."""
+    cfg = get_config("c1_cic_fp64").with_(galilean=galilean)
+    ctx, parts, inp = setup(cfg, gp.GP_FP64)
+    sim = oracle_sim(cfg)
+    st = sim.initial_state(inp["x"], inp["u"])
+    for n in range(steps):
+        ctx.step()
+        st = sim.step(st)
+        we, wb = ctx.field_energy(0)
+        ow, ob = odg.field_energy(st.E, st.B, 1.0)
+        assert abs((we + wb) - (ow + ob)) <= tol * (ow + ob), (n, we + wb, ow + ob)
+    compare_state(ctx, parts, st, cfg, tol, 1e-9)
+    ctx.close()
+
+
+def test_step_calls_equal_gp_step(gpu_lib):
+    """The five ABI calls in order do exactly what gp_step does."""
+    cfg = get_config("c1_cic_fp64").with_(u_th=0.3)
+    ctx1, p1, inp = setup(cfg, gp.GP_FP64)
+    ctx2, p2, _ = setup(cfg, gp.GP_FP64, inp)
+    for _ in range(3):
+        ctx1.deposit()
+        ctx1.fft_fwd()
+        ctx1.galilean_psatd_update()
+        ctx1.fft_inv()
+        ctx1.gather_push()
+        ctx2.step()
+    for c in ("EX", "EY", "EZ", "BX", "BY", "BZ"):
+        assert rel_l2(ctx1.read_field(0, c), ctx2.read_field(0, c)) <= 1e-13
+    assert rel_l2(p1.momenta(), p2.momenta()) <= 1e-13
+    ctx1.close()
+    ctx2.close()
+
+
+@pytest.mark.parametrize("precision", [gp.GP_FP64, gp.GP_MIXED])
+def test_graph_replay_matches_eager(gpu_lib, precision):
+    """Graph replays (several, with eager work and synchronisation between
+    them) give the same state as eager steps."""
+    cfg = get_config("c2_lite").with_(u_th=0.2)
+    ctx1, p1, inp = setup(cfg, precision)
+    ctx2, p2, _ = setup(cfg, precision, inp)
+    tol = 1e-12 if precision == gp.GP_FP64 else 2e-5
+    for rep in range(3):
+        ctx2.step_graph(3)
+        ctx2.synchronize()
+        for _ in range(3):
+            ctx1.step()
+        ctx1.field_energy(0)     # eager work between replays
+        for c in ("EX", "EZ", "BY"):
+            assert rel_l2(ctx2.read_field(0, c), ctx1.read_field(0, c)) <= tol, (rep, c)
+        assert rel_l2(p2.momenta(), p1.momenta()) <= tol
+    assert ctx2.last_graph_ms() > 0
+    ctx1.close()
+    ctx2.close()
+
+
+@pytest.mark.parametrize("name", ["c2_lite", "c3_lite"])
+def test_mixed_one_step(gpu_lib, name):
+    """Mixed precision, cubic: one step from an identical state matches the
+    FP64 oracle to the mixed tolerance."""
+    from workload import laser_fields
+
+    cfg = get_config(name)
+    ctx, parts, inp = setup(cfg, gp.GP_MIXED)
+    sim = oracle_sim(cfg)
+    lf = laser_fields(cfg)
+    if lf is not None:
+        E0 = tuple(a.astype(np.float32).astype(np.float64) for a in lf[0])
+        B0 = tuple(a.astype(np.float32).astype(np.float64) for a in lf[1])
+        ctx.set_fields(0, E0, B0, project_transverse=True)
+        st = sim.initial_state(inp["x"], inp["u"], E0, B0, project_transverse=True)
+    else:
+        st = sim.initial_state(inp["x"], inp["u"])
+    ctx.step()
+    st = sim.step(st)
+    compare_state(ctx, parts, st, cfg, 1e-5, 2e-6)
+    ctx.close()
+
+
+def test_mixed_history_c2_lite(gpu_lib):
+    """Mixed precision over 20 steps: per-field error and energy drift vs the
+    FP64 oracle stay small (reported growth, stated bound)."""
+    cfg = get_config("c2_lite")
+    ctx, parts, inp = setup(cfg, gp.GP_MIXED)
+    sim = oracle_sim(cfg)
+    st = sim.initial_state(inp["x"], inp["u"])
+    for n in range(cfg.steps):
+        ctx.step()
+        st = sim.step(st)
+        we, wb = ctx.field_energy(0)
+        ow, ob = odg.field_energy(st.E, st.B, 1.0)
+        assert abs((we + wb) - (ow + ob)) <= 1e-4 * (ow + ob), n
+    compare_state(ctx, parts, st, cfg, 1e-4, 1e-5)
+    ctx.close()
+
+
+def test_nci_pair_gpu(gpu_lib):
+    """Galilean (v_gal = v0) stays quiet, standard PSATD (v_gal = 0) grows;
+    same thresholds as the oracle's calibrated pair."""
+    cfg = get_config("c1_cic_fp64")
+    hist = {}
+    for galilean in (True, False):
+        c = cfg.with_(galilean=galilean)
+        ctx, parts, _ = setup(c, gp.GP_FP64)
+        W = []
+        for _ in range(50):
+            ctx.step()
+            we, wb = ctx.field_energy(0)
+            W.append(we + wb)
+        hist[galilean] = np.array(W)
+        ctx.close()
+    Wg, Ws = hist[True], hist[False]
+    assert np.max(Wg) <= 6.0 * Wg[0]
+    assert Ws[-1] >= 30.0 * Ws[0]
+    assert Ws[-1] >= 10.0 * Wg[-1]
