@@ -1,0 +1,230 @@
+"""Benchmark of the Galilean-PSATD PIC step on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+
+Runs W untimed steps, then K timed steps of the whole hot path (deposit,
+forward FFT, k-space update, inverse FFT, gather + Boris push) on the
+workload's seeded synthetic plasma, inputs resident in HBM, and prints one
+JSON line: particle-steps/s (the whole job), the per-kernel device times
+measured with HIP events on the library's stream, the roofline of the
+dominant kernel, the FP64 GPU path on the same workload, and the CPU
+oracle timed on a bounded sample of the workload on this host.
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+METRIC = "particle-steps/s per Galilean-PSATD PIC step (mixed vs FP64); % HBM peak"
+
+
+def stage_bytes(cfg, precision_fp64):
+    """Algorithmic HBM bytes of one launch of each stage (each array read or
+    written once): particles read/write their state once, grids once."""
+    rb = 8 if precision_fp64 else 4
+    cb = 2 * rb
+    pos = 24 if precision_fp64 else 16          # 3 doubles | int32 cell + 3 floats
+    nc, nk, npart = cfg.n_cells, cfg.n_modes, cfg.n_particles
+    return {
+        "zero_sources": 4 * nc * rb,
+        "sort": 0,                              # a flag check unless a re-sort is due
+        "deposit": npart * (pos + 3 * rb + pos) + 4 * nc * rb,
+        # read x, u; write u, x; read E, B (6 grids); write J, rho (4 grids)
+        "fused_push_deposit": npart * (pos + 3 * rb + 3 * rb + pos) + 10 * nc * rb,
+        "fft_fwd_z": 4 * (nc * rb + nk * cb),
+        "fft_fwd_y": 4 * 2 * nk * cb,
+        "fft_fwd_x": 4 * 2 * nk * cb,
+        "update": nk * cb * (11 + 6 + 6),
+        "fft_inv_x": 6 * 2 * nk * cb,
+        "fft_inv_y": 6 * 2 * nk * cb,
+        "fft_inv_z": 6 * (nk * cb + nc * rb),
+        "gather_push": npart * (pos + 3 * rb + 3 * rb) + 6 * nc * rb,
+    }
+
+
+def run_gpu(cfg, precision, steps, warmup, inputs):
+    import torch
+
+    from paper_1608_00215_amd import galpic as gp
+
+    ctx = gp.Context([gp.grid_from_config(cfg, precision)])
+    ctx.set_v_gal(0, cfg.v_gal())
+    parts = gp.particles_from_inputs(inputs, cfg, precision, with_ids=False)
+    ctx.bind_particles([parts])
+    if warmup > 0:
+        ctx.run(warmup)
+    ctx.synchronize()
+    ctx.stage_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.run(steps)
+    ctx.synchronize()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    stage = ctx.stage_times()
+    ctx.stage_timing(False)
+    sorts = ctx.sort_count(0)
+    # the same steps replayed from a captured HIP graph
+    ctx.step_graph(1)
+    ctx.synchronize()
+    ctx.step_graph(steps)
+    graph_ms = ctx.last_graph_ms()
+    we, wb = ctx.field_energy(0)
+    ctx.close()
+    del parts
+    torch.cuda.empty_cache()
+    return {"wall_s": wall,
+            "stage_ms": {k: ms / n for k, (ms, n) in stage.items() if n > 0},
+            "stage_launches": {k: n for k, (ms, n) in stage.items() if n > 0},
+            "graph_ms_per_step": graph_ms / steps, "field_energy": we + wb, "sorts": sorts}
+
+
+def traffic_from_profiles(kernel_stage, fp64):
+    """HBM bytes per launch measured with rocprofv3 counters, if a summary for
+    this kernel exists and its source has not changed since."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path)).get(("fp64:" if fp64 else "mixed:") + kernel_stage)
+    except (OSError, ValueError):
+        return None
+    if not rec:
+        return None
+    src = os.path.join(ROOT, rec["source"])
+    if not os.path.exists(src):
+        return None
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    return rec["bytes_per_launch"] if digest == rec["source_sha256"] else None
+
+
+def cpu_baseline(cfg):
+    """The oracle, as it stands, on a sub-box of the workload (same
+    particles per cell, shape, drift and thermal spread; fewer cells)."""
+    from oracle import pic
+    from workload import particles_for
+
+    sub = cfg.with_(shape=(64, 64, 64))
+    inp = particles_for(sub)
+    g = pic.Grid(sub.shape, sub.spacing, sub.dt, sub.order)
+    sim = pic.Simulation(g, pic.Species(sub.q, sub.m, sub.w), sub.v_gal())
+    st = sim.initial_state(inp["x"], inp["u"])
+    t0 = time.perf_counter()
+    st = sim.step(st)
+    t = time.perf_counter() - t0
+    return {"value": sub.n_particles / t, "unit": "particle-steps/s", "cores": 1,
+            "kind": "oracle",
+            "sample": (f"one oracle step (numpy, single thread) on a {sub.shape[0]}x"
+                       f"{sub.shape[1]}x{sub.shape[2]} sub-box of the workload "
+                       f"({sub.n_particles} particles, same ppc/shape/drift), "
+                       f"{t:.1f} s; coefficient set-up not timed")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c2_cubic_mixed")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU comparison")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); the "
+              "multi-GPU decomposition is a design, not an implementation", file=sys.stderr)
+        sys.exit(2)
+    rank = int(os.environ.get("RANK", "0"))
+
+    from paper_1608_00215_amd import galpic as gp
+    from workload import get_config, particles_for
+
+    cfg = get_config(args.workload)
+    inputs = particles_for(cfg)
+    print(f"[bench] {cfg.name}: grid {cfg.shape}, {cfg.n_particles} particles", file=sys.stderr,
+          flush=True)
+    mixed = run_gpu(cfg, gp.GP_MIXED, args.steps, args.warmup, inputs)
+    print(f"[bench] mixed: {mixed['wall_s'] / args.steps * 1e3:.3f} ms/step", file=sys.stderr,
+          flush=True)
+    fp64 = None
+    if not args.no_fp64:
+        fp64 = run_gpu(cfg, gp.GP_FP64, args.steps, args.warmup, inputs)
+        print(f"[bench] fp64: {fp64['wall_s'] / args.steps * 1e3:.3f} ms/step",
+              file=sys.stderr, flush=True)
+    del inputs
+
+    ms_step = mixed["wall_s"] / args.steps * 1e3
+    value = cfg.n_particles * args.steps / mixed["wall_s"]
+    alg = stage_bytes(cfg, False)
+    # dominant = the kernel with the largest share of the step
+    share = {k: v * mixed["stage_launches"][k] for k, v in mixed["stage_ms"].items()}
+    dominant = max(share, key=share.get)
+    dom_ms = mixed["stage_ms"][dominant]
+    achieved = alg[dominant] / (dom_ms * 1e-3) / 1e9
+    stages = {k: {"ms_per_launch": round(v, 5), "launches": mixed["stage_launches"][k],
+                  "gbs": round(alg[k] / (v * 1e-3) / 1e9, 1) if (v > 0 and alg[k]) else None}
+              for k, v in mixed["stage_ms"].items()}
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"{cfg.name}: {cfg.shape[0]}x{cfg.shape[1]}x{cfg.shape[2]} periodic "
+                         f"grid, {cfg.ppc} electrons/cell, gamma {cfg.gamma:g} drift, u_th "
+                         f"{cfg.u_th:g}, v_gal = drift, order-{cfg.order} shape, mixed "
+                         "precision (int32 cell + f32 offsets, f32 FFT/update/push, f64 "
+                         "coefficients)"),
+            "grid": list(cfg.shape),
+            "particles": cfg.n_particles,
+            "cells": cfg.n_cells,
+            "precision": "mixed",
+        },
+        "grid_updates_per_s": cfg.n_cells * args.steps / mixed["wall_s"],
+        "graph_ms_per_step": mixed["graph_ms_per_step"],
+        "tile_sorts": mixed["sorts"],
+        "stages": stages,
+        "roofline": {
+            "kernel": dominant,
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic_from_profiles(dominant, False),
+        },
+    }
+    if fp64 is not None:
+        line["fp64_gpu"] = {
+            "value": cfg.n_particles * args.steps / fp64["wall_s"],
+            "unit": "particle-steps/s",
+            "ms_per_step": fp64["wall_s"] / args.steps * 1e3,
+            "graph_ms_per_step": fp64["graph_ms_per_step"],
+            "stages_ms": {k: round(v, 5) for k, v in fp64["stage_ms"].items()},
+            "field_energy_rel_diff_vs_mixed": abs(fp64["field_energy"] - mixed["field_energy"])
+            / max(abs(fp64["field_energy"]), 1e-300),
+        }
+    if rank == 0 and not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(cfg)
+    if rank == 0:
+        print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

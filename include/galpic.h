@@ -15,8 +15,9 @@
  * One step is the sequence
  *     gp_deposit -> gp_fft_fwd -> gp_galilean_psatd_update -> gp_fft_inv
  *     -> gp_gather_push
- * or gp_step / gp_step_graph, which run the same work (the gather-push of
- * one step fused with the deposit of the next).
+ * or gp_step / gp_run / gp_step_graph, which run the same work (over
+ * several steps the gather-push of one step is fused with the deposit of
+ * the next).
  *
  * Conventions
  *  - Normalised units: c = eps0 = 1.  Lengths in c/omega_p, times in
@@ -178,8 +179,14 @@ gp_status gp_gather_push(gp_ctx *ctx, const gp_particles *p);
  * gather_push), equivalent to the five calls above. */
 gp_status gp_step(gp_ctx *ctx, const gp_particles *p);
 
-/* nsteps full steps replayed from a captured HIP graph (captured on first
- * use per particle binding).  Equivalent to nsteps gp_step calls. */
+/* nsteps full steps, equivalent to nsteps gp_step calls; the gather-push
+ * of each step is fused with the deposit of the next into one particle
+ * pass. */
+gp_status gp_run(gp_ctx *ctx, const gp_particles *p, int nsteps);
+
+/* As gp_run, replayed from HIP graphs captured on first use (recaptured
+ * after gp_bind_particles or gp_set_v_gal).  The context stream must not
+ * be the null stream. */
 gp_status gp_step_graph(gp_ctx *ctx, const gp_particles *p, int nsteps);
 
 /* Set E^0 and B^0 of one run from real-space arrays (device or host
@@ -206,6 +213,21 @@ gp_status gp_field_energy(gp_ctx *ctx, int run, double *we, double *wb);
 /* Device time of the last gp_step_graph replay in milliseconds (HIP
  * events on the context stream; synchronising). */
 gp_status gp_last_graph_ms(gp_ctx *ctx, double *ms);
+
+/* Per-kernel device timing.  While enabled, gp_step, gp_run and the
+ * single-call entry points record HIP events on the context stream around
+ * each kernel stage (one launch per run each; names from gp_stage_name).
+ * gp_stage_times returns, per stage, the summed milliseconds and the number
+ * of recorded launches, then clears them (synchronising).  Graph replays
+ * are not recorded. */
+#define GP_N_STAGES 12
+gp_status gp_stage_timing(gp_ctx *ctx, int enable);
+gp_status gp_stage_times(gp_ctx *ctx, double ms[GP_N_STAGES], int count[GP_N_STAGES]);
+const char *gp_stage_name(int stage);
+
+/* Number of tile sorts performed on run's particles since binding
+ * (synchronising). */
+gp_status gp_sort_count(gp_ctx *ctx, int run, int *sorts);
 
 /* Wait until all work enqueued on the context's stream has finished. */
 gp_status gp_synchronize(gp_ctx *ctx);

@@ -1,9 +1,10 @@
 // C ABI of the Galilean-PSATD step (declared in include/galpic.h).
 //
 // Host-side orchestration only: validation, device allocation, the order of
-// kernel launches, the rho^n / rho^{n+1} buffer rotation and HIP graph
-// capture.  All arithmetic of the step runs in the kernels.
-#include "../../include/galpic.h"
+// kernel launches, the rho^n / rho^{n+1} buffer rotation, per-kernel event
+// timing and HIP graph capture.  All arithmetic of the step runs in the
+// kernels.
+#include "galpic.h"
 
 #include <cmath>
 #include <cstring>
@@ -30,10 +31,10 @@ gp_status fail(gp_status st, const std::string &msg) {
       return fail(GP_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_));      \
   } while (0)
 
-#define GP_TRY(expr)                \
-  do {                              \
-    gp_status st_ = (expr);         \
-    if (st_ != GP_OK) return st_;   \
+#define GP_TRY(expr)              \
+  do {                            \
+    gp_status st_ = (expr);       \
+    if (st_ != GP_OK) return st_; \
   } while (0)
 
 gp_status check_launch(const char *what) {
@@ -49,21 +50,40 @@ int ilog2(int n) {
   return l;
 }
 
+// Kernel stages of a step (names: gp_stage_name).
+enum {
+  kStZero = 0, kStSort, kStDeposit, kStFused, kStFwdZ, kStFwdY, kStFwdX, kStUpdate, kStInvX,
+  kStInvY, kStInvZ, kStGather, kNStages
+};
+static_assert(kNStages == GP_N_STAGES, "stage count");
+const char *const kStageNames[kNStages] = {
+    "zero_sources", "sort",      "deposit",   "fused_push_deposit", "fft_fwd_z", "fft_fwd_y",
+    "fft_fwd_x",    "update",    "fft_inv_x", "fft_inv_y",          "fft_inv_z", "gather_push"};
+
 enum { kReal = 10, kSpec = 11 };
+// real[] slots: 0-2 E, 3-5 B, 6-8 J, 9 rho
 // spec[] slots: 0-2 E^, 3-5 B^, 6-8 J^, 9-10 rho buffers (rotating)
 
 struct Run {
   RunGeom g{};
+  TileGeom tg{};
   void *real[kReal] = {};
   void *spec[kSpec] = {};
   void *coef[6] = {};
   void *scratch[6] = {};
-  int rho_old = 9;          // spec slot holding rho^n; the other holds rho^{n+1}
+  int rho_old = 9;              // spec slot holding rho^n; the other holds rho^{n+1}
   PartPtrs parts{};
   bool bound = false;
+  SortBufs sb{};
+  std::vector<void *> sort_allocs;  // freed on re-binding
   bool src_real_ready = false;  // J, rho deposited since the last forward FFT
   bool src_spec_ready = false;  // J^, rho^{n+1} ready for the update
   bool eb_real_ready = true;    // real E, B match the spectral state
+};
+
+struct StageRec {
+  int stage;
+  hipEvent_t a, b;
 };
 
 }  // namespace
@@ -78,29 +98,40 @@ struct gp_ctx {
   std::vector<void *> allocs;
   void *tw = nullptr;
   double *d_sum = nullptr;
-  hipGraphExec_t graph[2] = {nullptr, nullptr};
+  // captured graphs: first deposit; per rho parity: field cycle + fused
+  // particle pass; field cycle + final gather-push
+  hipGraphExec_t g_first = nullptr;
+  hipGraphExec_t g_mid[2] = {nullptr, nullptr};
+  hipGraphExec_t g_last[2] = {nullptr, nullptr};
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   bool timed = false;
+  bool stage_timing = false;
+  std::vector<StageRec> stage_recs;
 };
 
 namespace {
 
-gp_status dev_alloc(gp_ctx *c, size_t bytes, void **out) {
+gp_status dev_alloc(std::vector<void *> &list, size_t bytes, void **out) {
   void *p = nullptr;
   hipError_t e = hipMalloc(&p, bytes < 256 ? 256 : bytes);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     return fail(GP_ERR_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
   }
-  c->allocs.push_back(p);
+  list.push_back(p);
   *out = p;
   return GP_OK;
 }
 
 void drop_graphs(gp_ctx *c) {
-  for (auto &gx : c->graph) {
+  auto drop = [](hipGraphExec_t &gx) {
     if (gx) (void)hipGraphExecDestroy(gx);
     gx = nullptr;
+  };
+  drop(c->g_first);
+  for (int k = 0; k < 2; ++k) {
+    drop(c->g_mid[k]);
+    drop(c->g_last[k]);
   }
 }
 
@@ -115,14 +146,15 @@ gp_status validate_desc(const gp_grid_desc &d, int i) {
     return fail(GP_ERR_ARG, w + "nx, ny, nz must be powers of two");
   if (d.nx < 8 || d.ny < 8 || d.nz < 8 || d.nx > 1024 || d.ny > 1024 || d.nz > 1024)
     return fail(GP_ERR_ARG, w + "nx, ny, nz must lie in [8, 1024]");
-  if (!(d.dx > 0) || !(d.dy > 0) || !(d.dz > 0) || !(d.dt > 0))
-    return fail(GP_ERR_ARG, w + "dx, dy, dz, dt must be positive");
+  if (!(d.dx > 0) || !(d.dy > 0) || !(d.dz > 0) || !(d.dt > 0) || !std::isfinite(d.dx) ||
+      !std::isfinite(d.dy) || !std::isfinite(d.dz) || !std::isfinite(d.dt))
+    return fail(GP_ERR_ARG, w + "dx, dy, dz, dt must be positive and finite");
   if (d.shape_order != 1 && d.shape_order != 3)
     return fail(GP_ERR_ARG, w + "shape_order must be 1 or 3");
   if (d.precision != GP_FP64 && d.precision != GP_MIXED)
     return fail(GP_ERR_ARG, w + "precision must be GP_FP64 or GP_MIXED");
-  if (int64_t(d.nx) * d.ny * d.nz > (int64_t(1) << 31) - 1)
-    return fail(GP_ERR_ARG, w + "grid too large for int32 cell indices");
+  if (int64_t(d.nx) * d.ny * d.nz > (int64_t(1) << 30))
+    return fail(GP_ERR_ARG, w + "grid too large (at most 2^30 cells)");
   return GP_OK;
 }
 
@@ -146,6 +178,27 @@ GridPtrs<T> grid_ptrs(const Run &r) {
   g.rho = R<T>(r, 9);
   return g;
 }
+
+// Records device events around one stage when timing is on.
+struct Stamp {
+  gp_ctx *c;
+  StageRec rec{};
+  bool on;
+  Stamp(gp_ctx *ctx, int stage) : c(ctx), on(ctx->stage_timing) {
+    if (!on) return;
+    rec.stage = stage;
+    if (hipEventCreate(&rec.a) != hipSuccess || hipEventCreate(&rec.b) != hipSuccess) {
+      on = false;
+      return;
+    }
+    (void)hipEventRecord(rec.a, c->stream);
+  }
+  ~Stamp() {
+    if (!on) return;
+    (void)hipEventRecord(rec.b, c->stream);
+    c->stage_recs.push_back(rec);
+  }
+};
 
 // Forward 3D FFT of nf real arrays into nf half spectra (held modes zeroed).
 template <typename T>
@@ -181,17 +234,24 @@ void fft_inverse(gp_ctx *c, const Run &r, const void *const *in, void *const *ou
   launch_c2r_z<T>(z, nf, r.g, tw, c->stream);
 }
 
+// Zero J and rho, sort if flagged, then deposit (mode kPartDeposit) or run
+// the fused gather-push + deposit (kPartFused).
 template <typename T>
-void do_deposit(gp_ctx *c, Run &r) {
-  for (int q = 6; q < 10; ++q) launch_zero(r.real[q], real_bytes(c, r), c->stream);
-  launch_deposit<T>(r.g, r.parts, grid_ptrs<T>(r), c->stream);
-}
-
-template <typename T>
-void do_fft_fwd(gp_ctx *c, Run &r) {
-  const void *in[4] = {r.real[6], r.real[7], r.real[8], r.real[9]};
-  void *out[4] = {r.spec[6], r.spec[7], r.spec[8], r.spec[r.rho_old == 9 ? 10 : 9]};
-  fft_forward<T>(c, r, in, out, 4);
+void enqueue_sources(gp_ctx *c, int mode) {
+  {
+    Stamp s(c, kStZero);
+    for (auto &r : c->runs)
+      for (int q = 6; q < 10; ++q) launch_zero(r.real[q], real_bytes(c, r), c->stream);
+  }
+  {
+    Stamp s(c, kStSort);
+    for (auto &r : c->runs) launch_sort<T>(r.g, r.tg, r.parts, r.sb, c->stream);
+  }
+  {
+    Stamp s(c, mode == kPartFused ? kStFused : kStDeposit);
+    for (auto &r : c->runs)
+      launch_particles<T>(mode, r.g, r.tg, r.parts, grid_ptrs<T>(r), r.sb, r.g.dt, c->stream);
+  }
 }
 
 template <typename T>
@@ -210,41 +270,107 @@ void do_update(gp_ctx *c, Run &r) {
 }
 
 template <typename T>
-void do_fft_inv(gp_ctx *c, Run &r) {
-  const void *in[6] = {r.spec[0], r.spec[1], r.spec[2], r.spec[3], r.spec[4], r.spec[5]};
-  void *out[6] = {r.real[0], r.real[1], r.real[2], r.real[3], r.real[4], r.real[5]};
-  fft_inverse<T>(c, r, in, out, 6);
+void enqueue_fft_fwd(gp_ctx *c) {
+  const Cx<T> *tw = static_cast<const Cx<T> *>(c->tw);
+  auto set = [&](const Run &r, bool z) {
+    FieldSet fs{};
+    void *out[4] = {r.spec[6], r.spec[7], r.spec[8], r.spec[r.rho_old == 9 ? 10 : 9]};
+    for (int f = 0; f < 4; ++f) {
+      fs.in[f] = z ? r.real[6 + f] : out[f];
+      fs.out[f] = out[f];
+    }
+    return fs;
+  };
+  {
+    Stamp s(c, kStFwdZ);
+    for (auto &r : c->runs) launch_r2c_z<T>(set(r, true), 4, r.g, tw, c->stream);
+  }
+  {
+    Stamp s(c, kStFwdY);
+    for (auto &r : c->runs) launch_c2c<T>(set(r, false), 4, r.g, 1, false, false, tw, c->stream);
+  }
+  {
+    Stamp s(c, kStFwdX);
+    for (auto &r : c->runs) launch_c2c<T>(set(r, false), 4, r.g, 0, false, true, tw, c->stream);
+  }
 }
 
 template <typename T>
-void do_gather_push(gp_ctx *c, Run &r, double dt) {
-  launch_gather_push<T>(r.g, r.parts, grid_ptrs<T>(r), dt, c->stream);
-}
-
-// Enqueue one full step of every run (no state checks).
-template <typename T>
-void enqueue_step(gp_ctx *c) {
-  for (auto &r : c->runs) do_deposit<T>(c, r);
-  for (auto &r : c->runs) do_fft_fwd<T>(c, r);
+void enqueue_update(gp_ctx *c) {
+  Stamp s(c, kStUpdate);
   for (auto &r : c->runs) do_update<T>(c, r);
-  for (auto &r : c->runs) do_fft_inv<T>(c, r);
-  for (auto &r : c->runs) do_gather_push<T>(c, r, r.g.dt);
+}
+
+template <typename T>
+void enqueue_fft_inv(gp_ctx *c) {
+  const Cx<T> *tw = static_cast<const Cx<T> *>(c->tw);
+  auto set = [&](const Run &r, int pass) {
+    FieldSet fs{};
+    for (int f = 0; f < 6; ++f) {
+      fs.in[f] = pass == 0 ? r.spec[f] : r.scratch[f];
+      fs.out[f] = pass == 2 ? r.real[f] : r.scratch[f];
+    }
+    return fs;
+  };
+  {
+    Stamp s(c, kStInvX);
+    for (auto &r : c->runs) launch_c2c<T>(set(r, 0), 6, r.g, 0, true, false, tw, c->stream);
+  }
+  {
+    Stamp s(c, kStInvY);
+    for (auto &r : c->runs) launch_c2c<T>(set(r, 1), 6, r.g, 1, true, false, tw, c->stream);
+  }
+  {
+    Stamp s(c, kStInvZ);
+    for (auto &r : c->runs) launch_c2r_z<T>(set(r, 2), 6, r.g, tw, c->stream);
+  }
+}
+
+template <typename T>
+void enqueue_push(gp_ctx *c, double dt_factor) {
+  Stamp s(c, kStGather);
+  for (auto &r : c->runs)
+    launch_particles<T>(kPartPush, r.g, r.tg, r.parts, grid_ptrs<T>(r), r.sb,
+                        dt_factor * r.g.dt, c->stream);
+}
+
+template <typename T>
+void enqueue_field_cycle(gp_ctx *c) {
+  enqueue_fft_fwd<T>(c);
+  enqueue_update<T>(c);
+  enqueue_fft_inv<T>(c);
+}
+
+// nsteps whole steps; the gather-push of each step is fused with the
+// deposit of the next.
+template <typename T>
+void enqueue_run(gp_ctx *c, int nsteps) {
+  if (nsteps <= 0) return;
+  enqueue_sources<T>(c, kPartDeposit);
+  for (int s = 0; s + 1 < nsteps; ++s) {
+    enqueue_field_cycle<T>(c);
+    enqueue_sources<T>(c, kPartFused);
+  }
+  enqueue_field_cycle<T>(c);
+  enqueue_push<T>(c, 1.0);
 }
 
 gp_status check_particles(gp_ctx *c, const gp_particles *p) {
   if (!p) return fail(GP_ERR_ARG, "particles pointer is NULL");
   for (size_t i = 0; i < c->runs.size(); ++i) {
     const gp_particles &q = p[i];
-    if (q.n < 0) return fail(GP_ERR_ARG, "run " + std::to_string(i) + ": n < 0");
+    const std::string w = "run " + std::to_string(i) + ": ";
+    if (q.n < 0 || q.n > (int64_t(1) << 31) - 1)
+      return fail(GP_ERR_ARG, w + "n must lie in [0, 2^31)");
     if (q.n == 0) continue;
-    if (!q.x || !q.ux || !q.uy || !q.uz)
-      return fail(GP_ERR_ARG, "run " + std::to_string(i) + ": NULL particle array");
+    if (!q.x || !q.ux || !q.uy || !q.uz) return fail(GP_ERR_ARG, w + "NULL particle array");
     if (c->precision == GP_FP64 && (!q.y || !q.z))
-      return fail(GP_ERR_ARG, "run " + std::to_string(i) + ": NULL position array");
+      return fail(GP_ERR_ARG, w + "NULL position array");
     if (c->precision == GP_MIXED && (!q.off_x || !q.off_y || !q.off_z))
-      return fail(GP_ERR_ARG, "run " + std::to_string(i) + ": NULL offset array");
-    if (!(q.m > 0) || !(q.w >= 0))
-      return fail(GP_ERR_ARG, "run " + std::to_string(i) + ": mass must be > 0, weight >= 0");
+      return fail(GP_ERR_ARG, w + "NULL offset array");
+    if (!(q.m > 0) || !(q.w >= 0) || !std::isfinite(q.q) || !std::isfinite(q.m) ||
+        !std::isfinite(q.w))
+      return fail(GP_ERR_ARG, w + "mass must be > 0 and weight >= 0, all finite");
   }
   return GP_OK;
 }
@@ -271,7 +397,7 @@ PartPtrs to_parts(const gp_particles &q) {
 bool same_parts(const PartPtrs &a, const gp_particles &b) {
   return a.n == b.n && a.x == b.x && a.y == b.y && a.z == b.z && a.ox == b.off_x &&
          a.oy == b.off_y && a.oz == b.off_z && a.ux == b.ux && a.uy == b.uy && a.uz == b.uz &&
-         a.q == b.q && a.m == b.m && a.w == b.w;
+         a.id == b.id && a.q == b.q && a.m == b.m && a.w == b.w;
 }
 
 gp_status require_bound(gp_ctx *c, const gp_particles *p) {
@@ -283,6 +409,12 @@ gp_status require_bound(gp_ctx *c, const gp_particles *p) {
       return fail(GP_ERR_STATE, "run " + std::to_string(i) +
                                     ": particle arrays differ from the bound ones");
   }
+  return GP_OK;
+}
+
+gp_status require_eb(gp_ctx *c, const char *who) {
+  for (auto &r : c->runs)
+    if (!r.eb_real_ready) return fail(GP_ERR_STATE, std::string(who) + " needs real E and B");
   return GP_OK;
 }
 
@@ -324,11 +456,154 @@ void *field_slot(gp_ctx *c, Run &r, int which, size_t *bytes) {
   return nullptr;
 }
 
+void free_sort(Run &r) {
+  for (void *p : r.sort_allocs) (void)hipFree(p);
+  r.sort_allocs.clear();
+}
+
+gp_status alloc_sort(gp_ctx *c, Run &r) {
+  free_sort(r);
+  const size_t nt = size_t(r.tg.n_tiles) + 1;
+  const size_t ncell = size_t(r.tg.n_tiles) << r.tg.lcpt;
+  const size_t n = size_t(r.parts.n);
+  void *p = nullptr;
+  GP_TRY(dev_alloc(r.sort_allocs, ncell * sizeof(int), &p));
+  r.sb.cell_count = static_cast<int *>(p);
+  GP_TRY(dev_alloc(r.sort_allocs, ncell * sizeof(int), &p));
+  r.sb.cell_off = static_cast<int *>(p);
+  GP_TRY(dev_alloc(r.sort_allocs, nt * sizeof(int), &p));
+  r.sb.tile_total = static_cast<int *>(p);
+  GP_TRY(dev_alloc(r.sort_allocs, nt * sizeof(int), &p));
+  r.sb.start = static_cast<int *>(p);
+  GP_TRY(dev_alloc(r.sort_allocs, n * sizeof(int), &p));
+  r.sb.key = static_cast<int *>(p);
+  GP_TRY(dev_alloc(r.sort_allocs, n * sizeof(int), &p));
+  r.sb.rank = static_cast<int *>(p);
+  GP_TRY(dev_alloc(r.sort_allocs, 4 * sizeof(int), &p));
+  r.sb.state = static_cast<int *>(p);
+  const int ncol = c->precision == GP_FP64 ? 6 : 7;
+  for (int k = 0; k < 8; ++k) r.sb.tmp[k] = nullptr;
+  for (int k = 0; k < ncol; ++k) {
+    GP_TRY(dev_alloc(r.sort_allocs, n * c->real_size, &p));
+    r.sb.tmp[k] = p;
+  }
+  if (r.parts.id) {
+    GP_TRY(dev_alloc(r.sort_allocs, n * sizeof(int64_t), &p));
+    r.sb.tmp[ncol] = p;
+  }
+  // a sort is forced at the first decision; the tile table starts empty
+  const int init[4] = {0, 0, 0, 1};
+  GP_HIP(hipMemcpyAsync(r.sb.state, init, sizeof(init), hipMemcpyHostToDevice, c->stream));
+  launch_zero(r.sb.start, nt * sizeof(int), c->stream);
+  GP_HIP(hipStreamSynchronize(c->stream));
+  return GP_OK;
+}
+
+gp_status capture(gp_ctx *c, hipGraphExec_t *out, void (*body)(gp_ctx *)) {
+  hipGraph_t graph = nullptr;
+  GP_HIP(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+  body(c);
+  hipError_t le = hipGetLastError();
+  hipError_t ee = hipStreamEndCapture(c->stream, &graph);
+  if (le != hipSuccess || ee != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return fail(GP_ERR_HIP, std::string("graph capture failed: ") +
+                                hipGetErrorString(le != hipSuccess ? le : ee));
+  }
+  hipError_t ie = hipGraphInstantiateWithFlags(out, graph, 0);
+  (void)hipGraphDestroy(graph);
+  if (ie != hipSuccess)
+    return fail(GP_ERR_HIP, std::string("graph instantiate failed: ") + hipGetErrorString(ie));
+  return GP_OK;
+}
+
+template <typename T>
+void body_first(gp_ctx *c) {
+  enqueue_sources<T>(c, kPartDeposit);
+}
+template <typename T>
+void body_mid(gp_ctx *c) {
+  enqueue_field_cycle<T>(c);
+  enqueue_sources<T>(c, kPartFused);
+}
+template <typename T>
+void body_last(gp_ctx *c) {
+  enqueue_field_cycle<T>(c);
+  enqueue_push<T>(c, 1.0);
+}
+
+template <typename T>
+gp_status build_graphs(gp_ctx *c) {
+  const bool timing = c->stage_timing;
+  c->stage_timing = false;
+  std::vector<int> saved(c->runs.size());
+  for (size_t i = 0; i < c->runs.size(); ++i) saved[i] = c->runs[i].rho_old;
+  gp_status st = capture(c, &c->g_first, body_first<T>);
+  for (int k = 0; k < 2 && st == GP_OK; ++k) {
+    for (auto &r : c->runs) r.rho_old = 9 + k;
+    st = capture(c, &c->g_mid[k], body_mid<T>);
+    if (st == GP_OK) {
+      for (auto &r : c->runs) r.rho_old = 9 + k;
+      st = capture(c, &c->g_last[k], body_last<T>);
+    }
+  }
+  for (size_t i = 0; i < c->runs.size(); ++i) c->runs[i].rho_old = saved[i];
+  c->stage_timing = timing;
+  if (st != GP_OK) drop_graphs(c);
+  return st;
+}
+
+void mark_step_done(gp_ctx *c) {
+  for (auto &r : c->runs) {
+    r.src_real_ready = false;
+    r.src_spec_ready = false;
+    r.eb_real_ready = true;
+  }
+}
+
+gp_status check_run(gp_ctx *c, int run) {
+  GP_TRY(check_ctx(c));
+  if (run < 0 || run >= int(c->runs.size())) return fail(GP_ERR_ARG, "run out of range");
+  return GP_OK;
+}
+
 }  // namespace
 
 extern "C" {
 
 const char *gp_last_error(void) { return g_err.c_str(); }
+
+const char *gp_stage_name(int i) { return (i >= 0 && i < kNStages) ? kStageNames[i] : ""; }
+
+gp_status gp_stage_timing(gp_ctx *c, int enable) {
+  GP_TRY(check_ctx(c));
+  c->stage_timing = enable != 0;
+  return GP_OK;
+}
+
+gp_status gp_stage_times(gp_ctx *c, double *ms, int *count) {
+  GP_TRY(check_ctx(c));
+  if (!ms || !count) return fail(GP_ERR_ARG, "output pointer is NULL");
+  for (int i = 0; i < kNStages; ++i) {
+    ms[i] = 0.0;
+    count[i] = 0;
+  }
+  GP_HIP(hipStreamSynchronize(c->stream));
+  gp_status st = GP_OK;
+  for (const StageRec &rec : c->stage_recs) {
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, rec.a, rec.b) == hipSuccess) {
+      ms[rec.stage] += t;
+      count[rec.stage] += 1;
+    } else {
+      st = fail(GP_ERR_HIP, "hipEventElapsedTime failed");
+    }
+    (void)hipEventDestroy(rec.a);
+    (void)hipEventDestroy(rec.b);
+  }
+  c->stage_recs.clear();
+  return st;
+}
 
 gp_status gp_synchronize(gp_ctx *c) {
   GP_TRY(check_ctx(c));
@@ -338,8 +613,13 @@ gp_status gp_synchronize(gp_ctx *c) {
 
 gp_status gp_destroy(gp_ctx *c) {
   if (!c) return GP_OK;
-  drop_graphs(c);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
+  drop_graphs(c);
+  for (const StageRec &rec : c->stage_recs) {
+    (void)hipEventDestroy(rec.a);
+    (void)hipEventDestroy(rec.b);
+  }
+  for (auto &r : c->runs) free_sort(r);
   for (void *p : c->allocs) (void)hipFree(p);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
@@ -396,28 +676,29 @@ gp_status gp_init_grid(const gp_grid_desc *runs, int n_runs, void *hip_stream, g
     g.vgal[0] = g.vgal[1] = g.vgal[2] = 0.0;
     g.ncell = int64_t(d.nx) * d.ny * d.nz;
     g.nmode = int64_t(d.nx) * d.ny * g.nzh;
+    r.tg = make_tile_geom(g, c->real_size);
     for (auto &p : r.real) {
-      gp_status st = dev_alloc(c, real_bytes(c, r), &p);
+      gp_status st = dev_alloc(c->allocs, real_bytes(c, r), &p);
       if (st) return bail(st);
       launch_zero(p, real_bytes(c, r), c->stream);
     }
     for (auto &p : r.spec) {
-      gp_status st = dev_alloc(c, spec_bytes(c, r), &p);
+      gp_status st = dev_alloc(c->allocs, spec_bytes(c, r), &p);
       if (st) return bail(st);
       launch_zero(p, spec_bytes(c, r), c->stream);
     }
     for (auto &p : r.coef) {
-      gp_status st = dev_alloc(c, spec_bytes(c, r), &p);
+      gp_status st = dev_alloc(c->allocs, spec_bytes(c, r), &p);
       if (st) return bail(st);
     }
     for (auto &p : r.scratch) {
-      gp_status st = dev_alloc(c, spec_bytes(c, r), &p);
+      gp_status st = dev_alloc(c->allocs, spec_bytes(c, r), &p);
       if (st) return bail(st);
     }
   }
   {
     const size_t twb = 1024 * 2 * c->real_size;
-    gp_status st = dev_alloc(c, twb, &c->tw);
+    gp_status st = dev_alloc(c->allocs, twb, &c->tw);
     if (st) return bail(st);
     std::vector<char> host(twb);
     if (c->precision == GP_FP64)
@@ -429,7 +710,7 @@ gp_status gp_init_grid(const gp_grid_desc *runs, int n_runs, void *hip_stream, g
     if (hipStreamSynchronize(c->stream) != hipSuccess)
       return bail(fail(GP_ERR_HIP, "stream synchronize failed"));
     void *sum = nullptr;
-    st = dev_alloc(c, 2 * sizeof(double), &sum);
+    st = dev_alloc(c->allocs, 2 * sizeof(double), &sum);
     if (st) return bail(st);
     c->d_sum = static_cast<double *>(sum);
   }
@@ -444,14 +725,13 @@ gp_status gp_init_grid(const gp_grid_desc *runs, int n_runs, void *hip_stream, g
 }
 
 gp_status gp_set_v_gal(gp_ctx *c, int run, double vx, double vy, double vz) {
-  GP_TRY(check_ctx(c));
-  if (run < 0 || run >= int(c->runs.size())) return fail(GP_ERR_ARG, "run out of range");
+  GP_TRY(check_run(c, run));
   if (!std::isfinite(vx) || !std::isfinite(vy) || !std::isfinite(vz) ||
       vx * vx + vy * vy + vz * vz >= 1.0)
     return fail(GP_ERR_ARG, "|v_gal| must be finite and below c");
   Run &r = c->runs[run];
   RunGeom &g = r.g;
-  // largest |k.v_gal| dt over non-Nyquist modes
+  // largest |k.v_gal| dt over the non-Nyquist modes
   const int n[3] = {g.nx, g.ny, g.nz};
   const double d[3] = {g.dx, g.dy, g.dz};
   const double v[3] = {vx, vy, vz};
@@ -471,7 +751,7 @@ gp_status gp_set_v_gal(gp_ctx *c, int run, double vx, double vy, double vz) {
   else
     launch_coefficients<float>(g, cp, c->stream);
   GP_TRY(check_launch("coefficients"));
-  drop_graphs(c);
+  drop_graphs(c);  // kernel arguments carry v_gal
   return GP_OK;
 }
 
@@ -479,23 +759,28 @@ gp_status gp_bind_particles(gp_ctx *c, const gp_particles *p) {
   GP_TRY(check_ctx(c));
   GP_TRY(check_particles(c, p));
   drop_graphs(c);
+  GP_HIP(hipStreamSynchronize(c->stream));
   for (size_t i = 0; i < c->runs.size(); ++i) {
     Run &r = c->runs[i];
+    r.bound = false;
     r.parts = to_parts(p[i]);
+    GP_TRY(alloc_sort(c, r));
     r.bound = true;
   }
-  return dispatch(c, [&](auto t) {
+  GP_TRY(dispatch(c, [&](auto t) {
     using T = decltype(t);
     for (auto &r : c->runs) {
       launch_zero(r.real[9], real_bytes(c, r), c->stream);
-      launch_deposit_rho<T>(r.g, r.parts, grid_ptrs<T>(r), c->stream);
+      launch_sort<T>(r.g, r.tg, r.parts, r.sb, c->stream);
+      launch_particles<T>(kPartRho, r.g, r.tg, r.parts, grid_ptrs<T>(r), r.sb, 0.0, c->stream);
       const void *in[1] = {r.real[9]};
       void *out[1] = {r.spec[r.rho_old]};
       fft_forward<T>(c, r, in, out, 1);
       r.src_real_ready = false;
       r.src_spec_ready = false;
     }
-  });
+  }));
+  return GP_OK;
 }
 
 gp_status gp_deposit(gp_ctx *c, const gp_particles *p) {
@@ -503,7 +788,7 @@ gp_status gp_deposit(gp_ctx *c, const gp_particles *p) {
   GP_TRY(require_bound(c, p));
   GP_TRY(dispatch(c, [&](auto t) {
     using T = decltype(t);
-    for (auto &r : c->runs) do_deposit<T>(c, r);
+    enqueue_sources<T>(c, kPartDeposit);
   }));
   for (auto &r : c->runs) r.src_real_ready = true;
   return GP_OK;
@@ -515,7 +800,7 @@ gp_status gp_fft_fwd(gp_ctx *c) {
     if (!r.src_real_ready) return fail(GP_ERR_STATE, "gp_fft_fwd needs a deposit first");
   GP_TRY(dispatch(c, [&](auto t) {
     using T = decltype(t);
-    for (auto &r : c->runs) do_fft_fwd<T>(c, r);
+    enqueue_fft_fwd<T>(c);
   }));
   for (auto &r : c->runs) {
     r.src_real_ready = false;
@@ -531,7 +816,7 @@ gp_status gp_galilean_psatd_update(gp_ctx *c) {
       return fail(GP_ERR_STATE, "gp_galilean_psatd_update needs gp_fft_fwd first");
   GP_TRY(dispatch(c, [&](auto t) {
     using T = decltype(t);
-    for (auto &r : c->runs) do_update<T>(c, r);
+    enqueue_update<T>(c);
   }));
   for (auto &r : c->runs) {
     r.src_spec_ready = false;
@@ -544,7 +829,7 @@ gp_status gp_fft_inv(gp_ctx *c) {
   GP_TRY(check_ctx(c));
   GP_TRY(dispatch(c, [&](auto t) {
     using T = decltype(t);
-    for (auto &r : c->runs) do_fft_inv<T>(c, r);
+    enqueue_fft_inv<T>(c);
   }));
   for (auto &r : c->runs) r.eb_real_ready = true;
   return GP_OK;
@@ -553,39 +838,36 @@ gp_status gp_fft_inv(gp_ctx *c) {
 gp_status gp_gather_push(gp_ctx *c, const gp_particles *p) {
   GP_TRY(check_ctx(c));
   GP_TRY(require_bound(c, p));
-  for (auto &r : c->runs)
-    if (!r.eb_real_ready) return fail(GP_ERR_STATE, "gp_gather_push needs gp_fft_inv first");
+  GP_TRY(require_eb(c, "gp_gather_push"));
   return dispatch(c, [&](auto t) {
     using T = decltype(t);
-    for (auto &r : c->runs) do_gather_push<T>(c, r, r.g.dt);
+    enqueue_push<T>(c, 1.0);
   });
 }
 
 gp_status gp_half_push(gp_ctx *c, const gp_particles *p) {
   GP_TRY(check_ctx(c));
   GP_TRY(require_bound(c, p));
-  for (auto &r : c->runs)
-    if (!r.eb_real_ready) return fail(GP_ERR_STATE, "gp_half_push needs real E and B");
+  GP_TRY(require_eb(c, "gp_half_push"));
   return dispatch(c, [&](auto t) {
     using T = decltype(t);
-    for (auto &r : c->runs) do_gather_push<T>(c, r, 0.5 * r.g.dt);
+    enqueue_push<T>(c, 0.5);
   });
 }
 
-gp_status gp_step(gp_ctx *c, const gp_particles *p) {
+gp_status gp_step(gp_ctx *c, const gp_particles *p) { return gp_run(c, p, 1); }
+
+gp_status gp_run(gp_ctx *c, const gp_particles *p, int nsteps) {
   GP_TRY(check_ctx(c));
   GP_TRY(require_bound(c, p));
-  for (auto &r : c->runs)
-    if (!r.eb_real_ready) return fail(GP_ERR_STATE, "gp_step needs real E and B");
+  if (nsteps < 0) return fail(GP_ERR_ARG, "nsteps < 0");
+  GP_TRY(require_eb(c, "gp_run"));
+  if (nsteps == 0) return GP_OK;
   GP_TRY(dispatch(c, [&](auto t) {
     using T = decltype(t);
-    enqueue_step<T>(c);
+    enqueue_run<T>(c, nsteps);
   }));
-  for (auto &r : c->runs) {
-    r.src_real_ready = false;
-    r.src_spec_ready = false;
-    r.eb_real_ready = true;
-  }
+  mark_step_done(c);
   return GP_OK;
 }
 
@@ -593,56 +875,28 @@ gp_status gp_step_graph(gp_ctx *c, const gp_particles *p, int nsteps) {
   GP_TRY(check_ctx(c));
   GP_TRY(require_bound(c, p));
   if (nsteps < 0) return fail(GP_ERR_ARG, "nsteps < 0");
-  for (auto &r : c->runs)
-    if (!r.eb_real_ready) return fail(GP_ERR_STATE, "gp_step_graph needs real E and B");
-  if (c->own_stream == false && c->stream == nullptr)
-    return fail(GP_ERR_STATE, "graph capture needs a non-null stream");
-  // graph[k] is one step starting with rho^n in slot 9 + k
-  const int parity = c->runs[0].rho_old - 9;
-  if (!c->graph[0] || !c->graph[1]) {
-    drop_graphs(c);
-    std::vector<int> saved(c->runs.size());
-    for (size_t i = 0; i < c->runs.size(); ++i) saved[i] = c->runs[i].rho_old;
-    for (int k = 0; k < 2; ++k) {
-      for (auto &r : c->runs) r.rho_old = 9 + k;
-      hipGraph_t graph = nullptr;
-      GP_HIP(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-      if (c->precision == GP_FP64)
-        enqueue_step<double>(c);
-      else
-        enqueue_step<float>(c);
-      hipError_t le = hipGetLastError();
-      hipError_t ee = hipStreamEndCapture(c->stream, &graph);
-      if (le != hipSuccess || ee != hipSuccess) {
-        for (size_t i = 0; i < c->runs.size(); ++i) c->runs[i].rho_old = saved[i];
-        if (graph) (void)hipGraphDestroy(graph);
-        return fail(GP_ERR_HIP, std::string("graph capture failed: ") +
-                                    hipGetErrorString(le != hipSuccess ? le : ee));
-      }
-      hipError_t ie = hipGraphInstantiateWithFlags(&c->graph[k], graph, 0);
-      (void)hipGraphDestroy(graph);
-      if (ie != hipSuccess) {
-        for (size_t i = 0; i < c->runs.size(); ++i) c->runs[i].rho_old = saved[i];
-        drop_graphs(c);
-        return fail(GP_ERR_HIP, std::string("graph instantiate failed: ") + hipGetErrorString(ie));
-      }
-    }
-    for (size_t i = 0; i < c->runs.size(); ++i) c->runs[i].rho_old = saved[i];
+  GP_TRY(require_eb(c, "gp_step_graph"));
+  if (nsteps == 0) return GP_OK;
+  if (!c->g_first) {
+    if (c->precision == GP_FP64)
+      GP_TRY(build_graphs<double>(c));
+    else
+      GP_TRY(build_graphs<float>(c));
   }
-  int par = parity;
+  // all runs rotate their rho buffers together
+  int par = c->runs[0].rho_old - 9;
   GP_HIP(hipEventRecord(c->ev0, c->stream));
-  for (int s = 0; s < nsteps; ++s) {
-    GP_HIP(hipGraphLaunch(c->graph[par], c->stream));
+  GP_HIP(hipGraphLaunch(c->g_first, c->stream));
+  for (int s = 0; s + 1 < nsteps; ++s) {
+    GP_HIP(hipGraphLaunch(c->g_mid[par], c->stream));
     par ^= 1;
   }
+  GP_HIP(hipGraphLaunch(c->g_last[par], c->stream));
+  par ^= 1;
   GP_HIP(hipEventRecord(c->ev1, c->stream));
   c->timed = true;
-  for (auto &r : c->runs) {
-    r.rho_old = 9 + par;
-    r.src_real_ready = false;
-    r.src_spec_ready = false;
-    r.eb_real_ready = true;
-  }
+  for (auto &r : c->runs) r.rho_old = 9 + par;
+  mark_step_done(c);
   return GP_OK;
 }
 
@@ -657,10 +911,21 @@ gp_status gp_last_graph_ms(gp_ctx *c, double *ms) {
   return GP_OK;
 }
 
+gp_status gp_sort_count(gp_ctx *c, int run, int *sorts) {
+  GP_TRY(check_run(c, run));
+  if (!sorts) return fail(GP_ERR_ARG, "sorts is NULL");
+  Run &r = c->runs[run];
+  if (!r.bound) return fail(GP_ERR_STATE, "particles not bound");
+  int st[4];
+  GP_HIP(hipMemcpyAsync(st, r.sb.state, sizeof(st), hipMemcpyDeviceToHost, c->stream));
+  GP_HIP(hipStreamSynchronize(c->stream));
+  *sorts = st[2];
+  return GP_OK;
+}
+
 gp_status gp_set_fields(gp_ctx *c, int run, const void *const E[3], const void *const B[3],
                         int project_transverse) {
-  GP_TRY(check_ctx(c));
-  if (run < 0 || run >= int(c->runs.size())) return fail(GP_ERR_ARG, "run out of range");
+  GP_TRY(check_run(c, run));
   Run &r = c->runs[run];
   const size_t rb = real_bytes(c, r);
   for (int a = 0; a < 6; ++a) {
@@ -679,7 +944,7 @@ gp_status gp_set_fields(gp_ctx *c, int run, const void *const E[3], const void *
                       c->stream);
     launch_project<T>(r.g, S<T>(r, 3), S<T>(r, 4), S<T>(r, 5), project_transverse != 0,
                       c->stream);
-    do_fft_inv<T>(c, r);
+    fft_inverse<T>(c, r, out, r.real, 6);
   }));
   GP_HIP(hipStreamSynchronize(c->stream));
   r.eb_real_ready = true;
@@ -687,8 +952,7 @@ gp_status gp_set_fields(gp_ctx *c, int run, const void *const E[3], const void *
 }
 
 gp_status gp_read_field(gp_ctx *c, int run, int which, void *dst) {
-  GP_TRY(check_ctx(c));
-  if (run < 0 || run >= int(c->runs.size())) return fail(GP_ERR_ARG, "run out of range");
+  GP_TRY(check_run(c, run));
   if (!dst) return fail(GP_ERR_ARG, "dst is NULL");
   size_t bytes = 0;
   void *src = field_slot(c, c->runs[run], which, &bytes);
@@ -699,8 +963,7 @@ gp_status gp_read_field(gp_ctx *c, int run, int which, void *dst) {
 }
 
 gp_status gp_write_field(gp_ctx *c, int run, int which, const void *src) {
-  GP_TRY(check_ctx(c));
-  if (run < 0 || run >= int(c->runs.size())) return fail(GP_ERR_ARG, "run out of range");
+  GP_TRY(check_run(c, run));
   if (!src) return fail(GP_ERR_ARG, "src is NULL");
   if (which >= GP_COEF0 && which <= GP_COEF5)
     return fail(GP_ERR_ARG, "coefficient tables are read-only");
@@ -718,8 +981,7 @@ gp_status gp_write_field(gp_ctx *c, int run, int which, const void *src) {
 }
 
 gp_status gp_field_energy(gp_ctx *c, int run, double *we, double *wb) {
-  GP_TRY(check_ctx(c));
-  if (run < 0 || run >= int(c->runs.size())) return fail(GP_ERR_ARG, "run out of range");
+  GP_TRY(check_run(c, run));
   if (!we || !wb) return fail(GP_ERR_ARG, "output pointer is NULL");
   Run &r = c->runs[run];
   launch_zero(c->d_sum, 2 * sizeof(double), c->stream);

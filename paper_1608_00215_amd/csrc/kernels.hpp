@@ -71,18 +71,45 @@ struct GridPtrs {
   T *J[3];
   T *rho;
 };
-// Deposit J at the half-way position and rho at the end position, moving
-// the particles by (v - v_gal) dt in two halves.  Grids must be zeroed.
+
+// Particles are grouped by tiles of t[a] cells per axis; a tile's node
+// region spans e[a] = t[a] + (shape width - 1) nodes per axis.
+struct TileGeom {
+  int t[3], lt[3], nt[3], e[3];
+  int margin;    // cells beyond the tile still covered by its node region
+  int lcpt;      // log2 of cells per tile
+  int n_tiles;
+  int region;
+};
+TileGeom make_tile_geom(const RunGeom &g, size_t real_size);
+
+// Device buffers of the tile sort of one run.
+struct SortBufs {
+  int *cell_count;  // n_cells: particles per (tile-major) cell
+  int *cell_off;    // n_cells: first particle of the cell inside its tile
+  int *tile_total;  // n_tiles
+  int *start;       // n_tiles + 1: first particle of each tile, then the total
+  int *key;         // n particles: tile-major cell index
+  int *rank;        // n particles: rank inside the cell
+  int *state;       // [0] fallback count, [1] sort flag, [2] sorts done, [3] force
+  void *tmp[8];     // scratch columns for the scatter
+};
+
+// Sort the particles by tile when flagged (state[3] forces it; otherwise
+// when more than n/64 particles used the global fallback since the last
+// decision).  Every kernel checks the flag on the device, so the launch
+// sequence is fixed and can be captured in a graph.
 template <typename T>
-void launch_deposit(const RunGeom &g, const PartPtrs &p, const GridPtrs<T> &gr,
-                    hipStream_t s);
-// rho at the current positions (no move).
+void launch_sort(const RunGeom &g, const TileGeom &tg, const PartPtrs &p, const SortBufs &sb,
+                 hipStream_t s);
+
+enum { kPartRho = 0, kPartDeposit = 1, kPartFused = 2, kPartPush = 3 };
+// Tile kernels: rho at the current positions; deposit (move, J, move, rho);
+// fused (gather + push through dt_push, then deposit); push (gather + push).
+// Deposits add into the grids, which the caller zeroes first.
 template <typename T>
-void launch_deposit_rho(const RunGeom &g, const PartPtrs &p, const GridPtrs<T> &gr,
-                        hipStream_t s);
-// Gather E, B at the positions and Boris-push u through dt_push.
-template <typename T>
-void launch_gather_push(const RunGeom &g, const PartPtrs &p, const GridPtrs<T> &gr,
-                        double dt_push, hipStream_t s);
+void launch_particles(int mode, const RunGeom &g, const TileGeom &tg, const PartPtrs &p,
+                      const GridPtrs<T> &gr, const SortBufs &sb, double dt_push,
+                      hipStream_t s);
 
 }  // namespace galpic

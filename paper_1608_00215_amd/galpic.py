@@ -29,7 +29,9 @@ EXPORTS = ["gp_init_grid", "gp_set_v_gal", "gp_bind_particles", "gp_deposit", "g
            "gp_galilean_psatd_update", "gp_fft_inv", "gp_gather_push", "gp_step",
            "gp_step_graph", "gp_set_fields", "gp_half_push", "gp_read_field",
            "gp_write_field", "gp_field_energy", "gp_last_graph_ms", "gp_synchronize",
-           "gp_destroy", "gp_last_error"]
+           "gp_stage_timing", "gp_stage_times", "gp_stage_name", "gp_sort_count",
+           "gp_run", "gp_destroy", "gp_last_error"]
+GP_N_STAGES = 12
 
 
 class GridDesc(ctypes.Structure):
@@ -86,6 +88,10 @@ def load(path=LIB_PATH):
         "gp_field_energy": [vp, i32, ctypes.POINTER(dbl), ctypes.POINTER(dbl)],
         "gp_last_graph_ms": [vp, ctypes.POINTER(dbl)],
         "gp_synchronize": [vp],
+        "gp_stage_timing": [vp, i32],
+        "gp_stage_times": [vp, ctypes.POINTER(dbl), ctypes.POINTER(i32)],
+        "gp_sort_count": [vp, i32, ctypes.POINTER(i32)],
+        "gp_run": [vp, vp, i32],
         "gp_destroy": [vp],
     }
     for name, args in sig.items():
@@ -94,8 +100,21 @@ def load(path=LIB_PATH):
         fn.restype = ctypes.c_int
     lib.gp_last_error.argtypes = []
     lib.gp_last_error.restype = ctypes.c_char_p
+    lib.gp_stage_name.argtypes = [i32]
+    lib.gp_stage_name.restype = ctypes.c_char_p
     _LIB = lib
     return lib
+
+
+def _init_torch_first():
+    """Let PyTorch initialise the HIP runtime before the library touches it,
+    so torch tensors and the library share one device context."""
+    try:
+        import torch
+    except ImportError:
+        return
+    if torch.cuda.is_available():
+        torch.cuda.init()
 
 
 def _check(lib, status):
@@ -179,6 +198,7 @@ class Context:
     def __init__(self, grids, stream=None):
         """grids: list of dicts with nx, ny, nz, dx, dy, dz, dt, order, precision."""
         self.lib = load()
+        _init_torch_first()
         n = len(grids)
         arr = (GridDesc * n)()
         for i, g in enumerate(grids):
@@ -255,6 +275,25 @@ class Context:
 
     def synchronize(self):
         self._call("gp_synchronize")
+
+    def stage_timing(self, enable=True):
+        self._call("gp_stage_timing", 1 if enable else 0)
+
+    def stage_times(self):
+        """{stage name: (summed ms, launches)} recorded since timing was enabled."""
+        ms = (ctypes.c_double * GP_N_STAGES)()
+        n = (ctypes.c_int * GP_N_STAGES)()
+        self._call("gp_stage_times", ms, n)
+        names = [self.lib.gp_stage_name(i).decode() for i in range(GP_N_STAGES)]
+        return {nm: (ms[i], n[i]) for i, nm in enumerate(names)}
+
+    def sort_count(self, run=0):
+        n = ctypes.c_int()
+        self._call("gp_sort_count", int(run), ctypes.byref(n))
+        return n.value
+
+    def run(self, nsteps):
+        self._call("gp_run", self._parts_c, int(nsteps))
 
     def set_fields(self, run, E=None, B=None, project_transverse=False):
         """E, B: tuples of three real numpy arrays (host) or None."""
