@@ -1,0 +1,212 @@
+"""GPU parity at the benchmark size (128 x 128 x 256 grid, 33,554,432
+cubic-shape particles, mixed precision, the same launch configuration as
+bench.py), on outputs the oracle can compute one by one: sampled modes,
+sampled grid nodes from the particles around them, and sampled particles.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import coefficients as oco
+from oracle import particles as opt
+from oracle import spectral as osp
+from paper_1608_00215_amd import galpic as gp
+from workload import get_config, particles_for
+from tests.gpu_common import rel_l2
+
+pytestmark = pytest.mark.gpu
+
+CFG = get_config("c2_cubic_mixed")
+
+
+@pytest.fixture(scope="module")
+def full_inputs():
+    return particles_for(CFG)
+
+
+def fresh_ctx(precision=gp.GP_MIXED):
+    ctx = gp.Context([gp.grid_from_config(CFG, precision)])
+    ctx.set_v_gal(0, CFG.v_gal())
+    return ctx
+
+
+def sample_modes(shape, n, seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    nzh = shape[2] // 2 + 1
+    return (rng.integers(0, shape[0], n), rng.integers(0, shape[1], n), rng.integers(0, nzh, n))
+
+
+def half_k_at(idx, shape, spacing):
+    ix, iy, iz = idx
+    kx = osp.axis_wavenumbers(shape[0], spacing[0])[ix]
+    ky = osp.axis_wavenumbers(shape[1], spacing[1])[iy]
+    kz = 2 * np.pi * iz / (shape[2] * spacing[2])
+    return kx, ky, kz
+
+
+def held(idx, shape):
+    ix, iy, iz = idx
+    return ((ix == shape[0] // 2) | (iy == shape[1] // 2) | (iz == shape[2] // 2) |
+            ((ix == 0) & (iy == 0) & (iz == 0)))
+
+
+def test_coefficients_sampled(gpu_lib):
+    ctx = fresh_ctx()
+    idx = sample_modes(CFG.shape, 4000, 31)
+    live = ~held(idx, CFG.shape)
+    k = half_k_at(idx, CFG.shape, CFG.spacing)
+    coef = oco.galilean_psatd_coefficients(k, CFG.v_gal(), CFG.dt)
+    for i, key in enumerate(("c_EE", "s", "c_BJ", "c_EJ", "c_R1", "c_R0")):
+        got = ctx.read_field(0, f"COEF{i}")[idx]
+        assert rel_l2(got[live], coef[key][live]) <= 2e-7, key
+    ctx.close()
+
+
+def test_fft_forward_and_inverse_full(gpu_lib):
+    ctx = fresh_ctx()
+    rng = np.random.Generator(np.random.PCG64(32))
+    f = rng.standard_normal(CFG.shape).astype(np.float32)
+    ctx.write_field(0, "RHO", f)
+    for c in "XYZ":
+        ctx.write_field(0, "J" + c, np.zeros(CFG.shape, np.float32))
+    ctx.fft_fwd()
+    ref = osp.forward(f.astype(np.float64))
+    ref[osp.held_zero_mask(CFG.shape)] = 0
+    got = ctx.read_field(0, "RHO_HAT_NEW")
+    nzh = CFG.shape[2] // 2 + 1
+    assert rel_l2(got, ref[:, :, :nzh]) <= 1e-6
+    # inverse of the same spectrum through the E slot
+    ctx.write_field(0, "EX_HAT", got)
+    ctx.fft_inv()
+    back = ctx.read_field(0, "EX")
+    assert rel_l2(back, osp.inverse(ref)) <= 1e-6
+    ctx.close()
+
+
+def test_update_sampled(gpu_lib):
+    ctx = fresh_ctx()
+    rng = np.random.Generator(np.random.PCG64(33))
+    nzh = CFG.shape[2] // 2 + 1
+    hshape = (CFG.shape[0], CFG.shape[1], nzh)
+    arrays = {}
+    for name in ("EX_HAT", "EY_HAT", "EZ_HAT", "BX_HAT", "BY_HAT", "BZ_HAT", "JX_HAT",
+                 "JY_HAT", "JZ_HAT", "RHO_HAT_OLD", "RHO_HAT_NEW"):
+        a = (rng.standard_normal(hshape) + 1j * rng.standard_normal(hshape)).astype(np.complex64)
+        ctx.write_field(0, name, a)
+        arrays[name] = a
+    ctx.galilean_psatd_update()
+    idx = sample_modes(CFG.shape, 4000, 34)
+    k = half_k_at(idx, CFG.shape, CFG.spacing)
+    coef = oco.galilean_psatd_coefficients(k, CFG.v_gal(), CFG.dt)
+    take = lambda n: arrays[n][idx].astype(np.complex128)
+    E = tuple(take("E" + c + "_HAT") for c in "XYZ")
+    B = tuple(take("B" + c + "_HAT") for c in "XYZ")
+    J = tuple(take("J" + c + "_HAT") for c in "XYZ")
+    En, Bn = osp.galilean_psatd_update(E, B, J, take("RHO_HAT_OLD"), take("RHO_HAT_NEW"), k,
+                                       coef, held(idx, CFG.shape))
+    for a, c in enumerate("XYZ"):
+        assert rel_l2(ctx.read_field(0, "E" + c + "_HAT")[idx], En[a]) <= 1e-6
+        assert rel_l2(ctx.read_field(0, "B" + c + "_HAT")[idx], Bn[a]) <= 1e-6
+    ctx.close()
+
+
+def _window_particles(inp, lo, hi):
+    """Particles generated in cells lo..hi (inclusive, per axis, periodic)."""
+    nx, ny, nz = CFG.shape
+    xs = np.arange(lo[0], hi[0] + 1) % nx
+    ys = np.arange(lo[1], hi[1] + 1) % ny
+    zs = np.arange(lo[2], hi[2] + 1) % nz
+    cells = ((xs[:, None, None] * ny + ys[None, :, None]) * nz + zs[None, None, :]).ravel()
+    sel = (cells[:, None] * CFG.ppc + np.arange(CFG.ppc)[None, :]).ravel()
+    return sel
+
+
+def test_deposit_sampled_nodes(gpu_lib, full_inputs):
+    """J and rho at the nodes of a few 4x4x4 windows (including ones across
+    the periodic seams and tile edges) from the particles that can reach
+    them, deposited one by one by the oracle."""
+    inp = full_inputs
+    ctx = fresh_ctx()
+    cfg = CFG
+    rng = np.random.Generator(np.random.PCG64(35))
+    u = inp["u"].copy()
+    # transverse momenta ~ 10: |v_perp| up to ~0.5 c, so particles cross
+    # cells and tile edges during the two half moves
+    u[:, :2] = (10.0 * rng.standard_normal((u.shape[0], 2))).astype(np.float32)
+    parts = gp.particles_from_inputs({**inp, "u": u}, cfg, gp.GP_MIXED, with_ids=False)
+    ctx.bind_particles([parts])
+    ctx.deposit()
+    J = [ctx.read_field(0, "J" + c) for c in "XYZ"]
+    rho = ctx.read_field(0, "RHO")
+    v = opt.lab_velocity(u)
+    L = np.array(CFG.shape) * np.array(CFG.spacing)
+    qw = CFG.q * CFG.w
+    for corner in [(0, 0, 0), (61, 17, 130), (127, 127, 255), (40, 100, 7)]:
+        lo = np.array(corner) - 4
+        hi = np.array(corner) + 7
+        sel = _window_particles(inp, lo, hi)
+        x, vv = inp["x"][sel], v[sel]
+        xh = opt.half_move(x, vv, CFG.v_gal(), CFG.dt, L)
+        x1 = opt.half_move(xh, vv, CFG.v_gal(), CFG.dt, L)
+        Jref = opt.deposit(xh, vv, CFG.shape, CFG.spacing, 3) * qw
+        rref = opt.deposit(x1, np.ones(len(sel)), CFG.shape, CFG.spacing, 3)[0] * qw
+        nodes = tuple((np.asarray(corner)[:, None] + np.arange(4)[None, :]) % np.array(CFG.shape)[:, None])
+        win = np.ix_(*nodes)
+        for a in range(3):
+            assert rel_l2(J[a][win], Jref[a][win]) <= 1e-5, (corner, a)
+        assert rel_l2(rho[win], rref[win]) <= 1e-5, corner
+    ctx.close()
+
+
+def test_gather_push_sampled(gpu_lib, full_inputs):
+    inp = full_inputs
+    ctx = fresh_ctx()
+    parts = gp.particles_from_inputs(inp, CFG, gp.GP_MIXED, with_ids=True)
+    ctx.bind_particles([parts])
+    rng = np.random.Generator(np.random.PCG64(36))
+    fields = [(0.2 * rng.standard_normal(CFG.shape)).astype(np.float32) for _ in range(6)]
+    for nm, f in zip(("EX", "EY", "EZ", "BX", "BY", "BZ"), fields):
+        ctx.write_field(0, nm, f)
+    ctx.gather_push()
+    ctx.synchronize()
+    ids = parts.id_array()
+    got = parts.momenta()
+    pick = rng.integers(0, len(ids), 20000)
+    orig = ids[pick]
+    x = parts.positions(CFG.shape, CFG.spacing)[pick]
+    F = opt.gather([f.astype(np.float64) for f in fields], x, CFG.shape, CFG.spacing, 3)
+    uref = opt.boris_push(inp["u"][orig], F[:3].T, F[3:].T, CFG.q, CFG.m, CFG.dt)
+    assert rel_l2(got[pick], uref) <= 1e-5
+    ctx.close()
+
+
+def test_full_step_properties(gpu_lib, full_inputs):
+    """One full step at the benchmark size: the deposited charge equals the
+    particles' total charge, the Galilean cold plasma does not move on the
+    first step (continuity holds: rho^1 = rho^0), and Gauss's law evolves as
+    the update prescribes (ik.E^1 - rho^1 = -theta^2 C rho^0 from E^0 = 0)."""
+    inp = full_inputs
+    cfg = CFG.with_(u_th=0.0)
+    ctx = fresh_ctx()
+    u = inp["u"].copy()
+    u[:, :2] = 0.0
+    u[:, 2] = cfg.drift_u()
+    parts = gp.particles_from_inputs({**inp, "u": u}, cfg, gp.GP_MIXED, with_ids=False)
+    ctx.bind_particles([parts])
+    rho0_hat = ctx.read_field(0, "RHO_HAT_OLD")
+    ctx.step()
+    rho = ctx.read_field(0, "RHO")
+    total = CFG.n_particles * CFG.q * CFG.w
+    assert abs(rho.astype(np.float64).sum() - total) <= 1e-6 * abs(total)
+    rho1_hat = ctx.read_field(0, "RHO_HAT_OLD")
+    assert rel_l2(rho1_hat, rho0_hat) <= 1e-6
+    idx = sample_modes(CFG.shape, 4000, 37)
+    live = ~held(idx, CFG.shape)
+    kx, ky, kz = half_k_at(idx, CFG.shape, CFG.spacing)
+    E = [ctx.read_field(0, "E" + c + "_HAT")[idx].astype(np.complex128) for c in "XYZ"]
+    gauss = 1j * (kx * E[0] + ky * E[1] + kz * E[2]) - rho1_hat[idx]
+    kmag = np.sqrt(kx * kx + ky * ky + kz * kz)
+    theta2 = np.exp(1j * kz * CFG.v_gal()[2] * CFG.dt)
+    expect = -theta2 * np.cos(kmag * CFG.dt) * rho0_hat[idx]
+    assert rel_l2(gauss[live], expect[live]) <= 1e-5
+    ctx.close()
