@@ -52,14 +52,26 @@ def stage_bytes(cfg, precision_fp64):
 
 
 def run_gpu(cfg, precision, steps, warmup, inputs):
+    """Time one run (cfg, inputs) or a batch of runs (lists of both)."""
     import torch
 
     from paper_1608_00215_amd import galpic as gp
+    from workload import laser_fields
 
-    ctx = gp.Context([gp.grid_from_config(cfg, precision)])
-    ctx.set_v_gal(0, cfg.v_gal())
-    parts = gp.particles_from_inputs(inputs, cfg, precision, with_ids=False)
-    ctx.bind_particles([parts])
+    cfgs = cfg if isinstance(cfg, list) else [cfg]
+    inps = inputs if isinstance(inputs, list) else [inputs]
+    ctx = gp.Context([gp.grid_from_config(c, precision) for c in cfgs])
+    for r, c in enumerate(cfgs):
+        ctx.set_v_gal(r, c.v_gal())
+    parts = [gp.particles_from_inputs(i, c, precision, with_ids=False)
+             for c, i in zip(cfgs, inps)]
+    ctx.bind_particles(parts)
+    for r, c in enumerate(cfgs):
+        lf = laser_fields(c)
+        if lf is not None:
+            ctx.set_fields(r, lf[0], lf[1], project_transverse=True)
+    if any(c.laser is not None for c in cfgs):
+        ctx.half_push()
     if warmup > 0:
         ctx.run(warmup)
     ctx.synchronize()
@@ -72,7 +84,7 @@ def run_gpu(cfg, precision, steps, warmup, inputs):
     wall = time.perf_counter() - t0
     stage = ctx.stage_times()
     ctx.stage_timing(False)
-    sorts = ctx.sort_count(0)
+    sorts = sum(ctx.sort_count(r) for r in range(len(cfgs)))
     # the same steps replayed from a captured HIP graph
     ctx.step_graph(1)
     ctx.synchronize()
@@ -100,11 +112,28 @@ def traffic_from_profiles(kernel_stage, fp64):
         return None
     if not rec:
         return None
-    src = os.path.join(ROOT, rec["source"])
-    if not os.path.exists(src):
-        return None
-    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    return rec["bytes_per_launch"] if digest == rec["source_sha256"] else None
+    for rel, want in rec["sources"].items():
+        src = os.path.join(ROOT, rel)
+        if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != want:
+            return None
+    return rec["bytes_per_launch"]
+
+
+class BatchView:
+    """Totals of a batch of runs, shaped like a RunConfig for the report."""
+
+    def __init__(self, runs):
+        self.runs = runs
+        self.name = "c5_batched"
+        self.shape = ("batch of %d runs" % len(runs),)
+        self.n_particles = sum(r.n_particles for r in runs)
+        self.n_cells = sum(r.n_cells for r in runs)
+        self.n_modes = sum(r.n_modes for r in runs)
+        self.ppc = runs[0].ppc
+        self.order = runs[0].order
+        self.gamma = float(np.mean([r.gamma for r in runs]))
+        self.u_th = runs[0].u_th
+        self.laser = None
 
 
 def cpu_baseline(cfg):
@@ -129,6 +158,24 @@ def cpu_baseline(cfg):
                        f"{t:.1f} s; coefficient set-up not timed")}
 
 
+def workload_text(cfg):
+    prec = ("mixed precision (int32 cell + f32 offsets, f32 FFT/update/push, f64 "
+            "coefficients, double tile sums)")
+    if isinstance(cfg, BatchView):
+        return (f"{cfg.name}: {len(cfg.runs)} independent drifting-plasma runs, grids from "
+                "{32,64}^2 x {64,128,256}, gamma ~ U[5,50], density ~ U[0.5,2], "
+                f"{cfg.ppc} electrons/cell, u_th {cfg.u_th:g}, v_gal = drift, order-{cfg.order} "
+                f"shape, {prec}; one context, per-run kernels in one captured graph")
+    laser = ""
+    if cfg.laser is not None:
+        lp = cfg.laser
+        laser = (f", Gaussian laser a0 {lp['a0']:g} waist {lp['waist']:g} wavelength "
+                 f"{lp['wavelength']:g} length {lp['length']:g} cells moving +z")
+    return (f"{cfg.name}: {cfg.shape[0]}x{cfg.shape[1]}x{cfg.shape[2]} periodic grid, "
+            f"{cfg.ppc} electrons/cell, gamma {cfg.gamma:g} drift, u_th {cfg.u_th:g}, "
+            f"v_gal = drift{laser}, order-{cfg.order} shape, {prec}")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -137,6 +184,9 @@ def main():
     ap.add_argument("--workload", default="c2_cubic_mixed")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first copy MIB MiB device-to-device three times (a plain copy "
+                         "kernel of known size for scaling HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); the "
@@ -147,16 +197,38 @@ def main():
     from paper_1608_00215_amd import galpic as gp
     from workload import get_config, particles_for
 
-    cfg = get_config(args.workload)
-    inputs = particles_for(cfg)
+    if args.copy_calibration > 0:
+        import torch
+
+        n = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] copy calibration: {args.copy_calibration} MiB x 3", file=sys.stderr,
+              flush=True)
+        del src, dst
+
+    if args.workload == "c5_batched":
+        from workload import batched_runs
+
+        runs = batched_runs()
+        cfg = BatchView(runs)
+        inputs = [particles_for(c) for c in runs]
+        run_arg = runs
+    else:
+        cfg = get_config(args.workload)
+        inputs = particles_for(cfg)
+        run_arg = cfg
     print(f"[bench] {cfg.name}: grid {cfg.shape}, {cfg.n_particles} particles", file=sys.stderr,
           flush=True)
-    mixed = run_gpu(cfg, gp.GP_MIXED, args.steps, args.warmup, inputs)
+    mixed = run_gpu(run_arg, gp.GP_MIXED, args.steps, args.warmup, inputs)
     print(f"[bench] mixed: {mixed['wall_s'] / args.steps * 1e3:.3f} ms/step", file=sys.stderr,
           flush=True)
     fp64 = None
     if not args.no_fp64:
-        fp64 = run_gpu(cfg, gp.GP_FP64, args.steps, args.warmup, inputs)
+        fp64 = run_gpu(run_arg, gp.GP_FP64, args.steps, args.warmup, inputs)
         print(f"[bench] fp64: {fp64['wall_s'] / args.steps * 1e3:.3f} ms/step",
               file=sys.stderr, flush=True)
     del inputs
@@ -186,11 +258,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": (f"{cfg.name}: {cfg.shape[0]}x{cfg.shape[1]}x{cfg.shape[2]} periodic "
-                         f"grid, {cfg.ppc} electrons/cell, gamma {cfg.gamma:g} drift, u_th "
-                         f"{cfg.u_th:g}, v_gal = drift, order-{cfg.order} shape, mixed "
-                         "precision (int32 cell + f32 offsets, f32 FFT/update/push, f64 "
-                         "coefficients)"),
+            "workload": workload_text(cfg),
             "grid": list(cfg.shape),
             "particles": cfg.n_particles,
             "cells": cfg.n_cells,
@@ -221,7 +289,7 @@ def main():
             / max(abs(fp64["field_energy"]), 1e-300),
         }
     if rank == 0 and not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(cfg)
+        line["cpu_baseline"] = cpu_baseline(cfg.runs[0] if isinstance(cfg, BatchView) else cfg)
     if rank == 0:
         print(json.dumps(line), flush=True)
 
