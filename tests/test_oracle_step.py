@@ -83,3 +83,39 @@ def test_nci_pair_galilean_quiet_standard_grows():
     assert np.max(Wg) <= 6.0 * Wg[0]
     assert Ws[-1] >= 30.0 * Ws[0]
     assert Ws[-1] >= 10.0 * Wg[-1]
+
+
+def test_transverse_projection():
+    """The laser start removes the part of E^0, B^0 along k: a field built
+    as a curl (transverse) plus a gradient (longitudinal) comes back as the
+    curl alone, and the result has no divergence."""
+    shape, spacing = (8, 8, 16), (1.0, 1.0, 0.7)
+    cfg = get_config("c1_cic_fp64").with_(shape=shape, spacing=spacing, ppc=1)
+    sim = make_sim(cfg)
+    rng = np.random.Generator(np.random.PCG64(77))
+    kk = np.meshgrid(*[2 * np.pi * np.fft.fftfreq(n, d) for n, d in zip(shape, spacing)],
+                     indexing="ij")
+    nyq = np.zeros(shape, bool)
+    nyq[shape[0] // 2] = nyq[:, shape[1] // 2] = nyq[:, :, shape[2] // 2] = True
+
+    def smooth(a):
+        h = np.fft.fftn(a)
+        h[nyq] = 0
+        return h
+
+    A = [smooth(rng.standard_normal(shape)) for _ in range(3)]
+    phi = smooth(rng.standard_normal(shape))
+    curl = [1j * (kk[(a + 1) % 3] * A[(a + 2) % 3] - kk[(a + 2) % 3] * A[(a + 1) % 3])
+            for a in range(3)]
+    grad = [1j * kk[a] * phi for a in range(3)]
+    FT = [np.fft.ifftn(c).real for c in curl]
+    FL = [np.fft.ifftn(g).real for g in grad]
+    x = np.full((1, 3), 0.5)
+    u = np.zeros((1, 3))
+    st = sim.initial_state(x, u, [FT[a] + FL[a] for a in range(3)], FT, project_transverse=True)
+    scale = max(np.abs(f).max() for f in FT)
+    for a in range(3):
+        np.testing.assert_allclose(st.E[a], FT[a], atol=1e-12 * scale)
+        np.testing.assert_allclose(st.B[a], FT[a], atol=1e-12 * scale)
+    div = sum(kk[a] * np.fft.fftn(st.E[a]) for a in range(3))
+    assert np.abs(div).max() <= 1e-11 * scale * np.prod(shape)
