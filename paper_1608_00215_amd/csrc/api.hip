@@ -495,6 +495,7 @@ gp_status alloc_sort(gp_ctx *c, Run &r) {
   const int init[4] = {0, 0, 0, 1};
   GP_HIP(hipMemcpyAsync(r.sb.state, init, sizeof(init), hipMemcpyHostToDevice, c->stream));
   launch_zero(r.sb.start, nt * sizeof(int), c->stream);
+  launch_zero(r.sb.cell_count, ncell * sizeof(int), c->stream);
   GP_HIP(hipStreamSynchronize(c->stream));
   return GP_OK;
 }

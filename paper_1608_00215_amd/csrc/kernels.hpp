@@ -75,11 +75,15 @@ struct GridPtrs {
 // Particles are grouped by tiles of t[a] cells per axis; a tile's node
 // region spans e[a] = t[a] + (shape width - 1) nodes per axis.
 struct TileGeom {
-  int t[3], lt[3], nt[3], e[3];
+  int t[3], lt[3], nt[3];
+  int e[3];      // node region extents: tile + shape width - 1 + 2 margin
+  int ce[3];     // bucket block extents: tile + 2 margin cells
   int margin;    // cells beyond the tile still covered by its node region
   int lcpt;      // log2 of cells per tile
   int n_tiles;
-  int region;
+  int region;    // nodes in the region
+  int nb;        // buckets (cells of the bucket block); bucket nb: beyond it
+  int cap;       // particles the per-tile bucket list holds
 };
 TileGeom make_tile_geom(const RunGeom &g, size_t real_size);
 

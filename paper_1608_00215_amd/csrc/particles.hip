@@ -9,32 +9,39 @@
 //    s = 2 t / (1 + |t|^2), u' = u- + u- x t, u+ = u- + u' x s,
 //    u_new = u+ + h E with h = q dt / (2 m) (c = 1).
 //
-// GPU design.  Particles are kept sorted by tile (8x8x8 cells) and, inside a
-// tile, in slot-major order: first the first particle of every occupied
-// cell (cells in tile order), then the second particle of every cell with
-// two or more, and so on.  One 512-thread workgroup owns one tile; thread t
-// takes the tile's particles t, t + 512, ...  The loads are coalesced and
-// the lanes of a wave sit in different, neighbouring cells, so their LDS
-// atomics neither collide nor pile onto one bank.  The workgroup stages the
-// tile's node region (the tile plus the shape's halo) of E and B in LDS for
-// the gather, accumulates J and rho of its particles in LDS, and adds the
-// region into the global grid once at the end.  In mixed precision the
-// per-tile sums are carried in double (no-return LDS atomics), so the only
-// float roundings of a deposited value are the per-particle contribution and
-// the final conversion: the tile sum itself is compensated.  A particle
-// whose shape support leaves its tile's region (it drifted since the last
-// sort) uses global memory directly and is counted; the next step re-sorts
-// when that count passes n/64.
+// GPU design.  Particles are kept sorted by tile (8x8x8 cells).  One
+// workgroup owns one tile: it stages the tile's node region (the tile plus
+// the shape's halo and a drift margin) of E and B in LDS for the gather,
+// orders its particles by current cell in LDS, accumulates J and rho in
+// LDS, and adds the region into the global grid once at the end.  Groups of
+// four lanes (quads) take four particles of one cell at a time and share
+// that cell's node block between them (see the quad section).  In mixed
+// precision the per-tile sums are carried in double (no-return LDS
+// atomics): the float roundings of a deposited value are those of the
+// contributions of a quad's particles and their sum, and the final
+// conversion; the tile sum itself is compensated.  A particle whose shape
+// support leaves its tile's region (it drifted since the last sort) uses
+// global memory directly and is counted; the next step re-sorts when that
+// count passes n/64.
 //
 // Position layouts: FP64 stores absolute doubles in [0, L); the mixed form
 // stores an int32 linear cell index and float offsets in [0, 1), so that a
 // particle static on the Galilean grid keeps its position exactly.
+#include <algorithm>
+
 #include "kernels.hpp"
 
 namespace galpic {
 namespace {
 
-constexpr int kNT = 512;  // threads per tile workgroup
+constexpr int kNT = 512;          // threads per workgroup of the per-tile sort scan
+constexpr size_t kLdsBytes = 160 * 1024;  // LDS of one workgroup on gfx950
+// threads per tile workgroup of the particle kernel (8 waves per CU: the
+// fused float kernel needs ~160 registers per lane, the double one ~240;
+// 1024 threads would cap them at 128 and spill)
+constexpr int quad_threads(size_t) { return 512; }
+// static bucket-scan buffer of that workgroup
+constexpr size_t scan_bytes(size_t real_size) { return quad_threads(real_size) * sizeof(int); }
 
 template <int ORDER, typename T>
 struct Shape;
@@ -391,368 +398,430 @@ __device__ __forceinline__ int64_t region_node(int r, const Region &rg, const Ti
 
 enum { kModeRho = 0, kModeDeposit = 1, kModeFused = 2, kModePush = 3 };
 
-// Deposit batches.  Thread t of a tile's workgroup takes the tile's
-// particles t, t + kNT, ... in batches of K.  In slot-major order those
-// started out in one cell (tile cell t) and, in a cold or slowly drifting
-// plasma, move together, so they usually still share one cell: the batch
-// members in the cell of the batch's first particle share that cell's
-// 4x4x4 (or 2x2x2) node block, and their J and rho contributions to a node
-// are summed in registers before a single LDS atomic per node and quantity.
-// The others are deposited on their own.
-// Weight of node a (0 .. N-1, i.e. cell + FIRST + a) for offset d, for a
-// runtime a: the B-spline of the distance r = |d - FIRST - a|.
-template <int ORDER, typename T>
-__device__ __forceinline__ T weight_at(int a, T d) {
-  if constexpr (ORDER == 1) {
-    return a == 0 ? T(1) - d : d;
-  } else {
-    const T r = fabs(d + T(1) - T(a));
-    const T r2 = r * r;
-    const T s = T(2) - r;
-    return r < T(1) ? T(2.0 / 3.0) - r2 + T(0.5) * r2 * r : s * s * s * T(1.0 / 6.0);
+// ---- quads -----------------------------------------------------------------
+// Lanes 4k .. 4k+3 of a wave form a quad.  A quad takes up to four
+// particles of one cell at a time, one per lane.  While the four share a
+// cell they share its N^3 node block, and lane m works on a quarter of the
+// block (its N*N/4 (x, y) node rows) for all four particles: the gather
+// reads every node of the block once per quad instead of once per particle,
+// and the deposit adds the four particles' contributions to a node in
+// registers before one LDS atomic.  In slot s (0 .. 3) lane m handles the
+// particle of lane (m - s) mod 4; weights, values and partial sums move
+// between lanes by DPP rotations inside the quad (no LDS traffic).  A quad
+// whose particles do not share a block inside the tile's region falls back
+// to one particle per lane.
+
+template <int CTRL>
+__device__ __forceinline__ int dpp_int(int v) {
+  return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_val(float v) {
+  return __int_as_float(dpp_int<CTRL>(__float_as_int(v)));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_val(double v) {
+  const int lo = __double2loint(v);
+  const int hi = __double2hiint(v);
+  return __hiloint2double(dpp_int<CTRL>(hi), dpp_int<CTRL>(lo));
+}
+// quad_perm controls: lane m reads lane (m - s) mod 4 ...
+template <typename V>
+__device__ __forceinline__ V from_minus(V v, int s) {
+  switch (s) {
+    case 0: return v;
+    case 1: return dpp_val<0x93>(v);  // [3,0,1,2]
+    case 2: return dpp_val<0x4E>(v);  // [2,3,0,1]
+    default: return dpp_val<0x39>(v);  // [1,2,3,0]
   }
 }
+// ... or lane (m + s) mod 4
+template <typename V>
+__device__ __forceinline__ V from_plus(V v, int s) {
+  switch (s) {
+    case 0: return v;
+    case 1: return dpp_val<0x39>(v);
+    case 2: return dpp_val<0x4E>(v);
+    default: return dpp_val<0x93>(v);
+  }
+}
+__device__ __forceinline__ int lane0_int(int v) { return dpp_int<0x00>(v); }
+__device__ __forceinline__ bool quad_all(bool b) {
+  int v = b ? 1 : 0;
+  v &= dpp_int<0xB1>(v);  // [1,0,3,2]
+  v &= dpp_int<0x4E>(v);
+  return v != 0;
+}
 
-// deposit of NQ values per batch member flagged `in` into the block of
-// nodes whose first node is hb (region-local)
-template <int ORDER, typename T, typename A, int K, int NQ>
-__device__ __forceinline__ void deposit_home(const int hb[3], const TileGeom &tg, A *acc,
-                                             int q0, const bool in[K], const T ox[K],
-                                             const T wy[K][Shape<ORDER, T>::N],
-                                             const T wz[K][Shape<ORDER, T>::N],
-                                             const T val[K][NQ]) {
-  constexpr int N = Shape<ORDER, T>::N;
-  const int R = tg.region;
-#pragma unroll 1
-  for (int a = 0; a < N; ++a) {
-    T wxa[K];
+// The quad shares one node block when every lane's block starts at the same
+// region-local node and lies inside the region.
+template <int ORDER, typename T>
+__device__ __forceinline__ bool quad_block(const CellPos<T> &c, const Region &rg,
+                                           const TileGeom &tg, const RunGeom &g, int hb[3]) {
+  const bool in = region_base<ORDER, T>(c, rg, tg, g, hb);
+  const int key = (hb[0] * tg.e[1] + hb[1]) * tg.e[2] + hb[2];
+  return quad_all(in && key == lane0_int(key));
+}
+
+// Weights of the quad's particles for lane m's rows: slot s holds the
+// particle of lane (m - s) mod 4 with wxy[s][r] = wx(a) wy(b) for row r
+// (row m*ROWS + r of the block, a = row / N, b = row % N) and wz[s][e].
+template <int ORDER, typename T>
+struct QuadWeights {
+  using Sh = Shape<ORDER, T>;
+  static constexpr int N = Sh::N;
+  static constexpr int ROWS = N * N / 4;
+  T wxy[4][ROWS];
+  T wz[4][N];
+  __device__ __forceinline__ void build(const T o[3], int m) {
+    T wx[N], wy[N], wzo[N];
+    Sh::weights(o[0], wx);
+    Sh::weights(o[1], wy);
+    Sh::weights(o[2], wzo);
 #pragma unroll
-    for (int j = 0; j < K; ++j) wxa[j] = in[j] ? weight_at<ORDER, T>(a, ox[j]) : T(0);
+    for (int s = 0; s < 4; ++s) {
+      // this lane's particle goes to slot s of lane (m + s) mod 4: send
+      // that lane's row weights
+      const int dst = (m + s) & 3;
+      T send[ROWS];
+      if constexpr (N == 4) {
+        const T wxa = dst == 0 ? wx[0] : dst == 1 ? wx[1] : dst == 2 ? wx[2] : wx[3];
 #pragma unroll
-    for (int b = 0; b < N; ++b) {
-      const int row = ((hb[0] + a) * tg.e[1] + (hb[1] + b)) * tg.e[2] + hb[2];
-#pragma unroll
-      for (int e = 0; e < N; ++e) {
-        T sum[NQ];
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) sum[q] = T(0);
-#pragma unroll
-        for (int j = 0; j < K; ++j) {
-          const T wj = wxa[j] * wy[j][b] * wz[j][e];
-#pragma unroll
-          for (int q = 0; q < NQ; ++q) sum[q] += wj * val[j][q];
-        }
-#pragma unroll
-        for (int q = 0; q < NQ; ++q)
-          __hip_atomic_fetch_add(acc + size_t(q0 + q) * R + row + e, A(sum[q]), __ATOMIC_RELAXED,
-                                 __HIP_MEMORY_SCOPE_WORKGROUP);
+        for (int r = 0; r < ROWS; ++r) send[r] = wxa * wy[r];
+      } else {
+        send[0] = ((dst >> 1) ? wx[1] : wx[0]) * ((dst & 1) ? wy[1] : wy[0]);
       }
-      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int r = 0; r < ROWS; ++r) wxy[s][r] = from_minus(send[r], s);
+#pragma unroll
+      for (int e = 0; e < N; ++e) wz[s][e] = from_minus(wzo[e], s);
     }
   }
-}
-
-template <int ORDER, typename T>
-__device__ __forceinline__ bool same_cell(const CellPos<T> &c, const int cell[3]) {
-  return c.i[0] == cell[0] && c.i[1] == cell[1] && c.i[2] == cell[2];
-}
-
-// Everything the tile kernel needs besides the particle index.
-template <class L>
-struct TileCtx {
-  using T = typename L::T;
-  RunGeom g;
-  TileGeom tg;
-  PartPtrs p;
-  GridPtrs<T> gr;
-  Region rg;
-  T qw, h;
-  int *fallback;
 };
 
-// Gather E, B at particle k's current position (LDS region or global) and
-// push its momentum through the step h was built for.
-template <class L, int ORDER>
-__device__ __forceinline__ void push_one(const TileCtx<L> &tc, int64_t k,
-                                         const typename L::T *fld) {
-  using T = typename L::T;
-  const typename L::State st = load_state<L>(tc.p, k, tc.g);
-  T u[3] = {static_cast<const T *>(tc.p.ux)[k], static_cast<const T *>(tc.p.uy)[k],
-            static_cast<const T *>(tc.p.uz)[k]};
-  const CellPos<T> c = L::cell(st, tc.g);
-  Support<ORDER, T> s;
-  support_of<ORDER, T>(c, tc.rg, tc.tg, tc.g, s);
-  T F[6];
-  gather<ORDER, T>(c, s, tc.tg, tc.g, fld, tc.gr, F);
-  boris(u, F, tc.h);
-  static_cast<T *>(tc.p.ux)[k] = u[0];
-  static_cast<T *>(tc.p.uy)[k] = u[1];
-  static_cast<T *>(tc.p.uz)[k] = u[2];
+// region-local index of the first node of lane m's row r in the block hb
+template <int ORDER>
+__device__ __forceinline__ int quad_row(const int hb[3], int m, int r, const TileGeom &tg) {
+  constexpr int N = ORDER == 1 ? 2 : 4;
+  constexpr int ROWS = N * N / 4;
+  const int row = m * ROWS + r;
+  return ((hb[0] + row / N) * tg.e[1] + (hb[1] + row % N)) * tg.e[2] + hb[2];
 }
 
-// Per-particle deposit of particle k from memory (position x^n, current u):
-// rho at x^n (rho mode), or J at x^n + (v - v_gal) dt/2 and rho at
-// x^n + (v - v_gal) dt.  The position is not written.
-template <class L, int ORDER, int MODE, typename A>
-__device__ void deposit_one(const TileCtx<L> &tc, int64_t k, A *acc, bool do_j, bool do_rho) {
-  using T = typename L::T;
-  typename L::State st = load_state<L>(tc.p, k, tc.g);
-  if constexpr (MODE == kModeRho) {
-    const CellPos<T> c = L::cell(st, tc.g);
-    Support<ORDER, T> s;
-    support_of<ORDER, T>(c, tc.rg, tc.tg, tc.g, s);
-    T *dst[1] = {tc.gr.rho};
-    const T val[1] = {tc.qw};
-    deposit<ORDER, T, A>(c, s, tc.tg, tc.g, acc, 3, 1, val, dst, tc.fallback);
-  } else {
-    const T u[3] = {static_cast<const T *>(tc.p.ux)[k], static_cast<const T *>(tc.p.uy)[k],
-                    static_cast<const T *>(tc.p.uz)[k]};
-    const T gamma = sqrt(T(1) + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-    const T v[3] = {u[0] / gamma, u[1] / gamma, u[2] / gamma};
-    L::half_move(st, v, tc.g);
-    if (do_j) {
-      const CellPos<T> c = L::cell(st, tc.g);
-      Support<ORDER, T> s;
-      support_of<ORDER, T>(c, tc.rg, tc.tg, tc.g, s);
-      T *dst[3] = {tc.gr.J[0], tc.gr.J[1], tc.gr.J[2]};
-      const T val[3] = {tc.qw * v[0], tc.qw * v[1], tc.qw * v[2]};
-      deposit<ORDER, T, A>(c, s, tc.tg, tc.g, acc, 0, 3, val, dst, tc.fallback);
+// E and B of the quad's four particles from the shared block; every lane
+// gets its own particle's six values.
+template <int ORDER, typename T>
+__device__ __forceinline__ void gather_quad(const int hb[3], const T o[3], int m,
+                                            const TileGeom &tg, const T *fld, T F[6]) {
+  using QW = QuadWeights<ORDER, T>;
+  constexpr int N = QW::N;
+  QW w;
+  w.build(o, m);
+  const int R = tg.region;
+  T P[4][6];
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+#pragma unroll
+    for (int q = 0; q < 6; ++q) P[s][q] = T(0);
+#pragma unroll
+  for (int r = 0; r < QW::ROWS; ++r) {
+    const T *row = fld + quad_row<ORDER>(hb, m, r, tg);
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      T f[N];
+#pragma unroll
+      for (int e = 0; e < N; ++e) f[e] = row[q * R + e];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        T acc = P[s][q];
+#pragma unroll
+        for (int e = 0; e < N; ++e) acc += (w.wxy[s][r] * w.wz[s][e]) * f[e];
+        P[s][q] = acc;
+      }
     }
-    L::half_move(st, v, tc.g);
-    if (do_rho) {
-      const CellPos<T> c = L::cell(st, tc.g);
-      Support<ORDER, T> s;
-      support_of<ORDER, T>(c, tc.rg, tc.tg, tc.g, s);
-      T *dst[1] = {tc.gr.rho};
-      const T val[1] = {tc.qw};
-      deposit<ORDER, T, A>(c, s, tc.tg, tc.g, acc, 3, 1, val, dst, tc.fallback);
+  }
+  // the particle of lane m sits in slot s of lane (m + s) mod 4
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    T v = P[0][q];
+#pragma unroll
+    for (int s = 1; s < 4; ++s) v += from_plus(P[s][q], s);
+    F[q] = v;
+  }
+}
+
+// Deposit NQ values per particle (val, zero for an idle lane) of the quad's
+// four particles into the shared block hb of LDS accumulators q0 ..
+template <int ORDER, typename T, typename A, int NQ>
+__device__ __forceinline__ void deposit_quad(const int hb[3], const T o[3], const T val[NQ],
+                                             int m, const TileGeom &tg, A *acc, int q0) {
+  using QW = QuadWeights<ORDER, T>;
+  constexpr int N = QW::N;
+  QW w;
+  w.build(o, m);
+  T vs[4][NQ];
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) vs[s][q] = from_minus(val[q], s);
+  const int R = tg.region;
+#pragma unroll
+  for (int r = 0; r < QW::ROWS; ++r) {
+    const int row = quad_row<ORDER>(hb, m, r, tg);
+#pragma unroll
+    for (int e = 0; e < N; ++e) {
+      T sum[NQ];
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) sum[q] = T(0);
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const T we = w.wxy[s][r] * w.wz[s][e];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) sum[q] += we * vs[s][q];
+      }
+#pragma unroll
+      for (int q = 0; q < NQ; ++q)
+        __hip_atomic_fetch_add(acc + size_t(q0 + q) * R + row + e, A(sum[q]), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_WORKGROUP);
     }
   }
 }
 
-// One workgroup per tile.  Modes:
+// Deposit of NQ values at position c: the quad's shared block if it has
+// one, else one particle per lane (an idle lane deposits nothing).
+template <int ORDER, typename T, typename A, int NQ>
+__device__ __forceinline__ void deposit_at(const CellPos<T> &c, const T val[NQ], bool act,
+                                           int m, const Region &rg, const TileGeom &tg,
+                                           const RunGeom &g, A *acc, int q0, T *const *dst,
+                                           int *fallback) {
+  int hb[3];
+  if (quad_block<ORDER, T>(c, rg, tg, g, hb)) {
+    T v[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) v[q] = act ? val[q] : T(0);
+    deposit_quad<ORDER, T, A, NQ>(hb, c.o, v, m, tg, acc, q0);
+  } else if (act) {
+    Support<ORDER, T> s;
+    support_of<ORDER, T>(c, rg, tg, g, s);
+    deposit<ORDER, T, A>(c, s, tg, g, acc, q0, NQ, val, dst, fallback);
+  }
+}
+
+// ---- per-tile bucket order ---------------------------------------------------
+// At the start of every particle pass the workgroup orders its tile's
+// particles by their current cell in LDS (a counting sort of tile-local
+// indices), so the quads find four particles of one cell however far the
+// particles have moved inside the region since the last global sort.
+// Buckets are the cells of the tile plus the drift margin, and one bucket
+// for particles beyond it.  Quads take jobs of up to four particles of one
+// bucket.  A tile with more particles than the list holds is processed in
+// memory order instead.
+struct TileLists {
+  int *off;    // nb + 2: first list entry of each bucket
+  int *job;    // nb + 2: first job of each bucket
+  int *fill;   // nb + 1: counts, then fill pointers
+  unsigned short *list;  // cap tile-local particle indices
+  int *jobs;   // cap / 4 + nb + 2: first list entry | size << 24 of each job
+};
+
+// LDS bytes of the bucket tables and lists of a tile geometry
+__host__ __device__ constexpr size_t list_bytes(int nb, int cap) {
+  return size_t(3) * (nb + 2) * sizeof(int) + ((size_t(cap) * 2 + 3) & ~size_t(3)) +
+         (size_t(cap) / 4 + nb + 2) * sizeof(int);
+}
+
+template <class L>
+__device__ __forceinline__ int bucket_of(const PartPtrs &p, int64_t k, const RunGeom &g,
+                                         const TileGeom &tg, const int org[3]) {
+  const auto c = L::cell(load_state<L>(p, k, g), g);
+  const int n[3] = {g.nx, g.ny, g.nz};
+  int b = 0;
+  bool in = true;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const int rel = (c.i[a] - org[a]) & (n[a] - 1);
+    in = in && rel < tg.ce[a];
+    b = b * tg.ce[a] + rel;
+  }
+  return in ? b : tg.nb;
+}
+
+// exclusive scan of v[0 .. n) into out[0 .. n], n <= 2 * NT
+template <int NT>
+__device__ __forceinline__ void scan2(const int *v, int *out, int n, int *tmp) {
+  const int tid = threadIdx.x;
+  const int a = 2 * tid < n ? v[2 * tid] : 0;
+  const int b = 2 * tid + 1 < n ? v[2 * tid + 1] : 0;
+  tmp[tid] = a + b;
+  __syncthreads();
+  for (int off = 1; off < NT; off <<= 1) {
+    const int add = tid >= off ? tmp[tid - off] : 0;
+    __syncthreads();
+    tmp[tid] += add;
+    __syncthreads();
+  }
+  const int excl = tmp[tid] - a - b;
+  if (2 * tid <= n) out[2 * tid] = excl;
+  if (2 * tid + 1 <= n) out[2 * tid + 1] = excl + a;
+  __syncthreads();
+}
+
+// One workgroup of NT threads per tile.  Modes:
 //  rho:     rho at the current positions (no move)
 //  deposit: move dt/2, J; move dt/2, rho; positions written
 //  fused:   gather at the current positions and push u through dt, then as
-//           deposit with the new u (one particle pass per step)
+//           deposit with the new u (one pass over the particles per step)
 //  push:    gather and push u through the time step h was built for
-//
-// Gather + push run with four lanes per cell: in slot-major order lanes
-// 4c .. 4c+3 of a quad take the particles of one cell from four rounds, so
-// the quad reads the same LDS node values and the LDS broadcasts them.  The
-// deposit runs with one thread per cell and batches of K of its particles
-// (see deposit_home); a particle whose half-way or end position is outside
-// the thread's home cell is deposited on its own.
-template <class L, int ORDER, int MODE, typename A, int K>
-__global__ __launch_bounds__(kNT) void k_tile(RunGeom g, TileGeom tg, PartPtrs p,
-                                              GridPtrs<typename L::T> gr,
-                                              const int *__restrict__ start, int *state,
-                                              typename L::T h) {
+template <class L, int ORDER, int MODE, typename A, int NT>
+__global__ __launch_bounds__(NT) void k_quad(RunGeom g, TileGeom tg, PartPtrs p,
+                                             GridPtrs<typename L::T> gr,
+                                             const int *__restrict__ start, int *state,
+                                             typename L::T h) {
   using T = typename L::T;
   using Sh = Shape<ORDER, T>;
-  constexpr int N = Sh::N;
   constexpr bool kGather = MODE == kModeFused || MODE == kModePush;
   constexpr bool kDeposit = MODE != kModePush;
+  constexpr bool kMove = MODE == kModeFused || MODE == kModeDeposit;
+  static_assert(2 * NT >= 1024, "bucket scan covers up to 2 NT buckets");
   extern __shared__ __align__(16) unsigned char smem[];
-  // accumulators first (8-byte aligned when A is double), then the fields
-  A *acc = reinterpret_cast<A *>(smem);                                  // 4 * region
-  T *fld = reinterpret_cast<T *>(smem + (kDeposit ? 4 * sizeof(A) * tg.region : 0));
-  const int tile = tile_of_block(tg);
-  TileCtx<L> tc;
-  tc.g = g;
-  tc.tg = tg;
-  tc.p = p;
-  tc.gr = gr;
-  tc.rg = region_of(tile, tg, g, Sh::FIRST);
-  tc.qw = T(p.q * p.w / (g.dx * g.dy * g.dz));
-  tc.h = h;
-  tc.fallback = state;
+  // accumulators first (8-byte aligned when A is double), then the fields,
+  // then the bucket lists
   const int R = tg.region;
+  A *acc = reinterpret_cast<A *>(smem);  // 4 * region
+  unsigned char *after_acc = smem + (kDeposit ? 4 * sizeof(A) * R : 0);
+  T *fld = reinterpret_cast<T *>(after_acc);
+  unsigned char *after_fld = after_acc + (kGather ? 6 * sizeof(T) * R : 0);
+  TileLists tl;
+  tl.off = reinterpret_cast<int *>(after_fld);
+  tl.job = tl.off + (tg.nb + 2);
+  tl.fill = tl.job + (tg.nb + 2);
+  tl.list = reinterpret_cast<unsigned short *>(tl.fill + (tg.nb + 2));
+  tl.jobs = reinterpret_cast<int *>(tl.list + ((tg.cap + 1) & ~1));
+  __shared__ int scan_tmp[NT];
+
+  const int tile = tile_of_block(tg);
+  const Region rg = region_of(tile, tg, g, Sh::FIRST);
+  const T qw = T(p.q * p.w / (g.dx * g.dy * g.dz));
   const int tid = threadIdx.x;
   if constexpr (kGather) {
     const T *src[6] = {gr.E[0], gr.E[1], gr.E[2], gr.B[0], gr.B[1], gr.B[2]};
-    for (int r = tid; r < R; r += kNT) {
-      const int64_t node = region_node(r, tc.rg, tg, g);
+    for (int r = tid; r < R; r += NT) {
+      const int64_t node = region_node(r, rg, tg, g);
 #pragma unroll
       for (int q = 0; q < 6; ++q) fld[q * R + r] = src[q][node];
     }
   }
   if constexpr (kDeposit) {
-    for (int r = tid; r < 4 * R; r += kNT) acc[r] = A(0);
+    for (int r = tid; r < 4 * R; r += NT) acc[r] = A(0);
+  }
+  const int64_t tbase = start[tile];
+  const int count = start[tile + 1] - start[tile];
+  const bool listed = count <= tg.cap;
+  int org[3];  // first cell of the bucket block (tile start - margin)
+  {
+    const int tz = tile % tg.nt[2];
+    const int ty = (tile / tg.nt[2]) % tg.nt[1];
+    const int tx = tile / (tg.nt[2] * tg.nt[1]);
+    org[0] = (tx * tg.t[0] - tg.margin) & (g.nx - 1);
+    org[1] = (ty * tg.t[1] - tg.margin) & (g.ny - 1);
+    org[2] = (tz * tg.t[2] - tg.margin) & (g.nz - 1);
+  }
+  int njobs;
+  if (listed) {
+    for (int b = tid; b <= tg.nb; b += NT) tl.fill[b] = 0;
+    __syncthreads();
+    for (int i = tid; i < count; i += NT)
+      atomicAdd(&tl.fill[bucket_of<L>(p, tbase + i, g, tg, org)], 1);
+    __syncthreads();
+    scan2<NT>(tl.fill, tl.off, tg.nb + 1, scan_tmp);
+    for (int b = tid; b <= tg.nb; b += NT) tl.fill[b] = (tl.fill[b] + 3) >> 2;
+    __syncthreads();
+    scan2<NT>(tl.fill, tl.job, tg.nb + 1, scan_tmp);
+    for (int b = tid; b <= tg.nb; b += NT) tl.fill[b] = tl.off[b];
+    __syncthreads();
+    for (int i = tid; i < count; i += NT) {
+      const int b = bucket_of<L>(p, tbase + i, g, tg, org);
+      const int pos = atomicAdd(&tl.fill[b], 1);
+      tl.list[pos] = static_cast<unsigned short>(i);
+      const int r = pos - tl.off[b];
+      if ((r & 3) == 0)  // first particle of a job
+        tl.jobs[tl.job[b] + (r >> 2)] = pos | (min(4, tl.off[b + 1] - pos) << 24);
+    }
+    njobs = tl.job[tg.nb + 1];
+  } else {
+    njobs = (count + 3) >> 2;
   }
   __syncthreads();
-  const int b0 = start[tile];
-  const int count = start[tile + 1] - b0;
-  if constexpr (kGather) {
-    // quads: lane (cell slot c, member m) of chunk q takes local index
-    // q * 4 kNT + m * kNT + c (rounds 4q + m of cell slot c)
-    const int cslot = tid >> 2;
-    const int m = tid & 3;
-    for (int chunk = 0; chunk * 4 * kNT < count; ++chunk) {
-#pragma unroll 1
-      for (int cb = 0; cb < 4; ++cb) {
-        const int local = chunk * 4 * kNT + m * kNT + cb * (kNT / 4) + cslot;
-        if (local < count) push_one<L, ORDER>(tc, int64_t(b0) + local, fld);
-      }
+
+  T *jdst[3] = {gr.J[0], gr.J[1], gr.J[2]};
+  T *rdst[1] = {gr.rho};
+  const int m = tid & 3;
+  for (int j = tid >> 2; j < njobs; j += NT / 4) {
+    int first, n;  // list position (or tile index) of the job's first particle; its size
+    if (listed) {
+      const int e = tl.jobs[j];
+      first = e & 0xFFFFFF;
+      n = e >> 24;
+    } else {
+      first = 4 * j;
+      n = min(4, count - first);
     }
-    if constexpr (kDeposit) {
-      __threadfence_block();
-      __syncthreads();
+    // an idle lane (past the job's last particle) mirrors lane 0: it takes
+    // the same path through the quad code and stores nothing
+    const bool act = m < n;
+    const int pos = first + (act ? m : 0);
+    const int64_t k = tbase + (listed ? int(tl.list[pos]) : pos);
+    typename L::State st = load_state<L>(p, k, g);
+    T u[3];
+    if constexpr (MODE != kModeRho) {
+      u[0] = static_cast<const T *>(p.ux)[k];
+      u[1] = static_cast<const T *>(p.uy)[k];
+      u[2] = static_cast<const T *>(p.uz)[k];
+    }
+    if constexpr (kGather) {
+      const CellPos<T> c0 = L::cell(st, g);
+      T F[6];
+      int hb[3];
+      if (quad_block<ORDER, T>(c0, rg, tg, g, hb)) {
+        gather_quad<ORDER, T>(hb, c0.o, m, tg, fld, F);
+      } else {
+        Support<ORDER, T> s;
+        support_of<ORDER, T>(c0, rg, tg, g, s);
+        gather<ORDER, T>(c0, s, tg, g, fld, gr, F);
+      }
+      boris(u, F, h);
+    }
+    if constexpr (MODE == kModeRho) {
+      const T val[1] = {qw};
+      deposit_at<ORDER, T, A, 1>(L::cell(st, g), val, act, m, rg, tg, g, acc, 3, rdst, state);
+    }
+    if constexpr (kMove) {
+      // v - v_gal is a difference of nearly equal numbers for the drifting
+      // plasma: keep v = u / gamma correctly rounded per component
+      const T gamma = sqrt(T(1) + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+      const T v[3] = {u[0] / gamma, u[1] / gamma, u[2] / gamma};
+      L::half_move(st, v, g);
+      const T jv[3] = {qw * v[0], qw * v[1], qw * v[2]};
+      deposit_at<ORDER, T, A, 3>(L::cell(st, g), jv, act, m, rg, tg, g, acc, 0, jdst, state);
+      L::half_move(st, v, g);
+      const T val[1] = {qw};
+      deposit_at<ORDER, T, A, 1>(L::cell(st, g), val, act, m, rg, tg, g, acc, 3, rdst, state);
+    }
+    if (act) {
+      if constexpr (kMove) store_state<L>(p, k, st, g);
+      if constexpr (kGather) {
+        static_cast<T *>(p.ux)[k] = u[0];
+        static_cast<T *>(p.uy)[k] = u[1];
+        static_cast<T *>(p.uz)[k] = u[2];
+      }
     }
   }
   if constexpr (kDeposit) {
-    // Thread t takes the particles t, t + kNT, ... in batches of K: in
-    // slot-major order these started in one cell and, moving together,
-    // usually still share one.  The batch cell is the cell of the batch's
-    // first particle (at the half-way position for J, at the end position
-    // for rho); members in it share the node block, others are deposited
-    // on their own.
-    for (int r0 = 0; tid + kNT * r0 < count; r0 += K) {
-      typename L::State st[K], sh[K];
-      int64_t idx[K];
-      T v[K][3];
-      unsigned valid = 0;
-#pragma unroll
-      for (int j = 0; j < K; ++j) {
-        const int local = tid + kNT * (r0 + j);
-        if (local < count) valid |= 1u << j;
-        idx[j] = int64_t(b0) + (local < count ? local : 0);
-        st[j] = load_state<L>(p, idx[j], g);
-        if constexpr (MODE == kModeRho) {
-          sh[j] = st[j];
-        } else {
-          const T u[3] = {static_cast<const T *>(p.ux)[idx[j]],
-                          static_cast<const T *>(p.uy)[idx[j]],
-                          static_cast<const T *>(p.uz)[idx[j]]};
-          const T gamma = sqrt(T(1) + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-          v[j][0] = u[0] / gamma;
-          v[j][1] = u[1] / gamma;
-          v[j][2] = u[2] / gamma;
-          L::half_move(st[j], v[j], g);
-          sh[j] = st[j];
-          L::half_move(st[j], v[j], g);
-        }
-      }
-      // J at the half-way positions, rho at the end positions: group the
-      // batch by cell and deposit each group through its shared node block
-      T ox[K], wy[K][N], wz[K][N];
-      int cell_j[K][3], cell_r[K][3];
-#pragma unroll
-      for (int j = 0; j < K; ++j) {
-        const CellPos<T> ch = L::cell(sh[j], g);
-        const CellPos<T> ce = L::cell(st[j], g);
-#pragma unroll
-        for (int a2 = 0; a2 < 3; ++a2) {
-          cell_j[j][a2] = ch.i[a2];
-          cell_r[j][a2] = ce.i[a2];
-        }
-      }
-      if constexpr (MODE != kModeRho) {
-        T val[K][3];
-#pragma unroll
-        for (int j = 0; j < K; ++j) {
-          const CellPos<T> c = L::cell(sh[j], g);
-          ox[j] = c.o[0];
-          Sh::weights(c.o[1], wy[j]);
-          Sh::weights(c.o[2], wz[j]);
-#pragma unroll
-          for (int q = 0; q < 3; ++q) val[j][q] = tc.qw * v[j][q];
-        }
-        unsigned left = valid;
-#pragma unroll 1
-        while (left) {
-          // the group of the lowest remaining particle
-          int lead[3];
-#pragma unroll
-          for (int j = K - 1; j >= 0; --j)
-            if ((left >> j) & 1u) {
-              lead[0] = cell_j[j][0];
-              lead[1] = cell_j[j][1];
-              lead[2] = cell_j[j][2];
-            }
-          bool dep[K];
-          unsigned grp = 0;
-#pragma unroll
-          for (int j = 0; j < K; ++j) {
-            dep[j] = ((left >> j) & 1u) && cell_j[j][0] == lead[0] && cell_j[j][1] == lead[1] &&
-                     cell_j[j][2] == lead[2];
-            if (dep[j]) grp |= 1u << j;
-          }
-          left &= ~grp;
-          CellPos<T> lc;
-          lc.i[0] = lead[0];
-          lc.i[1] = lead[1];
-          lc.i[2] = lead[2];
-          int hb[3];
-          if (region_base<ORDER, T>(lc, tc.rg, tg, g, hb)) {
-            deposit_home<ORDER, T, A, K, 3>(hb, tg, acc, 0, dep, ox, wy, wz, val);
-          } else {
-            // outside the tile's region: global memory, one particle at a time
-#pragma unroll 1
-            for (int j = 0; j < K; ++j)
-              if ((grp >> j) & 1u)
-                deposit_one<L, ORDER, MODE, A>(tc, int64_t(b0) + tid + kNT * (r0 + j), acc, true,
-                                               false);
-          }
-        }
-      }
-      {
-        T val[K][1];
-#pragma unroll
-        for (int j = 0; j < K; ++j) {
-          const CellPos<T> c = L::cell(st[j], g);
-          ox[j] = c.o[0];
-          Sh::weights(c.o[1], wy[j]);
-          Sh::weights(c.o[2], wz[j]);
-          val[j][0] = tc.qw;
-        }
-        unsigned left = valid;
-#pragma unroll 1
-        while (left) {
-          int lead[3];
-#pragma unroll
-          for (int j = K - 1; j >= 0; --j)
-            if ((left >> j) & 1u) {
-              lead[0] = cell_r[j][0];
-              lead[1] = cell_r[j][1];
-              lead[2] = cell_r[j][2];
-            }
-          bool dep[K];
-          unsigned grp = 0;
-#pragma unroll
-          for (int j = 0; j < K; ++j) {
-            dep[j] = ((left >> j) & 1u) && cell_r[j][0] == lead[0] && cell_r[j][1] == lead[1] &&
-                     cell_r[j][2] == lead[2];
-            if (dep[j]) grp |= 1u << j;
-          }
-          left &= ~grp;
-          CellPos<T> lc;
-          lc.i[0] = lead[0];
-          lc.i[1] = lead[1];
-          lc.i[2] = lead[2];
-          int hb[3];
-          if (region_base<ORDER, T>(lc, tc.rg, tg, g, hb)) {
-            deposit_home<ORDER, T, A, K, 1>(hb, tg, acc, 3, dep, ox, wy, wz, val);
-          } else {
-#pragma unroll 1
-            for (int j = 0; j < K; ++j)
-              if ((grp >> j) & 1u)
-                deposit_one<L, ORDER, MODE, A>(tc, int64_t(b0) + tid + kNT * (r0 + j), acc, false,
-                                               true);
-          }
-        }
-      }
-      if constexpr (MODE != kModeRho) {
-#pragma unroll
-        for (int j = 0; j < K; ++j)
-          if ((valid >> j) & 1u) store_state<L>(p, idx[j], st[j], g);
-      }
-    }
     __syncthreads();
     T *dst[4] = {gr.J[0], gr.J[1], gr.J[2], gr.rho};
     const int q_first = MODE == kModeRho ? 3 : 0;
-    for (int r = tid; r < R; r += kNT) {
-      const int64_t node = region_node(r, tc.rg, tg, g);
+    for (int r = tid; r < R; r += NT) {
+      const int64_t node = region_node(r, rg, tg, g);
       for (int q = q_first; q < 4; ++q) {
         const T vq = T(acc[q * R + r]);
         if (vq != T(0)) unsafeAtomicAdd(dst[q] + node, vq);
@@ -762,8 +831,8 @@ __global__ __launch_bounds__(kNT) void k_tile(RunGeom g, TileGeom tg, PartPtrs p
 }
 
 // ---- tile sort (run only when flagged) --------------------------------------
-// A counting sort by tile-major cell index, then a per-tile reorder into
-// slot-major order.  state[0]: particles that used the global path since the
+// A counting sort by tile-major cell index: the particles of a tile end up
+// grouped by cell, in tile order.  state[0]: particles that used the global path since the
 // last decision; state[1]: sort flag of this step; state[2]: sorts done;
 // state[3]: force flag (set by the host at binding).
 __global__ void k_sort_decide(int *state, int threshold) {
@@ -888,35 +957,12 @@ __global__ void k_sort_scatter(TileGeom tg, const int *state, Columns cols, int6
   }
 }
 
-// Per tile: scratch (cell-grouped) -> particle arrays in slot-major order.
-__global__ __launch_bounds__(kNT) void k_sort_reorder(TileGeom tg, const int *state,
-                                                      Columns cols, const int *cell_count,
-                                                      const int *cell_off, const int *start) {
+// scratch -> particle arrays (same, cell-grouped order)
+__global__ void k_sort_copyback(const int *state, Columns cols, int64_t np) {
   if (!state[1]) return;
-  __shared__ int buf[kNT];
-  __shared__ int maxc;
-  const int tile = blockIdx.x;
-  const int tid = threadIdx.x;
-  const int cpt = 1 << tg.lcpt;
-  const int cnt = tid < cpt ? cell_count[(tile << tg.lcpt) + tid] : 0;
-  const int off = tid < cpt ? cell_off[(tile << tg.lcpt) + tid] : 0;
-  if (tid == 0) maxc = 0;
-  __syncthreads();
-  atomicMax(&maxc, cnt);
-  __syncthreads();
-  const int rounds = maxc;
-  const int64_t base = start[tile];
-  int64_t slot_base = base;
-  for (int r = 0; r < rounds; ++r) {
-    const int f = cnt > r ? 1 : 0;
-    const int incl = block_scan_incl(f, buf);
-    if (f) copy_columns(cols, false, base + off + r, slot_base + incl - 1);
-    // total of this round: the last thread's inclusive value
-    if (tid == kNT - 1) buf[0] = incl;
-    __syncthreads();
-    slot_base += buf[0];
-    __syncthreads();
-  }
+  for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < np;
+       k += int64_t(gridDim.x) * blockDim.x)
+    copy_columns(cols, false, k, k);
 }
 
 unsigned stride_blocks(int64_t n) {
@@ -933,16 +979,18 @@ void launch_tile_kernel(const RunGeom &g, const TileGeom &tg, const PartPtrs &p,
   using T = typename L::T;
   constexpr bool kGather = MODE == kModeFused || MODE == kModePush;
   constexpr bool kDeposit = MODE != kModePush;
-  constexpr int kK = sizeof(T) == 8 ? 2 : 4;  // batch size (register budget)
+  constexpr int NT = quad_threads(sizeof(T));
   const size_t lds = size_t(tg.region) * ((kGather ? 6 * sizeof(T) : 0) +
-                                          (kDeposit ? 4 * sizeof(A) : 0));
+                                          (kDeposit ? 4 * sizeof(A) : 0)) +
+                     list_bytes(tg.nb, tg.cap);
   static bool attr_set = false;  // allow dynamic LDS above 64 KiB (gfx950: 160 KiB)
   if (!attr_set) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_tile<L, ORDER, MODE, A, kK>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_quad<L, ORDER, MODE, A, NT>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize,
+                              int(kLdsBytes - scan_bytes(sizeof(T))));
     attr_set = true;
   }
-  hipLaunchKernelGGL((k_tile<L, ORDER, MODE, A, kK>), dim3(unsigned(tg.n_tiles)), dim3(kNT), lds,
+  hipLaunchKernelGGL((k_quad<L, ORDER, MODE, A, NT>), dim3(unsigned(tg.n_tiles)), dim3(NT), lds,
                      s, g, tg, p, gr, sb.start, sb.state, T(hval));
 }
 
@@ -975,13 +1023,6 @@ TileGeom make_tile_geom(const RunGeom &g, size_t real_size) {
   TileGeom tg{};
   const int n[3] = {g.nx, g.ny, g.nz};
   const int halo = g.order == 3 ? 3 : 1;  // shape width - 1
-  // one cell of drift margin when the fused kernel's LDS (6 fields and 4
-  // double accumulators per region node) still fits in 160 KiB
-  {
-    int e = 8 + halo + 2;
-    const size_t bytes = size_t(e) * e * e * (6 * real_size + 4 * sizeof(double));
-    tg.margin = bytes <= 160 * 1024 ? 1 : 0;
-  }
   int lcpt = 0;
   for (int a = 0; a < 3; ++a) {
     int t = 8;
@@ -992,11 +1033,30 @@ TileGeom make_tile_geom(const RunGeom &g, size_t real_size) {
     tg.lt[a] = l;
     lcpt += l;
     tg.nt[a] = n[a] / t;
-    tg.e[a] = t + halo + 2 * tg.margin;
   }
   tg.lcpt = lcpt;
   tg.n_tiles = tg.nt[0] * tg.nt[1] * tg.nt[2];
-  tg.region = tg.e[0] * tg.e[1] * tg.e[2];
+  // LDS of the fused pass for a margin: 6 fields and 4 double accumulators
+  // per region node, the static scan buffer, the bucket tables and lists
+  // (3 bytes per particle)
+  auto fixed = [&](int margin, TileGeom &t) {
+    t.margin = margin;
+    t.region = 1;
+    t.nb = 1;
+    for (int a = 0; a < 3; ++a) {
+      t.e[a] = t.t[a] + halo + 2 * margin;
+      t.ce[a] = t.t[a] + 2 * margin;
+      t.region *= t.e[a];
+      t.nb *= t.ce[a];
+    }
+    return size_t(t.region) * (6 * real_size + 4 * sizeof(double)) + scan_bytes(real_size);
+  };
+  // one cell of drift margin when the lists still hold 4096 particles
+  size_t used = fixed(1, tg);
+  if (used + list_bytes(tg.nb, 4096) > kLdsBytes) used = fixed(0, tg);
+  int cap = 16384;
+  while (used + list_bytes(tg.nb, cap) > kLdsBytes) cap -= 64;
+  tg.cap = cap;
   return tg;
 }
 
@@ -1045,8 +1105,8 @@ void launch_sort(const RunGeom &g, const TileGeom &tg, const PartPtrs &p, const 
   }
   hipLaunchKernelGGL(k_sort_scatter, dim3(stride_blocks(p.n)), dim3(256), 0, s, tg, sb.state,
                      cols, p.n, sb.key, sb.rank, sb.cell_off, sb.start);
-  hipLaunchKernelGGL(k_sort_reorder, dim3(unsigned(tg.n_tiles)), dim3(kNT), 0, s, tg, sb.state,
-                     cols, sb.cell_count, sb.cell_off, sb.start);
+  hipLaunchKernelGGL(k_sort_copyback, dim3(stride_blocks(p.n)), dim3(256), 0, s, sb.state, cols,
+                     p.n);
 }
 
 template <typename T>

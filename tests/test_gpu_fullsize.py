@@ -199,7 +199,12 @@ def test_full_step_properties(gpu_lib, full_inputs):
     total = CFG.n_particles * CFG.q * CFG.w
     assert abs(rho.astype(np.float64).sum() - total) <= 1e-6 * abs(total)
     rho1_hat = ctx.read_field(0, "RHO_HAT_OLD")
-    assert rel_l2(rho1_hat, rho0_hat) <= 1e-6
+    # float32 floor: a node value carries a few roundings of 2^-24 of itself
+    # (contribution products and sums, the final conversion, the adds of up
+    # to eight overlapping tile regions), while the k != 0 spectrum holds
+    # only the charge fluctuation, ~12 % of a node's value at 8 cubic
+    # particles per cell: ~1e-6 expected, bound 5e-6
+    assert rel_l2(rho1_hat, rho0_hat) <= 5e-6
     idx = sample_modes(CFG.shape, 4000, 37)
     live = ~held(idx, CFG.shape)
     kx, ky, kz = half_k_at(idx, CFG.shape, CFG.spacing)
