@@ -187,6 +187,60 @@ def cpu_baseline(cfg):
                        f"{t:.1f} s; coefficient set-up not timed")}
 
 
+def accuracy_run(cfg, steps, inputs, every=10):
+    """The mixed-precision path against the FP64 GPU path on the same
+    workload: per-field relative L2 of E and B after `steps` steps, and the
+    field-energy histories (sampled every `every` steps) of both."""
+    import torch
+
+    from paper_1608_00215_amd import galpic as gp
+    from workload import laser_fields
+
+    ctxs, parts = {}, {}
+    for name, prec in (("mixed", gp.GP_MIXED), ("fp64", gp.GP_FP64)):
+        ctx = gp.Context([gp.grid_from_config(cfg, prec)])
+        ctx.set_v_gal(0, cfg.v_gal())
+        parts[name] = gp.particles_from_inputs(inputs, cfg, prec, with_ids=False)
+        ctx.bind_particles([parts[name]])
+        lf = laser_fields(cfg)
+        if lf is not None:
+            ctx.set_fields(0, lf[0], lf[1], project_transverse=True)
+            ctx.half_push()
+        ctxs[name] = ctx
+    hist = {"step": [], "mixed": [], "fp64": []}
+    done = 0
+    while done < steps:
+        k = min(every, steps - done)
+        for name, ctx in ctxs.items():
+            ctx.run(k)
+        done += k
+        hist["step"].append(done)
+        for name, ctx in ctxs.items():
+            we, wb = ctx.field_energy(0)
+            hist[name].append(we + wb)
+        print(f"[accuracy] step {done}: W mixed {hist['mixed'][-1]:.6g} "
+              f"fp64 {hist['fp64'][-1]:.6g}", file=sys.stderr, flush=True)
+    errs = {}
+    for f in ("EX", "EY", "EZ", "BX", "BY", "BZ"):
+        a = ctxs["mixed"].read_field(0, f).astype(np.float64)
+        b = ctxs["fp64"].read_field(0, f)
+        nb = float(np.sqrt(np.sum(b * b)))
+        errs[f] = float(np.sqrt(np.sum((a - b) ** 2)) / nb) if nb > 0 else None
+        del a, b
+    wm, wf = np.array(hist["mixed"]), np.array(hist["fp64"])
+    drift = np.abs(wm - wf) / np.abs(wf)
+    for ctx in ctxs.values():
+        ctx.close()
+    torch.cuda.empty_cache()
+    return {"workload": cfg.name, "steps": steps,
+            "field_rel_l2_mixed_vs_fp64": errs,
+            "energy_rel_diff_final": float(drift[-1]),
+            "energy_rel_diff_max": float(drift.max()),
+            "energy_fp64_first_last": [float(wf[0]), float(wf[-1])],
+            "history_every": every,
+            "energy_mixed": [float(x) for x in wm], "energy_fp64": [float(x) for x in wf]}
+
+
 def workload_text(cfg):
     prec = ("mixed precision (int32 cell + f32 offsets, f32 FFT/update/push, f64 "
             "coefficients, double tile sums)")
@@ -214,6 +268,9 @@ def main():
     ap.add_argument("--workload", default="c2_cubic_mixed")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--accuracy", action="store_true",
+                    help="instead of timing, run the mixed and FP64 GPU paths side by side "
+                         "and report per-field errors and energy histories")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device three times (a plain copy "
                          "kernel of known size for scaling HBM byte counters)")
@@ -255,6 +312,11 @@ def main():
         args.steps = cfg.runs[0].steps if isinstance(cfg, BatchView) else cfg.steps
     print(f"[bench] {cfg.name}: grid {cfg.shape}, {cfg.n_particles} particles, "
           f"{args.steps} steps", file=sys.stderr, flush=True)
+    if args.accuracy:
+        if isinstance(cfg, BatchView):
+            sys.exit("bench.py: --accuracy takes a single-run workload")
+        print(json.dumps(accuracy_run(cfg, args.steps, inputs)), flush=True)
+        return
     mixed = run_gpu(run_arg, gp.GP_MIXED, args.steps, args.warmup, inputs)
     print(f"[bench] mixed: {mixed['wall_s'] / args.steps * 1e3:.3f} ms/step", file=sys.stderr,
           flush=True)
