@@ -86,6 +86,40 @@ struct StageRec {
   hipEvent_t a, b;
 };
 
+// Device tables of the batched launches.  FieldSet tables hold one entry per
+// run in class order: runs of one grid shape sit next to each other, so one
+// launch covers a class (a slice of the table) and a set-up call covers one
+// run (a slice of one).
+enum {
+  kTabFwdZ0, kTabFwdZ1,           // real J, rho -> J^, rho^{n+1} (per rho parity)
+  kTabFwdYX0, kTabFwdYX1,         // in place on J^, rho^{n+1}
+  kTabInvX, kTabInvY, kTabInvZ,   // E^, B^ -> scratch -> scratch -> real E, B
+  kTabEBZ, kTabEBYX,              // real E, B -> E^, B^ (setting fields)
+  kTabRhoZ0, kTabRhoZ1,           // real rho -> rho^n (binding particles)
+  kTabRhoYX0, kTabRhoYX1,
+  kNTab
+};
+
+struct Class {
+  RunGeom g;  // grid shape and spacing shared by the class
+  int first;  // first class-order position
+  int count;
+};
+
+struct Tables {
+  void *dev = nullptr;                // one device allocation ...
+  std::vector<unsigned char> host;    // ... mirrored on the host
+  size_t fs[kNTab] = {};              // byte offsets of the FieldSet tables
+  size_t upd[2] = {};                 // UpdatePtrs per rho parity (class order)
+  size_t zero = 0;                    // ZeroSeg of J and rho (four per run)
+  size_t jobs = 0;                    // PartJob per run (run order)
+  size_t bytes = 0;
+  std::vector<Class> classes;
+  std::vector<int> pos;               // run -> class-order position
+  size_t max_zero16 = 0;
+  PartBatch batch{};
+};
+
 }  // namespace
 
 struct gp_ctx {
@@ -107,6 +141,7 @@ struct gp_ctx {
   bool timed = false;
   bool stage_timing = false;
   std::vector<StageRec> stage_recs;
+  Tables tab;
 };
 
 namespace {
@@ -200,138 +235,254 @@ struct Stamp {
   }
 };
 
-// Forward 3D FFT of nf real arrays into nf half spectra (held modes zeroed).
+// ---- device tables ---------------------------------------------------------
+const FieldSet *fs_tab(gp_ctx *c, int kind, int pos) {
+  return reinterpret_cast<const FieldSet *>(static_cast<char *>(c->tab.dev) + c->tab.fs[kind]) +
+         pos;
+}
 template <typename T>
-void fft_forward(gp_ctx *c, const Run &r, const void *const *in, void *const *out, int nf) {
-  FieldSet z{}, yx{};
-  for (int f = 0; f < nf; ++f) {
-    z.in[f] = in[f];
-    z.out[f] = out[f];
-    yx.in[f] = out[f];
-    yx.out[f] = out[f];
-  }
-  const Cx<T> *tw = static_cast<const Cx<T> *>(c->tw);
-  launch_r2c_z<T>(z, nf, r.g, tw, c->stream);
-  launch_c2c<T>(yx, nf, r.g, 1, false, false, tw, c->stream);
-  launch_c2c<T>(yx, nf, r.g, 0, false, true, tw, c->stream);
+const UpdatePtrs<T> *upd_tab(gp_ctx *c, int parity, int pos) {
+  return reinterpret_cast<const UpdatePtrs<T> *>(static_cast<char *>(c->tab.dev) +
+                                                 c->tab.upd[parity]) +
+         pos;
+}
+template <typename T>
+const PartJob<T> *job_tab(gp_ctx *c) {
+  return reinterpret_cast<const PartJob<T> *>(static_cast<char *>(c->tab.dev) + c->tab.jobs);
+}
+const ZeroSeg *zero_tab(gp_ctx *c) {
+  return reinterpret_cast<const ZeroSeg *>(static_cast<char *>(c->tab.dev) + c->tab.zero);
 }
 
-// Inverse 3D FFT of nf half spectra into nf real arrays via the scratch.
+template <typename V>
+V *host_at(gp_ctx *c, size_t off, int i) {
+  return reinterpret_cast<V *>(c->tab.host.data() + off) + i;
+}
+
+size_t align16(size_t n) { return (n + 15) & ~size_t(15); }
+
+bool same_class(const RunGeom &a, const RunGeom &b) {
+  return a.nx == b.nx && a.ny == b.ny && a.nz == b.nz && a.dx == b.dx && a.dy == b.dy &&
+         a.dz == b.dz;
+}
+
+// Classes, table layout and the grid-side tables (fixed once the grids are
+// allocated); the particle jobs are filled when particles are bound.
 template <typename T>
-void fft_inverse(gp_ctx *c, const Run &r, const void *const *in, void *const *out, int nf) {
-  FieldSet x{}, y{}, z{};
-  for (int f = 0; f < nf; ++f) {
-    x.in[f] = in[f];
-    x.out[f] = r.scratch[f];
-    y.in[f] = r.scratch[f];
-    y.out[f] = r.scratch[f];
-    z.in[f] = r.scratch[f];
-    z.out[f] = out[f];
+gp_status build_tables(gp_ctx *c) {
+  Tables &t = c->tab;
+  const int n = int(c->runs.size());
+  t.classes.clear();
+  t.pos.assign(n, -1);
+  std::vector<int> order;
+  for (int i = 0; i < n; ++i) {
+    if (t.pos[i] >= 0) continue;
+    Class k{c->runs[i].g, int(order.size()), 0};
+    for (int j = i; j < n; ++j)
+      if (t.pos[j] < 0 && same_class(c->runs[j].g, c->runs[i].g)) {
+        t.pos[j] = int(order.size());
+        order.push_back(j);
+        ++k.count;
+      }
+    t.classes.push_back(k);
   }
+  size_t off = 0;
+  for (int k = 0; k < kNTab; ++k) {
+    t.fs[k] = off;
+    off = align16(off + size_t(n) * sizeof(FieldSet));
+  }
+  for (int k = 0; k < 2; ++k) {
+    t.upd[k] = off;
+    off = align16(off + size_t(n) * sizeof(UpdatePtrs<T>));
+  }
+  t.zero = off;
+  off = align16(off + size_t(4 * n) * sizeof(ZeroSeg));
+  t.jobs = off;
+  off = align16(off + size_t(n) * sizeof(PartJob<T>));
+  t.bytes = off;
+  t.host.assign(off, 0);
+  GP_TRY(dev_alloc(c->allocs, off, &t.dev));
+  t.max_zero16 = 0;
+  for (int i = 0; i < n; ++i) {
+    const Run &r = c->runs[i];
+    const int q = t.pos[i];
+    auto set = [&](int kind, int nf, auto in, auto out) {
+      FieldSet *fs = host_at<FieldSet>(c, t.fs[kind], q);
+      for (int f = 0; f < nf; ++f) {
+        fs->in[f] = in(f);
+        fs->out[f] = out(f);
+      }
+    };
+    for (int par = 0; par < 2; ++par) {
+      // parity par: rho^n in spec slot 9 + par, rho^{n+1} in the other
+      void *src[4] = {r.spec[6], r.spec[7], r.spec[8], r.spec[10 - par]};
+      set(kTabFwdZ0 + par, 4, [&](int f) { return r.real[6 + f]; },
+          [&](int f) { return src[f]; });
+      set(kTabFwdYX0 + par, 4, [&](int f) { return src[f]; }, [&](int f) { return src[f]; });
+      set(kTabRhoZ0 + par, 1, [&](int) { return r.real[9]; },
+          [&](int) { return r.spec[9 + par]; });
+      set(kTabRhoYX0 + par, 1, [&](int) { return r.spec[9 + par]; },
+          [&](int) { return r.spec[9 + par]; });
+      UpdatePtrs<T> *u = host_at<UpdatePtrs<T>>(c, t.upd[par], q);
+      for (int a = 0; a < 3; ++a) {
+        u->E[a] = S<T>(r, a);
+        u->B[a] = S<T>(r, 3 + a);
+        u->J[a] = S<T>(r, 6 + a);
+      }
+      u->rho_old = S<T>(r, 9 + par);
+      u->rho_new = S<T>(r, 10 - par);
+      for (int k = 0; k < 6; ++k) u->coef[k] = static_cast<const Cx<T> *>(r.coef[k]);
+    }
+    set(kTabInvX, 6, [&](int f) { return r.spec[f]; }, [&](int f) { return r.scratch[f]; });
+    set(kTabInvY, 6, [&](int f) { return r.scratch[f]; }, [&](int f) { return r.scratch[f]; });
+    set(kTabInvZ, 6, [&](int f) { return r.scratch[f]; }, [&](int f) { return r.real[f]; });
+    set(kTabEBZ, 6, [&](int f) { return r.real[f]; }, [&](int f) { return r.spec[f]; });
+    set(kTabEBYX, 6, [&](int f) { return r.spec[f]; }, [&](int f) { return r.spec[f]; });
+    for (int q = 0; q < 4; ++q) {  // J and rho
+      ZeroSeg *z = host_at<ZeroSeg>(c, t.zero, 4 * i + q);
+      z->p = r.real[6 + q];
+      z->n16 = real_bytes(c, r) / 16;
+      if (z->n16 > t.max_zero16) t.max_zero16 = z->n16;
+    }
+  }
+  return GP_OK;
+}
+
+// Per-run particle jobs (pointers, geometry with v_gal, sort buffers).
+template <typename T>
+void fill_jobs(gp_ctx *c) {
+  Tables &t = c->tab;
+  PartBatch &b = t.batch;
+  b = PartBatch{};
+  b.order = c->order;
+  b.njobs = int(c->runs.size());
+  for (size_t i = 0; i < c->runs.size(); ++i) {
+    const Run &r = c->runs[i];
+    PartJob<T> *j = host_at<PartJob<T>>(c, t.jobs, int(i));
+    j->g = r.g;
+    j->tg = r.tg;
+    j->p = r.parts;
+    j->gr = grid_ptrs<T>(r);
+    j->sb = r.sb;
+    j->block0 = b.nblocks;
+    b.nblocks += r.tg.n_tiles;
+    if (r.parts.n > b.max_n) b.max_n = r.parts.n;
+    const int64_t cells = int64_t(r.tg.n_tiles) << r.tg.lcpt;
+    if (cells > b.max_cells) b.max_cells = cells;
+    for (int m = 0; m < 4; ++m) {
+      const size_t l = particle_lds_bytes<T>(m, r.tg);
+      if (l > b.lds[m]) b.lds[m] = l;
+    }
+  }
+}
+
+gp_status upload_tables(gp_ctx *c) {
+  GP_HIP(hipMemcpyAsync(c->tab.dev, c->tab.host.data(), c->tab.bytes, hipMemcpyHostToDevice,
+                        c->stream));
+  GP_HIP(hipStreamSynchronize(c->stream));
+  return GP_OK;
+}
+
+// ---- launch sequences --------------------------------------------------------
+// Forward 3D FFT of the run at class-order position pos (or a whole class:
+// count runs) through a pair of tables.
+template <typename T>
+void fft_forward(gp_ctx *c, int tab_z, int tab_yx, int nf, int pos, int count,
+                 const RunGeom &g) {
   const Cx<T> *tw = static_cast<const Cx<T> *>(c->tw);
-  launch_c2c<T>(x, nf, r.g, 0, true, false, tw, c->stream);
-  launch_c2c<T>(y, nf, r.g, 1, true, false, tw, c->stream);
-  launch_c2r_z<T>(z, nf, r.g, tw, c->stream);
+  launch_r2c_z<T>(fs_tab(c, tab_z, pos), count, nf, g, tw, c->stream);
+  launch_c2c<T>(fs_tab(c, tab_yx, pos), count, nf, g, 1, false, false, tw, c->stream);
+  launch_c2c<T>(fs_tab(c, tab_yx, pos), count, nf, g, 0, false, true, tw, c->stream);
+}
+
+// Inverse 3D FFT of E^, B^ into real E, B (via the scratch spectra).
+template <typename T>
+void fft_inverse(gp_ctx *c, int pos, int count, const RunGeom &g) {
+  const Cx<T> *tw = static_cast<const Cx<T> *>(c->tw);
+  launch_c2c<T>(fs_tab(c, kTabInvX, pos), count, 6, g, 0, true, false, tw, c->stream);
+  launch_c2c<T>(fs_tab(c, kTabInvY, pos), count, 6, g, 1, true, false, tw, c->stream);
+  launch_c2r_z<T>(fs_tab(c, kTabInvZ, pos), count, 6, g, tw, c->stream);
 }
 
 // Zero J and rho, sort if flagged, then deposit (mode kPartDeposit) or run
-// the fused gather-push + deposit (kPartFused).
+// the fused gather-push + deposit (kPartFused), for every run at once.
 template <typename T>
 void enqueue_sources(gp_ctx *c, int mode) {
   {
     Stamp s(c, kStZero);
-    for (auto &r : c->runs)
-      for (int q = 6; q < 10; ++q) launch_zero(r.real[q], real_bytes(c, r), c->stream);
+    launch_zero_segments(zero_tab(c), 4 * int(c->runs.size()), c->tab.max_zero16, c->stream);
   }
   {
     Stamp s(c, kStSort);
-    for (auto &r : c->runs) launch_sort<T>(r.g, r.tg, r.parts, r.sb, c->stream);
+    launch_sort<T>(job_tab<T>(c), c->tab.batch, c->stream);
   }
   {
     Stamp s(c, mode == kPartFused ? kStFused : kStDeposit);
-    for (auto &r : c->runs)
-      launch_particles<T>(mode, r.g, r.tg, r.parts, grid_ptrs<T>(r), r.sb, r.g.dt, c->stream);
+    launch_particles<T>(mode, job_tab<T>(c), c->tab.batch, 1.0, c->stream);
   }
 }
 
-template <typename T>
-void do_update(gp_ctx *c, Run &r) {
-  UpdatePtrs<T> p;
-  for (int a = 0; a < 3; ++a) {
-    p.E[a] = S<T>(r, a);
-    p.B[a] = S<T>(r, 3 + a);
-    p.J[a] = S<T>(r, 6 + a);
-  }
-  p.rho_old = S<T>(r, r.rho_old);
-  p.rho_new = S<T>(r, r.rho_old == 9 ? 10 : 9);
-  for (int i = 0; i < 6; ++i) p.coef[i] = static_cast<const Cx<T> *>(r.coef[i]);
-  launch_update<T>(r.g, p, c->stream);
-  r.rho_old = r.rho_old == 9 ? 10 : 9;
-}
+// all runs rotate their rho buffers together
+int rho_parity(const gp_ctx *c) { return c->runs[0].rho_old - 9; }
 
 template <typename T>
 void enqueue_fft_fwd(gp_ctx *c) {
   const Cx<T> *tw = static_cast<const Cx<T> *>(c->tw);
-  auto set = [&](const Run &r, bool z) {
-    FieldSet fs{};
-    void *out[4] = {r.spec[6], r.spec[7], r.spec[8], r.spec[r.rho_old == 9 ? 10 : 9]};
-    for (int f = 0; f < 4; ++f) {
-      fs.in[f] = z ? r.real[6 + f] : out[f];
-      fs.out[f] = out[f];
-    }
-    return fs;
-  };
+  const int par = rho_parity(c);
   {
     Stamp s(c, kStFwdZ);
-    for (auto &r : c->runs) launch_r2c_z<T>(set(r, true), 4, r.g, tw, c->stream);
+    for (const Class &k : c->tab.classes)
+      launch_r2c_z<T>(fs_tab(c, kTabFwdZ0 + par, k.first), k.count, 4, k.g, tw, c->stream);
   }
   {
     Stamp s(c, kStFwdY);
-    for (auto &r : c->runs) launch_c2c<T>(set(r, false), 4, r.g, 1, false, false, tw, c->stream);
+    for (const Class &k : c->tab.classes)
+      launch_c2c<T>(fs_tab(c, kTabFwdYX0 + par, k.first), k.count, 4, k.g, 1, false, false, tw,
+                    c->stream);
   }
   {
     Stamp s(c, kStFwdX);
-    for (auto &r : c->runs) launch_c2c<T>(set(r, false), 4, r.g, 0, false, true, tw, c->stream);
+    for (const Class &k : c->tab.classes)
+      launch_c2c<T>(fs_tab(c, kTabFwdYX0 + par, k.first), k.count, 4, k.g, 0, false, true, tw,
+                    c->stream);
   }
 }
 
 template <typename T>
 void enqueue_update(gp_ctx *c) {
   Stamp s(c, kStUpdate);
-  for (auto &r : c->runs) do_update<T>(c, r);
+  const int par = rho_parity(c);
+  for (const Class &k : c->tab.classes)
+    launch_update<T>(k.g, upd_tab<T>(c, par, k.first), k.count, c->stream);
+  for (auto &r : c->runs) r.rho_old = r.rho_old == 9 ? 10 : 9;
 }
 
 template <typename T>
 void enqueue_fft_inv(gp_ctx *c) {
   const Cx<T> *tw = static_cast<const Cx<T> *>(c->tw);
-  auto set = [&](const Run &r, int pass) {
-    FieldSet fs{};
-    for (int f = 0; f < 6; ++f) {
-      fs.in[f] = pass == 0 ? r.spec[f] : r.scratch[f];
-      fs.out[f] = pass == 2 ? r.real[f] : r.scratch[f];
-    }
-    return fs;
-  };
   {
     Stamp s(c, kStInvX);
-    for (auto &r : c->runs) launch_c2c<T>(set(r, 0), 6, r.g, 0, true, false, tw, c->stream);
+    for (const Class &k : c->tab.classes)
+      launch_c2c<T>(fs_tab(c, kTabInvX, k.first), k.count, 6, k.g, 0, true, false, tw,
+                    c->stream);
   }
   {
     Stamp s(c, kStInvY);
-    for (auto &r : c->runs) launch_c2c<T>(set(r, 1), 6, r.g, 1, true, false, tw, c->stream);
+    for (const Class &k : c->tab.classes)
+      launch_c2c<T>(fs_tab(c, kTabInvY, k.first), k.count, 6, k.g, 1, true, false, tw,
+                    c->stream);
   }
   {
     Stamp s(c, kStInvZ);
-    for (auto &r : c->runs) launch_c2r_z<T>(set(r, 2), 6, r.g, tw, c->stream);
+    for (const Class &k : c->tab.classes)
+      launch_c2r_z<T>(fs_tab(c, kTabInvZ, k.first), k.count, 6, k.g, tw, c->stream);
   }
 }
 
 template <typename T>
 void enqueue_push(gp_ctx *c, double dt_factor) {
   Stamp s(c, kStGather);
-  for (auto &r : c->runs)
-    launch_particles<T>(kPartPush, r.g, r.tg, r.parts, grid_ptrs<T>(r), r.sb,
-                        dt_factor * r.g.dt, c->stream);
+  launch_particles<T>(kPartPush, job_tab<T>(c), c->tab.batch, dt_factor, c->stream);
 }
 
 template <typename T>
@@ -678,6 +829,8 @@ gp_status gp_init_grid(const gp_grid_desc *runs, int n_runs, void *hip_stream, g
     g.ncell = int64_t(d.nx) * d.ny * d.nz;
     g.nmode = int64_t(d.nx) * d.ny * g.nzh;
     r.tg = make_tile_geom(g, c->real_size);
+    // one allocation per grid: grids at power-of-two distances in one block
+    // would send the gather's six same-node loads to the same HBM channel
     for (auto &p : r.real) {
       gp_status st = dev_alloc(c->allocs, real_bytes(c, r), &p);
       if (st) return bail(st);
@@ -714,6 +867,10 @@ gp_status gp_init_grid(const gp_grid_desc *runs, int n_runs, void *hip_stream, g
     st = dev_alloc(c->allocs, 2 * sizeof(double), &sum);
     if (st) return bail(st);
     c->d_sum = static_cast<double *>(sum);
+    st = c->precision == GP_FP64 ? build_tables<double>(c) : build_tables<float>(c);
+    if (st) return bail(st);
+    st = upload_tables(c);
+    if (st) return bail(st);
   }
   for (int i = 0; i < n_runs; ++i) {
     gp_status st = gp_set_v_gal(c, i, 0.0, 0.0, 0.0);
@@ -752,7 +909,14 @@ gp_status gp_set_v_gal(gp_ctx *c, int run, double vx, double vy, double vz) {
   else
     launch_coefficients<float>(g, cp, c->stream);
   GP_TRY(check_launch("coefficients"));
-  drop_graphs(c);  // kernel arguments carry v_gal
+  drop_graphs(c);
+  if (r.bound) {  // the particle jobs carry v_gal
+    if (c->precision == GP_FP64)
+      fill_jobs<double>(c);
+    else
+      fill_jobs<float>(c);
+    GP_TRY(upload_tables(c));
+  }
   return GP_OK;
 }
 
@@ -768,19 +932,24 @@ gp_status gp_bind_particles(gp_ctx *c, const gp_particles *p) {
     GP_TRY(alloc_sort(c, r));
     r.bound = true;
   }
+  if (c->precision == GP_FP64)
+    fill_jobs<double>(c);
+  else
+    fill_jobs<float>(c);
+  GP_TRY(upload_tables(c));
   GP_TRY(dispatch(c, [&](auto t) {
     using T = decltype(t);
-    for (auto &r : c->runs) {
-      launch_zero(r.real[9], real_bytes(c, r), c->stream);
-      launch_sort<T>(r.g, r.tg, r.parts, r.sb, c->stream);
-      launch_particles<T>(kPartRho, r.g, r.tg, r.parts, grid_ptrs<T>(r), r.sb, 0.0, c->stream);
-      const void *in[1] = {r.real[9]};
-      void *out[1] = {r.spec[r.rho_old]};
-      fft_forward<T>(c, r, in, out, 1);
-      r.src_real_ready = false;
-      r.src_spec_ready = false;
-    }
+    for (auto &r : c->runs) launch_zero(r.real[9], real_bytes(c, r), c->stream);
+    launch_sort<T>(job_tab<T>(c), c->tab.batch, c->stream);
+    launch_particles<T>(kPartRho, job_tab<T>(c), c->tab.batch, 0.0, c->stream);
+    const int par = rho_parity(c);
+    for (const Class &k : c->tab.classes)
+      fft_forward<T>(c, kTabRhoZ0 + par, kTabRhoYX0 + par, 1, k.first, k.count, k.g);
   }));
+  for (auto &r : c->runs) {
+    r.src_real_ready = false;
+    r.src_spec_ready = false;
+  }
   return GP_OK;
 }
 
@@ -938,14 +1107,13 @@ gp_status gp_set_fields(gp_ctx *c, int run, const void *const E[3], const void *
   }
   GP_TRY(dispatch(c, [&](auto t) {
     using T = decltype(t);
-    const void *in[6] = {r.real[0], r.real[1], r.real[2], r.real[3], r.real[4], r.real[5]};
-    void *out[6] = {r.spec[0], r.spec[1], r.spec[2], r.spec[3], r.spec[4], r.spec[5]};
-    fft_forward<T>(c, r, in, out, 6);
+    const int pos = c->tab.pos[run];
+    fft_forward<T>(c, kTabEBZ, kTabEBYX, 6, pos, 1, r.g);
     launch_project<T>(r.g, S<T>(r, 0), S<T>(r, 1), S<T>(r, 2), project_transverse != 0,
                       c->stream);
     launch_project<T>(r.g, S<T>(r, 3), S<T>(r, 4), S<T>(r, 5), project_transverse != 0,
                       c->stream);
-    fft_inverse<T>(c, r, out, r.real, 6);
+    fft_inverse<T>(c, pos, 1, r.g);
   }));
   GP_HIP(hipStreamSynchronize(c->stream));
   r.eb_real_ready = true;

@@ -68,4 +68,15 @@ struct PartPtrs {
 
 constexpr double kPi = 3.14159265358979323846;
 
+// A pointer read from a table in memory is generic to the compiler, which
+// then emits flat instructions for it.  Every device buffer of the library
+// is global memory: rebuilding the pointer from its integer value as a
+// global-space pointer lets the compiler emit global loads, stores and
+// atomics (a direct cast round trip would be folded away).
+template <typename P>
+__device__ __forceinline__ P *global_ptr(P *p) {
+  using G = __attribute__((address_space(1))) P;
+  return (P *)(G *)(uintptr_t)p;
+}
+
 }  // namespace galpic

@@ -183,16 +183,18 @@ constexpr int kThreads = 256;
 
 // ---- z pass, forward: real lines -> half spectra ---------------------------
 template <typename T, int LOGM>
-__global__ __launch_bounds__(kThreads) void k_r2c_z(FieldSet fs, int64_t nlines,
+__global__ __launch_bounds__(kThreads) void k_r2c_z(const FieldSet *__restrict__ sets, int nf,
+                                                    int64_t nlines,
                                                     const Cx<T> *__restrict__ tw) {
   constexpr int CW = TileCols<T>::value;
   constexpr int S = CW + 1;
   constexpr int M = 1 << LOGM;
   constexpr int NZH = M + 1;
   __shared__ Cx<T> lds[M * S];
-  const int f = blockIdx.y;
-  const Cx<T> *__restrict__ in = static_cast<const Cx<T> *>(fs.in[f]);
-  Cx<T> *__restrict__ out = static_cast<Cx<T> *>(fs.out[f]);
+  const FieldSet &fs = sets[blockIdx.y / nf];
+  const int f = blockIdx.y % nf;
+  const Cx<T> *__restrict__ in = static_cast<const Cx<T> *>(global_ptr(fs.in[f]));
+  Cx<T> *__restrict__ out = static_cast<Cx<T> *>(global_ptr(fs.out[f]));
   const int64_t line0 = int64_t(blockIdx.x) * CW;
   const int tid = threadIdx.x;
   for (int it = tid; it < CW * M; it += kThreads) {
@@ -222,16 +224,18 @@ __global__ __launch_bounds__(kThreads) void k_r2c_z(FieldSet fs, int64_t nlines,
 
 // ---- z pass, inverse: half spectra -> real lines, scaled -------------------
 template <typename T, int LOGM>
-__global__ __launch_bounds__(kThreads) void k_c2r_z(FieldSet fs, int64_t nlines, T scale,
+__global__ __launch_bounds__(kThreads) void k_c2r_z(const FieldSet *__restrict__ sets, int nf,
+                                                    int64_t nlines, T scale,
                                                     const Cx<T> *__restrict__ tw) {
   constexpr int CW = TileCols<T>::value;
   constexpr int S = CW + 1;
   constexpr int M = 1 << LOGM;
   constexpr int NZH = M + 1;
   __shared__ Cx<T> lds[M * S];
-  const int f = blockIdx.y;
-  const Cx<T> *__restrict__ in = static_cast<const Cx<T> *>(fs.in[f]);
-  Cx<T> *__restrict__ out = static_cast<Cx<T> *>(fs.out[f]);
+  const FieldSet &fs = sets[blockIdx.y / nf];
+  const int f = blockIdx.y % nf;
+  const Cx<T> *__restrict__ in = static_cast<const Cx<T> *>(global_ptr(fs.in[f]));
+  Cx<T> *__restrict__ out = static_cast<Cx<T> *>(global_ptr(fs.out[f]));
   const int64_t line0 = int64_t(blockIdx.x) * CW;
   const int tid = threadIdx.x;
   for (int it = tid; it < CW * M; it += kThreads) {
@@ -272,16 +276,17 @@ struct StridedGeom {
 };
 
 template <typename T, int LOGL>
-__global__ __launch_bounds__(kThreads) void k_c2c_strided(FieldSet fs, StridedGeom sg,
-                                                          int inverse,
+__global__ __launch_bounds__(kThreads) void k_c2c_strided(const FieldSet *__restrict__ sets,
+                                                          int nf, StridedGeom sg, int inverse,
                                                           const Cx<T> *__restrict__ tw) {
   constexpr int CW = TileCols<T>::value;
   constexpr int S = CW + 1;
   constexpr int L = 1 << LOGL;
   __shared__ Cx<T> lds[L * S];
-  const int f = blockIdx.y;
-  const Cx<T> *__restrict__ in = static_cast<const Cx<T> *>(fs.in[f]);
-  Cx<T> *__restrict__ out = static_cast<Cx<T> *>(fs.out[f]);
+  const FieldSet &fs = sets[blockIdx.y / nf];
+  const int f = blockIdx.y % nf;
+  const Cx<T> *__restrict__ in = static_cast<const Cx<T> *>(global_ptr(fs.in[f]));
+  Cx<T> *__restrict__ out = static_cast<Cx<T> *>(global_ptr(fs.out[f]));
   const int outer = blockIdx.x / sg.col_tiles;
   const int col0 = (blockIdx.x % sg.col_tiles) * CW;
   const int64_t base = int64_t(outer) * sg.outer_stride + col0;
@@ -310,27 +315,31 @@ __global__ __launch_bounds__(kThreads) void k_c2c_strided(FieldSet fs, StridedGe
   }
 }
 
+// Workgroup row blockIdx.y = set * nf + field: one launch transforms nf
+// fields of every run in the table.
 template <typename T, int LOG>
-void dispatch_r2c(const FieldSet &fs, int nf, int64_t nlines, const Cx<T> *tw, hipStream_t s) {
-  constexpr int CW = TileCols<T>::value;
-  dim3 grid(unsigned((nlines + CW - 1) / CW), unsigned(nf));
-  hipLaunchKernelGGL((k_r2c_z<T, LOG>), grid, dim3(kThreads), 0, s, fs, nlines, tw);
-}
-
-template <typename T, int LOG>
-void dispatch_c2r(const FieldSet &fs, int nf, int64_t nlines, T scale, const Cx<T> *tw,
+void dispatch_r2c(const FieldSet *sets, int nsets, int nf, int64_t nlines, const Cx<T> *tw,
                   hipStream_t s) {
   constexpr int CW = TileCols<T>::value;
-  dim3 grid(unsigned((nlines + CW - 1) / CW), unsigned(nf));
-  hipLaunchKernelGGL((k_c2r_z<T, LOG>), grid, dim3(kThreads), 0, s, fs, nlines, scale, tw);
+  dim3 grid(unsigned((nlines + CW - 1) / CW), unsigned(nf * nsets));
+  hipLaunchKernelGGL((k_r2c_z<T, LOG>), grid, dim3(kThreads), 0, s, sets, nf, nlines, tw);
 }
 
 template <typename T, int LOG>
-void dispatch_c2c(const FieldSet &fs, int nf, const StridedGeom &sg, int n_outer, int inverse,
+void dispatch_c2r(const FieldSet *sets, int nsets, int nf, int64_t nlines, T scale,
                   const Cx<T> *tw, hipStream_t s) {
-  dim3 grid(unsigned(n_outer * sg.col_tiles), unsigned(nf));
-  hipLaunchKernelGGL((k_c2c_strided<T, LOG>), grid, dim3(kThreads), 0, s, fs, sg, inverse,
+  constexpr int CW = TileCols<T>::value;
+  dim3 grid(unsigned((nlines + CW - 1) / CW), unsigned(nf * nsets));
+  hipLaunchKernelGGL((k_c2r_z<T, LOG>), grid, dim3(kThreads), 0, s, sets, nf, nlines, scale,
                      tw);
+}
+
+template <typename T, int LOG>
+void dispatch_c2c(const FieldSet *sets, int nsets, int nf, const StridedGeom &sg, int n_outer,
+                  int inverse, const Cx<T> *tw, hipStream_t s) {
+  dim3 grid(unsigned(n_outer * sg.col_tiles), unsigned(nf * nsets));
+  hipLaunchKernelGGL((k_c2c_strided<T, LOG>), grid, dim3(kThreads), 0, s, sets, nf, sg,
+                     inverse, tw);
 }
 
 }  // namespace
@@ -345,43 +354,43 @@ void fill_twiddles(Cx<T> *h) {
 }
 
 template <typename T>
-void launch_r2c_z(const FieldSet &fs, int nf, const RunGeom &g, const Cx<T> *tw,
+void launch_r2c_z(const FieldSet *sets, int nsets, int nf, const RunGeom &g, const Cx<T> *tw,
                   hipStream_t s) {
   const int64_t nlines = int64_t(g.nx) * g.ny;
   switch (g.lz - 1) {
-    case 2: dispatch_r2c<T, 2>(fs, nf, nlines, tw, s); break;
-    case 3: dispatch_r2c<T, 3>(fs, nf, nlines, tw, s); break;
-    case 4: dispatch_r2c<T, 4>(fs, nf, nlines, tw, s); break;
-    case 5: dispatch_r2c<T, 5>(fs, nf, nlines, tw, s); break;
-    case 6: dispatch_r2c<T, 6>(fs, nf, nlines, tw, s); break;
-    case 7: dispatch_r2c<T, 7>(fs, nf, nlines, tw, s); break;
-    case 8: dispatch_r2c<T, 8>(fs, nf, nlines, tw, s); break;
-    case 9: dispatch_r2c<T, 9>(fs, nf, nlines, tw, s); break;
+    case 2: dispatch_r2c<T, 2>(sets, nsets, nf, nlines, tw, s); break;
+    case 3: dispatch_r2c<T, 3>(sets, nsets, nf, nlines, tw, s); break;
+    case 4: dispatch_r2c<T, 4>(sets, nsets, nf, nlines, tw, s); break;
+    case 5: dispatch_r2c<T, 5>(sets, nsets, nf, nlines, tw, s); break;
+    case 6: dispatch_r2c<T, 6>(sets, nsets, nf, nlines, tw, s); break;
+    case 7: dispatch_r2c<T, 7>(sets, nsets, nf, nlines, tw, s); break;
+    case 8: dispatch_r2c<T, 8>(sets, nsets, nf, nlines, tw, s); break;
+    case 9: dispatch_r2c<T, 9>(sets, nsets, nf, nlines, tw, s); break;
     default: break;  // sizes are validated by the caller
   }
 }
 
 template <typename T>
-void launch_c2r_z(const FieldSet &fs, int nf, const RunGeom &g, const Cx<T> *tw,
+void launch_c2r_z(const FieldSet *sets, int nsets, int nf, const RunGeom &g, const Cx<T> *tw,
                   hipStream_t s) {
   const int64_t nlines = int64_t(g.nx) * g.ny;
   const T scale = T(1.0 / double(g.ncell));
   switch (g.lz - 1) {
-    case 2: dispatch_c2r<T, 2>(fs, nf, nlines, scale, tw, s); break;
-    case 3: dispatch_c2r<T, 3>(fs, nf, nlines, scale, tw, s); break;
-    case 4: dispatch_c2r<T, 4>(fs, nf, nlines, scale, tw, s); break;
-    case 5: dispatch_c2r<T, 5>(fs, nf, nlines, scale, tw, s); break;
-    case 6: dispatch_c2r<T, 6>(fs, nf, nlines, scale, tw, s); break;
-    case 7: dispatch_c2r<T, 7>(fs, nf, nlines, scale, tw, s); break;
-    case 8: dispatch_c2r<T, 8>(fs, nf, nlines, scale, tw, s); break;
-    case 9: dispatch_c2r<T, 9>(fs, nf, nlines, scale, tw, s); break;
+    case 2: dispatch_c2r<T, 2>(sets, nsets, nf, nlines, scale, tw, s); break;
+    case 3: dispatch_c2r<T, 3>(sets, nsets, nf, nlines, scale, tw, s); break;
+    case 4: dispatch_c2r<T, 4>(sets, nsets, nf, nlines, scale, tw, s); break;
+    case 5: dispatch_c2r<T, 5>(sets, nsets, nf, nlines, scale, tw, s); break;
+    case 6: dispatch_c2r<T, 6>(sets, nsets, nf, nlines, scale, tw, s); break;
+    case 7: dispatch_c2r<T, 7>(sets, nsets, nf, nlines, scale, tw, s); break;
+    case 8: dispatch_c2r<T, 8>(sets, nsets, nf, nlines, scale, tw, s); break;
+    case 9: dispatch_c2r<T, 9>(sets, nsets, nf, nlines, scale, tw, s); break;
     default: break;
   }
 }
 
 template <typename T>
-void launch_c2c(const FieldSet &fs, int nf, const RunGeom &g, int axis, bool inverse,
-                bool mask_held, const Cx<T> *tw, hipStream_t s) {
+void launch_c2c(const FieldSet *sets, int nsets, int nf, const RunGeom &g, int axis,
+                bool inverse, bool mask_held, const Cx<T> *tw, hipStream_t s) {
   constexpr int CW = TileCols<T>::value;
   StridedGeom sg;
   sg.ncols = g.nzh;
@@ -406,31 +415,31 @@ void launch_c2c(const FieldSet &fs, int nf, const RunGeom &g, int axis, bool inv
   sg.half_col = g.nz / 2;
   const int inv = inverse ? 1 : 0;
   switch (logl) {
-    case 3: dispatch_c2c<T, 3>(fs, nf, sg, n_outer, inv, tw, s); break;
-    case 4: dispatch_c2c<T, 4>(fs, nf, sg, n_outer, inv, tw, s); break;
-    case 5: dispatch_c2c<T, 5>(fs, nf, sg, n_outer, inv, tw, s); break;
-    case 6: dispatch_c2c<T, 6>(fs, nf, sg, n_outer, inv, tw, s); break;
-    case 7: dispatch_c2c<T, 7>(fs, nf, sg, n_outer, inv, tw, s); break;
-    case 8: dispatch_c2c<T, 8>(fs, nf, sg, n_outer, inv, tw, s); break;
-    case 9: dispatch_c2c<T, 9>(fs, nf, sg, n_outer, inv, tw, s); break;
-    case 10: dispatch_c2c<T, 10>(fs, nf, sg, n_outer, inv, tw, s); break;
+    case 3: dispatch_c2c<T, 3>(sets, nsets, nf, sg, n_outer, inv, tw, s); break;
+    case 4: dispatch_c2c<T, 4>(sets, nsets, nf, sg, n_outer, inv, tw, s); break;
+    case 5: dispatch_c2c<T, 5>(sets, nsets, nf, sg, n_outer, inv, tw, s); break;
+    case 6: dispatch_c2c<T, 6>(sets, nsets, nf, sg, n_outer, inv, tw, s); break;
+    case 7: dispatch_c2c<T, 7>(sets, nsets, nf, sg, n_outer, inv, tw, s); break;
+    case 8: dispatch_c2c<T, 8>(sets, nsets, nf, sg, n_outer, inv, tw, s); break;
+    case 9: dispatch_c2c<T, 9>(sets, nsets, nf, sg, n_outer, inv, tw, s); break;
+    case 10: dispatch_c2c<T, 10>(sets, nsets, nf, sg, n_outer, inv, tw, s); break;
     default: break;
   }
 }
 
 template void fill_twiddles<float>(Cx<float> *);
 template void fill_twiddles<double>(Cx<double> *);
-template void launch_r2c_z<float>(const FieldSet &, int, const RunGeom &, const Cx<float> *,
+template void launch_r2c_z<float>(const FieldSet *, int, int, const RunGeom &, const Cx<float> *,
                                   hipStream_t);
-template void launch_r2c_z<double>(const FieldSet &, int, const RunGeom &,
+template void launch_r2c_z<double>(const FieldSet *, int, int, const RunGeom &,
                                    const Cx<double> *, hipStream_t);
-template void launch_c2r_z<float>(const FieldSet &, int, const RunGeom &, const Cx<float> *,
+template void launch_c2r_z<float>(const FieldSet *, int, int, const RunGeom &, const Cx<float> *,
                                   hipStream_t);
-template void launch_c2r_z<double>(const FieldSet &, int, const RunGeom &,
+template void launch_c2r_z<double>(const FieldSet *, int, int, const RunGeom &,
                                    const Cx<double> *, hipStream_t);
-template void launch_c2c<float>(const FieldSet &, int, const RunGeom &, int, bool, bool,
+template void launch_c2c<float>(const FieldSet *, int, int, const RunGeom &, int, bool, bool,
                                 const Cx<float> *, hipStream_t);
-template void launch_c2c<double>(const FieldSet &, int, const RunGeom &, int, bool, bool,
+template void launch_c2c<double>(const FieldSet *, int, int, const RunGeom &, int, bool, bool,
                                  const Cx<double> *, hipStream_t);
 
 }  // namespace galpic

@@ -5,7 +5,9 @@
 
 namespace galpic {
 
-// Up to six field arrays processed by one launch (blockIdx.y = field).
+// Up to six field arrays of one run.  Launches take a device table of
+// FieldSets, one per run: workgroup row blockIdx.y = run * nf + field, so one
+// launch covers every run of a grid shape.
 struct FieldSet {
   const void *in[6];
   void *out[6];
@@ -17,18 +19,19 @@ template <typename T>
 void fill_twiddles(Cx<T> *host1024);
 
 // Forward real-to-complex transform along z of nf real arrays [x][y][z] into
-// half spectra [x][y][nz/2+1].
+// half spectra [x][y][nz/2+1], for the nsets runs (all of grid shape g) of
+// the device table sets.
 template <typename T>
-void launch_r2c_z(const FieldSet &fs, int nf, const RunGeom &g, const Cx<T> *tw,
+void launch_r2c_z(const FieldSet *sets, int nsets, int nf, const RunGeom &g, const Cx<T> *tw,
                   hipStream_t s);
 // Complex transform along y (axis 1) or x (axis 0) of nf half spectra.
 // mask_held: write zero on the k = 0 mode and every Nyquist plane.
 template <typename T>
-void launch_c2c(const FieldSet &fs, int nf, const RunGeom &g, int axis, bool inverse,
-                bool mask_held, const Cx<T> *tw, hipStream_t s);
+void launch_c2c(const FieldSet *sets, int nsets, int nf, const RunGeom &g, int axis,
+                bool inverse, bool mask_held, const Cx<T> *tw, hipStream_t s);
 // Inverse complex-to-real transform along z with the 1/(nx ny nz) scale.
 template <typename T>
-void launch_c2r_z(const FieldSet &fs, int nf, const RunGeom &g, const Cx<T> *tw,
+void launch_c2r_z(const FieldSet *sets, int nsets, int nf, const RunGeom &g, const Cx<T> *tw,
                   hipStream_t s);
 
 // ---- coefficients (coef.hip) ----------------------------------------------
@@ -48,8 +51,9 @@ struct UpdatePtrs {
   const Cx<T> *rho_new;
   const Cx<T> *coef[6];
 };
+// The update of the nsets runs (all of grid shape g) of the device table.
 template <typename T>
-void launch_update(const RunGeom &g, const UpdatePtrs<T> &p, hipStream_t s);
+void launch_update(const RunGeom &g, const UpdatePtrs<T> *sets, int nsets, hipStream_t s);
 // Transverse projection F <- F - k (k.F)/k^2 of a spectral 3-vector, held
 // modes zeroed.
 template <typename T>
@@ -58,6 +62,13 @@ void launch_project(const RunGeom &g, Cx<T> *F0, Cx<T> *F1, Cx<T> *F2, bool tran
 // Fill nbytes (a multiple of 4) with zeros; a kernel, so it can be captured
 // in a graph.
 void launch_zero(void *p, size_t nbytes, hipStream_t s);
+// Zero every segment of a device table (max_n16: the longest, in 16-byte
+// units).
+struct ZeroSeg {
+  void *p;
+  size_t n16;
+};
+void launch_zero_segments(const ZeroSeg *segs, int nseg, size_t max_n16, hipStream_t s);
 // out[0] += sum of squares over n values of each of the three arrays.
 template <typename T>
 void launch_sum_squares(const T *a, const T *b, const T *c, int64_t n, double *out,
@@ -99,21 +110,44 @@ struct SortBufs {
   void *tmp[8];     // scratch columns for the scatter
 };
 
-// Sort the particles by tile when flagged (state[3] forces it; otherwise
-// when more than n/64 particles used the global fallback since the last
-// decision).  Every kernel checks the flag on the device, so the launch
+// One run of a batched particle or sort launch: an entry of a device table.
+template <typename T>
+struct PartJob {
+  RunGeom g;
+  TileGeom tg;
+  PartPtrs p;
+  GridPtrs<T> gr;
+  SortBufs sb;
+  int block0;  // first workgroup of the run in a launch with one workgroup per tile
+};
+
+// What the launchers need to know about a table of PartJobs.
+struct PartBatch {
+  int order;          // shape order (all runs of a context share it)
+  int njobs;
+  int nblocks;        // tiles of all runs
+  int64_t max_n;      // most particles in one run
+  int64_t max_cells;  // most cells in one run
+  size_t lds[4];      // dynamic LDS of the particle kernel per mode: the most of any run
+};
+
+// Sort the particles of each run by tile when flagged (state[3] forces it;
+// otherwise when more than n/64 particles used the global fallback since the
+// last decision).  Every kernel checks the flag on the device, so the launch
 // sequence is fixed and can be captured in a graph.
 template <typename T>
-void launch_sort(const RunGeom &g, const TileGeom &tg, const PartPtrs &p, const SortBufs &sb,
-                 hipStream_t s);
+void launch_sort(const PartJob<T> *jobs, const PartBatch &b, hipStream_t s);
 
 enum { kPartRho = 0, kPartDeposit = 1, kPartFused = 2, kPartPush = 3 };
-// Tile kernels: rho at the current positions; deposit (move, J, move, rho);
-// fused (gather + push through dt_push, then deposit); push (gather + push).
-// Deposits add into the grids, which the caller zeroes first.
+// Tile kernels over every run of the table: rho at the current positions;
+// deposit (move, J, move, rho); fused (gather + push through dt_factor * dt,
+// then deposit); push (gather + push through dt_factor * dt).  Deposits add
+// into the grids, which the caller zeroes first.
 template <typename T>
-void launch_particles(int mode, const RunGeom &g, const TileGeom &tg, const PartPtrs &p,
-                      const GridPtrs<T> &gr, const SortBufs &sb, double dt_push,
+void launch_particles(int mode, const PartJob<T> *jobs, const PartBatch &b, double dt_factor,
                       hipStream_t s);
+// Dynamic LDS bytes of the particle kernel of a mode for one run's tiles.
+template <typename T>
+size_t particle_lds_bytes(int mode, const TileGeom &tg);
 
 }  // namespace galpic

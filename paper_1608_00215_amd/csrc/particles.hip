@@ -230,10 +230,70 @@ struct Region {
   int org[3];
 };
 
-__device__ __forceinline__ int tile_of_block(const TileGeom &tg) {
-  // XCD-aware: consecutive workgroups go to different XCDs round-robin;
-  // give each XCD a contiguous run of tiles so neighbours share its L2.
-  const int b = blockIdx.x;
+// A value of a table that no kernel writes during the launch, read through
+// the constant address space (word by word): the loads need not wait behind
+// the kernel's own stores and may be hoisted or repeated freely.
+template <typename V>
+__device__ __forceinline__ V load_const(const V *ptr) {
+  static_assert(sizeof(V) % 4 == 0, "whole words");
+  using CU = __attribute__((address_space(4))) const unsigned;
+  CU *q = (CU *)ptr;
+  V v;
+  unsigned *d = reinterpret_cast<unsigned *>(&v);
+#pragma unroll
+  for (size_t i = 0; i < sizeof(V) / 4; ++i) d[i] = q[i];
+  return v;
+}
+
+// The buffers of a run's table entry as global pointers.
+__device__ __forceinline__ void globalize(PartPtrs &p) {
+  p.x = global_ptr(p.x);
+  p.y = global_ptr(p.y);
+  p.z = global_ptr(p.z);
+  p.ox = global_ptr(p.ox);
+  p.oy = global_ptr(p.oy);
+  p.oz = global_ptr(p.oz);
+  p.ux = global_ptr(p.ux);
+  p.uy = global_ptr(p.uy);
+  p.uz = global_ptr(p.uz);
+  p.id = global_ptr(p.id);
+}
+template <typename T>
+__device__ __forceinline__ void globalize(GridPtrs<T> &g) {
+  for (int a = 0; a < 3; ++a) {
+    g.E[a] = global_ptr(g.E[a]);
+    g.B[a] = global_ptr(g.B[a]);
+    g.J[a] = global_ptr(g.J[a]);
+  }
+  g.rho = global_ptr(g.rho);
+}
+__device__ __forceinline__ void globalize(SortBufs &b) {
+  b.cell_count = global_ptr(b.cell_count);
+  b.cell_off = global_ptr(b.cell_off);
+  b.tile_total = global_ptr(b.tile_total);
+  b.start = global_ptr(b.start);
+  b.key = global_ptr(b.key);
+  b.rank = global_ptr(b.rank);
+  b.state = global_ptr(b.state);
+  for (int c = 0; c < 8; ++c) b.tmp[c] = global_ptr(b.tmp[c]);
+}
+
+// Run of a batched launch that owns workgroup b: the last job whose first
+// workgroup is at or before b (block0 ascends).
+template <typename J>
+__device__ __forceinline__ int job_of_block(const J *jobs, int njobs, int b) {
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].block0 <= b) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Tile of the run's b-th workgroup.  XCD-aware: consecutive workgroups go
+// to different XCDs round-robin; give each XCD a contiguous run of tiles so
+// neighbours share its L2.
+__device__ __forceinline__ int tile_of_block(const TileGeom &tg, int b) {
   if ((tg.n_tiles & 7) != 0) return b;
   const int per = tg.n_tiles >> 3;
   return (b & 7) * per + (b >> 3);
@@ -673,12 +733,24 @@ __device__ __forceinline__ void scan2(const int *v, int *out, int n, int *tmp) {
 //           deposit with the new u (one pass over the particles per step)
 //  push:    gather and push u through the time step h was built for
 template <class L, int ORDER, int MODE, typename A, int NT>
-__global__ __launch_bounds__(NT) void k_quad(RunGeom g, TileGeom tg, PartPtrs p,
-                                             GridPtrs<typename L::T> gr,
-                                             const int *__restrict__ start, int *state,
-                                             typename L::T h) {
+__global__ __launch_bounds__(NT) void k_quad(const PartJob<typename L::T> *__restrict__ jobs,
+                                             int njobs, double dt_factor) {
   using T = typename L::T;
   using Sh = Shape<ORDER, T>;
+  // the run's entry of the table, through the constant address space
+  using CJob = __attribute__((address_space(4))) const PartJob<T>;
+  CJob *cjobs = (CJob *)jobs;
+  const PartJob<T> *jp = jobs + job_of_block(cjobs, njobs, blockIdx.x);
+  const RunGeom g = load_const(&jp->g);
+  const TileGeom tg = load_const(&jp->tg);
+  PartPtrs p = load_const(&jp->p);
+  globalize(p);
+  GridPtrs<T> gr = load_const(&jp->gr);
+  globalize(gr);
+  const int *__restrict__ start = global_ptr(load_const(&jp->sb.start));
+  int *state = global_ptr(load_const(&jp->sb.state));
+  const int block0 = load_const(&jp->block0);
+  const T h = T(p.q * (dt_factor * g.dt) / (2.0 * p.m));
   constexpr bool kGather = MODE == kModeFused || MODE == kModePush;
   constexpr bool kDeposit = MODE != kModePush;
   constexpr bool kMove = MODE == kModeFused || MODE == kModeDeposit;
@@ -699,7 +771,7 @@ __global__ __launch_bounds__(NT) void k_quad(RunGeom g, TileGeom tg, PartPtrs p,
   tl.jobs = reinterpret_cast<int *>(tl.list + ((tg.cap + 1) & ~1));
   __shared__ int scan_tmp[NT];
 
-  const int tile = tile_of_block(tg);
+  const int tile = tile_of_block(tg, int(blockIdx.x) - block0);
   const Region rg = region_of(tile, tg, g, Sh::FIRST);
   const T qw = T(p.q * p.w / (g.dx * g.dy * g.dz));
   const int tid = threadIdx.x;
@@ -726,7 +798,7 @@ __global__ __launch_bounds__(NT) void k_quad(RunGeom g, TileGeom tg, PartPtrs p,
     org[1] = (ty * tg.t[1] - tg.margin) & (g.ny - 1);
     org[2] = (tz * tg.t[2] - tg.margin) & (g.nz - 1);
   }
-  int njobs;
+  int nwork;  // jobs of up to four particles in this tile
   if (listed) {
     for (int b = tid; b <= tg.nb; b += NT) tl.fill[b] = 0;
     __syncthreads();
@@ -747,16 +819,16 @@ __global__ __launch_bounds__(NT) void k_quad(RunGeom g, TileGeom tg, PartPtrs p,
       if ((r & 3) == 0)  // first particle of a job
         tl.jobs[tl.job[b] + (r >> 2)] = pos | (min(4, tl.off[b + 1] - pos) << 24);
     }
-    njobs = tl.job[tg.nb + 1];
+    nwork = tl.job[tg.nb + 1];
   } else {
-    njobs = (count + 3) >> 2;
+    nwork = (count + 3) >> 2;
   }
   __syncthreads();
 
   T *jdst[3] = {gr.J[0], gr.J[1], gr.J[2]};
   T *rdst[1] = {gr.rho};
   const int m = tid & 3;
-  for (int j = tid >> 2; j < njobs; j += NT / 4) {
+  for (int j = tid >> 2; j < nwork; j += NT / 4) {
     int first, n;  // list position (or tile index) of the job's first particle; its size
     if (listed) {
       const int e = tl.jobs[j];
@@ -832,22 +904,35 @@ __global__ __launch_bounds__(NT) void k_quad(RunGeom g, TileGeom tg, PartPtrs p,
 
 // ---- tile sort (run only when flagged) --------------------------------------
 // A counting sort by tile-major cell index: the particles of a tile end up
-// grouped by cell, in tile order.  state[0]: particles that used the global path since the
-// last decision; state[1]: sort flag of this step; state[2]: sorts done;
-// state[3]: force flag (set by the host at binding).
-__global__ void k_sort_decide(int *state, int threshold) {
-  const int need = (state[3] != 0 || state[0] > threshold) ? 1 : 0;
-  state[1] = need;
-  state[0] = 0;
-  state[3] = 0;
-  if (need) state[2] += 1;
+// grouped by cell, in tile order.  Per run, state[0]: particles that used
+// the global path since the last decision; state[1]: sort flag of this
+// step; state[2]: sorts done; state[3]: force flag (set by the host at
+// binding).  Every kernel covers all runs of the table: workgroup row
+// blockIdx.y (or the workgroup, for the per-tile and per-run kernels) picks
+// the run, and a run whose flag is off returns at once.
+template <typename T>
+__global__ void k_sort_decide(const PartJob<T> *__restrict__ jobs, int njobs) {
+  for (int j = threadIdx.x; j < njobs; j += blockDim.x) {
+    int *state = global_ptr(jobs[j].sb.state);
+    const int threshold = int(jobs[j].p.n / 64);
+    const int need = (state[3] != 0 || state[0] > threshold) ? 1 : 0;
+    state[1] = need;
+    state[0] = 0;
+    state[3] = 0;
+    if (need) state[2] += 1;
+  }
 }
 
-__global__ void k_sort_clear(const int *state, int *cell_count, int64_t n) {
-  if (!state[1]) return;
+template <typename T>
+__global__ void k_sort_clear(const PartJob<T> *__restrict__ jobs) {
+  PartJob<T> job = jobs[blockIdx.y];
+  globalize(job.p);
+  globalize(job.sb);
+  if (!job.sb.state[1]) return;
+  const int64_t n = int64_t(job.tg.n_tiles) << job.tg.lcpt;
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
        i += int64_t(gridDim.x) * blockDim.x)
-    cell_count[i] = 0;
+    job.sb.cell_count[i] = 0;
 }
 
 // tile-major cell index: tile * cells_per_tile + (x, y, z) inside the tile
@@ -860,16 +945,18 @@ __device__ __forceinline__ int tile_major_cell(const int i[3], const TileGeom &t
 }
 
 template <class L>
-__global__ void k_sort_count(RunGeom g, TileGeom tg, PartPtrs p, const int *state,
-                             int *cell_count, int *key, int *rank) {
-  if (!state[1]) return;
-  for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < p.n;
+__global__ void k_sort_count(const PartJob<typename L::T> *__restrict__ jobs) {
+  PartJob<typename L::T> job = jobs[blockIdx.y];
+  globalize(job.p);
+  globalize(job.sb);
+  if (!job.sb.state[1]) return;
+  for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < job.p.n;
        k += int64_t(gridDim.x) * blockDim.x) {
-    const typename L::State st = load_state<L>(p, k, g);
-    const auto c = L::cell(st, g);
-    const int cell = tile_major_cell(c.i, tg);
-    key[k] = cell;
-    rank[k] = atomicAdd(cell_count + cell, 1);
+    const typename L::State st = load_state<L>(job.p, k, job.g);
+    const auto c = L::cell(st, job.g);
+    const int cell = tile_major_cell(c.i, job.tg);
+    job.sb.key[k] = cell;
+    job.sb.rank[k] = atomicAdd(job.sb.cell_count + cell, 1);
   }
 }
 
@@ -889,27 +976,36 @@ __device__ __forceinline__ int block_scan_incl(int v, int *buf) {
   return r;
 }
 
-// Per tile: offsets of its cells inside the tile (cell-grouped order) and
-// the tile total.  One workgroup of kNT >= cells per tile threads per tile.
-__global__ __launch_bounds__(kNT) void k_sort_tile_scan(TileGeom tg, const int *state,
-                                                        const int *cell_count, int *cell_off,
-                                                        int *tile_total) {
-  if (!state[1]) return;
+// Per tile (one workgroup of kNT >= cells per tile threads each, over the
+// tiles of all runs): offsets of its cells inside the tile and the tile
+// total.
+template <typename T>
+__global__ __launch_bounds__(kNT) void k_sort_tile_scan(const PartJob<T> *__restrict__ jobs,
+                                                        int njobs) {
   __shared__ int buf[kNT];
-  const int tile = blockIdx.x;
+  PartJob<T> job = jobs[job_of_block(jobs, njobs, blockIdx.x)];
+  globalize(job.sb);
+  if (!job.sb.state[1]) return;
+  const int tile = int(blockIdx.x) - job.block0;
   const int tid = threadIdx.x;
-  const int cpt = 1 << tg.lcpt;
-  const int v = tid < cpt ? cell_count[(tile << tg.lcpt) + tid] : 0;
+  const int cpt = 1 << job.tg.lcpt;
+  const int v = tid < cpt ? job.sb.cell_count[(tile << job.tg.lcpt) + tid] : 0;
   const int incl = block_scan_incl(v, buf);
-  if (tid < cpt) cell_off[(tile << tg.lcpt) + tid] = incl - v;
-  if (tid == kNT - 1) tile_total[tile] = incl;
+  if (tid < cpt) job.sb.cell_off[(tile << job.tg.lcpt) + tid] = incl - v;
+  if (tid == kNT - 1) job.sb.tile_total[tile] = incl;
 }
 
-// exclusive scan of tile_total[0..n) into start[0..n] (one workgroup)
-__global__ __launch_bounds__(1024) void k_sort_scan(const int *state, const int *total,
-                                                    int *start, int n) {
-  if (!state[1]) return;
+// Per run (one workgroup each): exclusive scan of the tile totals into
+// start[0 .. n_tiles].
+template <typename T>
+__global__ __launch_bounds__(1024) void k_sort_scan(const PartJob<T> *__restrict__ jobs) {
   __shared__ int part[1024];
+  PartJob<T> job = jobs[blockIdx.x];
+  globalize(job.sb);
+  if (!job.sb.state[1]) return;
+  const int n = job.tg.n_tiles;
+  const int *total = job.sb.tile_total;
+  int *start = job.sb.start;
   const int tid = threadIdx.x;
   const int chunk = (n + 1023) / 1024;
   const int lo = tid * chunk;
@@ -932,11 +1028,41 @@ struct Columns {
   int n;
 };
 
+// The particle arrays of a run and their scratch columns (same order as
+// the host allocates the scratch: positions, momenta, then ids).
+template <typename T>
+__device__ __forceinline__ Columns columns_of(const PartJob<T> &job) {
+  Columns c{};
+  int n = 0;
+  auto add = [&](void *a, int size) {
+    c.a[n] = a;
+    c.b[n] = job.sb.tmp[n];
+    c.size[n] = size;
+    ++n;
+  };
+  if constexpr (sizeof(T) == 8) {
+    add(job.p.x, 8);
+    add(job.p.y, 8);
+    add(job.p.z, 8);
+  } else {
+    add(job.p.x, 4);
+    add(job.p.ox, 4);
+    add(job.p.oy, 4);
+    add(job.p.oz, 4);
+  }
+  add(job.p.ux, int(sizeof(T)));
+  add(job.p.uy, int(sizeof(T)));
+  add(job.p.uz, int(sizeof(T)));
+  if (job.p.id) add(job.p.id, 8);
+  c.n = n;
+  return c;
+}
+
 __device__ __forceinline__ void copy_columns(const Columns &cols, bool to_scratch, int64_t src,
                                              int64_t dst) {
   for (int c = 0; c < cols.n; ++c) {
-    const void *from = to_scratch ? cols.a[c] : cols.b[c];
-    void *to = to_scratch ? cols.b[c] : cols.a[c];
+    const void *from = global_ptr(to_scratch ? cols.a[c] : cols.b[c]);
+    void *to = global_ptr(to_scratch ? cols.b[c] : cols.a[c]);
     if (cols.size[c] == 8)
       static_cast<int64_t *>(to)[dst] = static_cast<const int64_t *>(from)[src];
     else
@@ -945,22 +1071,31 @@ __device__ __forceinline__ void copy_columns(const Columns &cols, bool to_scratc
 }
 
 // particle k -> scratch position start[tile] + cell_off[cell] + rank
-__global__ void k_sort_scatter(TileGeom tg, const int *state, Columns cols, int64_t np,
-                               const int *key, const int *rank, const int *cell_off,
-                               const int *start) {
-  if (!state[1]) return;
-  for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < np;
+template <typename T>
+__global__ void k_sort_scatter(const PartJob<T> *__restrict__ jobs) {
+  PartJob<T> job = jobs[blockIdx.y];
+  globalize(job.p);
+  globalize(job.sb);
+  if (!job.sb.state[1]) return;
+  const Columns cols = columns_of(job);
+  for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < job.p.n;
        k += int64_t(gridDim.x) * blockDim.x) {
-    const int cell = key[k];
-    const int64_t pos = int64_t(start[cell >> tg.lcpt]) + cell_off[cell] + rank[k];
+    const int cell = job.sb.key[k];
+    const int64_t pos =
+        int64_t(job.sb.start[cell >> job.tg.lcpt]) + job.sb.cell_off[cell] + job.sb.rank[k];
     copy_columns(cols, true, k, pos);
   }
 }
 
 // scratch -> particle arrays (same, cell-grouped order)
-__global__ void k_sort_copyback(const int *state, Columns cols, int64_t np) {
-  if (!state[1]) return;
-  for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < np;
+template <typename T>
+__global__ void k_sort_copyback(const PartJob<T> *__restrict__ jobs) {
+  PartJob<T> job = jobs[blockIdx.y];
+  globalize(job.p);
+  globalize(job.sb);
+  if (!job.sb.state[1]) return;
+  const Columns cols = columns_of(job);
+  for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < job.p.n;
        k += int64_t(gridDim.x) * blockDim.x)
     copy_columns(cols, false, k, k);
 }
@@ -973,16 +1108,10 @@ unsigned stride_blocks(int64_t n) {
 }
 
 template <class L, int ORDER, int MODE, typename A>
-void launch_tile_kernel(const RunGeom &g, const TileGeom &tg, const PartPtrs &p,
-                        const GridPtrs<typename L::T> &gr, const SortBufs &sb, double hval,
+void launch_tile_kernel(const PartJob<typename L::T> *jobs, const PartBatch &b, double dt_factor,
                         hipStream_t s) {
   using T = typename L::T;
-  constexpr bool kGather = MODE == kModeFused || MODE == kModePush;
-  constexpr bool kDeposit = MODE != kModePush;
   constexpr int NT = quad_threads(sizeof(T));
-  const size_t lds = size_t(tg.region) * ((kGather ? 6 * sizeof(T) : 0) +
-                                          (kDeposit ? 4 * sizeof(A) : 0)) +
-                     list_bytes(tg.nb, tg.cap);
   static bool attr_set = false;  // allow dynamic LDS above 64 KiB (gfx950: 160 KiB)
   if (!attr_set) {
     (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_quad<L, ORDER, MODE, A, NT>),
@@ -990,18 +1119,17 @@ void launch_tile_kernel(const RunGeom &g, const TileGeom &tg, const PartPtrs &p,
                               int(kLdsBytes - scan_bytes(sizeof(T))));
     attr_set = true;
   }
-  hipLaunchKernelGGL((k_quad<L, ORDER, MODE, A, NT>), dim3(unsigned(tg.n_tiles)), dim3(NT), lds,
-                     s, g, tg, p, gr, sb.start, sb.state, T(hval));
+  hipLaunchKernelGGL((k_quad<L, ORDER, MODE, A, NT>), dim3(unsigned(b.nblocks)), dim3(NT),
+                     b.lds[MODE], s, jobs, b.njobs, dt_factor);
 }
 
 template <class L, int MODE, typename A>
-void launch_tile_order(const RunGeom &g, const TileGeom &tg, const PartPtrs &p,
-                       const GridPtrs<typename L::T> &gr, const SortBufs &sb, double hval,
-                       hipStream_t s) {
-  if (g.order == 1)
-    launch_tile_kernel<L, 1, MODE, A>(g, tg, p, gr, sb, hval, s);
+void launch_tile_order(int order, const PartJob<typename L::T> *jobs, const PartBatch &b,
+                       double dt_factor, hipStream_t s) {
+  if (order == 1)
+    launch_tile_kernel<L, 1, MODE, A>(jobs, b, dt_factor, s);
   else
-    launch_tile_kernel<L, 3, MODE, A>(g, tg, p, gr, sb, hval, s);
+    launch_tile_kernel<L, 3, MODE, A>(jobs, b, dt_factor, s);
 }
 
 template <typename T>
@@ -1061,80 +1189,58 @@ TileGeom make_tile_geom(const RunGeom &g, size_t real_size) {
 }
 
 template <typename T>
-void launch_sort(const RunGeom &g, const TileGeom &tg, const PartPtrs &p, const SortBufs &sb,
-                 hipStream_t s) {
+void launch_sort(const PartJob<T> *jobs, const PartBatch &b, hipStream_t s) {
   using L = typename LayoutOf<T>::type;
-  if (p.n == 0) return;
-  const int threshold = int(p.n / 64);
-  const int64_t ncell = int64_t(tg.n_tiles) << tg.lcpt;
-  hipLaunchKernelGGL(k_sort_decide, dim3(1), dim3(1), 0, s, sb.state, threshold);
-  hipLaunchKernelGGL(k_sort_clear, dim3(stride_blocks(ncell)), dim3(256), 0, s, sb.state,
-                     sb.cell_count, ncell);
-  hipLaunchKernelGGL((k_sort_count<L>), dim3(stride_blocks(p.n)), dim3(256), 0, s, g, tg, p,
-                     sb.state, sb.cell_count, sb.key, sb.rank);
-  hipLaunchKernelGGL(k_sort_tile_scan, dim3(unsigned(tg.n_tiles)), dim3(kNT), 0, s, tg,
-                     sb.state, sb.cell_count, sb.cell_off, sb.tile_total);
-  hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(1024), 0, s, sb.state, sb.tile_total, sb.start,
-                     tg.n_tiles);
-  Columns cols{};
-  void *arrays[8];
-  int sizes[8];
-  int nc = 0;
-  if (sizeof(T) == 8) {
-    arrays[nc] = p.x; sizes[nc++] = 8;
-    arrays[nc] = p.y; sizes[nc++] = 8;
-    arrays[nc] = p.z; sizes[nc++] = 8;
-  } else {
-    arrays[nc] = p.x; sizes[nc++] = 4;
-    arrays[nc] = p.ox; sizes[nc++] = 4;
-    arrays[nc] = p.oy; sizes[nc++] = 4;
-    arrays[nc] = p.oz; sizes[nc++] = 4;
-  }
-  arrays[nc] = p.ux; sizes[nc++] = int(sizeof(T));
-  arrays[nc] = p.uy; sizes[nc++] = int(sizeof(T));
-  arrays[nc] = p.uz; sizes[nc++] = int(sizeof(T));
-  if (p.id) {
-    arrays[nc] = p.id;
-    sizes[nc++] = 8;
-  }
-  cols.n = nc;
-  for (int c = 0; c < nc; ++c) {
-    cols.a[c] = arrays[c];
-    cols.b[c] = sb.tmp[c];
-    cols.size[c] = sizes[c];
-  }
-  hipLaunchKernelGGL(k_sort_scatter, dim3(stride_blocks(p.n)), dim3(256), 0, s, tg, sb.state,
-                     cols, p.n, sb.key, sb.rank, sb.cell_off, sb.start);
-  hipLaunchKernelGGL(k_sort_copyback, dim3(stride_blocks(p.n)), dim3(256), 0, s, sb.state, cols,
-                     p.n);
+  if (b.njobs <= 0) return;
+  const unsigned nj = unsigned(b.njobs);
+  const unsigned pblocks = stride_blocks(b.max_n);
+  hipLaunchKernelGGL((k_sort_decide<T>), dim3(1), dim3(256), 0, s, jobs, b.njobs);
+  hipLaunchKernelGGL((k_sort_clear<T>), dim3(stride_blocks(b.max_cells), nj), dim3(256), 0, s,
+                     jobs);
+  hipLaunchKernelGGL((k_sort_count<L>), dim3(pblocks, nj), dim3(256), 0, s, jobs);
+  hipLaunchKernelGGL((k_sort_tile_scan<T>), dim3(unsigned(b.nblocks)), dim3(kNT), 0, s, jobs,
+                     b.njobs);
+  hipLaunchKernelGGL((k_sort_scan<T>), dim3(nj), dim3(1024), 0, s, jobs);
+  hipLaunchKernelGGL((k_sort_scatter<T>), dim3(pblocks, nj), dim3(256), 0, s, jobs);
+  hipLaunchKernelGGL((k_sort_copyback<T>), dim3(pblocks, nj), dim3(256), 0, s, jobs);
 }
 
 template <typename T>
-void launch_particles(int mode, const RunGeom &g, const TileGeom &tg, const PartPtrs &p,
-                      const GridPtrs<T> &gr, const SortBufs &sb, double dt_push,
+void launch_particles(int mode, const PartJob<T> *jobs, const PartBatch &b, double dt_factor,
                       hipStream_t s) {
   using L = typename LayoutOf<T>::type;
   using A = typename LayoutOf<T>::acc;
-  if (p.n == 0) return;
-  const double h = p.q * dt_push / (2.0 * p.m);
+  if (b.njobs <= 0) return;
+  const int order = b.order;
   switch (mode) {
-    case kPartRho: launch_tile_order<L, kModeRho, A>(g, tg, p, gr, sb, h, s); break;
-    case kPartDeposit: launch_tile_order<L, kModeDeposit, A>(g, tg, p, gr, sb, h, s); break;
-    case kPartFused: launch_tile_order<L, kModeFused, A>(g, tg, p, gr, sb, h, s); break;
-    case kPartPush: launch_tile_order<L, kModePush, A>(g, tg, p, gr, sb, h, s); break;
+    case kPartRho: launch_tile_order<L, kModeRho, A>(order, jobs, b, dt_factor, s); break;
+    case kPartDeposit: launch_tile_order<L, kModeDeposit, A>(order, jobs, b, dt_factor, s); break;
+    case kPartFused: launch_tile_order<L, kModeFused, A>(order, jobs, b, dt_factor, s); break;
+    case kPartPush: launch_tile_order<L, kModePush, A>(order, jobs, b, dt_factor, s); break;
     default: break;
   }
 }
 
-template void launch_sort<float>(const RunGeom &, const TileGeom &, const PartPtrs &,
-                                 const SortBufs &, hipStream_t);
-template void launch_sort<double>(const RunGeom &, const TileGeom &, const PartPtrs &,
-                                  const SortBufs &, hipStream_t);
-template void launch_particles<float>(int, const RunGeom &, const TileGeom &, const PartPtrs &,
-                                      const GridPtrs<float> &, const SortBufs &, double,
+template <typename T>
+size_t particle_lds_bytes(int mode, const TileGeom &tg) {
+  using A = typename LayoutOf<T>::acc;
+  const bool gather = mode == kPartFused || mode == kPartPush;
+  const bool deposit = mode != kPartPush;
+  return size_t(tg.region) * ((gather ? 6 * sizeof(T) : 0) + (deposit ? 4 * sizeof(A) : 0)) +
+         list_bytes(tg.nb, tg.cap);
+}
+
+static_assert(int(kPartRho) == int(kModeRho) && int(kPartDeposit) == int(kModeDeposit) &&
+                  int(kPartFused) == int(kModeFused) && int(kPartPush) == int(kModePush),
+              "launcher modes name the kernel modes");
+
+template void launch_sort<float>(const PartJob<float> *, const PartBatch &, hipStream_t);
+template void launch_sort<double>(const PartJob<double> *, const PartBatch &, hipStream_t);
+template void launch_particles<float>(int, const PartJob<float> *, const PartBatch &, double,
                                       hipStream_t);
-template void launch_particles<double>(int, const RunGeom &, const TileGeom &,
-                                       const PartPtrs &, const GridPtrs<double> &,
-                                       const SortBufs &, double, hipStream_t);
+template void launch_particles<double>(int, const PartJob<double> *, const PartBatch &, double,
+                                       hipStream_t);
+template size_t particle_lds_bytes<float>(int, const TileGeom &);
+template size_t particle_lds_bytes<double>(int, const TileGeom &);
 
 }  // namespace galpic

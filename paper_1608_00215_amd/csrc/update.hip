@@ -32,9 +32,19 @@ __device__ __forceinline__ void ik_cross(T kx, T ky, T kz, const Cx<T> F[3], Cx<
   out[2] = mul_i(c2);
 }
 
+// Workgroup row blockIdx.y picks the run of the table (all of one grid shape).
 template <typename T>
-__global__ __launch_bounds__(256) void k_update(RunGeom g, UpdatePtrs<T> p, T kfx, T kfy,
-                                                T kfz) {
+__global__ __launch_bounds__(256) void k_update(RunGeom g, const UpdatePtrs<T> *__restrict__ sets,
+                                                T kfx, T kfy, T kfz) {
+  UpdatePtrs<T> p = sets[blockIdx.y];
+  for (int a = 0; a < 3; ++a) {
+    p.E[a] = global_ptr(p.E[a]);
+    p.B[a] = global_ptr(p.B[a]);
+    p.J[a] = global_ptr(p.J[a]);
+  }
+  p.rho_old = global_ptr(p.rho_old);
+  p.rho_new = global_ptr(p.rho_new);
+  for (int k = 0; k < 6; ++k) p.coef[k] = global_ptr(p.coef[k]);
   const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (idx >= g.nmode) return;
   const int iz = int(idx % g.nzh);
@@ -130,6 +140,15 @@ __global__ __launch_bounds__(256) void k_sum_squares(const T *__restrict__ a,
   if ((threadIdx.x & 63) == 0) atomicAdd(out, acc);
 }
 
+// Workgroup row blockIdx.y clears segment blockIdx.y (a multiple of 16 bytes).
+__global__ __launch_bounds__(256) void k_zero_segments(const ZeroSeg *__restrict__ segs) {
+  const ZeroSeg &sg = segs[blockIdx.y];
+  uint4 *p16 = static_cast<uint4 *>(global_ptr(sg.p));
+  const size_t stride = size_t(gridDim.x) * blockDim.x;
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < sg.n16; i += stride)
+    p16[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+
 __global__ __launch_bounds__(256) void k_zero(uint4 *p16, size_t n16, uint32_t *p4, size_t n4) {
   const size_t stride = size_t(gridDim.x) * blockDim.x;
   for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n16; i += stride)
@@ -145,10 +164,10 @@ T kfac(int n, double d) {
 }  // namespace
 
 template <typename T>
-void launch_update(const RunGeom &g, const UpdatePtrs<T> &p, hipStream_t s) {
+void launch_update(const RunGeom &g, const UpdatePtrs<T> *sets, int nsets, hipStream_t s) {
   const unsigned blocks = unsigned((g.nmode + 255) / 256);
-  hipLaunchKernelGGL((k_update<T>), dim3(blocks), dim3(256), 0, s, g, p, kfac<T>(g.nx, g.dx),
-                     kfac<T>(g.ny, g.dy), kfac<T>(g.nz, g.dz));
+  hipLaunchKernelGGL((k_update<T>), dim3(blocks, unsigned(nsets)), dim3(256), 0, s, g, sets,
+                     kfac<T>(g.nx, g.dx), kfac<T>(g.ny, g.dy), kfac<T>(g.nz, g.dz));
 }
 
 template <typename T>
@@ -170,6 +189,14 @@ void launch_sum_squares(const T *a, const T *b, const T *c, int64_t n, double *o
                      out);
 }
 
+void launch_zero_segments(const ZeroSeg *segs, int nseg, size_t max_n16, hipStream_t s) {
+  if (nseg <= 0 || max_n16 == 0) return;
+  size_t blocks = (max_n16 + 255) / 256;
+  if (blocks > 2048) blocks = 2048;
+  hipLaunchKernelGGL(k_zero_segments, dim3(unsigned(blocks), unsigned(nseg)), dim3(256), 0, s,
+                     segs);
+}
+
 void launch_zero(void *p, size_t nbytes, hipStream_t s) {
   if (nbytes == 0) return;
   // allocations are 256-byte aligned; the tail (if any) is cleared by words
@@ -183,8 +210,9 @@ void launch_zero(void *p, size_t nbytes, hipStream_t s) {
                      static_cast<uint4 *>(p), n16, tail, n4);
 }
 
-template void launch_update<float>(const RunGeom &, const UpdatePtrs<float> &, hipStream_t);
-template void launch_update<double>(const RunGeom &, const UpdatePtrs<double> &, hipStream_t);
+template void launch_update<float>(const RunGeom &, const UpdatePtrs<float> *, int, hipStream_t);
+template void launch_update<double>(const RunGeom &, const UpdatePtrs<double> *, int,
+                                    hipStream_t);
 template void launch_project<float>(const RunGeom &, Cx<float> *, Cx<float> *, Cx<float> *,
                                     bool, hipStream_t);
 template void launch_project<double>(const RunGeom &, Cx<double> *, Cx<double> *,
