@@ -369,6 +369,7 @@ void fill_jobs(gp_ctx *c) {
     if (r.parts.n > b.max_n) b.max_n = r.parts.n;
     const int64_t cells = int64_t(r.tg.n_tiles) << r.tg.lcpt;
     if (cells > b.max_cells) b.max_cells = cells;
+    if (r.tg.n_tiles > b.max_tiles) b.max_tiles = r.tg.n_tiles;
     for (int m = 0; m < 4; ++m) {
       const size_t l = particle_lds_bytes<T>(m, r.tg);
       if (l > b.lds[m]) b.lds[m] = l;

@@ -128,6 +128,7 @@ struct PartBatch {
   int nblocks;        // tiles of all runs
   int64_t max_n;      // most particles in one run
   int64_t max_cells;  // most cells in one run
+  int max_tiles;      // most tiles in one run
   size_t lds[4];      // dynamic LDS of the particle kernel per mode: the most of any run
 };
 

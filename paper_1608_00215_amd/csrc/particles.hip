@@ -976,23 +976,23 @@ __device__ __forceinline__ int block_scan_incl(int v, int *buf) {
   return r;
 }
 
-// Per tile (one workgroup of kNT >= cells per tile threads each, over the
-// tiles of all runs): offsets of its cells inside the tile and the tile
-// total.
+// Per tile (workgroups of kNT >= cells per tile threads; row blockIdx.y
+// is the run, each workgroup takes tiles blockIdx.x, + gridDim.x, ...):
+// offsets of its cells inside the tile and the tile total.
 template <typename T>
-__global__ __launch_bounds__(kNT) void k_sort_tile_scan(const PartJob<T> *__restrict__ jobs,
-                                                        int njobs) {
+__global__ __launch_bounds__(kNT) void k_sort_tile_scan(const PartJob<T> *__restrict__ jobs) {
   __shared__ int buf[kNT];
-  PartJob<T> job = jobs[job_of_block(jobs, njobs, blockIdx.x)];
+  PartJob<T> job = jobs[blockIdx.y];
   globalize(job.sb);
   if (!job.sb.state[1]) return;
-  const int tile = int(blockIdx.x) - job.block0;
   const int tid = threadIdx.x;
   const int cpt = 1 << job.tg.lcpt;
-  const int v = tid < cpt ? job.sb.cell_count[(tile << job.tg.lcpt) + tid] : 0;
-  const int incl = block_scan_incl(v, buf);
-  if (tid < cpt) job.sb.cell_off[(tile << job.tg.lcpt) + tid] = incl - v;
-  if (tid == kNT - 1) job.sb.tile_total[tile] = incl;
+  for (int tile = blockIdx.x; tile < job.tg.n_tiles; tile += gridDim.x) {
+    const int v = tid < cpt ? job.sb.cell_count[(tile << job.tg.lcpt) + tid] : 0;
+    const int incl = block_scan_incl(v, buf);
+    if (tid < cpt) job.sb.cell_off[(tile << job.tg.lcpt) + tid] = incl - v;
+    if (tid == kNT - 1) job.sb.tile_total[tile] = incl;
+  }
 }
 
 // Per run (one workgroup each): exclusive scan of the tile totals into
@@ -1193,13 +1193,16 @@ void launch_sort(const PartJob<T> *jobs, const PartBatch &b, hipStream_t s) {
   using L = typename LayoutOf<T>::type;
   if (b.njobs <= 0) return;
   const unsigned nj = unsigned(b.njobs);
-  const unsigned pblocks = stride_blocks(b.max_n);
+  // most steps sort nothing and every workgroup returns at once: keep the
+  // grids near 4096 workgroups in all, however many runs
+  const unsigned per_run = std::max(16u, 4096u / nj);
+  const unsigned pblocks = std::min(stride_blocks(b.max_n), per_run);
+  const unsigned cblocks = std::min(stride_blocks(b.max_cells), per_run);
+  const unsigned tblocks = unsigned(std::min<int64_t>(b.max_tiles, per_run));
   hipLaunchKernelGGL((k_sort_decide<T>), dim3(1), dim3(256), 0, s, jobs, b.njobs);
-  hipLaunchKernelGGL((k_sort_clear<T>), dim3(stride_blocks(b.max_cells), nj), dim3(256), 0, s,
-                     jobs);
+  hipLaunchKernelGGL((k_sort_clear<T>), dim3(cblocks, nj), dim3(256), 0, s, jobs);
   hipLaunchKernelGGL((k_sort_count<L>), dim3(pblocks, nj), dim3(256), 0, s, jobs);
-  hipLaunchKernelGGL((k_sort_tile_scan<T>), dim3(unsigned(b.nblocks)), dim3(kNT), 0, s, jobs,
-                     b.njobs);
+  hipLaunchKernelGGL((k_sort_tile_scan<T>), dim3(tblocks, nj), dim3(kNT), 0, s, jobs);
   hipLaunchKernelGGL((k_sort_scan<T>), dim3(nj), dim3(1024), 0, s, jobs);
   hipLaunchKernelGGL((k_sort_scatter<T>), dim3(pblocks, nj), dim3(256), 0, s, jobs);
   hipLaunchKernelGGL((k_sort_copyback<T>), dim3(pblocks, nj), dim3(256), 0, s, jobs);
