@@ -140,6 +140,16 @@ gp_status gp_init_grid(const gp_grid_desc *runs, int n_runs, void *hip_stream,
  * 2 pi (1 - 1e-6). */
 gp_status gp_set_v_gal(gp_ctx *ctx, int run, double vx, double vy, double vz);
 
+/* Option, off by default: before each update replace the longitudinal part
+ * of J^ of every run so that the Galilean continuity equation of the
+ * transformed equations, integrated over the step with J constant
+ * (rho^{n+1} = theta^2 rho^n + F k.J, F = (1 - theta^2) / (k.v_gal), -> -i dt
+ * as k.v_gal -> 0), holds exactly for the deposited rho^n, rho^{n+1}; the
+ * transverse part of J is kept.  Gauss's law then evolves exactly as the
+ * update prescribes for any deposition.  Not part of the printed update.
+ * enable: 0 or 1.  Takes effect at the next update.  Errors: GP_ERR_ARG. */
+gp_status gp_set_current_correction(gp_ctx *ctx, int enable);
+
 /* Register the particle arrays p[0..n_runs-1] with the context, sort them
  * into deposition tiles (reordering them in place), deposit rho at the
  * current positions and transform it into rho^n.  Must precede

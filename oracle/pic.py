@@ -72,10 +72,14 @@ class State:
 class Simulation:
     """Holds the grid, species, v_gal and the per-mode coefficients."""
 
-    def __init__(self, grid, species, v_gal, c=sp.C_LIGHT, eps0=sp.EPS0):
+    def __init__(self, grid, species, v_gal, c=sp.C_LIGHT, eps0=sp.EPS0,
+                 current_correction=False):
         self.grid = grid
         self.species = species
         self.v_gal = np.asarray(v_gal, dtype=np.float64)
+        # optional: J made to satisfy the Galilean continuity equation
+        # exactly before the update (spectral.galilean_current_correction)
+        self.current_correction = current_correction
         self.c = c
         self.eps0 = eps0
         self.k = sp.wavevectors(grid.shape, grid.spacing)
@@ -147,6 +151,9 @@ class Simulation:
         rho_new = self.deposit_charge(x_new)
         J_hat = tuple(self.to_spectral_source(J[a]) for a in range(3))
         rho_new_hat = self.to_spectral_source(rho_new)
+        if self.current_correction:
+            J_hat = sp.galilean_current_correction(J_hat, state.rho_hat, rho_new_hat, self.k,
+                                                   self.v_gal, g.dt, self.mask)
         E_hat, B_hat = sp.galilean_psatd_update(
             state.E_hat, state.B_hat, J_hat, state.rho_hat, rho_new_hat,
             self.k, self.coef, self.mask, self.c)

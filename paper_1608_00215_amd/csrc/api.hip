@@ -142,6 +142,7 @@ struct gp_ctx {
   bool stage_timing = false;
   std::vector<StageRec> stage_recs;
   Tables tab;
+  bool current_correction = false;
 };
 
 namespace {
@@ -346,6 +347,20 @@ gp_status build_tables(gp_ctx *c) {
     }
   }
   return GP_OK;
+}
+
+// Per-run scalars of the update tables (v_gal, dt, correction flag).
+template <typename T>
+void fill_update_scalars(gp_ctx *c) {
+  for (size_t i = 0; i < c->runs.size(); ++i) {
+    const Run &r = c->runs[i];
+    for (int par = 0; par < 2; ++par) {
+      UpdatePtrs<T> *u = host_at<UpdatePtrs<T>>(c, c->tab.upd[par], c->tab.pos[i]);
+      for (int a = 0; a < 3; ++a) u->vgal[a] = r.g.vgal[a];
+      u->dt = r.g.dt;
+      u->correct = c->current_correction ? 1 : 0;
+    }
+  }
 }
 
 // Per-run particle jobs (pointers, geometry with v_gal, sort buffers).
@@ -911,13 +926,29 @@ gp_status gp_set_v_gal(gp_ctx *c, int run, double vx, double vy, double vz) {
     launch_coefficients<float>(g, cp, c->stream);
   GP_TRY(check_launch("coefficients"));
   drop_graphs(c);
-  if (r.bound) {  // the particle jobs carry v_gal
-    if (c->precision == GP_FP64)
-      fill_jobs<double>(c);
-    else
-      fill_jobs<float>(c);
+  if (c->tab.dev) {  // the update tables and particle jobs carry v_gal
+    if (c->precision == GP_FP64) {
+      fill_update_scalars<double>(c);
+      if (r.bound) fill_jobs<double>(c);
+    } else {
+      fill_update_scalars<float>(c);
+      if (r.bound) fill_jobs<float>(c);
+    }
     GP_TRY(upload_tables(c));
   }
+  return GP_OK;
+}
+
+gp_status gp_set_current_correction(gp_ctx *c, int enable) {
+  GP_TRY(check_ctx(c));
+  if (enable != 0 && enable != 1) return fail(GP_ERR_ARG, "enable must be 0 or 1");
+  c->current_correction = enable != 0;
+  drop_graphs(c);
+  if (c->precision == GP_FP64)
+    fill_update_scalars<double>(c);
+  else
+    fill_update_scalars<float>(c);
+  GP_TRY(upload_tables(c));
   return GP_OK;
 }
 

@@ -50,6 +50,10 @@ struct UpdatePtrs {
   const Cx<T> *rho_old;
   const Cx<T> *rho_new;
   const Cx<T> *coef[6];
+  double vgal[3];  // the run's v_gal and dt, for the current correction
+  double dt;
+  int correct;     // nonzero: correct J before the update (see update.hip)
+  int pad;
 };
 // The update of the nsets runs (all of grid shape g) of the device table.
 template <typename T>

@@ -73,6 +73,26 @@ __global__ __launch_bounds__(256) void k_update(RunGeom g, const UpdatePtrs<T> *
   }
   const Cx<T> r0 = p.rho_old[idx];
   const Cx<T> r1 = p.rho_new[idx];
+  if (p.correct) {
+    // Optional Galilean current correction: keep the transverse part of J
+    // and set k.J so that the k-space continuity equation, integrated over
+    // the step with J constant, holds exactly:
+    //   rho^{n+1} = theta^2 rho^n + F k.J,  F = -i dt theta sinc(k.v_gal dt/2)
+    const T kdv = kx * T(p.vgal[0]) + ky * T(p.vgal[1]) + kz * T(p.vgal[2]);
+    const T half = T(0.5) * kdv * T(p.dt);
+    const T sn = sin(half);
+    const T cs = cos(half);
+    const T sinc = half != T(0) ? sn / half : T(1);
+    const Cx<T> th = cx(cs, sn);
+    const Cx<T> num = r1 - (th * th) * r0;
+    // target k.J = num / F = i num conj(theta) / (dt sinc)
+    const Cx<T> target = (T(1) / (T(p.dt) * sinc)) * mul_i(num * conj(th));
+    const Cx<T> kJ = kx * J[0] + ky * J[1] + kz * J[2];
+    const Cx<T> alpha = (T(1) / (kx * kx + ky * ky + kz * kz)) * (target - kJ);
+    J[0] = J[0] + kx * alpha;
+    J[1] = J[1] + ky * alpha;
+    J[2] = J[2] + kz * alpha;
+  }
   const Cx<T> c0 = p.coef[0][idx];
   const Cx<T> c1 = p.coef[1][idx];
   const Cx<T> c2 = p.coef[2][idx];

@@ -25,7 +25,7 @@ FIELDS = ["EX", "EY", "EZ", "BX", "BY", "BZ", "JX", "JY", "JZ", "RHO",
 FIELD = {name: i for i, name in enumerate(FIELDS)}
 
 #: every symbol the header declares
-EXPORTS = ["gp_init_grid", "gp_set_v_gal", "gp_bind_particles", "gp_deposit", "gp_fft_fwd",
+EXPORTS = ["gp_init_grid", "gp_set_v_gal", "gp_set_current_correction", "gp_bind_particles", "gp_deposit", "gp_fft_fwd",
            "gp_galilean_psatd_update", "gp_fft_inv", "gp_gather_push", "gp_step",
            "gp_step_graph", "gp_set_fields", "gp_half_push", "gp_read_field",
            "gp_write_field", "gp_field_energy", "gp_last_graph_ms", "gp_synchronize",
@@ -73,6 +73,7 @@ def load(path=LIB_PATH):
     sig = {
         "gp_init_grid": [ctypes.POINTER(GridDesc), i32, vp, ctypes.POINTER(vp)],
         "gp_set_v_gal": [vp, i32, dbl, dbl, dbl],
+        "gp_set_current_correction": [vp, i32],
         "gp_bind_particles": [vp, vp],
         "gp_deposit": [vp, vp],
         "gp_fft_fwd": [vp],
@@ -232,6 +233,9 @@ class Context:
     # -- the C ABI, one method per call ---------------------------------------
     def set_v_gal(self, run, v):
         self._call("gp_set_v_gal", int(run), float(v[0]), float(v[1]), float(v[2]))
+
+    def set_current_correction(self, enable):
+        self._call("gp_set_current_correction", 1 if enable else 0)
 
     def bind_particles(self, parts):
         import torch
