@@ -75,7 +75,7 @@ def stage_flops(cfg):
     }
 
 
-def run_gpu(cfg, precision, steps, warmup, inputs):
+def run_gpu(cfg, precision, steps, warmup, inputs, tile=(0, 0, 0), resort_div=0):
     """Time one run (cfg, inputs) or a batch of runs (lists of both)."""
     import torch
 
@@ -84,7 +84,10 @@ def run_gpu(cfg, precision, steps, warmup, inputs):
 
     cfgs = cfg if isinstance(cfg, list) else [cfg]
     inps = inputs if isinstance(inputs, list) else [inputs]
-    ctx = gp.Context([gp.grid_from_config(c, precision) for c in cfgs])
+    grids = [gp.grid_from_config(c, precision,
+                                 tile=tuple(min(tile[a], c.shape[a]) for a in range(3)),
+                                 resort_div=resort_div) for c in cfgs]
+    ctx = gp.Context(grids)
     for r, c in enumerate(cfgs):
         ctx.set_v_gal(r, c.v_gal())
     parts = [gp.particles_from_inputs(i, c, precision, with_ids=False)
@@ -271,6 +274,9 @@ def main():
     ap.add_argument("--accuracy", action="store_true",
                     help="instead of timing, run the mixed and FP64 GPU paths side by side "
                          "and report per-field errors and energy histories")
+    ap.add_argument("--autotune", action="store_true",
+                    help="first time candidate tile shapes and re-sort thresholds on the "
+                         "workload (outside the timed steps) and use the fastest")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device three times (a plain copy "
                          "kernel of known size for scaling HBM byte counters)")
@@ -317,7 +323,23 @@ def main():
             sys.exit("bench.py: --accuracy takes a single-run workload")
         print(json.dumps(accuracy_run(cfg, args.steps, inputs)), flush=True)
         return
-    mixed = run_gpu(run_arg, gp.GP_MIXED, args.steps, args.warmup, inputs)
+    tuning = None
+    setting = {"tile": (0, 0, 0), "resort_div": 0}
+    if args.autotune:
+        from paper_1608_00215_amd import autotune
+
+        t0 = time.perf_counter()
+        tcfgs = run_arg if isinstance(run_arg, list) else [run_arg]
+        tinps = inputs if isinstance(inputs, list) else [inputs]
+        best, res = autotune.tune(tcfgs, tinps, gp.GP_MIXED,
+                                  log=lambda m: print(f"[autotune] {m}", file=sys.stderr,
+                                                      flush=True))
+        setting = {"tile": best[0], "resort_div": best[1]}
+        tuning = {"tile": list(best[0]), "resort_div": best[1],
+                  "tuning_s": round(time.perf_counter() - t0, 1),
+                  "candidates_ms_per_step": {f"{k[0][0]}x{k[0][1]}x{k[0][2]}/n{k[1]}": round(v, 4)
+                                             for k, v in res.items()}}
+    mixed = run_gpu(run_arg, gp.GP_MIXED, args.steps, args.warmup, inputs, **setting)
     print(f"[bench] mixed: {mixed['wall_s'] / args.steps * 1e3:.3f} ms/step", file=sys.stderr,
           flush=True)
     fp64 = None
@@ -374,6 +396,7 @@ def main():
         "tile_sorts": mixed["sorts"],
         "stages": stages,
         "roofline": roof,
+        "tuning": tuning,
     }
     if fp64 is not None:
         line["fp64_gpu"] = {

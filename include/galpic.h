@@ -94,12 +94,21 @@ enum {
 
 /* One run's grid.  nx, ny, nz: powers of two in [8, 1024]; dx, dy, dz > 0;
  * dt > 0; shape_order 1 or 3; precision GP_FP64 or GP_MIXED (all runs of a
- * context use the same precision and shape order). */
+ * context use the same precision and shape order).
+ * Tuning knobs (0 = default; results do not depend on them beyond float
+ * summation order):
+ *   tile[3]     cells per deposition tile and axis: powers of two, at most 8
+ *               and at most the grid (default 8, or the grid if smaller);
+ *   resort_div  re-sort the particles by tile when more than n / resort_div
+ *               of them used the global path since the last decision
+ *               (default 64; at least 1). */
 typedef struct {
   int nx, ny, nz;
   double dx, dy, dz, dt;
   int shape_order;
   int precision;
+  int tile[3];
+  int resort_div;
 } gp_grid_desc;
 
 /* One run's macro-particles (one species, uniform weights).

@@ -72,6 +72,7 @@ struct Run {
   void *coef[6] = {};
   void *scratch[6] = {};
   int rho_old = 9;              // spec slot holding rho^n; the other holds rho^{n+1}
+  int resort_div = 64;          // re-sort when > n / resort_div particles went global
   PartPtrs parts{};
   bool bound = false;
   SortBufs sb{};
@@ -191,6 +192,11 @@ gp_status validate_desc(const gp_grid_desc &d, int i) {
     return fail(GP_ERR_ARG, w + "precision must be GP_FP64 or GP_MIXED");
   if (int64_t(d.nx) * d.ny * d.nz > (int64_t(1) << 30))
     return fail(GP_ERR_ARG, w + "grid too large (at most 2^30 cells)");
+  const int n[3] = {d.nx, d.ny, d.nz};
+  for (int a = 0; a < 3; ++a)
+    if (d.tile[a] != 0 && (!is_pow2(d.tile[a]) || d.tile[a] > 8 || d.tile[a] > n[a]))
+      return fail(GP_ERR_ARG, w + "tile sizes must be 0 or powers of two <= min(8, grid)");
+  if (d.resort_div < 0) return fail(GP_ERR_ARG, w + "resort_div must be >= 0");
   return GP_OK;
 }
 
@@ -380,6 +386,7 @@ void fill_jobs(gp_ctx *c) {
     j->gr = grid_ptrs<T>(r);
     j->sb = r.sb;
     j->block0 = b.nblocks;
+    j->resort_threshold = int(r.parts.n / r.resort_div);
     b.nblocks += r.tg.n_tiles;
     if (r.parts.n > b.max_n) b.max_n = r.parts.n;
     const int64_t cells = int64_t(r.tg.n_tiles) << r.tg.lcpt;
@@ -844,7 +851,8 @@ gp_status gp_init_grid(const gp_grid_desc *runs, int n_runs, void *hip_stream, g
     g.vgal[0] = g.vgal[1] = g.vgal[2] = 0.0;
     g.ncell = int64_t(d.nx) * d.ny * d.nz;
     g.nmode = int64_t(d.nx) * d.ny * g.nzh;
-    r.tg = make_tile_geom(g, c->real_size);
+    r.tg = make_tile_geom(g, c->real_size, d.tile);
+    r.resort_div = d.resort_div > 0 ? d.resort_div : 64;
     // one allocation per grid: grids at power-of-two distances in one block
     // would send the gather's six same-node loads to the same HBM channel
     for (auto &p : r.real) {

@@ -100,7 +100,8 @@ struct TileGeom {
   int nb;        // buckets (cells of the bucket block); bucket nb: beyond it
   int cap;       // particles the per-tile bucket list holds
 };
-TileGeom make_tile_geom(const RunGeom &g, size_t real_size);
+// tile[a]: requested cells per tile (0: 8, or the grid if smaller)
+TileGeom make_tile_geom(const RunGeom &g, size_t real_size, const int tile[3]);
 
 // Device buffers of the tile sort of one run.
 struct SortBufs {
@@ -122,7 +123,8 @@ struct PartJob {
   PartPtrs p;
   GridPtrs<T> gr;
   SortBufs sb;
-  int block0;  // first workgroup of the run in a launch with one workgroup per tile
+  int block0;            // first workgroup of the run in a launch with one workgroup per tile
+  int resort_threshold;  // re-sort when more particles than this used the global path
 };
 
 // What the launchers need to know about a table of PartJobs.

@@ -914,7 +914,7 @@ template <typename T>
 __global__ void k_sort_decide(const PartJob<T> *__restrict__ jobs, int njobs) {
   for (int j = threadIdx.x; j < njobs; j += blockDim.x) {
     int *state = global_ptr(jobs[j].sb.state);
-    const int threshold = int(jobs[j].p.n / 64);
+    const int threshold = jobs[j].resort_threshold;
     const int need = (state[3] != 0 || state[0] > threshold) ? 1 : 0;
     state[1] = need;
     state[0] = 0;
@@ -1147,13 +1147,13 @@ struct LayoutOf<float> {
 
 }  // namespace
 
-TileGeom make_tile_geom(const RunGeom &g, size_t real_size) {
+TileGeom make_tile_geom(const RunGeom &g, size_t real_size, const int tile[3]) {
   TileGeom tg{};
   const int n[3] = {g.nx, g.ny, g.nz};
   const int halo = g.order == 3 ? 3 : 1;  // shape width - 1
   int lcpt = 0;
   for (int a = 0; a < 3; ++a) {
-    int t = 8;
+    int t = tile && tile[a] > 0 ? tile[a] : 8;
     while (t > n[a]) t >>= 1;
     tg.t[a] = t;
     int l = 0;

@@ -38,7 +38,8 @@ class GridDesc(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
                 ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", ctypes.c_double),
                 ("dt", ctypes.c_double), ("shape_order", ctypes.c_int),
-                ("precision", ctypes.c_int)]
+                ("precision", ctypes.c_int), ("tile", ctypes.c_int * 3),
+                ("resort_div", ctypes.c_int)]
 
 
 class ParticlesC(ctypes.Structure):
@@ -203,8 +204,10 @@ class Context:
         n = len(grids)
         arr = (GridDesc * n)()
         for i, g in enumerate(grids):
+            tile = (ctypes.c_int * 3)(*g.get("tile", (0, 0, 0)))
             arr[i] = GridDesc(g["nx"], g["ny"], g["nz"], g.get("dx", 1.0), g.get("dy", 1.0),
-                              g.get("dz", 1.0), g["dt"], g["order"], g["precision"])
+                              g.get("dz", 1.0), g["dt"], g["order"], g["precision"], tile,
+                              g.get("resort_div", 0))
         self.grids = grids
         self.precision = grids[0]["precision"]
         self.real = np.float64 if self.precision == GP_FP64 else np.float32
@@ -341,13 +344,15 @@ class Context:
         return we.value, wb.value
 
 
-def grid_from_config(cfg, precision=None):
-    """Grid descriptor dict of a workload.RunConfig."""
+def grid_from_config(cfg, precision=None, tile=(0, 0, 0), resort_div=0):
+    """Grid descriptor dict of a workload.RunConfig (tile, resort_div: the
+    tuning knobs of gp_grid_desc, 0 = default)."""
     prec = precision if precision is not None else (
         GP_FP64 if cfg.precision == "fp64" else GP_MIXED)
     return {"nx": cfg.shape[0], "ny": cfg.shape[1], "nz": cfg.shape[2],
             "dx": cfg.spacing[0], "dy": cfg.spacing[1], "dz": cfg.spacing[2],
-            "dt": cfg.dt, "order": cfg.order, "precision": prec}
+            "dt": cfg.dt, "order": cfg.order, "precision": prec,
+            "tile": tuple(tile), "resort_div": int(resort_div)}
 
 
 def particles_from_inputs(inputs, cfg, precision, with_ids=True, device="cuda"):
