@@ -73,7 +73,7 @@ class Simulation:
     """Holds the grid, species, v_gal and the per-mode coefficients."""
 
     def __init__(self, grid, species, v_gal, c=sp.C_LIGHT, eps0=sp.EPS0,
-                 current_correction=False):
+                 current_correction=False, stencil=(0, 0, 0)):
         self.grid = grid
         self.species = species
         self.v_gal = np.asarray(v_gal, dtype=np.float64)
@@ -82,7 +82,10 @@ class Simulation:
         self.current_correction = current_correction
         self.c = c
         self.eps0 = eps0
-        self.k = sp.wavevectors(grid.shape, grid.spacing)
+        # per-axis stencil order of the field update (0: exact spectral k);
+        # the wavevector then is the stencil's symbol [k]
+        self.stencil = tuple(int(p) for p in stencil)
+        self.k = sp.wavevectors(grid.shape, grid.spacing, self.stencil)
         self.mask = sp.held_zero_mask(grid.shape)
         self.coef = galilean_psatd_coefficients(self.k, self.v_gal, grid.dt, c, eps0)
 

@@ -9,8 +9,13 @@ Conventions (readings of points the paper leaves silent):
   derivative with respect to the Galilean coordinates becomes +i k, which is
   the convention under which the printed theta = exp(i k.v_gal dt / 2) is
   consistent with the transformed Maxwell equations.
-* k is the exact spectral wavevector 2 pi m / L per axis (pseudo-spectral,
-  no finite-difference modification).
+* k is the exact spectral wavevector 2 pi m / L per axis (pseudo-spectral)
+  unless a finite stencil order is asked for: then every spatial derivative
+  of the update, the curls, the divergences in the charge terms and the
+  Galilean advection v_gal.grad in theta alike, uses the symbol [k] of the
+  centered difference of that order on the colocated grid (the paper names
+  arbitrary-order spectral solvers only as future work; this reading
+  replaces k by [k] everywhere in the field update and nowhere else).
 * Grid quantities are colocated on the nodes x_i = i * d (no staggering).
 * The k = 0 mode and every Nyquist plane (index N_a / 2 on any axis) of the
   sources and of the fields are held at zero.  On Nyquist planes the update
@@ -18,6 +23,9 @@ Conventions (readings of points the paper leaves silent):
   mode carries the mean current of the electrons, which the co-moving
   neutralising ion background cancels.
 """
+
+from fractions import Fraction
+from math import factorial
 
 import numpy as np
 
@@ -30,12 +38,38 @@ def axis_wavenumbers(n, d):
     return 2.0 * np.pi * np.fft.fftfreq(n, d)
 
 
-def wavevectors(shape, spacing):
-    """Full (C2C) wavevector grid, each component shaped like the grid."""
-    kx = axis_wavenumbers(shape[0], spacing[0])
-    ky = axis_wavenumbers(shape[1], spacing[1])
-    kz = axis_wavenumbers(shape[2], spacing[2])
-    return np.meshgrid(kx, ky, kz, indexing="ij")
+def centered_difference_weights(half_width):
+    """Weights a_1 .. a_M (M = half_width) of the centered first-derivative
+    stencil of order 2M on a colocated grid,
+
+        (D f)_i = (1 / d) sum_{l=1}^{M} a_l (f_{i+l} - f_{i-l}),
+
+    the unique one exact for polynomials of degree 2M:
+    a_l = (-1)^(l+1) (M!)^2 / (l (M - l)! (M + l)!), computed exactly."""
+    M = int(half_width)
+    return [float(Fraction((-1) ** (l + 1) * factorial(M) ** 2,
+                           l * factorial(M - l) * factorial(M + l)))
+            for l in range(1, M + 1)]
+
+
+def modified_wavenumbers(n, d, order):
+    """Symbol [k] of one axis in FFT index order: D exp(i k x) = i [k]
+    exp(i k x) for the centered stencil of even ``order`` 2M,
+    [k] = (2 / d) sum_l a_l sin(l k d).  ``order`` 0 is the exact k."""
+    k = axis_wavenumbers(n, d)
+    if order == 0:
+        return k
+    if order < 2 or order % 2:
+        raise ValueError("stencil order must be 0 or even and >= 2")
+    a = centered_difference_weights(order // 2)
+    return (2.0 / d) * sum(al * np.sin(l * k * d) for l, al in enumerate(a, start=1))
+
+
+def wavevectors(shape, spacing, stencil=(0, 0, 0)):
+    """Full (C2C) wavevector grid, each component shaped like the grid;
+    ``stencil`` gives each axis's stencil order (0: exact k)."""
+    ks = [modified_wavenumbers(n, d, p) for n, d, p in zip(shape, spacing, stencil)]
+    return np.meshgrid(*ks, indexing="ij")
 
 
 def held_zero_mask(shape):

@@ -45,6 +45,7 @@ class RunConfig:
     galilean: bool = True   # v_gal = drift velocity if True else 0
     laser: dict = field(default=None)
     seed: int = 1000
+    stencil: tuple = (0, 0, 0)  # field-solve stencil order per axis (0: spectral)
 
     @property
     def n_cells(self):
