@@ -95,6 +95,15 @@ enum {
 /* One run's grid.  nx, ny, nz: powers of two in [8, 1024]; dx, dy, dz > 0;
  * dt > 0; shape_order 1 or 3; precision GP_FP64 or GP_MIXED (all runs of a
  * context use the same precision and shape order).
+ * stencil[3]: spatial derivative of the field solve per axis.  0 (the
+ * paper's solver): the exact spectral wavenumber k.  An even order p in
+ * [2, 64]: the centered difference of order p on the colocated grid, whose
+ * symbol [k] = (2/d) sum_{l=1}^{p/2} a_l sin(l k d) replaces k in every
+ * part of the field update (curls, charge terms, the Galilean phase
+ * theta, the current correction and the transverse projection); a
+ * finite-order solve has a local real-space stencil, the prerequisite of
+ * domain decomposition with local transforms and guard cells, which the
+ * paper names as future work.  Deposition and gather do not change.
  * Tuning knobs (0 = default; results do not depend on them beyond float
  * summation order):
  *   tile[3]     cells per deposition tile and axis: powers of two, at most 8
@@ -109,6 +118,7 @@ typedef struct {
   int precision;
   int tile[3];
   int resort_div;
+  int stencil[3];
 } gp_grid_desc;
 
 /* One run's macro-particles (one species, uniform weights).

@@ -6,6 +6,7 @@
 // kernels.
 #include "galpic.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -71,6 +72,9 @@ struct Run {
   void *spec[kSpec] = {};
   void *coef[6] = {};
   void *scratch[6] = {};
+  int stencil[3] = {};          // field-solve stencil order per axis (0: spectral)
+  double *kd = nullptr;         // wavenumbers x | y | z (nx + ny + nz/2+1), double
+  void *kt = nullptr;           // the same in the run's real type (kd for FP64)
   int rho_old = 9;              // spec slot holding rho^n; the other holds rho^{n+1}
   int resort_div = 64;          // re-sort when > n / resort_div particles went global
   PartPtrs parts{};
@@ -197,6 +201,62 @@ gp_status validate_desc(const gp_grid_desc &d, int i) {
     if (d.tile[a] != 0 && (!is_pow2(d.tile[a]) || d.tile[a] > 8 || d.tile[a] > n[a]))
       return fail(GP_ERR_ARG, w + "tile sizes must be 0 or powers of two <= min(8, grid)");
   if (d.resort_div < 0) return fail(GP_ERR_ARG, w + "resort_div must be >= 0");
+  for (int a = 0; a < 3; ++a)
+    if (d.stencil[a] != 0 && (d.stencil[a] < 2 || d.stencil[a] > 64 || d.stencil[a] % 2))
+      return fail(GP_ERR_ARG, w + "stencil orders must be 0 or even in [2, 64]");
+  return GP_OK;
+}
+
+// Wavenumbers of one axis in transform index order (index n/2 stands for
+// -n/2; its modes are held at zero): the exact k = 2 pi s / (n d), or for
+// an even stencil order p = 2M the symbol of the centered difference
+// (D f)_i = (1/d) sum_{l=1}^{M} a_l (f_{i+l} - f_{i-l}) acting on exp(ikx),
+// [k] = (2/d) sum_l a_l sin(l k d), with the weights that make it exact for
+// polynomials of degree 2M: a_l = (-1)^(l+1) r_l / l,
+// r_l = (M!)^2 / ((M-l)! (M+l)!) = prod_{j<l} (M - j) / (M + 1 + j).
+void axis_wavenumbers(int n, double d, int order, int count, double *out) {
+  const int M = order / 2;
+  std::vector<double> a(M + 1, 0.0);
+  double r = 1.0;
+  for (int l = 1; l <= M; ++l) {
+    r *= double(M - (l - 1)) / double(M + l);
+    a[l] = (l % 2 ? 1.0 : -1.0) * r / double(l);
+  }
+  for (int i = 0; i < count; ++i) {
+    const int s = i < n / 2 ? i : i - n;
+    const double k = 2.0 * kPi * double(s) / (double(n) * d);
+    if (order == 0) {
+      out[i] = k;
+      continue;
+    }
+    double sum = 0.0;
+    for (int l = M; l >= 1; --l) sum += a[l] * std::sin(double(l) * k * d);
+    out[i] = 2.0 * sum / d;
+  }
+}
+
+// The run's wavenumber tables on the device (double, and float for the
+// mixed update).  Synchronising.
+gp_status upload_wavenumbers(gp_ctx *c, Run &r) {
+  const RunGeom &g = r.g;
+  const int cnt = g.nx + g.ny + g.nzh;
+  std::vector<double> kd(cnt);
+  axis_wavenumbers(g.nx, g.dx, r.stencil[0], g.nx, kd.data());
+  axis_wavenumbers(g.ny, g.dy, r.stencil[1], g.ny, kd.data() + g.nx);
+  axis_wavenumbers(g.nz, g.dz, r.stencil[2], g.nzh, kd.data() + g.nx + g.ny);
+  const size_t dbytes = size_t(cnt) * sizeof(double);
+  const bool mixed = c->precision != GP_FP64;
+  std::vector<float> kf(mixed ? cnt : 0);
+  for (int i = 0; i < int(kf.size()); ++i) kf[i] = float(kd[i]);
+  void *p = nullptr;
+  GP_TRY(dev_alloc(c->allocs, dbytes + kf.size() * sizeof(float), &p));
+  r.kd = static_cast<double *>(p);
+  r.kt = mixed ? static_cast<void *>(static_cast<char *>(p) + dbytes) : p;
+  if (hipMemcpyAsync(r.kd, kd.data(), dbytes, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+      (mixed && hipMemcpyAsync(r.kt, kf.data(), kf.size() * sizeof(float),
+                               hipMemcpyHostToDevice, c->stream) != hipSuccess) ||
+      hipStreamSynchronize(c->stream) != hipSuccess)
+    return fail(GP_ERR_HIP, "wavenumber upload failed");
   return GP_OK;
 }
 
@@ -339,6 +399,10 @@ gp_status build_tables(gp_ctx *c) {
       u->rho_old = S<T>(r, 9 + par);
       u->rho_new = S<T>(r, 10 - par);
       for (int k = 0; k < 6; ++k) u->coef[k] = static_cast<const Cx<T> *>(r.coef[k]);
+      const T *kt = static_cast<const T *>(r.kt);
+      u->k[0] = kt;
+      u->k[1] = kt + r.g.nx;
+      u->k[2] = kt + r.g.nx + r.g.ny;
     }
     set(kTabInvX, 6, [&](int f) { return r.spec[f]; }, [&](int f) { return r.scratch[f]; });
     set(kTabInvY, 6, [&](int f) { return r.scratch[f]; }, [&](int f) { return r.scratch[f]; });
@@ -853,6 +917,11 @@ gp_status gp_init_grid(const gp_grid_desc *runs, int n_runs, void *hip_stream, g
     g.nmode = int64_t(d.nx) * d.ny * g.nzh;
     r.tg = make_tile_geom(g, c->real_size, d.tile);
     r.resort_div = d.resort_div > 0 ? d.resort_div : 64;
+    for (int a = 0; a < 3; ++a) r.stencil[a] = d.stencil[a];
+    {
+      gp_status st = upload_wavenumbers(c, r);
+      if (st) return bail(st);
+    }
     // one allocation per grid: grids at power-of-two distances in one block
     // would send the gather's six same-node loads to the same HBM channel
     for (auto &p : r.real) {
@@ -913,13 +982,21 @@ gp_status gp_set_v_gal(gp_ctx *c, int run, double vx, double vy, double vz) {
     return fail(GP_ERR_ARG, "|v_gal| must be finite and below c");
   Run &r = c->runs[run];
   RunGeom &g = r.g;
-  // largest |k.v_gal| dt over the non-Nyquist modes
+  // bound on |k.v_gal| dt over the non-Nyquist modes: sum over the axes of
+  // |v_a| max |k_a| (k exact or the stencil's symbol)
   const int n[3] = {g.nx, g.ny, g.nz};
   const double d[3] = {g.dx, g.dy, g.dz};
   const double v[3] = {vx, vy, vz};
   double phase = 0.0;
-  for (int a = 0; a < 3; ++a)
-    phase += std::fabs(v[a]) * 2.0 * kPi * double(n[a] / 2 - 1) / (double(n[a]) * d[a]);
+  for (int a = 0; a < 3; ++a) {
+    const int cnt = a < 2 ? n[a] : g.nzh;
+    std::vector<double> k(cnt);
+    axis_wavenumbers(n[a], d[a], r.stencil[a], cnt, k.data());
+    double kmax = 0.0;
+    for (int i = 0; i < cnt; ++i)
+      if (i != n[a] / 2) kmax = std::max(kmax, std::fabs(k[i]));
+    phase += std::fabs(v[a]) * kmax;
+  }
   phase *= g.dt;
   if (phase >= 2.0 * kPi * (1.0 - 1e-6))
     return fail(GP_ERR_UNSTABLE, "some mode has |k.v_gal| dt >= 2 pi; the update is singular");
@@ -929,9 +1006,9 @@ gp_status gp_set_v_gal(gp_ctx *c, int run, double vx, double vy, double vz) {
   CoefPtrs cp;
   for (int i = 0; i < 6; ++i) cp.c[i] = r.coef[i];
   if (c->precision == GP_FP64)
-    launch_coefficients<double>(g, cp, c->stream);
+    launch_coefficients<double>(g, r.kd, cp, c->stream);
   else
-    launch_coefficients<float>(g, cp, c->stream);
+    launch_coefficients<float>(g, r.kd, cp, c->stream);
   GP_TRY(check_launch("coefficients"));
   drop_graphs(c);
   if (c->tab.dev) {  // the update tables and particle jobs carry v_gal
@@ -1149,9 +1226,10 @@ gp_status gp_set_fields(gp_ctx *c, int run, const void *const E[3], const void *
     using T = decltype(t);
     const int pos = c->tab.pos[run];
     fft_forward<T>(c, kTabEBZ, kTabEBYX, 6, pos, 1, r.g);
-    launch_project<T>(r.g, S<T>(r, 0), S<T>(r, 1), S<T>(r, 2), project_transverse != 0,
+    const T *kt = static_cast<const T *>(r.kt);
+    launch_project<T>(r.g, kt, S<T>(r, 0), S<T>(r, 1), S<T>(r, 2), project_transverse != 0,
                       c->stream);
-    launch_project<T>(r.g, S<T>(r, 3), S<T>(r, 4), S<T>(r, 5), project_transverse != 0,
+    launch_project<T>(r.g, kt, S<T>(r, 3), S<T>(r, 4), S<T>(r, 5), project_transverse != 0,
                       c->stream);
     fft_inverse<T>(c, pos, 1, r.g);
   }));

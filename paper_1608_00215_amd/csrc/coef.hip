@@ -87,21 +87,17 @@ __device__ __forceinline__ Cd cdiv(Cd a, Cd b) {
   return {(a.re * b.re + a.im * b.im) / d, (a.im * b.re - a.re * b.im) / d};
 }
 
-__device__ __forceinline__ double wavenumber(int i, int n, double d) {
-  const int s = i < n / 2 ? i : i - n;  // FFT index order; n/2 maps to -n/2
-  return 2.0 * kPi * double(s) / (double(n) * d);
-}
-
 template <typename T>
-__global__ __launch_bounds__(256) void k_coefficients(RunGeom g, GLRule gl, CoefPtrs cp) {
+__global__ __launch_bounds__(256) void k_coefficients(RunGeom g, const double *__restrict__ kt,
+                                                      GLRule gl, CoefPtrs cp) {
   const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (idx >= g.nmode) return;
   const int iz = int(idx % g.nzh);
   const int iy = int((idx / g.nzh) % g.ny);
   const int ix = int(idx / (int64_t(g.nzh) * g.ny));
-  const double kx = wavenumber(ix, g.nx, g.dx);
-  const double ky = wavenumber(iy, g.ny, g.dy);
-  const double kz = 2.0 * kPi * double(iz) / (double(g.nz) * g.dz);
+  const double kx = kt[ix];
+  const double ky = kt[g.nx + iy];
+  const double kz = kt[g.nx + g.ny + iz];
   const double k2 = kx * kx + ky * ky + kz * kz;
   const double dt = g.dt;
   Cd c[6];
@@ -167,13 +163,15 @@ __global__ __launch_bounds__(256) void k_coefficients(RunGeom g, GLRule gl, Coef
 }  // namespace
 
 template <typename T>
-void launch_coefficients(const RunGeom &g, const CoefPtrs &cp, hipStream_t s) {
+void launch_coefficients(const RunGeom &g, const double *kt, const CoefPtrs &cp, hipStream_t s) {
   static const GLRule rule = make_rule();
   const unsigned blocks = unsigned((g.nmode + 255) / 256);
-  hipLaunchKernelGGL((k_coefficients<T>), dim3(blocks), dim3(256), 0, s, g, rule, cp);
+  hipLaunchKernelGGL((k_coefficients<T>), dim3(blocks), dim3(256), 0, s, g, kt, rule, cp);
 }
 
-template void launch_coefficients<float>(const RunGeom &, const CoefPtrs &, hipStream_t);
-template void launch_coefficients<double>(const RunGeom &, const CoefPtrs &, hipStream_t);
+template void launch_coefficients<float>(const RunGeom &, const double *, const CoefPtrs &,
+                                         hipStream_t);
+template void launch_coefficients<double>(const RunGeom &, const double *, const CoefPtrs &,
+                                          hipStream_t);
 
 }  // namespace galpic

@@ -38,8 +38,10 @@ void launch_c2r_z(const FieldSet *sets, int nsets, int nf, const RunGeom &g, con
 struct CoefPtrs {
   void *c[6];  // c_EE, s, c_BJ, c_EJ, c_R1, c_R0 as Cx<T>
 };
+// kt: the run's wavenumbers per axis (nx values of x, ny of y, nz/2+1 of
+// z, in transform index order), exact or a stencil's symbol.
 template <typename T>
-void launch_coefficients(const RunGeom &g, const CoefPtrs &cp, hipStream_t s);
+void launch_coefficients(const RunGeom &g, const double *kt, const CoefPtrs &cp, hipStream_t s);
 
 // ---- k-space update and reductions (update.hip) ----------------------------
 template <typename T>
@@ -50,6 +52,7 @@ struct UpdatePtrs {
   const Cx<T> *rho_old;
   const Cx<T> *rho_new;
   const Cx<T> *coef[6];
+  const T *k[3];   // wavenumbers of x (nx), y (ny), z (nz/2+1), index order
   double vgal[3];  // the run's v_gal and dt, for the current correction
   double dt;
   int correct;     // nonzero: correct J before the update (see update.hip)
@@ -61,8 +64,8 @@ void launch_update(const RunGeom &g, const UpdatePtrs<T> *sets, int nsets, hipSt
 // Transverse projection F <- F - k (k.F)/k^2 of a spectral 3-vector, held
 // modes zeroed.
 template <typename T>
-void launch_project(const RunGeom &g, Cx<T> *F0, Cx<T> *F1, Cx<T> *F2, bool transverse,
-                    hipStream_t s);
+void launch_project(const RunGeom &g, const T *kt, Cx<T> *F0, Cx<T> *F1, Cx<T> *F2,
+                    bool transverse, hipStream_t s);
 // Fill nbytes (a multiple of 4) with zeros; a kernel, so it can be captured
 // in a graph.
 void launch_zero(void *p, size_t nbytes, hipStream_t s);

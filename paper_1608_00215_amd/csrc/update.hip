@@ -7,19 +7,14 @@
 //   B' = c0 B - c1 (ik x E) + c2 (ik x J)
 //   E' = c0 E + c1 (ik x B) + c3 J + (c4 rho^{n+1} + c5 rho^n) ik
 //
-// k is rebuilt from the mode index.  Modes on a Nyquist plane and k = 0 are
-// written as zero.  HBM-bound: 17 complex values per mode move (136 B in
-// float, 272 B in double) plus the 6 coefficients.
+// k comes from the run's per-axis wavenumber tables (the exact k, or the
+// symbol [k] of a finite-order stencil).  Modes on a Nyquist plane and
+// k = 0 are written as zero.  HBM-bound: 17 complex values per mode move
+// (136 B in float, 272 B in double) plus the 6 coefficients.
 #include "kernels.hpp"
 
 namespace galpic {
 namespace {
-
-template <typename T>
-__device__ __forceinline__ T wavenumber_t(int i, int n, T kfac) {
-  const int s = i < n / 2 ? i : i - n;
-  return T(s) * kfac;
-}
 
 // (ik x F)_a for real k and complex F
 template <typename T>
@@ -34,8 +29,7 @@ __device__ __forceinline__ void ik_cross(T kx, T ky, T kz, const Cx<T> F[3], Cx<
 
 // Workgroup row blockIdx.y picks the run of the table (all of one grid shape).
 template <typename T>
-__global__ __launch_bounds__(256) void k_update(RunGeom g, const UpdatePtrs<T> *__restrict__ sets,
-                                                T kfx, T kfy, T kfz) {
+__global__ __launch_bounds__(256) void k_update(RunGeom g, const UpdatePtrs<T> *__restrict__ sets) {
   UpdatePtrs<T> p = sets[blockIdx.y];
   for (int a = 0; a < 3; ++a) {
     p.E[a] = global_ptr(p.E[a]);
@@ -45,6 +39,7 @@ __global__ __launch_bounds__(256) void k_update(RunGeom g, const UpdatePtrs<T> *
   p.rho_old = global_ptr(p.rho_old);
   p.rho_new = global_ptr(p.rho_new);
   for (int k = 0; k < 6; ++k) p.coef[k] = global_ptr(p.coef[k]);
+  for (int a = 0; a < 3; ++a) p.k[a] = global_ptr(p.k[a]);
   const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (idx >= g.nmode) return;
   const int iz = int(idx % g.nzh);
@@ -61,9 +56,9 @@ __global__ __launch_bounds__(256) void k_update(RunGeom g, const UpdatePtrs<T> *
     }
     return;
   }
-  const T kx = wavenumber_t(ix, g.nx, kfx);
-  const T ky = wavenumber_t(iy, g.ny, kfy);
-  const T kz = T(iz) * kfz;
+  const T kx = p.k[0][ix];
+  const T ky = p.k[1][iy];
+  const T kz = p.k[2][iz];
   Cx<T> E[3], B[3], J[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
@@ -116,8 +111,8 @@ __global__ __launch_bounds__(256) void k_update(RunGeom g, const UpdatePtrs<T> *
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_project(RunGeom g, Cx<T> *F0, Cx<T> *F1, Cx<T> *F2,
-                                                 int transverse, T kfx, T kfy, T kfz) {
+__global__ __launch_bounds__(256) void k_project(RunGeom g, const T *__restrict__ kt, Cx<T> *F0,
+                                                 Cx<T> *F1, Cx<T> *F2, int transverse) {
   const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (idx >= g.nmode) return;
   const int iz = int(idx % g.nzh);
@@ -133,9 +128,9 @@ __global__ __launch_bounds__(256) void k_project(RunGeom g, Cx<T> *F0, Cx<T> *F1
     return;
   }
   if (!transverse) return;
-  const T kx = wavenumber_t(ix, g.nx, kfx);
-  const T ky = wavenumber_t(iy, g.ny, kfy);
-  const T kz = T(iz) * kfz;
+  const T kx = kt[ix];
+  const T ky = kt[g.nx + iy];
+  const T kz = kt[g.nx + g.ny + iz];
   const T inv_k2 = T(1) / (kx * kx + ky * ky + kz * kz);
   const Cx<T> a = F0[idx], b = F1[idx], c = F2[idx];
   const Cx<T> kf = inv_k2 * (kx * a + ky * b + kz * c);
@@ -176,27 +171,20 @@ __global__ __launch_bounds__(256) void k_zero(uint4 *p16, size_t n16, uint32_t *
   for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n4; i += stride) p4[i] = 0u;
 }
 
-template <typename T>
-T kfac(int n, double d) {
-  return T(2.0 * kPi / (double(n) * d));
-}
-
 }  // namespace
 
 template <typename T>
 void launch_update(const RunGeom &g, const UpdatePtrs<T> *sets, int nsets, hipStream_t s) {
   const unsigned blocks = unsigned((g.nmode + 255) / 256);
-  hipLaunchKernelGGL((k_update<T>), dim3(blocks, unsigned(nsets)), dim3(256), 0, s, g, sets,
-                     kfac<T>(g.nx, g.dx), kfac<T>(g.ny, g.dy), kfac<T>(g.nz, g.dz));
+  hipLaunchKernelGGL((k_update<T>), dim3(blocks, unsigned(nsets)), dim3(256), 0, s, g, sets);
 }
 
 template <typename T>
-void launch_project(const RunGeom &g, Cx<T> *F0, Cx<T> *F1, Cx<T> *F2, bool transverse,
-                    hipStream_t s) {
+void launch_project(const RunGeom &g, const T *kt, Cx<T> *F0, Cx<T> *F1, Cx<T> *F2,
+                    bool transverse, hipStream_t s) {
   const unsigned blocks = unsigned((g.nmode + 255) / 256);
-  hipLaunchKernelGGL((k_project<T>), dim3(blocks), dim3(256), 0, s, g, F0, F1, F2,
-                     transverse ? 1 : 0, kfac<T>(g.nx, g.dx), kfac<T>(g.ny, g.dy),
-                     kfac<T>(g.nz, g.dz));
+  hipLaunchKernelGGL((k_project<T>), dim3(blocks), dim3(256), 0, s, g, kt, F0, F1, F2,
+                     transverse ? 1 : 0);
 }
 
 template <typename T>
@@ -233,10 +221,10 @@ void launch_zero(void *p, size_t nbytes, hipStream_t s) {
 template void launch_update<float>(const RunGeom &, const UpdatePtrs<float> *, int, hipStream_t);
 template void launch_update<double>(const RunGeom &, const UpdatePtrs<double> *, int,
                                     hipStream_t);
-template void launch_project<float>(const RunGeom &, Cx<float> *, Cx<float> *, Cx<float> *,
-                                    bool, hipStream_t);
-template void launch_project<double>(const RunGeom &, Cx<double> *, Cx<double> *,
-                                     Cx<double> *, bool, hipStream_t);
+template void launch_project<float>(const RunGeom &, const float *, Cx<float> *, Cx<float> *,
+                                    Cx<float> *, bool, hipStream_t);
+template void launch_project<double>(const RunGeom &, const double *, Cx<double> *,
+                                     Cx<double> *, Cx<double> *, bool, hipStream_t);
 template void launch_sum_squares<float>(const float *, const float *, const float *, int64_t,
                                         double *, hipStream_t);
 template void launch_sum_squares<double>(const double *, const double *, const double *,

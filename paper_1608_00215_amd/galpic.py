@@ -39,7 +39,7 @@ class GridDesc(ctypes.Structure):
                 ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", ctypes.c_double),
                 ("dt", ctypes.c_double), ("shape_order", ctypes.c_int),
                 ("precision", ctypes.c_int), ("tile", ctypes.c_int * 3),
-                ("resort_div", ctypes.c_int)]
+                ("resort_div", ctypes.c_int), ("stencil", ctypes.c_int * 3)]
 
 
 class ParticlesC(ctypes.Structure):
@@ -205,9 +205,10 @@ class Context:
         arr = (GridDesc * n)()
         for i, g in enumerate(grids):
             tile = (ctypes.c_int * 3)(*g.get("tile", (0, 0, 0)))
+            stencil = (ctypes.c_int * 3)(*g.get("stencil", (0, 0, 0)))
             arr[i] = GridDesc(g["nx"], g["ny"], g["nz"], g.get("dx", 1.0), g.get("dy", 1.0),
                               g.get("dz", 1.0), g["dt"], g["order"], g["precision"], tile,
-                              g.get("resort_div", 0))
+                              g.get("resort_div", 0), stencil)
         self.grids = grids
         self.precision = grids[0]["precision"]
         self.real = np.float64 if self.precision == GP_FP64 else np.float32
@@ -346,13 +347,15 @@ class Context:
 
 def grid_from_config(cfg, precision=None, tile=(0, 0, 0), resort_div=0):
     """Grid descriptor dict of a workload.RunConfig (tile, resort_div: the
-    tuning knobs of gp_grid_desc, 0 = default)."""
+    tuning knobs of gp_grid_desc, 0 = default; the stencil orders of the
+    field solve come from the config)."""
     prec = precision if precision is not None else (
         GP_FP64 if cfg.precision == "fp64" else GP_MIXED)
     return {"nx": cfg.shape[0], "ny": cfg.shape[1], "nz": cfg.shape[2],
             "dx": cfg.spacing[0], "dy": cfg.spacing[1], "dz": cfg.spacing[2],
             "dt": cfg.dt, "order": cfg.order, "precision": prec,
-            "tile": tuple(tile), "resort_div": int(resort_div)}
+            "tile": tuple(tile), "resort_div": int(resort_div),
+            "stencil": tuple(int(p) for p in cfg.stencil)}
 
 
 def particles_from_inputs(inputs, cfg, precision, with_ids=True, device="cuda"):

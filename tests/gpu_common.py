@@ -23,8 +23,8 @@ def half(spec, nz):
     return np.asarray(spec)[:, :, : nz // 2 + 1]
 
 
-def half_k(shape, spacing):
-    k = osp.wavevectors(shape, spacing)
+def half_k(shape, spacing, stencil=(0, 0, 0)):
+    k = osp.wavevectors(shape, spacing, stencil)
     nzh = shape[2] // 2 + 1
     kk = tuple(np.array(a[:, :, :nzh]) for a in k)
     # the z-Nyquist index is +nz/2 in the half spectrum (held at zero anyway)
@@ -38,12 +38,12 @@ def half_mask(shape):
 def oracle_sim(cfg, v_gal=None):
     g = opic.Grid(cfg.shape, cfg.spacing, cfg.dt, cfg.order)
     sim = opic.Simulation(g, opic.Species(cfg.q, cfg.m, cfg.w),
-                          cfg.v_gal() if v_gal is None else v_gal)
+                          cfg.v_gal() if v_gal is None else v_gal, stencil=cfg.stencil)
     return sim
 
 
-def oracle_half_coefficients(shape, spacing, v_gal, dt):
-    k = half_k(shape, spacing)
+def oracle_half_coefficients(shape, spacing, v_gal, dt, stencil=(0, 0, 0)):
+    k = half_k(shape, spacing, stencil)
     return oco.galilean_psatd_coefficients(k, v_gal, dt), k
 
 

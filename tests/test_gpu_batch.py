@@ -1,6 +1,6 @@
 """Batched launches: a context of several runs (two grid shapes, different
-drifts, densities and seeds) steps each run exactly as a context of that run
-alone does, eagerly and through graph replay."""
+drifts, densities, seeds and field-solve stencils) steps each run exactly as
+a context of that run alone does, eagerly and through graph replay."""
 
 import numpy as np
 import pytest
@@ -16,6 +16,8 @@ RUNS = [
     BASE,
     BASE.with_(gamma=10.0, u_th=0.3, seed=1201),
     BASE.with_(shape=(16, 32, 64), density=1.5, u_th=0.1, seed=1202),
+    # same grid shape as the first run (one launch class), own stencil
+    BASE.with_(stencil=(4, 4, 8), u_th=0.2, seed=1203),
 ]
 
 
