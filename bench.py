@@ -52,6 +52,7 @@ def stage_bytes(cfg, precision_fp64):
         "fft_inv_y": 6 * 2 * nk * cb,
         "fft_inv_z": 6 * (nk * cb + nc * rb),
         "gather_push": npart * (pos + 3 * rb + 3 * rb) + 6 * nc * rb,
+        "btd": 0,                               # a few planes per snapshot and step
     }
 
 
@@ -75,7 +76,17 @@ def stage_flops(cfg):
     }
 
 
-def run_gpu(cfg, precision, steps, warmup, inputs, tile=(0, 0, 0), resort_div=0):
+def btd_snapshot_times(c, nsnap, t_mid):
+    """Lab times of nsnap snapshots whose planes k_j = (j + 1/2) nz / nsnap
+    are reached at boosted time t_mid (v_gal = -beta c along z)."""
+    beta = -c.v_gal()[2]
+    g = 1.0 / np.sqrt(1.0 - beta * beta)
+    gap = c.shape[2] / nsnap * c.spacing[2]          # dz between the planes k_j
+    t_lab0 = (t_mid + g * g * beta * 0.5 * gap) / g
+    return t_lab0, g * beta * gap
+
+
+def run_gpu(cfg, precision, steps, warmup, inputs, tile=(0, 0, 0), resort_div=0, btd=0):
     """Time one run (cfg, inputs) or a batch of runs (lists of both)."""
     import torch
 
@@ -99,6 +110,11 @@ def run_gpu(cfg, precision, steps, warmup, inputs, tile=(0, 0, 0), resort_div=0)
             ctx.set_fields(r, lf[0], lf[1], project_transverse=True)
     if any(c.laser is not None for c in cfgs):
         ctx.half_push()
+    if btd > 0:
+        # lab-frame snapshots of the first run, recorded on the fly; their
+        # planes are reached in the middle of the timed steps
+        t_lab0, dt_lab = btd_snapshot_times(cfgs[0], btd, (warmup + 0.5 * steps) * cfgs[0].dt)
+        ctx.btd_configure(0, btd, t_lab0, dt_lab, 0.0)
     if warmup > 0:
         ctx.run(warmup)
     ctx.synchronize()
@@ -277,6 +293,9 @@ def main():
     ap.add_argument("--autotune", action="store_true",
                     help="first time candidate tile shapes and re-sort thresholds on the "
                          "workload (outside the timed steps) and use the fastest")
+    ap.add_argument("--btd", type=int, default=0, metavar="N",
+                    help="record N lab-frame snapshots of the (first) run on the fly in the "
+                         "mixed run and report the back-transformation's share of the step")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device three times (a plain copy "
                          "kernel of known size for scaling HBM byte counters)")
@@ -339,7 +358,8 @@ def main():
                   "tuning_s": round(time.perf_counter() - t0, 1),
                   "candidates_ms_per_step": {f"{k[0][0]}x{k[0][1]}x{k[0][2]}/n{k[1]}": round(v, 4)
                                              for k, v in res.items()}}
-    mixed = run_gpu(run_arg, gp.GP_MIXED, args.steps, args.warmup, inputs, **setting)
+    mixed = run_gpu(run_arg, gp.GP_MIXED, args.steps, args.warmup, inputs, btd=args.btd,
+                    **setting)
     print(f"[bench] mixed: {mixed['wall_s'] / args.steps * 1e3:.3f} ms/step", file=sys.stderr,
           flush=True)
     fp64 = None
@@ -398,6 +418,14 @@ def main():
         "roofline": roof,
         "tuning": tuning,
     }
+    if args.btd > 0:
+        c0 = cfg.runs[0] if isinstance(cfg, BatchView) else cfg
+        beta = -c0.v_gal()[2]
+        g = 1.0 / np.sqrt(1.0 - beta * beta)
+        btd_ms = mixed["stage_ms"].get("btd", 0.0) * mixed["stage_launches"].get("btd", 0)
+        line["btd"] = {"snapshots": args.btd, "ms_per_launch": mixed["stage_ms"].get("btd"),
+                       "share_of_step": btd_ms / (mixed["wall_s"] * 1e3),
+                       "planes_per_snapshot_per_step": c0.dt / (g * g * beta * c0.spacing[2])}
     if fp64 is not None:
         line["fp64_gpu"] = {
             "value": cfg.n_particles * args.steps / fp64["wall_s"],

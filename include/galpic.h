@@ -218,6 +218,44 @@ gp_status gp_run(gp_ctx *ctx, const gp_particles *p, int nsteps);
  * be the null stream. */
 gp_status gp_step_graph(gp_ctx *ctx, const gp_particles *p, int nsteps);
 
+/* Lab-frame snapshots of a boosted run (back-transformed diagnostics): the
+ * paper reports its boosted-frame results in the lab frame through an
+ * on-the-fly back-transformation, named as the boosted run's only
+ * overhead (closing results paragraph; the procedure itself is not
+ * printed).  The run's v_gal must be (0, 0, -beta c): the boosted frame
+ * moves at +beta c along z relative to the lab, where the plasma, at rest
+ * on the Galilean grid, is at rest.  Galilean plane k (z'_k = k dz) is
+ * then the fixed lab plane z_lab = gamma z'_k, and its event at boosted
+ * time t' has lab time t'/gamma + gamma beta z'_k / c.
+ *   n_snap   number of snapshots (at most 65535), at lab times
+ *            t_lab0 + j dt_lab; 0 turns the recording of this run off (out
+ *            may then be NULL);
+ *   t_boost0 boosted time of the current real E, B (level 0); every field
+ *            cycle of gp_step / gp_run / gp_step_graph, and every
+ *            gp_btd_record, adds the next level, dt later;
+ *   out      device buffer of 6 * n_snap * nx*ny*nz values of the run's
+ *            real type, layout [snapshot][Ex Ey Ez Bx By Bz][z][x][y] (lab
+ *            planes contiguous, since they complete one at a time), owned
+ *            by the caller and kept valid while recording; cleared here.
+ * Plane k of snapshot j receives the Lorentz-transformed fields (lab
+ * frame moving at -beta c: E_x = gamma (E'_x + beta c B'_y), E_y =
+ * gamma (E'_y - beta c B'_x), B_x = gamma (B'_x - beta E'_y / c), B_y =
+ * gamma (B'_y + beta E'_x / c), E_z, B_z unchanged) at boosted time
+ * t'_jk = gamma t_j - gamma^2 beta z'_k / c, linearly interpolated
+ * between the levels t'_n < t'_jk <= t'_{n+1}.  It is complete once the
+ * levels reach t'_jk; before that it holds part of the sum or zero.
+ * Records the current real E, B as level 0, so call it after setting the
+ * initial fields.  Changing v_gal needs the recording off.  Errors:
+ * GP_ERR_ARG (bad run, n_snap outside [0, 65535], NULL out, non-finite
+ * times, v_gal not along z), GP_ERR_STATE (real fields not current). */
+gp_status gp_btd_configure(gp_ctx *ctx, int run, int n_snap, double t_lab0, double dt_lab,
+                           double t_boost0, void *out);
+
+/* Record the current real E, B of every recording run as its next level
+ * (for callers that drive the stage calls themselves; the step drivers
+ * record by themselves).  Errors: GP_ERR_STATE (real fields not current). */
+gp_status gp_btd_record(gp_ctx *ctx);
+
 /* Set E^0 and B^0 of one run from real-space arrays (device or host
  * pointers to nx*ny*nz values of the run's real type, or NULL for zero):
  * transformed, held modes set to zero, and with project_transverse != 0
@@ -249,7 +287,7 @@ gp_status gp_last_graph_ms(gp_ctx *ctx, double *ms);
  * gp_stage_times returns, per stage, the summed milliseconds and the number
  * of recorded launches, then clears them (synchronising).  Graph replays
  * are not recorded. */
-#define GP_N_STAGES 12
+#define GP_N_STAGES 13
 gp_status gp_stage_timing(gp_ctx *ctx, int enable);
 gp_status gp_stage_times(gp_ctx *ctx, double ms[GP_N_STAGES], int count[GP_N_STAGES]);
 const char *gp_stage_name(int stage);

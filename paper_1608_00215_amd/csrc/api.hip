@@ -54,12 +54,13 @@ int ilog2(int n) {
 // Kernel stages of a step (names: gp_stage_name).
 enum {
   kStZero = 0, kStSort, kStDeposit, kStFused, kStFwdZ, kStFwdY, kStFwdX, kStUpdate, kStInvX,
-  kStInvY, kStInvZ, kStGather, kNStages
+  kStInvY, kStInvZ, kStGather, kStBtd, kNStages
 };
 static_assert(kNStages == GP_N_STAGES, "stage count");
 const char *const kStageNames[kNStages] = {
     "zero_sources", "sort",      "deposit",   "fused_push_deposit", "fft_fwd_z", "fft_fwd_y",
-    "fft_fwd_x",    "update",    "fft_inv_x", "fft_inv_y",          "fft_inv_z", "gather_push"};
+    "fft_fwd_x",    "update",    "fft_inv_x", "fft_inv_y",          "fft_inv_z", "gather_push",
+    "btd"};
 
 enum { kReal = 10, kSpec = 11 };
 // real[] slots: 0-2 E, 3-5 B, 6-8 J, 9 rho
@@ -84,6 +85,10 @@ struct Run {
   bool src_real_ready = false;  // J, rho deposited since the last forward FFT
   bool src_spec_ready = false;  // J^, rho^{n+1} ready for the update
   bool eb_real_ready = true;    // real E, B match the spectral state
+  // lab-frame snapshots (off while btd_nsnap == 0)
+  int btd_nsnap = 0;
+  double btd_t_lab0 = 0, btd_dt_lab = 0, btd_t0 = 0;
+  void *btd_out = nullptr;      // caller's buffer
 };
 
 struct StageRec {
@@ -118,11 +123,17 @@ struct Tables {
   size_t upd[2] = {};                 // UpdatePtrs per rho parity (class order)
   size_t zero = 0;                    // ZeroSeg of J and rho (four per run)
   size_t jobs = 0;                    // PartJob per run (run order)
+  size_t btd = 0;                     // BtdJob of the recording runs (compact)
   size_t bytes = 0;
   std::vector<Class> classes;
   std::vector<int> pos;               // run -> class-order position
   size_t max_zero16 = 0;
   PartBatch batch{};
+  int btd_count = 0;                  // recording runs
+  int btd_max_snap = 0;
+  int64_t btd_max_nxy = 0;
+  std::vector<int> btd_pos;           // run -> position in the BtdJob table, or -1
+  int *btd_level = nullptr;           // device level counters, one per run
 };
 
 }  // namespace
@@ -366,9 +377,17 @@ gp_status build_tables(gp_ctx *c) {
   off = align16(off + size_t(4 * n) * sizeof(ZeroSeg));
   t.jobs = off;
   off = align16(off + size_t(n) * sizeof(PartJob<T>));
+  t.btd = off;
+  off = align16(off + size_t(n) * sizeof(BtdJob<T>));
   t.bytes = off;
   t.host.assign(off, 0);
   GP_TRY(dev_alloc(c->allocs, off, &t.dev));
+  {
+    void *lv = nullptr;
+    GP_TRY(dev_alloc(c->allocs, size_t(n) * sizeof(int), &lv));
+    t.btd_level = static_cast<int *>(lv);
+    t.btd_pos.assign(n, -1);
+  }
   t.max_zero16 = 0;
   for (int i = 0; i < n; ++i) {
     const Run &r = c->runs[i];
@@ -461,6 +480,43 @@ void fill_jobs(gp_ctx *c) {
       if (l > b.lds[m]) b.lds[m] = l;
     }
   }
+}
+
+// BtdJob entries of the runs that record lab-frame snapshots.
+template <typename T>
+void fill_btd_jobs(gp_ctx *c) {
+  Tables &t = c->tab;
+  t.btd_count = 0;
+  t.btd_max_snap = 0;
+  t.btd_max_nxy = 0;
+  for (size_t i = 0; i < c->runs.size(); ++i) {
+    Run &r = c->runs[i];
+    t.btd_pos[i] = -1;
+    if (r.btd_nsnap <= 0) continue;
+    BtdJob<T> *b = host_at<BtdJob<T>>(c, t.btd, t.btd_count);
+    for (int f = 0; f < 6; ++f) b->F[f] = static_cast<const T *>(r.real[f]);
+    b->out = static_cast<T *>(r.btd_out);
+    b->level = t.btd_level + i;
+    b->nx = r.g.nx;
+    b->ny = r.g.ny;
+    b->nz = r.g.nz;
+    b->nsnap = r.btd_nsnap;
+    b->t_lab0 = r.btd_t_lab0;
+    b->dt_lab = r.btd_dt_lab;
+    b->t0 = r.btd_t0;
+    b->dt = r.g.dt;
+    b->dz = r.g.dz;
+    b->beta = -r.g.vgal[2];
+    b->gamma = 1.0 / std::sqrt(1.0 - b->beta * b->beta);
+    t.btd_pos[i] = t.btd_count++;
+    t.btd_max_snap = std::max(t.btd_max_snap, r.btd_nsnap);
+    t.btd_max_nxy = std::max(t.btd_max_nxy, int64_t(r.g.nx) * r.g.ny);
+  }
+}
+
+template <typename T>
+const BtdJob<T> *btd_tab(gp_ctx *c, int pos) {
+  return reinterpret_cast<const BtdJob<T> *>(static_cast<char *>(c->tab.dev) + c->tab.btd) + pos;
 }
 
 gp_status upload_tables(gp_ctx *c) {
@@ -572,11 +628,21 @@ void enqueue_push(gp_ctx *c, double dt_factor) {
   launch_particles<T>(kPartPush, job_tab<T>(c), c->tab.batch, dt_factor, c->stream);
 }
 
+// The current real E, B of every recording run as its next level.
+template <typename T>
+void enqueue_btd(gp_ctx *c) {
+  if (c->tab.btd_count == 0) return;
+  Stamp s(c, kStBtd);
+  launch_btd<T>(btd_tab<T>(c, 0), c->tab.btd_count, c->tab.btd_max_snap, c->tab.btd_max_nxy,
+                c->stream);
+}
+
 template <typename T>
 void enqueue_field_cycle(gp_ctx *c) {
   enqueue_fft_fwd<T>(c);
   enqueue_update<T>(c);
   enqueue_fft_inv<T>(c);
+  enqueue_btd<T>(c);
 }
 
 // nsteps whole steps; the gather-push of each step is fused with the
@@ -982,6 +1048,8 @@ gp_status gp_set_v_gal(gp_ctx *c, int run, double vx, double vy, double vz) {
     return fail(GP_ERR_ARG, "|v_gal| must be finite and below c");
   Run &r = c->runs[run];
   RunGeom &g = r.g;
+  if (r.btd_nsnap > 0)
+    return fail(GP_ERR_STATE, "turn the run's lab-frame snapshots off before changing v_gal");
   // bound on |k.v_gal| dt over the non-Nyquist modes: sum over the axes of
   // |v_a| max |k_a| (k exact or the stencil's symbol)
   const int n[3] = {g.nx, g.ny, g.nz};
@@ -1035,6 +1103,53 @@ gp_status gp_set_current_correction(gp_ctx *c, int enable) {
     fill_update_scalars<float>(c);
   GP_TRY(upload_tables(c));
   return GP_OK;
+}
+
+gp_status gp_btd_configure(gp_ctx *c, int run, int n_snap, double t_lab0, double dt_lab,
+                           double t_boost0, void *out) {
+  GP_TRY(check_run(c, run));
+  Run &r = c->runs[run];
+  if (n_snap < 0 || n_snap > 65535) return fail(GP_ERR_ARG, "n_snap must lie in [0, 65535]");
+  if (n_snap > 0) {
+    if (!out) return fail(GP_ERR_ARG, "snapshot buffer is NULL");
+    if (!std::isfinite(t_lab0) || !std::isfinite(dt_lab) || !std::isfinite(t_boost0))
+      return fail(GP_ERR_ARG, "t_lab0, dt_lab, t_boost0 must be finite");
+    if (r.g.vgal[0] != 0.0 || r.g.vgal[1] != 0.0)
+      return fail(GP_ERR_ARG, "lab-frame snapshots need v_gal = (0, 0, -beta c)");
+    if (!r.eb_real_ready) return fail(GP_ERR_STATE, "gp_btd_configure needs real E and B");
+  }
+  drop_graphs(c);
+  GP_HIP(hipStreamSynchronize(c->stream));
+  r.btd_nsnap = n_snap;
+  r.btd_t_lab0 = t_lab0;
+  r.btd_dt_lab = dt_lab;
+  r.btd_t0 = t_boost0;
+  r.btd_out = n_snap > 0 ? out : nullptr;
+  GP_TRY(dispatch(c, [&](auto t) {
+    using T = decltype(t);
+    fill_btd_jobs<T>(c);
+  }));
+  GP_TRY(upload_tables(c));
+  if (n_snap == 0) return GP_OK;
+  // clear the snapshots, start at level 0 and record the current fields
+  launch_zero(out, size_t(6) * n_snap * size_t(r.g.ncell) * c->real_size, c->stream);
+  launch_zero(c->tab.btd_level + run, sizeof(int), c->stream);
+  GP_TRY(dispatch(c, [&](auto t) {
+    using T = decltype(t);
+    launch_btd<T>(btd_tab<T>(c, c->tab.btd_pos[run]), 1, n_snap, int64_t(r.g.nx) * r.g.ny,
+                  c->stream);
+  }));
+  return check_launch("btd");
+}
+
+gp_status gp_btd_record(gp_ctx *c) {
+  GP_TRY(check_ctx(c));
+  GP_TRY(require_eb(c, "gp_btd_record"));
+  GP_TRY(dispatch(c, [&](auto t) {
+    using T = decltype(t);
+    enqueue_btd<T>(c);
+  }));
+  return check_launch("btd");
 }
 
 gp_status gp_bind_particles(gp_ctx *c, const gp_particles *p) {

@@ -76,6 +76,23 @@ struct ZeroSeg {
   size_t n16;
 };
 void launch_zero_segments(const ZeroSeg *segs, int nseg, size_t max_n16, hipStream_t s);
+// ---- lab-frame snapshots (btd.hip) ------------------------------------------
+template <typename T>
+struct BtdJob {
+  const T *F[6];          // real E, B of the run
+  T *out;                 // [snapshot][Ex Ey Ez Bx By Bz][z][x][y]
+  int *level;             // level of the fields in F; advanced by each launch
+  int nx, ny, nz, nsnap;
+  double t_lab0, dt_lab;  // snapshot j at lab time t_lab0 + j dt_lab
+  double t0, dt;          // boosted time of level m: t0 + m dt
+  double dz, gamma, beta;
+};
+// Add level m's share to the snapshots of every job, then advance the
+// levels (max_snap, max_nxy: the largest snapshot count and nx*ny over the
+// jobs).
+template <typename T>
+void launch_btd(const BtdJob<T> *jobs, int njobs, int max_snap, int64_t max_nxy, hipStream_t s);
+
 // out[0] += sum of squares over n values of each of the three arrays.
 template <typename T>
 void launch_sum_squares(const T *a, const T *b, const T *c, int64_t n, double *out,

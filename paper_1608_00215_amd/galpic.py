@@ -30,8 +30,8 @@ EXPORTS = ["gp_init_grid", "gp_set_v_gal", "gp_set_current_correction", "gp_bind
            "gp_step_graph", "gp_set_fields", "gp_half_push", "gp_read_field",
            "gp_write_field", "gp_field_energy", "gp_last_graph_ms", "gp_synchronize",
            "gp_stage_timing", "gp_stage_times", "gp_stage_name", "gp_sort_count",
-           "gp_run", "gp_destroy", "gp_last_error"]
-GP_N_STAGES = 12
+           "gp_run", "gp_destroy", "gp_last_error", "gp_btd_configure", "gp_btd_record"]
+GP_N_STAGES = 13
 
 
 class GridDesc(ctypes.Structure):
@@ -95,6 +95,8 @@ def load(path=LIB_PATH):
         "gp_sort_count": [vp, i32, ctypes.POINTER(i32)],
         "gp_run": [vp, vp, i32],
         "gp_destroy": [vp],
+        "gp_btd_configure": [vp, i32, i32, dbl, dbl, dbl, vp],
+        "gp_btd_record": [vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -302,6 +304,34 @@ class Context:
 
     def run(self, nsteps):
         self._call("gp_run", self._parts_c, int(nsteps))
+
+    def btd_configure(self, run, n_snap, t_lab0, dt_lab, t_boost0=0.0):
+        """Record lab-frame snapshots of run (gp_btd_configure) into a device
+        tensor [n_snap][6][nz][nx][ny] (plane-major) that this object
+        allocates, keeps alive while recording, and returns; n_snap = 0
+        stops recording."""
+        import torch
+
+        if not hasattr(self, "_btd"):
+            self._btd = {}
+        g = self.grids[run]
+        out = None
+        ptr = None
+        if n_snap > 0:
+            dtype = torch.float64 if self.precision == GP_FP64 else torch.float32
+            out = torch.empty((n_snap, 6, g["nz"], g["nx"], g["ny"]), dtype=dtype,
+                              device="cuda")
+            ptr = out.data_ptr()
+        self._call("gp_btd_configure", int(run), int(n_snap), float(t_lab0), float(dt_lab),
+                   float(t_boost0), ptr)
+        if n_snap == 0:
+            self._call("gp_synchronize")
+        self._btd[run] = out
+        return out
+
+    def btd_record(self):
+        """Record the current real E, B as the next level (gp_btd_record)."""
+        self._call("gp_btd_record")
 
     def set_fields(self, run, E=None, B=None, project_transverse=False):
         """E, B: tuples of three real numpy arrays (host) or None."""

@@ -1,0 +1,150 @@
+"""GPU parity of the lab-frame snapshots (back-transformed diagnostics)
+against the oracle's back-transformation of its own field history, and
+their consistency across graph replay, batched runs and the stage calls."""
+
+import numpy as np
+import pytest
+
+from oracle import btd as obtd
+from paper_1608_00215_amd import galpic as gp
+from workload import get_config, laser_fields, particles_for
+from tests.gpu_common import oracle_sim, rel_l2
+from tests.test_gpu_step import setup
+
+pytestmark = pytest.mark.gpu
+
+# a laser in a mildly boosted plasma: gamma_boost 1.25 (beta 0.6), so that
+# about one lab plane per step completes
+CFG = get_config("c3_lite").with_(gamma=1.25)
+STEPS = 30
+
+
+def _snap_times(cfg):
+    beta = -cfg.v_gal()[2]
+    g = 1.0 / np.sqrt(1.0 - beta * beta)
+    # boosted times of plane 0: 28.3 (planes 0..30 inside the 30 levels)
+    # and 45.7 (planes 17..48)
+    return 28.3 / g, (45.7 - 28.3) / g, beta
+
+
+def _laser_start(cfg, precision, inp=None):
+    ctx, parts, inp = setup(cfg, precision, inp)
+    lf = laser_fields(cfg)
+    E0 = tuple(a.astype(np.float32).astype(np.float64) for a in lf[0])
+    B0 = tuple(a.astype(np.float32).astype(np.float64) for a in lf[1])
+    ctx.set_fields(0, E0, B0, project_transverse=True)
+    return ctx, parts, inp, E0, B0
+
+
+@pytest.mark.parametrize("precision,tol", [(gp.GP_FP64, 1e-10), (gp.GP_MIXED, 1e-4)])
+def test_snapshots_match_the_oracle(gpu_lib, precision, tol):
+    ctx, parts, inp, E0, B0 = _laser_start(CFG, precision)
+    t_lab0, dt_lab, beta = _snap_times(CFG)
+    out = ctx.btd_configure(0, 2, t_lab0, dt_lab, 0.0)
+    ctx.run(STEPS)
+    ctx.synchronize()
+    # [snapshot][field][z][x][y] -> [snapshot][field][x][y][z]
+    got = np.moveaxis(out.cpu().numpy().astype(np.float64), 2, 4)
+
+    sim = oracle_sim(CFG)
+    st = sim.initial_state(inp["x"], inp["u"], E0, B0, project_transverse=True)
+    levels = [(list(st.E), list(st.B))]
+    for _ in range(STEPS):
+        st = sim.step(st)
+        levels.append((list(st.E), list(st.B)))
+    ref, filled = obtd.back_transform(levels, 0.0, CFG.dt, [t_lab0, t_lab0 + dt_lab],
+                                      CFG.spacing[2], beta)
+    assert filled[0].sum() >= 25 and filled[1].sum() >= 25
+    for j in range(2):
+        f = filled[j]
+        for q in range(6):
+            assert rel_l2(got[j, q][:, :, f], ref[j][q][:, :, f]) <= tol, (j, q)
+        # planes beyond the next level are untouched
+        tp = obtd.plane_time(t_lab0 + j * dt_lab, np.arange(CFG.shape[2]), CFG.spacing[2],
+                             beta)
+        far = (tp <= 0.0) | (tp > (STEPS + 1) * CFG.dt)
+        assert not np.any(got[j][:, :, :, far])
+    ctx.close()
+
+
+def test_graph_replay_and_stage_calls_record_like_run(gpu_lib):
+    """Snapshots recorded through graph replays, and through the five stage
+    calls plus gp_btd_record, equal those of gp_run (FP64)."""
+    t_lab0, dt_lab, _ = _snap_times(CFG)
+    outs = []
+    inp = None
+    for mode in ("run", "graph", "calls"):
+        ctx, parts, inp, _, _ = _laser_start(CFG, gp.GP_FP64, inp)
+        out = ctx.btd_configure(0, 2, t_lab0, dt_lab, 0.0)
+        if mode == "run":
+            ctx.run(12)
+        elif mode == "graph":
+            for _ in range(3):
+                ctx.step_graph(4)
+                ctx.synchronize()
+        else:
+            for _ in range(12):
+                ctx.deposit()
+                ctx.fft_fwd()
+                ctx.galilean_psatd_update()
+                ctx.fft_inv()
+                ctx.btd_record()
+                ctx.gather_push()
+        ctx.synchronize()
+        outs.append(out.cpu().numpy())
+        ctx.close()
+    assert np.any(outs[0])
+    for o in outs[1:]:
+        assert rel_l2(o, outs[0]) <= 1e-12
+
+
+def test_batched_recording_equals_single_runs(gpu_lib):
+    """Two recording runs (different snapshots) and one that does not record,
+    in one context, record what each records alone."""
+    t_lab0, dt_lab, _ = _snap_times(CFG)
+    cfgs = [CFG, CFG.with_(seed=1301, u_th=0.05), CFG.with_(seed=1302)]
+    snaps = [(2, t_lab0, dt_lab), (3, t_lab0 + 2.0, 0.5 * dt_lab), (0, 0.0, 0.0)]
+    inputs = [particles_for(c) for c in cfgs]
+    ctx = gp.Context([gp.grid_from_config(c, gp.GP_FP64) for c in cfgs])
+    for r, c in enumerate(cfgs):
+        ctx.set_v_gal(r, c.v_gal())
+    parts = [gp.particles_from_inputs(i, c, gp.GP_FP64) for c, i in zip(cfgs, inputs)]
+    ctx.bind_particles(parts)
+    lf = laser_fields(CFG)
+    for r in range(3):
+        ctx.set_fields(r, lf[0], lf[1], project_transverse=True)
+    outs = [ctx.btd_configure(r, *snaps[r]) for r in range(2)]
+    ctx.run(10)
+    ctx.synchronize()
+    for r in range(2):
+        single, sparts, _ = setup(cfgs[r], gp.GP_FP64, inputs[r])
+        single.set_fields(0, lf[0], lf[1], project_transverse=True)
+        o = single.btd_configure(0, *snaps[r])
+        single.run(10)
+        single.synchronize()
+        assert np.any(o.cpu().numpy())
+        assert rel_l2(outs[r].cpu().numpy(), o.cpu().numpy()) <= 1e-12, r
+        single.close()
+    ctx.close()
+
+
+def test_recording_errors_and_off(gpu_lib):
+    ctx, parts, _ = setup(CFG, gp.GP_FP64)
+    with pytest.raises(gp.GalpicError):
+        ctx.btd_configure(0, -1, 0.0, 1.0)
+    ctx.set_v_gal(0, (0.1, 0.0, -0.5))
+    with pytest.raises(gp.GalpicError):          # boost not along z
+        ctx.btd_configure(0, 1, 0.0, 1.0)
+    ctx.set_v_gal(0, CFG.v_gal())
+    out = ctx.btd_configure(0, 1, 10.0, 1.0)
+    with pytest.raises(gp.GalpicError):          # v_gal fixed while recording
+        ctx.set_v_gal(0, (0.0, 0.0, -0.5))
+    ctx.run(3)
+    ctx.synchronize()
+    before = out.cpu().numpy().copy()
+    ctx.btd_configure(0, 0, 0.0, 0.0)             # off
+    ctx.run(3)
+    ctx.synchronize()
+    assert np.array_equal(out.cpu().numpy(), before)
+    ctx.set_v_gal(0, (0.0, 0.0, -0.5))
+    ctx.close()
