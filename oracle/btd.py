@@ -20,6 +20,9 @@ boosted run, without writing the procedure down.  Readings taken here:
 * The fields at t'_jk are the linear interpolation in time of the two
   stored levels t'_n < t'_jk <= t'_{n+1} (levels t'_n = t'_0 + n dt); a
   plane whose t'_jk lies outside the stored levels is not filled.
+* Particles are recorded where their worldline over a step, taken as the
+  straight segment of the move with the momentum that made it, crosses a
+  snapshot's lab time (``particle_crossings``).
 * E and B of the Galilean grid are the boosted-frame fields (a Galilean
   change of coordinates leaves their values alone); the lab fields follow
   from the Lorentz transformation of the field tensor with the lab frame
@@ -79,3 +82,42 @@ def back_transform(levels, t0, dt, t_snap, dz, beta, c=C_LIGHT):
         snaps.append(tuple(out))
         filled.append(got)
     return snaps, filled
+
+
+def particle_crossings(x_new, u_move, dt, t_new, v_gal_z, t_snap, length, c=C_LIGHT):
+    """Lab-frame records of the particles whose worldline over one step
+    crosses a snapshot's lab time.
+
+    The step ends at boosted time t_new with each particle at x_new
+    (Galilean, in the box [0, L)), having moved by (v - v_gal) dt with
+    v = c u / gamma_p of the momentum u_move that moved it.  Its worldline
+    over the step is the segment ending there,
+        x(s) = x_new - (1 - s) (v - v_gal) dt,  t'(s) = t_new - (1 - s) dt,
+    0 <= s <= 1 (the copy of the periodic box that holds the end; the lab
+    time depends on which copy).  Along it t_lab(s) = t'(s) / gamma +
+    gamma beta z(s) / c (beta = -v_gal_z / c) increases strictly (|v| < c);
+    snapshot j is crossed when t_lab(0) < t_j <= t_lab(1), at
+    s_j = (t_j - t_lab(0)) / (t_lab(1) - t_lab(0)).  The record holds the
+    position there (wrapped to the box; z scaled to the lab plane gamma z)
+    and the lab momentum u_x, u_y, gamma (u_z + beta gamma_p).  Returns, per
+    snapshot, (index, values) with values[:, 0:6] = x, y, z_lab, u_x, u_y,
+    u_z."""
+    beta = -v_gal_z / c
+    g = 1.0 / np.sqrt(1.0 - beta * beta)
+    gp = np.sqrt(1.0 + np.sum(u_move * u_move, axis=1))
+    v = c * u_move / gp[:, None]
+    step = (v - np.array([0.0, 0.0, v_gal_z])[None, :]) * dt
+    ta = (t_new - dt) / g + g * beta * (x_new[:, 2] - step[:, 2]) / c
+    tb = t_new / g + g * beta * x_new[:, 2] / c
+    out = []
+    L = np.asarray(length, dtype=np.float64)
+    for tj in t_snap:
+        hit = np.nonzero((ta < tj) & (tj <= tb))[0]
+        s = (tj - ta[hit]) / (tb[hit] - ta[hit])
+        pos = x_new[hit] - (1.0 - s)[:, None] * step[hit]
+        pos = pos - np.floor(pos / L[None, :]) * L[None, :]
+        u = u_move[hit]
+        vals = np.stack([pos[:, 0], pos[:, 1], g * pos[:, 2], u[:, 0], u[:, 1],
+                         g * (u[:, 2] + beta * gp[hit])], axis=1)
+        out.append((hit, vals))
+    return out

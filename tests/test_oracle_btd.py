@@ -6,7 +6,11 @@ the Doppler factor; the plane timing is the lab time of the grid event; a
 history linear in time is interpolated exactly; and a vacuum wave advanced
 by the Galilean-PSATD update and back-transformed is the lab-frame wave
 (Doppler-shifted in amplitude and wavenumber) within the error bound of
-linear interpolation in time.
+linear interpolation in time.  Particles at rest in the lab are recorded
+once per snapshot their worldline passes, at z_lab = gamma z' with zero
+lab momentum; a particle in uniform motion is recorded along the lab
+worldline given by relativistic velocity addition, with a lab momentum on
+the mass shell.
 """
 
 import numpy as np
@@ -143,3 +147,79 @@ def test_vacuum_wave_back_transformed_to_the_lab():
             assert np.max(np.abs(got - ref[None, None, :])) <= bound * (1 + 1e-9) + 1e-12
         for f in (1, 2, 3, 5):
             assert np.max(np.abs(snaps[j][f])) <= 1e-12
+
+
+def _walk(x0, u, dt, nsteps, v_gal_z, t_snap, L):
+    """Steps of constant momentum (no fields); crossings of every step."""
+    recs = [[] for _ in t_snap]
+    x = x0.copy()
+    gp = np.sqrt(1.0 + np.sum(u * u, axis=1))
+    step = (u / gp[:, None] - np.array([0.0, 0.0, v_gal_z])[None, :]) * dt
+    for n in range(nsteps):
+        x = x + step
+        x = x - np.floor(x / L[None, :]) * L[None, :]
+        for j, (idx, vals) in enumerate(btd.particle_crossings(x, u, dt, (n + 1) * dt, v_gal_z,
+                                                                t_snap, L)):
+            recs[j].append((n, idx, vals))
+    return recs
+
+
+def test_particles_at_rest_in_the_lab_are_recorded_once():
+    """Particles at rest in the lab sit still on the Galilean grid: each is
+    recorded exactly once per snapshot whose lab time its worldline passes,
+    at z_lab = gamma z' with zero lab momentum."""
+    rng = np.random.default_rng(64)
+    beta, dt, nsteps = 0.8, 0.5, 40
+    g = 1.0 / np.sqrt(1 - beta * beta)
+    L = np.array([4.0, 4.0, 32.0])
+    x0 = rng.random((500, 3)) * L
+    u = np.zeros((500, 3))
+    u[:, 2] = -g * beta
+    t_snap = [3.0, 9.0, 40.0]
+    recs = _walk(x0, u, dt, nsteps, -beta, t_snap, L)
+    for j, tj in enumerate(t_snap):
+        idx = np.concatenate([r[1] for r in recs[j]])
+        vals = np.concatenate([r[2] for r in recs[j]])
+        assert len(np.unique(idx)) == len(idx)
+        # crossed within the run: t'_0 / gamma + gamma beta z < t_j <= t'_N / gamma + ...
+        expect = np.nonzero((0.0 / g + g * beta * x0[:, 2] < tj)
+                            & (tj <= nsteps * dt / g + g * beta * x0[:, 2]))[0]
+        assert np.array_equal(np.sort(idx), expect)
+        order = np.argsort(idx)
+        assert np.allclose(vals[order, 2], g * x0[expect, 2], rtol=1e-13, atol=1e-12)
+        assert np.max(np.abs(vals[:, 3:6])) <= 1e-12
+    assert any(len(np.concatenate([r[1] for r in recs[j]])) > 50 for j in range(3))
+
+
+def test_uniform_motion_has_the_lab_velocity_and_momentum():
+    """A particle of constant boosted-frame velocity v' is recorded at
+    successive snapshots with displacements of the lab velocity
+    (v'_z + beta) / (1 + beta v'_z) along z and v'_x / (gamma (1 + beta
+    v'_z)) across, and with a lab momentum on the mass shell:
+    1 + |u_lab|^2 = (gamma (gamma'_p + beta u'_z))^2."""
+    beta, dt, nsteps = 0.6, 0.25, 400
+    g = 1.0 / np.sqrt(1 - beta * beta)
+    L = np.array([1e6, 1e6, 1e6])                  # no wrap on the way
+    u = np.array([[0.3, -0.2, 0.5], [0.0, 0.1, -1.4], [2.0, 0.0, 0.0]])
+    x0 = np.full((3, 3), 5e5)
+    t_lab0 = g * beta * 5e5                        # lab time of z' = 5e5 at t' = 0
+    t_snap = [t_lab0 + 1.0 + 3.0 * j for j in range(15)]
+    recs = _walk(x0, u, dt, nsteps, -beta, t_snap, L)
+    gp = np.sqrt(1 + np.sum(u * u, axis=1))
+    vp = u / gp[:, None]
+    for p in range(3):
+        pts = []
+        for j, tj in enumerate(t_snap):
+            for n, idx, vals in recs[j]:
+                k = np.nonzero(idx == p)[0]
+                if len(k):
+                    pts.append((tj, vals[k[0]]))
+        assert len(pts) >= 5, p
+        den = 1 + beta * vp[p, 2]
+        for (t1, a), (t2, b) in zip(pts, pts[1:]):
+            dtl = t2 - t1
+            assert abs((b[2] - a[2]) / dtl - (vp[p, 2] + beta) / den) <= 1e-9
+            assert abs((b[0] - a[0]) / dtl - vp[p, 0] / (g * den)) <= 1e-9
+            assert abs((b[1] - a[1]) / dtl - vp[p, 1] / (g * den)) <= 1e-9
+        ul = pts[0][1][3:6]
+        assert abs(1 + ul @ ul - (g * (gp[p] + beta * u[p, 2])) ** 2) <= 1e-10 * (1 + ul @ ul)
