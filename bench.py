@@ -86,7 +86,8 @@ def btd_snapshot_times(c, nsnap, t_mid):
     return t_lab0, g * beta * gap
 
 
-def run_gpu(cfg, precision, steps, warmup, inputs, tile=(0, 0, 0), resort_div=0, btd=0):
+def run_gpu(cfg, precision, steps, warmup, inputs, tile=(0, 0, 0), resort_div=0, btd=0,
+            btd_cap=0):
     """Time one run (cfg, inputs) or a batch of runs (lists of both)."""
     import torch
 
@@ -115,6 +116,8 @@ def run_gpu(cfg, precision, steps, warmup, inputs, tile=(0, 0, 0), resort_div=0,
         # planes are reached in the middle of the timed steps
         t_lab0, dt_lab = btd_snapshot_times(cfgs[0], btd, (warmup + 0.5 * steps) * cfgs[0].dt)
         ctx.btd_configure(0, btd, t_lab0, dt_lab, 0.0)
+        if btd_cap > 0:
+            ctx.btd_particles(0, btd_cap, with_ids=False)
     if warmup > 0:
         ctx.run(warmup)
     ctx.synchronize()
@@ -296,6 +299,9 @@ def main():
     ap.add_argument("--btd", type=int, default=0, metavar="N",
                     help="record N lab-frame snapshots of the (first) run on the fly in the "
                          "mixed run and report the back-transformation's share of the step")
+    ap.add_argument("--btd-particles", type=int, default=0, metavar="CAP",
+                    help="with --btd: also record the particles crossing the snapshots' lab "
+                         "times (up to CAP per snapshot)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device three times (a plain copy "
                          "kernel of known size for scaling HBM byte counters)")
@@ -359,7 +365,7 @@ def main():
                   "candidates_ms_per_step": {f"{k[0][0]}x{k[0][1]}x{k[0][2]}/n{k[1]}": round(v, 4)
                                              for k, v in res.items()}}
     mixed = run_gpu(run_arg, gp.GP_MIXED, args.steps, args.warmup, inputs, btd=args.btd,
-                    **setting)
+                    btd_cap=args.btd_particles, **setting)
     print(f"[bench] mixed: {mixed['wall_s'] / args.steps * 1e3:.3f} ms/step", file=sys.stderr,
           flush=True)
     fp64 = None
@@ -423,7 +429,8 @@ def main():
         beta = -c0.v_gal()[2]
         g = 1.0 / np.sqrt(1.0 - beta * beta)
         btd_ms = mixed["stage_ms"].get("btd", 0.0) * mixed["stage_launches"].get("btd", 0)
-        line["btd"] = {"snapshots": args.btd, "ms_per_launch": mixed["stage_ms"].get("btd"),
+        line["btd"] = {"snapshots": args.btd, "particle_cap": args.btd_particles,
+                       "ms_per_launch": mixed["stage_ms"].get("btd"),
                        "share_of_step": btd_ms / (mixed["wall_s"] * 1e3),
                        "planes_per_snapshot_per_step": c0.dt / (g * g * beta * c0.spacing[2])}
     if fp64 is not None:

@@ -251,6 +251,32 @@ gp_status gp_step_graph(gp_ctx *ctx, const gp_particles *p, int nsteps);
 gp_status gp_btd_configure(gp_ctx *ctx, int run, int n_snap, double t_lab0, double dt_lab,
                            double t_boost0, void *out);
 
+/* Lab-frame particle records of a recording run (the particle side of the
+ * back-transformation).  After each particle move (the deposit or fused
+ * pass of gp_step / gp_run / gp_step_graph, and gp_deposit) a particle's
+ * worldline over the step is the straight segment of its move ending at
+ * its position in the box, at boosted time t_boost0 + m dt (m: the run's
+ * recorded field levels); along it the lab time t'/gamma + gamma beta z'/c
+ * increases strictly.  Each snapshot whose lab time the segment passes
+ * (t_lab(start) < t_j <= t_lab(end)) records the particle there: x, y
+ * (wrapped to the box), z_lab = gamma z' (z' wrapped to the box), and the
+ * lab momentum u_x, u_y, gamma (u_z + beta gamma_p).
+ *   cap     records per snapshot; 0 turns particle records off;
+ *   vals    device buffer [snapshot][x y z_lab u_x u_y u_z][cap] of the
+ *           run's real type;
+ *   ids     device int64 [snapshot][cap] for the particles' ids, or NULL
+ *           (needs bound particles that carry ids);
+ *   counts  device int [snapshot], cleared here: records made; records
+ *           past cap are dropped but counted, so counts[j] > cap flags an
+ *           overflow.  The order of records within a snapshot is not
+ *           fixed.
+ * All buffers are the caller's and stay valid while recording.  Requires
+ * gp_btd_configure with n_snap > 0 and dt_lab > 0 and bound particles; a
+ * new gp_btd_configure turns the records off; re-binding keeps them on
+ * (with the new arrays).  Errors: GP_ERR_ARG, GP_ERR_STATE. */
+gp_status gp_btd_particles(gp_ctx *ctx, int run, int cap, void *vals, int64_t *ids,
+                           int *counts);
+
 /* Record the current real E, B of every recording run as its next level
  * (for callers that drive the stage calls themselves; the step drivers
  * record by themselves).  Errors: GP_ERR_STATE (real fields not current). */

@@ -89,6 +89,10 @@ struct Run {
   int btd_nsnap = 0;
   double btd_t_lab0 = 0, btd_dt_lab = 0, btd_t0 = 0;
   void *btd_out = nullptr;      // caller's buffer
+  int btd_pcap = 0;             // particle records per snapshot (0: off)
+  void *btd_pvals = nullptr;    // caller's buffers for them
+  int64_t *btd_pids = nullptr;
+  int *btd_pcount = nullptr;
 };
 
 struct StageRec {
@@ -132,6 +136,8 @@ struct Tables {
   int btd_count = 0;                  // recording runs
   int btd_max_snap = 0;
   int64_t btd_max_nxy = 0;
+  int btd_pjobs = 0;                  // recording runs that also record particles
+  int64_t btd_max_n = 0;
   std::vector<int> btd_pos;           // run -> position in the BtdJob table, or -1
   int *btd_level = nullptr;           // device level counters, one per run
 };
@@ -489,6 +495,8 @@ void fill_btd_jobs(gp_ctx *c) {
   t.btd_count = 0;
   t.btd_max_snap = 0;
   t.btd_max_nxy = 0;
+  t.btd_pjobs = 0;
+  t.btd_max_n = 0;
   for (size_t i = 0; i < c->runs.size(); ++i) {
     Run &r = c->runs[i];
     t.btd_pos[i] = -1;
@@ -508,6 +516,20 @@ void fill_btd_jobs(gp_ctx *c) {
     b->dz = r.g.dz;
     b->beta = -r.g.vgal[2];
     b->gamma = 1.0 / std::sqrt(1.0 - b->beta * b->beta);
+    b->p = r.parts;
+    b->lx = r.g.lx;
+    b->ly = r.g.ly;
+    b->lz = r.g.lz;
+    b->dx = r.g.dx;
+    b->dy = r.g.dy;
+    b->pcap = r.bound ? r.btd_pcap : 0;
+    b->pvals = static_cast<T *>(r.btd_pvals);
+    b->pids = r.btd_pids;
+    b->pcount = r.btd_pcount;
+    if (b->pcap > 0) {
+      ++t.btd_pjobs;
+      t.btd_max_n = std::max(t.btd_max_n, r.parts.n);
+    }
     t.btd_pos[i] = t.btd_count++;
     t.btd_max_snap = std::max(t.btd_max_snap, r.btd_nsnap);
     t.btd_max_nxy = std::max(t.btd_max_nxy, int64_t(r.g.nx) * r.g.ny);
@@ -547,6 +569,14 @@ void fft_inverse(gp_ctx *c, int pos, int count, const RunGeom &g) {
   launch_c2r_z<T>(fs_tab(c, kTabInvZ, pos), count, 6, g, tw, c->stream);
 }
 
+// The lab-frame records of the particles the last particle pass moved.
+template <typename T>
+void enqueue_btd_particles(gp_ctx *c) {
+  if (c->tab.btd_pjobs == 0) return;
+  Stamp s(c, kStBtd);
+  launch_btd_particles<T>(btd_tab<T>(c, 0), c->tab.btd_count, c->tab.btd_max_n, c->stream);
+}
+
 // Zero J and rho, sort if flagged, then deposit (mode kPartDeposit) or run
 // the fused gather-push + deposit (kPartFused), for every run at once.
 template <typename T>
@@ -563,6 +593,7 @@ void enqueue_sources(gp_ctx *c, int mode) {
     Stamp s(c, mode == kPartFused ? kStFused : kStDeposit);
     launch_particles<T>(mode, job_tab<T>(c), c->tab.batch, 1.0, c->stream);
   }
+  enqueue_btd_particles<T>(c);
 }
 
 // all runs rotate their rho buffers together
@@ -1125,6 +1156,11 @@ gp_status gp_btd_configure(gp_ctx *c, int run, int n_snap, double t_lab0, double
   r.btd_dt_lab = dt_lab;
   r.btd_t0 = t_boost0;
   r.btd_out = n_snap > 0 ? out : nullptr;
+  // new snapshots: particle records start off (gp_btd_particles)
+  r.btd_pcap = 0;
+  r.btd_pvals = nullptr;
+  r.btd_pids = nullptr;
+  r.btd_pcount = nullptr;
   GP_TRY(dispatch(c, [&](auto t) {
     using T = decltype(t);
     fill_btd_jobs<T>(c);
@@ -1140,6 +1176,36 @@ gp_status gp_btd_configure(gp_ctx *c, int run, int n_snap, double t_lab0, double
                   c->stream);
   }));
   return check_launch("btd");
+}
+
+gp_status gp_btd_particles(gp_ctx *c, int run, int cap, void *vals, int64_t *ids,
+                           int *counts) {
+  GP_TRY(check_run(c, run));
+  Run &r = c->runs[run];
+  if (cap < 0) return fail(GP_ERR_ARG, "cap must be >= 0");
+  if (cap > 0) {
+    if (r.btd_nsnap <= 0)
+      return fail(GP_ERR_STATE, "particle records need the run's snapshots (gp_btd_configure)");
+    if (!(r.btd_dt_lab > 0)) return fail(GP_ERR_ARG, "particle records need dt_lab > 0");
+    if (!r.bound) return fail(GP_ERR_STATE, "particle records need bound particles");
+    if (!vals || !counts) return fail(GP_ERR_ARG, "record buffers are NULL");
+    if (ids && !r.parts.id) return fail(GP_ERR_ARG, "the run's particles carry no ids");
+    if (int64_t(cap) * 6 * r.btd_nsnap > (int64_t(1) << 40))
+      return fail(GP_ERR_ARG, "cap too large");
+  }
+  drop_graphs(c);
+  GP_HIP(hipStreamSynchronize(c->stream));
+  r.btd_pcap = cap;
+  r.btd_pvals = cap > 0 ? vals : nullptr;
+  r.btd_pids = cap > 0 ? ids : nullptr;
+  r.btd_pcount = cap > 0 ? counts : nullptr;
+  GP_TRY(dispatch(c, [&](auto t) {
+    using T = decltype(t);
+    fill_btd_jobs<T>(c);
+  }));
+  GP_TRY(upload_tables(c));
+  if (cap > 0) launch_zero(counts, size_t(r.btd_nsnap) * sizeof(int), c->stream);
+  return check_launch("btd particles");
 }
 
 gp_status gp_btd_record(gp_ctx *c) {
@@ -1164,10 +1230,13 @@ gp_status gp_bind_particles(gp_ctx *c, const gp_particles *p) {
     GP_TRY(alloc_sort(c, r));
     r.bound = true;
   }
-  if (c->precision == GP_FP64)
+  if (c->precision == GP_FP64) {
     fill_jobs<double>(c);
-  else
+    fill_btd_jobs<double>(c);  // particle records follow the new arrays
+  } else {
     fill_jobs<float>(c);
+    fill_btd_jobs<float>(c);
+  }
   GP_TRY(upload_tables(c));
   GP_TRY(dispatch(c, [&](auto t) {
     using T = decltype(t);

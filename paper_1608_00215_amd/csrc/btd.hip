@@ -91,6 +91,176 @@ __global__ __launch_bounds__(kThreads) void k_btd(const BtdJob<T> *__restrict__ 
   }
 }
 
+// Particle records.  After a move the particle sits at x (in the box) with
+// the momentum u that moved it by (v - v_gal) dt; its worldline over the
+// step is the segment ending there, x(s) = x - (1 - s) (v - v_gal) dt at
+// boosted time t_new - (1 - s) dt, along which the lab time
+// t'/gamma + gamma beta z / c increases strictly.  A snapshot whose lab time
+// lies in (t_lab(0), t_lab(1)] records the particle at that point: x, y,
+// gamma z (lab plane), u_x, u_y, gamma (u_z + beta gamma_p).  Since
+// |v| < c bounds the move, the end position's z alone rules out most
+// particles in a step: only those whose possible lab-time window holds a
+// snapshot time read their momentum.
+template <typename T>
+__device__ __forceinline__ double particle_z(const BtdJob<T> &jb, int64_t k) {
+  if constexpr (sizeof(T) == 8) {
+    return static_cast<const double *>(jb.p.z)[k];
+  } else {
+    const int iz = static_cast<const int *>(jb.p.x)[k] & (jb.nz - 1);
+    return (double(iz) + double(static_cast<const float *>(jb.p.oz)[k])) * jb.dz;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void particle_xy(const BtdJob<T> &jb, int64_t k, double x[2]) {
+  if constexpr (sizeof(T) == 8) {
+    x[0] = static_cast<const double *>(jb.p.x)[k];
+    x[1] = static_cast<const double *>(jb.p.y)[k];
+  } else {
+    const int cell = static_cast<const int *>(jb.p.x)[k];
+    const int iy = (cell >> jb.lz) & (jb.ny - 1);
+    const int ix = cell >> (jb.lz + jb.ly);
+    x[0] = (double(ix) + double(static_cast<const float *>(jb.p.ox)[k])) * jb.dx;
+    x[1] = (double(iy) + double(static_cast<const float *>(jb.p.oy)[k])) * jb.dy;
+  }
+}
+
+// snapshots j in [j0, j1] (clipped) may have t_lab0 + j dt_lab in (lo, hi]
+// (inv_dt: 1 / dt_lab; the range is widened by one on each side, so its
+// rounding does not matter: the callers test each candidate exactly)
+__device__ __forceinline__ bool snapshot_range(double lo, double hi, double t_lab0, double inv_dt,
+                                               int nsnap, int &j0, int &j1) {
+  const double ja = (lo - t_lab0) * inv_dt, jb = (hi - t_lab0) * inv_dt;
+  if (!(jb >= -1.0) || !(ja < double(nsnap))) return false;
+  j0 = max(0, int(fmax(floor(ja), -1.0)));
+  j1 = min(nsnap - 1, int(fmin(floor(jb), double(nsnap))) + 1);
+  return j0 <= j1;
+}
+
+// The exact crossing test of particle k (end position z, lab time tb at
+// the end of the step) against snapshots j0..j1, and its records.
+template <typename T>
+__device__ __forceinline__ void record_particle(const BtdJob<T> &jb, int64_t k, double z,
+                                                double tb, double t_start, int j0, int j1,
+                                                const double L[3]) {
+#pragma clang fp contract(off)
+  const double g = jb.gamma, gb = jb.gamma * jb.beta;
+  const double u[3] = {double(static_cast<const T *>(jb.p.ux)[k]),
+                       double(static_cast<const T *>(jb.p.uy)[k]),
+                       double(static_cast<const T *>(jb.p.uz)[k])};
+  const double gp = sqrt(1.0 + (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]));
+  // (v - v_gal)_z with v_gal = (0, 0, -beta c); x and y only on a crossing
+  const double step_z = (u[2] / gp + jb.beta) * jb.dt;
+  const double ta = t_start + gb * (z - step_z);
+  for (int j = j0; j <= j1; ++j) {
+    const double tj = jb.t_lab0 + double(j) * jb.dt_lab;
+    if (!(ta < tj && tj <= tb)) continue;
+    const double step[3] = {u[0] / gp * jb.dt, u[1] / gp * jb.dt, step_z};
+    const double s = (tj - ta) / (tb - ta);
+    double x[3];
+    particle_xy<T>(jb, k, x);
+    x[2] = z;
+    double q[3];
+    for (int a = 0; a < 3; ++a) {
+      q[a] = x[a] - (1.0 - s) * step[a];
+      q[a] = q[a] - floor(q[a] / L[a]) * L[a];
+    }
+    const int slot = atomicAdd(jb.pcount + j, 1);
+    if (slot >= jb.pcap) continue;
+    T *o = jb.pvals + int64_t(j) * 6 * jb.pcap + slot;
+    o[0] = T(q[0]);
+    o[jb.pcap] = T(q[1]);
+    o[2 * int64_t(jb.pcap)] = T(g * q[2]);
+    o[3 * int64_t(jb.pcap)] = T(u[0]);
+    o[4 * int64_t(jb.pcap)] = T(u[1]);
+    o[5 * int64_t(jb.pcap)] = T(g * (u[2] + jb.beta * gp));
+    if (jb.pids) jb.pids[int64_t(j) * jb.pcap + slot] = jb.p.id[k];
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_btd_particles(const BtdJob<T> *__restrict__ jobs) {
+  // the crossing decisions are the plain double expressions
+#pragma clang fp contract(off)
+  BtdJob<T> jb = jobs[blockIdx.y];
+  if (jb.pcap <= 0) return;
+  jb.p.x = global_ptr(jb.p.x);
+  jb.p.y = global_ptr(jb.p.y);
+  jb.p.z = global_ptr(jb.p.z);
+  jb.p.ox = global_ptr(jb.p.ox);
+  jb.p.oy = global_ptr(jb.p.oy);
+  jb.p.oz = global_ptr(jb.p.oz);
+  jb.p.ux = global_ptr(jb.p.ux);
+  jb.p.uy = global_ptr(jb.p.uy);
+  jb.p.uz = global_ptr(jb.p.uz);
+  jb.p.id = global_ptr(jb.p.id);
+  jb.pvals = global_ptr(jb.pvals);
+  jb.pids = global_ptr(jb.pids);
+  jb.pcount = global_ptr(jb.pcount);
+  const int m = *global_ptr(jb.level);
+  const double t_new = jb.t0 + double(m) * jb.dt;
+  const double g = jb.gamma, gb = jb.gamma * jb.beta;
+  const double L[3] = {jb.nx * jb.dx, jb.ny * jb.dy, jb.nz * jb.dz};
+  // |v| < c bounds the z move: gb (v_z + beta) dt lies below reach
+  const double reach = fmax(gb * (jb.beta + 1.0), gb * (jb.beta - 1.0)) * jb.dt;
+  const double inv_dt_lab = 1.0 / jb.dt_lab;
+  const double t_end = t_new / g, t_start = (t_new - jb.dt) / g;
+  // four particles per pass, their position loads issued together (the
+  // prefilter is a few flops per particle: the pass waits on memory); the
+  // few that pass the prefilter are compacted per wave in LDS, so that the
+  // exact test runs with full lanes instead of a few lanes per pass
+  constexpr int kBatch = 4;
+  __shared__ int64_t cand_k[kThreads / 64][kBatch * 64];
+  __shared__ double cand_z[kThreads / 64][kBatch * 64];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const uint64_t below = (uint64_t(1) << lane) - 1;
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  // every lane of a wave runs the same number of passes (the compaction
+  // needs all lanes): the loop bound is the wave's first lane's
+  const int64_t first = int64_t(blockIdx.x) * blockDim.x + (threadIdx.x & ~63);
+  for (int64_t w0 = first; w0 < jb.p.n; w0 += kBatch * stride) {
+    const int64_t k0 = w0 + lane;
+    // unconditional loads (index clamped to the last particle), so that
+    // all of them are in flight before the first is used
+    double zs[kBatch];
+#pragma unroll
+    for (int i = 0; i < kBatch; ++i) zs[i] = particle_z<T>(jb, min(k0 + i * stride, jb.p.n - 1));
+    int count = 0;
+#pragma unroll
+    for (int i = 0; i < kBatch; ++i) {
+      const int64_t k = k0 + i * stride;
+      const double z = zs[i];
+      const double tb = t_end + gb * z;
+      // prefilter on z alone: no snapshot in (lowest possible t_lab(0), tb]
+      const double ta_lo = t_start + gb * z - reach;
+      bool pass = false;
+      int j0, j1;
+      if (k < jb.p.n && snapshot_range(ta_lo, tb, jb.t_lab0, inv_dt_lab, jb.nsnap, j0, j1)) {
+        for (int j = j0; j <= j1; ++j) {
+          const double tj = jb.t_lab0 + double(j) * jb.dt_lab;
+          pass = pass || (ta_lo < tj && tj <= tb);
+        }
+      }
+      const uint64_t mask = __ballot(pass);
+      if (pass) {
+        const int at = count + __popcll(mask & below);
+        cand_k[wave][at] = k;
+        cand_z[wave][at] = z;
+      }
+      count += __popcll(mask);
+    }
+    __builtin_amdgcn_wave_barrier();
+    for (int c = lane; c < count; c += 64) {
+      const double z = cand_z[wave][c];
+      const double tb = t_end + gb * z;
+      int j0, j1;
+      snapshot_range(t_start + gb * z - reach, tb, jb.t_lab0, inv_dt_lab, jb.nsnap, j0, j1);
+      record_particle<T>(jb, cand_k[wave][c], z, tb, t_start, j0, j1, L);
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
 template <typename T>
 __global__ void k_btd_advance(const BtdJob<T> *__restrict__ jobs, int njobs) {
   for (int i = threadIdx.x; i < njobs; i += blockDim.x) *global_ptr(jobs[i].level) += 1;
@@ -107,6 +277,17 @@ void launch_btd(const BtdJob<T> *jobs, int njobs, int max_snap, int64_t max_nxy,
   hipLaunchKernelGGL((k_btd_advance<T>), dim3(1), dim3(64), 0, s, jobs, njobs);
 }
 
+template <typename T>
+void launch_btd_particles(const BtdJob<T> *jobs, int njobs, int64_t max_n, hipStream_t s) {
+  if (njobs <= 0 || max_n <= 0) return;
+  int64_t blocks = (max_n + kThreads - 1) / kThreads;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL((k_btd_particles<T>), dim3(unsigned(blocks), unsigned(njobs)),
+                     dim3(kThreads), 0, s, jobs);
+}
+
+template void launch_btd_particles<float>(const BtdJob<float> *, int, int64_t, hipStream_t);
+template void launch_btd_particles<double>(const BtdJob<double> *, int, int64_t, hipStream_t);
 template void launch_btd<float>(const BtdJob<float> *, int, int, int64_t, hipStream_t);
 template void launch_btd<double>(const BtdJob<double> *, int, int, int64_t, hipStream_t);
 

@@ -86,12 +86,24 @@ struct BtdJob {
   double t_lab0, dt_lab;  // snapshot j at lab time t_lab0 + j dt_lab
   double t0, dt;          // boosted time of level m: t0 + m dt
   double dz, gamma, beta;
+  // particle records (off while pcap == 0)
+  PartPtrs p;             // the run's particles
+  int lx, ly, lz;         // log2 of nx, ny, nz (cell index decoding)
+  int pcap;               // records per snapshot
+  double dx, dy;
+  T *pvals;               // [snapshot][x y z_lab u_x u_y u_z][pcap]
+  int64_t *pids;          // [snapshot][pcap], or null
+  int *pcount;            // [snapshot]: records made (past pcap: dropped)
 };
 // Add level m's share to the snapshots of every job, then advance the
 // levels (max_snap, max_nxy: the largest snapshot count and nx*ny over the
 // jobs).
 template <typename T>
 void launch_btd(const BtdJob<T> *jobs, int njobs, int max_snap, int64_t max_nxy, hipStream_t s);
+// Record the particles whose last move crossed a snapshot's lab time, for
+// every job with pcap > 0 (max_n: the largest particle count).
+template <typename T>
+void launch_btd_particles(const BtdJob<T> *jobs, int njobs, int64_t max_n, hipStream_t s);
 
 // out[0] += sum of squares over n values of each of the three arrays.
 template <typename T>

@@ -30,7 +30,8 @@ EXPORTS = ["gp_init_grid", "gp_set_v_gal", "gp_set_current_correction", "gp_bind
            "gp_step_graph", "gp_set_fields", "gp_half_push", "gp_read_field",
            "gp_write_field", "gp_field_energy", "gp_last_graph_ms", "gp_synchronize",
            "gp_stage_timing", "gp_stage_times", "gp_stage_name", "gp_sort_count",
-           "gp_run", "gp_destroy", "gp_last_error", "gp_btd_configure", "gp_btd_record"]
+           "gp_run", "gp_destroy", "gp_last_error", "gp_btd_configure", "gp_btd_record",
+           "gp_btd_particles"]
 GP_N_STAGES = 13
 
 
@@ -97,6 +98,7 @@ def load(path=LIB_PATH):
         "gp_destroy": [vp],
         "gp_btd_configure": [vp, i32, i32, dbl, dbl, dbl, vp],
         "gp_btd_record": [vp],
+        "gp_btd_particles": [vp, i32, i32, vp, vp, vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -328,6 +330,28 @@ class Context:
             self._call("gp_synchronize")
         self._btd[run] = out
         return out
+
+    def btd_particles(self, run, cap, with_ids=True):
+        """Lab-frame particle records of run (gp_btd_particles): returns
+        device tensors (vals [n_snap][6][cap], ids [n_snap][cap] or None,
+        counts [n_snap]) that this object keeps alive while recording; cap = 0
+        turns the records off."""
+        import torch
+
+        if not hasattr(self, "_btdp"):
+            self._btdp = {}
+        out = self._btd.get(run) if hasattr(self, "_btd") else None
+        nsnap = out.shape[0] if out is not None else 0
+        vals = ids = counts = None
+        if cap > 0:
+            dtype = torch.float64 if self.precision == GP_FP64 else torch.float32
+            vals = torch.empty((nsnap, 6, cap), dtype=dtype, device="cuda")
+            ids = torch.empty((nsnap, cap), dtype=torch.int64, device="cuda") if with_ids else None
+            counts = torch.empty((max(nsnap, 1),), dtype=torch.int32, device="cuda")
+        ptr = lambda t: None if t is None else t.data_ptr()
+        self._call("gp_btd_particles", int(run), int(cap), ptr(vals), ptr(ids), ptr(counts))
+        self._btdp[run] = (vals, ids, counts)
+        return vals, ids, counts
 
     def btd_record(self):
         """Record the current real E, B as the next level (gp_btd_record)."""

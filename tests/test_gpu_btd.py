@@ -1,6 +1,8 @@
 """GPU parity of the lab-frame snapshots (back-transformed diagnostics)
 against the oracle's back-transformation of its own field history, and
-their consistency across graph replay, batched runs and the stage calls."""
+their consistency across graph replay, batched runs and the stage calls;
+and of the lab-frame particle records against the oracle's crossings of
+its own particle history."""
 
 import numpy as np
 import pytest
@@ -16,6 +18,7 @@ pytestmark = pytest.mark.gpu
 # a laser in a mildly boosted plasma: gamma_boost 1.25 (beta 0.6), so that
 # about one lab plane per step completes
 CFG = get_config("c3_lite").with_(gamma=1.25)
+CFG_GAMMA = 1.0 / np.sqrt(1.0 - (CFG.v_gal()[2]) ** 2)
 STEPS = 30
 
 
@@ -147,4 +150,108 @@ def test_recording_errors_and_off(gpu_lib):
     ctx.synchronize()
     assert np.array_equal(out.cpu().numpy(), before)
     ctx.set_v_gal(0, (0.0, 0.0, -0.5))
+    ctx.close()
+
+
+def _oracle_particle_records(cfg, inp, E0, B0, t_snap, steps):
+    sim = oracle_sim(cfg)
+    st = sim.initial_state(inp["x"], inp["u"], E0, B0, project_transverse=True)
+    L = np.array(cfg.shape) * np.array(cfg.spacing)
+    recs = [[] for _ in t_snap]
+    for n in range(steps):
+        u_move = st.u.copy()
+        st = sim.step(st)
+        hits = obtd.particle_crossings(st.x, u_move, cfg.dt, (n + 1) * cfg.dt, cfg.v_gal()[2],
+                                       t_snap, L)
+        for j, (idx, vals) in enumerate(hits):
+            recs[j].append((idx, vals))
+    out = []
+    for j in range(len(t_snap)):
+        idx = np.concatenate([r[0] for r in recs[j]])
+        vals = np.concatenate([r[1] for r in recs[j]])
+        order = np.argsort(idx)
+        out.append((idx[order], vals[order]))
+    return out
+
+
+def _gpu_records(vals, ids, counts, j):
+    n = int(counts[j].item())
+    v = vals[j, :, :n].cpu().numpy().astype(np.float64).T
+    i = ids[j, :n].cpu().numpy()
+    order = np.argsort(i)
+    return n, i[order], v[order]
+
+
+@pytest.mark.parametrize("precision", [gp.GP_FP64, gp.GP_MIXED])
+def test_particle_records_match_the_oracle(gpu_lib, precision):
+    """Thermal plasma with the laser, 30 steps: the particles recorded at two
+    lab times and their lab positions and momenta match the oracle's
+    crossings of its own history (FP64: the same set; mixed: the same set
+    but for particles within rounding of a crossing)."""
+    cfg = CFG.with_(u_th=0.05)
+    ctx, parts, inp, E0, B0 = _laser_start(cfg, precision)
+    t_lab0, dt_lab, beta = _snap_times(cfg)
+    ctx.btd_configure(0, 2, t_lab0, dt_lab, 0.0)
+    vals, ids, counts = ctx.btd_particles(0, inp["n"])
+    ctx.run(STEPS)
+    ctx.synchronize()
+    ref = _oracle_particle_records(cfg, inp, E0, B0, [t_lab0, t_lab0 + dt_lab], STEPS)
+    for j in range(2):
+        n, gid, gv = _gpu_records(vals, ids, counts, j)
+        rid, rv = ref[j]
+        assert len(rid) > 0.2 * inp["n"], j
+        assert len(np.unique(gid)) == n, j                # once per particle
+        if precision == gp.GP_FP64:
+            assert np.array_equal(gid, rid), j
+            common_g, common_r = np.arange(n), np.arange(n)
+        else:
+            both, common_g, common_r = np.intersect1d(gid, rid, return_indices=True)
+            assert len(rid) - len(both) <= max(20, 1e-4 * len(rid)), j
+            assert n - len(both) <= max(20, 1e-4 * len(rid)), j
+        a, b = gv[common_g], rv[common_r]
+        tol = 1e-9 if precision == gp.GP_FP64 else 2e-4
+        for q in range(6):
+            scale = max(1.0, np.max(np.abs(b[:, q])))
+            d = np.abs(a[:, q] - b[:, q])
+            if q < 3:   # positions: the same point of a periodic box
+                L = (np.array(cfg.shape) * np.array(cfg.spacing))[q] * (CFG_GAMMA if q == 2 else 1)
+                d = np.minimum(d, L - d)
+            assert np.max(d) <= tol * scale, (j, q, np.max(d))
+    ctx.close()
+
+
+def test_particle_records_graph_equals_eager_and_overflow(gpu_lib):
+    t_lab0, dt_lab, _ = _snap_times(CFG)
+    got = []
+    inp = None
+    for mode in ("run", "graph"):
+        ctx, parts, inp, _, _ = _laser_start(CFG, gp.GP_FP64, inp)
+        ctx.btd_configure(0, 2, t_lab0, dt_lab, 0.0)
+        vals, ids, counts = ctx.btd_particles(0, inp["n"])
+        if mode == "run":
+            ctx.run(12)
+        else:
+            for _ in range(3):
+                ctx.step_graph(4)
+                ctx.synchronize()
+        ctx.synchronize()
+        got.append([_gpu_records(vals, ids, counts, j) for j in range(2)])
+        ctx.close()
+    for j in range(2):
+        assert got[0][j][0] > 0
+        assert np.array_equal(got[0][j][1], got[1][j][1])
+        assert np.max(np.abs(got[0][j][2] - got[1][j][2])) <= 1e-12 * (1 + np.max(np.abs(got[0][j][2])))
+    # a small cap: records past it are counted, not written
+    ctx, parts, inp, _, _ = _laser_start(CFG, gp.GP_FP64, inp)
+    ctx.btd_configure(0, 2, t_lab0, dt_lab, 0.0)
+    vals, ids, counts = ctx.btd_particles(0, 7)
+    ctx.run(12)
+    ctx.synchronize()
+    c = counts.cpu().numpy()
+    assert c[0] == got[0][0][0] and c[0] > 7
+    i = ids[0].cpu().numpy()
+    assert np.all(np.isin(i, got[0][0][1]))
+    with pytest.raises(gp.GalpicError):           # no snapshots on the run
+        ctx.btd_configure(0, 0, 0.0, 0.0)
+        ctx.btd_particles(0, 10)
     ctx.close()
