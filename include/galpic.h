@@ -17,7 +17,10 @@
  *     -> gp_gather_push
  * or gp_step / gp_run / gp_step_graph, which run the same work (over
  * several steps the gather-push of one step is fused with the deposit of
- * the next).
+ * the next).  Options beyond the printed scheme: the Galilean current
+ * correction (gp_set_current_correction), finite-order stencils for the
+ * field solve (gp_grid_desc.stencil), and lab-frame snapshots of fields
+ * and particles recorded on the fly (gp_btd_configure, gp_btd_particles).
  *
  * Conventions
  *  - Normalised units: c = eps0 = 1.  Lengths in c/omega_p, times in
@@ -26,7 +29,8 @@
  *    real arrays [x][y][z] row-major (z contiguous); spectral arrays are
  *    the half spectrum [x][y][nz/2+1] of interleaved complex values,
  *    forward kernel exp(-i k.x), unnormalised; the inverse carries 1/N.
- *    k is the exact spectral wavevector 2 pi m / L.
+ *    k is the exact spectral wavevector 2 pi m / L, or a finite-order
+ *    stencil's symbol where gp_grid_desc.stencil asks for one.
  *  - The k = 0 mode and every Nyquist plane of J, rho, E and B are held at
  *    zero (the co-moving ion background cancels the mean current).
  *  - Shapes: B-splines of order 1 (cloud-in-cell) or 3 (cubic), the same
@@ -36,8 +40,8 @@
  *    cell index (ix * ny + iy) * nz + iz plus three float offsets in
  *    [0, 1); momenta, real and spectral fields, FFT, update and push are
  *    float (complex64 spectra); the update coefficients are computed in
- *    double and rounded once; each deposition tile is summed with a
- *    compensated (two-term) float accumulator.
+ *    double and rounded once; each deposition tile is summed in double
+ *    (LDS) before its one float add into the grid.
  *
  * Ownership and threading
  *  - Particle arrays are owned by the caller (device memory, e.g. torch

@@ -19,7 +19,7 @@
 // precision the per-tile sums are carried in double (no-return LDS
 // atomics): the float roundings of a deposited value are those of the
 // contributions of a quad's particles and their sum, and the final
-// conversion; the tile sum itself is compensated.  A particle whose shape
+// conversion; the tile sum itself adds no float rounding.  A particle whose shape
 // support leaves its tile's region (it drifted since the last sort) uses
 // global memory directly and is counted; the next step re-sorts when that
 // count passes n/64.
@@ -354,7 +354,7 @@ __device__ __forceinline__ void support_of(const CellPos<T> &c, const Region &r,
 
 // ---- accumulation ----------------------------------------------------------
 // Deposit nq values (val[q] * weight) into LDS accumulators q0.. of the
-// region (type A: float, or double for compensated float sums) or, outside
+// region (type A: double, also for float contributions) or, outside
 // the region, straight into the global grids dst[q].
 template <int ORDER, typename T, typename A>
 __device__ __forceinline__ void deposit(const CellPos<T> &c, const Support<ORDER, T> &s,
@@ -1142,7 +1142,7 @@ struct LayoutOf<double> {
 template <>
 struct LayoutOf<float> {
   using type = LayoutCell;
-  using acc = double;  // compensated: float contributions, double tile sums
+  using acc = double;  // float contributions, double tile sums
 };
 
 }  // namespace
