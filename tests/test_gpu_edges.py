@@ -134,3 +134,24 @@ def test_empty_run_next_to_a_full_one(gpu_lib):
     assert rel_l2(u1, u2) <= 1e-12
     ctx.close()
     single.close()
+
+
+@pytest.mark.parametrize("shape,tile", [((8, 8, 8), (0, 0, 0)), ((16, 16, 32), (8, 2, 4))])
+def test_mixed_cubic_steps_small_grid_and_tiles(gpu_lib, shape, tile):
+    """Mixed precision, cubic shape, drift margin: on a grid smaller than a
+    tile's node region (every region holds some nodes twice) and with thin
+    tiles (up to four tiles' regions hold a node along an axis), three
+    steps match the FP64 oracle."""
+    cfg = get_config("c2_lite").with_(shape=shape, u_th=0.2)
+    inp = particles_for(cfg)
+    ctx = gp.Context([gp.grid_from_config(cfg, gp.GP_MIXED, tile=tile)])
+    ctx.set_v_gal(0, cfg.v_gal())
+    parts = gp.particles_from_inputs(inp, cfg, gp.GP_MIXED)
+    ctx.bind_particles([parts])
+    sim = oracle_sim(cfg)
+    st = sim.initial_state(inp["x"], inp["u"])
+    for _ in range(3):
+        ctx.step()
+        st = sim.step(st)
+    compare_state(ctx, parts, st, cfg, 2e-5, 5e-6)
+    ctx.close()
