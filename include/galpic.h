@@ -335,6 +335,90 @@ gp_status gp_destroy(gp_ctx *ctx);
 /* Message of the last failure on this thread ("" if none). */
 const char *gp_last_error(void);
 
+/* ---- Quasi-cylindrical field solve (option) ------------------------------
+ * The paper's own runs use a quasi-3D spectral code: fields expanded in
+ * azimuthal modes m, discrete Hankel transforms along r in place of the
+ * transverse Fourier transforms; the Galilean scheme does not depend on the
+ * geometry.  This context advances the fields of nmodes modes with the
+ * Galilean-PSATD update for given sources (particles in azimuthal modes are
+ * not part of it).  Readings (the paper does not print the scheme):
+ *  - a mode m field is F_m(r, z) exp(i m theta); G_+ = (F_r + i F_theta)/2
+ *    carries Hankel order m+1, G_- = (F_r - i F_theta)/2 order m-1, F_z
+ *    and rho order m;
+ *  - radial nodes r_j = (j + 1/2) dr, j < nr; spectral grid per mode
+ *    k_i = alpha_{m,i} / (nr dr) (zeros of J_m) for all three orders;
+ *    backward transform F(r_j) = sum_i F^_i J_p(k_i r_j), forward its
+ *    matrix inverse; z periodic with the Cartesian Fourier convention, the
+ *    k_z Nyquist plane held at zero;
+ *  - the update is the Cartesian Galilean-PSATD update at k = (k_r, 0, k_z)
+ *    applied to F^_x = i (G^_- - G^_+), F^_y = -(G^_+ + G^_-), F^_z = G^_z;
+ *    v_gal is along z.
+ * Fields are complex [mode][z][r] arrays (r contiguous) of the context's
+ * real type (interleaved re, im).  Calls are asynchronous on the context's
+ * stream unless noted; errors as for the Cartesian calls. */
+typedef struct gp_qc_ctx gp_qc_ctx;
+typedef struct {
+  int nz;        /* z nodes: power of two in [8, 1024] (periodic)          */
+  int nr;        /* radial nodes r_j = (j + 1/2) dr: [4, 512]              */
+  int nmodes;    /* azimuthal modes m = 0 .. nmodes-1: [1, 8]              */
+  double dz, dr, dt;
+  int precision; /* GP_FP64 or GP_MIXED (float fields, FP64-built tables)  */
+} gp_qc_desc;
+
+/* Selectors of gp_qc_read / gp_qc_write: real-space components, spectral
+ * G^_+, G^_-, G^_z of E, B, J, rho^n and rho^{n+1}, and (read only) the six
+ * update coefficients [mode][k_z][k_r] (as for GP_COEF0..5). */
+enum {
+  GP_QC_ER = 0, GP_QC_ET, GP_QC_EZ, GP_QC_BR, GP_QC_BT, GP_QC_BZ,
+  GP_QC_JR, GP_QC_JT, GP_QC_JZ, GP_QC_RHO,
+  GP_QC_E_PLUS, GP_QC_E_MINUS, GP_QC_E_Z_HAT,
+  GP_QC_B_PLUS, GP_QC_B_MINUS, GP_QC_B_Z_HAT,
+  GP_QC_J_PLUS, GP_QC_J_MINUS, GP_QC_J_Z_HAT,
+  GP_QC_RHO_HAT_OLD, GP_QC_RHO_HAT_NEW,
+  GP_QC_COEF0, GP_QC_COEF1, GP_QC_COEF2, GP_QC_COEF3, GP_QC_COEF4, GP_QC_COEF5,
+  GP_QC_N_FIELDS
+};
+
+/* Create a context (fields zero, v_gal 0, transform matrices and k_r built
+ * in double on the host).  hip_stream as for gp_init_grid.  Synchronising.
+ * Errors: GP_ERR_ARG (sizes), GP_ERR_OOM, GP_ERR_HIP. */
+gp_status gp_qc_init(const gp_qc_desc *d, void *hip_stream, gp_qc_ctx **out);
+/* v_gal = (0, 0, vz); rebuilds the coefficients in double.  Errors:
+ * GP_ERR_ARG (|vz| >= c), GP_ERR_UNSTABLE (|k_z vz| dt >= 2 pi (1 - 1e-6)). */
+gp_status gp_qc_set_v_gal(gp_qc_ctx *ctx, double vz);
+/* Copy nmodes*nz*nr complex values from or to src / dst (host or device
+ * memory).  Synchronising. */
+gp_status gp_qc_write(gp_qc_ctx *ctx, int which, const void *src);
+gp_status gp_qc_read(gp_qc_ctx *ctx, int which, void *dst);
+/* Real E, B -> spectral E^, B^ (initial fields). */
+gp_status gp_qc_fields_fwd(gp_qc_ctx *ctx);
+/* Real J, rho -> spectral J^ and rho^{n+1}. */
+gp_status gp_qc_sources_fwd(gp_qc_ctx *ctx);
+/* Real rho -> rho^n (the initial charge). */
+gp_status gp_qc_init_rho(gp_qc_ctx *ctx);
+/* The Galilean-PSATD update of every mode; then rho^{n+1} becomes rho^n. */
+gp_status gp_qc_update(gp_qc_ctx *ctx);
+/* Spectral E^, B^ -> real E, B. */
+gp_status gp_qc_fields_inv(gp_qc_ctx *ctx);
+/* nsteps of (gp_qc_sources_fwd, gp_qc_update, gp_qc_fields_inv) with the
+ * real J and rho as they stand. */
+gp_status gp_qc_step(gp_qc_ctx *ctx, int nsteps);
+gp_status gp_qc_synchronize(gp_qc_ctx *ctx);
+gp_status gp_qc_destroy(gp_qc_ctx *ctx);
+/* Host-only (no GPU, no context): the spectral grid and transform matrices
+ * a context builds, for callers that prepare or read spectral fields.
+ * gp_qc_wavenumbers writes k_i = alpha_{m,i} / (nr dr), i < nr, the first nr
+ * positive zeros of J_m over R.  gp_qc_hankel_matrix writes, row-major
+ * nr x nr, the backward matrix of Hankel order p on mode m's grid,
+ * M[j][i] = J_p(k_i r_j) with r_j = (j + 1/2) dr (radial j <- spectral i),
+ * or, with forward != 0, its inverse A[i][j] (spectral i <- radial j).  A
+ * context applies these (the backward one divided by nz, in the run's real
+ * type) along r.  Errors: GP_ERR_ARG (NULL output, m outside [0, 63], p
+ * outside [-64, 64], nr outside [1, 512], dr not positive and finite, a
+ * singular matrix). */
+gp_status gp_qc_wavenumbers(int m, int nr, double dr, double *kr);
+gp_status gp_qc_hankel_matrix(int p, int m, int nr, double dr, int forward, double *out);
+
 #ifdef __cplusplus
 }
 #endif

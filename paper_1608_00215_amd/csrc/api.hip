@@ -25,6 +25,12 @@ gp_status fail(gp_status st, const std::string &msg) {
   return st;
 }
 
+}  // namespace
+
+void galpic::set_last_error(const std::string &msg) { g_err = msg; }
+
+namespace {
+
 #define GP_HIP(call)                                                                    \
   do {                                                                                  \
     hipError_t e_ = (call);                                                             \

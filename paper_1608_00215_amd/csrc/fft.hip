@@ -427,6 +427,35 @@ void launch_c2c(const FieldSet *sets, int nsets, int nf, const RunGeom &g, int a
   }
 }
 
+template <typename T>
+void launch_c2c_lines(const FieldSet *sets, int nsets, int nf, int log_len, int ncols,
+                      int64_t row_stride, int64_t outer_stride, int n_outer, bool inverse,
+                      const Cx<T> *tw, hipStream_t s) {
+  constexpr int CW = TileCols<T>::value;
+  StridedGeom sg{};
+  sg.ncols = ncols;
+  sg.col_tiles = (ncols + CW - 1) / CW;
+  sg.row_stride = row_stride;
+  sg.outer_stride = outer_stride;
+  sg.mask = 0;
+  const int inv = inverse ? 1 : 0;
+  switch (log_len) {
+    case 3: dispatch_c2c<T, 3>(sets, nsets, nf, sg, n_outer, inv, tw, s); break;
+    case 4: dispatch_c2c<T, 4>(sets, nsets, nf, sg, n_outer, inv, tw, s); break;
+    case 5: dispatch_c2c<T, 5>(sets, nsets, nf, sg, n_outer, inv, tw, s); break;
+    case 6: dispatch_c2c<T, 6>(sets, nsets, nf, sg, n_outer, inv, tw, s); break;
+    case 7: dispatch_c2c<T, 7>(sets, nsets, nf, sg, n_outer, inv, tw, s); break;
+    case 8: dispatch_c2c<T, 8>(sets, nsets, nf, sg, n_outer, inv, tw, s); break;
+    case 9: dispatch_c2c<T, 9>(sets, nsets, nf, sg, n_outer, inv, tw, s); break;
+    case 10: dispatch_c2c<T, 10>(sets, nsets, nf, sg, n_outer, inv, tw, s); break;
+    default: break;
+  }
+}
+
+template void launch_c2c_lines<float>(const FieldSet *, int, int, int, int, int64_t, int64_t,
+                                      int, bool, const Cx<float> *, hipStream_t);
+template void launch_c2c_lines<double>(const FieldSet *, int, int, int, int, int64_t, int64_t,
+                                       int, bool, const Cx<double> *, hipStream_t);
 template void fill_twiddles<float>(Cx<float> *);
 template void fill_twiddles<double>(Cx<double> *);
 template void launch_r2c_z<float>(const FieldSet *, int, int, const RunGeom &, const Cx<float> *,

@@ -1,9 +1,14 @@
 // Host-side launchers of the gfx950 kernels (one translation unit each).
 #pragma once
 
+#include <string>
+
 #include "common.hpp"
 
 namespace galpic {
+
+// The message gp_last_error returns (set by entry points outside api.hip).
+void set_last_error(const std::string &msg);
 
 // Up to six field arrays of one run.  Launches take a device table of
 // FieldSets, one per run: workgroup row blockIdx.y = run * nf + field, so one
@@ -33,6 +38,15 @@ void launch_c2c(const FieldSet *sets, int nsets, int nf, const RunGeom &g, int a
 template <typename T>
 void launch_c2r_z(const FieldSet *sets, int nsets, int nf, const RunGeom &g, const Cx<T> *tw,
                   hipStream_t s);
+
+// Complex transforms along the lines of arrays of n_outer blocks: line
+// element j of column c of block o at o * outer_stride + j * row_stride + c
+// (ncols columns, 2^log_len elements per line), no held-mode mask, no
+// scaling.
+template <typename T>
+void launch_c2c_lines(const FieldSet *sets, int nsets, int nf, int log_len, int ncols,
+                      int64_t row_stride, int64_t outer_stride, int n_outer, bool inverse,
+                      const Cx<T> *tw, hipStream_t s);
 
 // ---- coefficients (coef.hip) ----------------------------------------------
 struct CoefPtrs {

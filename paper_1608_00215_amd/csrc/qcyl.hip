@@ -1,0 +1,872 @@
+// Quasi-cylindrical (azimuthal-mode) Galilean-PSATD field solve.
+//
+// The paper's own runs use a quasi-3D spectral code (azimuthal modes, with
+// discrete Hankel transforms along r in place of the transverse Fourier
+// transforms) and state that the Galilean scheme does not depend on the
+// geometry.  Readings (the paper does not print the cylindrical scheme):
+//  - a mode m field is F_m(r, z) exp(i m theta); its components combine as
+//    G_+ = (F_r + i F_theta) / 2 (Hankel order m+1), G_- = (F_r - i F_theta)
+//    / 2 (order m-1), F_z and rho (order m);
+//  - radial nodes r_j = (j + 1/2) dr; one spectral grid per mode for all
+//    three orders, k_i = alpha_{m,i} / R (zeros of J_m, R = nr dr); the
+//    backward transform of order p is F(r_j) = sum_i F^_i J_p(k_i r_j) and
+//    the forward one its matrix inverse; z is periodic with the Cartesian
+//    Fourier convention, and the k_z Nyquist plane is held at zero;
+//  - the update is the Cartesian Galilean-PSATD update at k = (k_r, 0, k_z)
+//    applied to F^_x = i (G^_- - G^_+), F^_y = -(G^_+ + G^_-), F^_z = G^_z
+//    (the azimuth-0 Cartesian spectral field of the mode, up to a factor
+//    common to every component), which is exact for v_gal along z since the
+//    update commutes with rotations about z.
+//
+// Layout: every field is complex [mode][z][r] (r contiguous).  A step:
+//  z transforms of J, rho (strided complex lines, the Cartesian c2c tile
+//  kernel) -> forward Hankel transforms (a real matrix times complex rows,
+//  matrices transposed so that a workgroup's threads read a matrix row
+//  together and reuse it over kRows z rows staged in LDS) -> the mode
+//  update (one streaming pass per mode) -> backward Hankel transforms of E, B
+//  -> inverse z transforms.
+#include "galpic.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+
+namespace galpic {
+namespace {
+
+constexpr int kQThreads = 256;
+constexpr int kRows = 8;     // z rows per Hankel-transform workgroup
+constexpr int kMaxOut = 2;   // radial outputs per thread: nr <= 2 * kQThreads
+
+enum { kVecFwd = 0, kVecBwd = 1, kScalarFwd = 2 };
+
+// In/out arrays of one field of a Hankel-transform launch.
+struct QcSet {
+  const void *in[3];
+  void *out[3];
+};
+
+// Matrix slots per mode: 0 = order m-1, 1 = order m, 2 = order m+1.
+//  kVecFwd:    in = F_r, F_theta, F_z (z-transformed) -> out = G^_+, G^_-, G^_z
+//  kVecBwd:    in = G^_+, G^_-, G^_z -> out = F_r, F_theta, F_z (before the
+//              inverse z transform; the backward matrices carry its 1/nz)
+//  kScalarFwd: in[0] -> out[0], order m
+// Workgroup (z row group, mode, field).  mats: [mode][slot][j][i], the
+// transpose of the transform (out_i = sum_j A_ij in_j).
+template <typename T, int KIND>
+__global__ __launch_bounds__(kQThreads) void k_qc_hankel(const QcSet *__restrict__ sets,
+                                                         const T *__restrict__ mats, int nz,
+                                                         int nr) {
+  extern __shared__ __align__(16) unsigned char qsm[];
+  Cx<T> *x = reinterpret_cast<Cx<T> *>(qsm);  // [kRows][nr]
+  const QcSet st = sets[blockIdx.z];
+  const int m = blockIdx.y;
+  const int z0 = blockIdx.x * kRows;
+  const int rows = min(kRows, nz - z0);
+  const int64_t base = int64_t(m) * nz * nr + int64_t(z0) * nr;
+  const Cx<T> *in[3] = {global_ptr(static_cast<const Cx<T> *>(st.in[0])),
+                        global_ptr(static_cast<const Cx<T> *>(st.in[1])),
+                        global_ptr(static_cast<const Cx<T> *>(st.in[2]))};
+  Cx<T> *out[3] = {global_ptr(static_cast<Cx<T> *>(st.out[0])),
+                   global_ptr(static_cast<Cx<T> *>(st.out[1])),
+                   global_ptr(static_cast<Cx<T> *>(st.out[2]))};
+  constexpr int ncomp = KIND == kScalarFwd ? 1 : 3;
+  Cx<T> keep[kRows][kMaxOut];  // kVecBwd: the backward G_+ until G_- is ready
+  for (int c = 0; c < ncomp; ++c) {
+    for (int t = threadIdx.x; t < rows * nr; t += kQThreads) {
+      const int64_t at = base + t;
+      Cx<T> v;
+      if (KIND == kVecFwd && c < 2) {
+        const Cx<T> ib = mul_i(in[1][at]);
+        const Cx<T> a = in[0][at];
+        v = c == 0 ? T(0.5) * (a + ib) : T(0.5) * (a - ib);
+      } else {
+        v = in[c][at];
+      }
+      x[t] = v;
+    }
+    __syncthreads();
+    const int slot = KIND == kScalarFwd ? 1 : (c == 0 ? 2 : (c == 1 ? 0 : 1));
+    const T *__restrict__ AT = global_ptr(mats) + (int64_t(m) * 3 + slot) * nr * nr;
+    Cx<T> acc[kRows][kMaxOut];
+#pragma unroll
+    for (int r = 0; r < kRows; ++r)
+#pragma unroll
+      for (int o = 0; o < kMaxOut; ++o) acc[r][o] = cx(T(0), T(0));
+    for (int j = 0; j < nr; ++j) {
+      T a[kMaxOut];
+#pragma unroll
+      for (int o = 0; o < kMaxOut; ++o) {
+        const int i = threadIdx.x + o * kQThreads;
+        a[o] = i < nr ? AT[int64_t(j) * nr + i] : T(0);
+      }
+#pragma unroll
+      for (int r = 0; r < kRows; ++r) {
+        if (r < rows) {
+          const Cx<T> xv = x[r * nr + j];
+#pragma unroll
+          for (int o = 0; o < kMaxOut; ++o) {
+            acc[r][o].re += a[o] * xv.re;
+            acc[r][o].im += a[o] * xv.im;
+          }
+        }
+      }
+    }
+    __syncthreads();  // x is restaged for the next component
+#pragma unroll
+    for (int r = 0; r < kRows; ++r) {
+#pragma unroll
+      for (int o = 0; o < kMaxOut; ++o) {
+        const int i = threadIdx.x + o * kQThreads;
+        if (r >= rows || i >= nr) continue;
+        const int64_t at = base + int64_t(r) * nr + i;
+        if (KIND == kVecBwd && c == 0) {
+          keep[r][o] = acc[r][o];
+        } else if (KIND == kVecBwd && c == 1) {
+          const Cx<T> gp = keep[r][o], gm = acc[r][o];
+          out[0][at] = gp + gm;                    // F_r
+          out[1][at] = T(-1) * mul_i(gp - gm);     // F_theta = -i (G_+ - G_-)
+        } else {
+          out[c][at] = acc[r][o];
+        }
+      }
+    }
+  }
+}
+
+// The mode update's arrays.
+template <typename T>
+struct QcUpd {
+  Cx<T> *E[3], *B[3];           // G^_+, G^_-, G^_z
+  const Cx<T> *J[3];
+  const Cx<T> *rho_old, *rho_new;
+  const Cx<T> *coef[6];         // [mode][k_z][k_r]
+  const T *kr;                  // [mode][k_r]
+};
+
+// (ik x F) for k = (kr, 0, kz)
+template <typename T>
+__device__ __forceinline__ void ik_cross_r0z(T kr, T kz, const Cx<T> F[3], Cx<T> o[3]) {
+  o[0] = mul_i(T(-1) * (kz * F[1]));
+  o[1] = mul_i(kz * F[0] - kr * F[2]);
+  o[2] = mul_i(kr * F[1]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_qc_update(QcUpd<T> p, int nmodes, int nz, int nr,
+                                                   T kzfac) {
+  const int64_t n = int64_t(nmodes) * nz * nr;
+  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= n) return;
+  const int i = int(idx % nr);
+  const int iz = int((idx / nr) % nz);
+  const int m = int(idx / (int64_t(nz) * nr));
+  if (iz == nz / 2) {
+    const Cx<T> z = cx(T(0), T(0));
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      p.E[a][idx] = z;
+      p.B[a][idx] = z;
+    }
+    return;
+  }
+  const T kr = p.kr[int64_t(m) * nr + i];
+  const T kz = T(iz < nz / 2 ? iz : iz - nz) * kzfac;
+  // azimuth-0 Cartesian components: x = i (G_- - G_+), y = -(G_+ + G_-), z
+  auto to_cart = [](const Cx<T> g[3], Cx<T> f[3]) {
+    f[0] = mul_i(g[1] - g[0]);
+    f[1] = T(-1) * (g[0] + g[1]);
+    f[2] = g[2];
+  };
+  Cx<T> Eg[3], Bg[3], Jg[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    Eg[a] = p.E[a][idx];
+    Bg[a] = p.B[a][idx];
+    Jg[a] = p.J[a][idx];
+  }
+  Cx<T> E[3], B[3], J[3];
+  to_cart(Eg, E);
+  to_cart(Bg, B);
+  to_cart(Jg, J);
+  const Cx<T> r0 = p.rho_old[idx], r1 = p.rho_new[idx];
+  const Cx<T> c0 = p.coef[0][idx], c1 = p.coef[1][idx], c2 = p.coef[2][idx];
+  const Cx<T> c3 = p.coef[3][idx], c4 = p.coef[4][idx], c5 = p.coef[5][idx];
+  Cx<T> kE[3], kB[3], kJ[3];
+  ik_cross_r0z(kr, kz, E, kE);
+  ik_cross_r0z(kr, kz, B, kB);
+  ik_cross_r0z(kr, kz, J, kJ);
+  const Cx<T> rho_i = mul_i(c4 * r1 + c5 * r0);
+  const T kk[3] = {kr, T(0), kz};
+  Cx<T> En[3], Bn[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    Bn[a] = c0 * B[a] - c1 * kE[a] + c2 * kJ[a];
+    En[a] = c0 * E[a] + c1 * kB[a] + c3 * J[a] + kk[a] * rho_i;
+  }
+  // back: G_+ = (i / 2)(x + i y), G_- = -(i / 2)(x - i y)
+  auto from_cart = [](const Cx<T> f[3], Cx<T> *const g[3], int64_t at) {
+    g[0][at] = T(0.5) * mul_i(f[0] + mul_i(f[1]));
+    g[1][at] = T(-0.5) * mul_i(f[0] - mul_i(f[1]));
+    g[2][at] = f[2];
+  };
+  from_cart(En, p.E, idx);
+  from_cart(Bn, p.B, idx);
+}
+
+// ---- host -------------------------------------------------------------------
+
+gp_status qfail(gp_status st, const std::string &msg) {
+  set_last_error(msg);
+  return st;
+}
+
+// J_0 .. J_n at x > 0 (n <= 64), to about 1e-15 absolute.  For x >= 25 and
+// x > 2 n: Hankel's asymptotic expansion of J_0 and J_1 (its terms fall
+// below 1e-17 long before they start to grow at k ~ 2x), then the upward
+// recurrence J_{k+1} = (2k / x) J_k - J_{k-1}, stable while k < x.  Else
+// Miller's method: the same recurrence run downward from an order far above
+// x and n with an arbitrary start, normalised by J_0 + 2 (J_2 + J_4 + ...)
+// = 1.  (The C++ library's cyl_bessel_j loses about 1e-11 relative at
+// arguments of several hundred, which the transform matrices of wide grids
+// reach.)
+void bessel_j_orders(int n, double x, double *J) {
+  if (x >= 25.0 && x > 2.0 * n) {
+    double P[2], Q[2];
+    for (int nu = 0; nu < 2; ++nu) {
+      const double mu = 4.0 * nu * nu;
+      double term = 1.0, prev = 2.0;
+      P[nu] = 1.0;
+      Q[nu] = 0.0;
+      for (int k = 1; k < 80; ++k) {
+        term *= (mu - double(2 * k - 1) * (2 * k - 1)) / (8.0 * k * x);
+        if (std::fabs(term) > std::fabs(prev)) break;  // the series turns
+        prev = term;
+        if (k % 2 == 0)
+          P[nu] += (k / 2) % 2 ? -term : term;
+        else
+          Q[nu] += ((k - 1) / 2) % 2 ? -term : term;
+        if (std::fabs(term) < 1e-17) break;
+      }
+    }
+    // chi_0 = x - pi/4, chi_1 = chi_0 - pi/2
+    const double c = std::cos(x), s = std::sin(x);
+    const double r2 = std::sqrt(0.5);
+    const double cq = (c + s) * r2, sq = (s - c) * r2;  // cos, sin of x - pi/4
+    const double A = std::sqrt(2.0 / (kPi * x));
+    J[0] = A * (P[0] * cq - Q[0] * sq);
+    if (n >= 1) J[1] = A * (P[1] * sq + Q[1] * cq);
+    for (int k = 1; k < n; ++k) J[k + 1] = (2.0 * k / x) * J[k] - J[k - 1];
+    return;
+  }
+  const int top = 2 * ((std::max(n, int(x)) + 60) / 2);  // even start order
+  double fk1 = 0.0, fk = 1e-30, sum = 0.0;
+  for (int i = 0; i <= n; ++i) J[i] = 0.0;
+  for (int k = top; k >= 1; --k) {
+    // fk = f_k, fk1 = f_{k+1}  ->  f_{k-1}
+    const double fm = (2.0 * k / x) * fk - fk1;
+    if (k <= n) J[k] = fk;
+    if (k % 2 == 0) sum += 2.0 * fk;
+    fk1 = fk;
+    fk = fm;
+    if (std::fabs(fk) > 1e250) {  // rescale everything held so far
+      fk *= 1e-250;
+      fk1 *= 1e-250;
+      sum *= 1e-250;
+      for (int i = 0; i <= n; ++i) J[i] *= 1e-250;
+    }
+  }
+  J[0] = fk;
+  sum += fk;
+  for (int i = 0; i <= n; ++i) J[i] /= sum;
+}
+
+// J_p for any integer |p| <= 64: J_{-p} = (-1)^p J_p
+double bessel_j(int p, double x) {
+  double J[66];
+  const int a = p < 0 ? -p : p;
+  bessel_j_orders(a, x, J);
+  return (p < 0 && (a % 2)) ? -J[a] : J[a];
+}
+
+// The first n positive zeros of J_m: sign changes on a fine scan from x = m
+// (J_m has none below), each refined by bisection to the nearest double.
+std::vector<double> bessel_zeros(int m, int n) {
+  std::vector<double> z;
+  const double h = 0.05;
+  double a = std::max(1e-6, double(m));
+  double fa = bessel_j(m, a);
+  while (int(z.size()) < n) {
+    const double b = a + h;
+    const double fb = bessel_j(m, b);
+    if (fa == 0.0) {
+      z.push_back(a);
+    } else if ((fa < 0) != (fb < 0)) {
+      // bisect down to adjacent doubles, then keep the end with the smaller |J_m|
+      double lo = a, hi = b, flo = fa, fhi = fb;
+      for (int it = 0; it < 200; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        const double fm = bessel_j(m, mid);
+        if (fm == 0.0) {
+          lo = hi = mid;
+          flo = fhi = 0.0;
+          break;
+        }
+        if ((fm < 0) == (flo < 0)) {
+          lo = mid;
+          flo = fm;
+        } else {
+          hi = mid;
+          fhi = fm;
+        }
+      }
+      z.push_back(std::fabs(flo) <= std::fabs(fhi) ? lo : hi);
+    }
+    a = b;
+    fa = fb;
+  }
+  return z;
+}
+
+// In-place inverse of an n x n row-major matrix (Gauss-Jordan, partial
+// pivoting); false if singular.
+bool invert(std::vector<double> &a, int n) {
+  std::vector<double> inv(size_t(n) * n, 0.0);
+  for (int i = 0; i < n; ++i) inv[size_t(i) * n + i] = 1.0;
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < n; ++r)
+      if (std::fabs(a[size_t(r) * n + c]) > std::fabs(a[size_t(piv) * n + c])) piv = r;
+    if (a[size_t(piv) * n + c] == 0.0) return false;
+    if (piv != c)
+      for (int k = 0; k < n; ++k) {
+        std::swap(a[size_t(c) * n + k], a[size_t(piv) * n + k]);
+        std::swap(inv[size_t(c) * n + k], inv[size_t(piv) * n + k]);
+      }
+    const double d = 1.0 / a[size_t(c) * n + c];
+    for (int k = 0; k < n; ++k) {
+      a[size_t(c) * n + k] *= d;
+      inv[size_t(c) * n + k] *= d;
+    }
+    for (int r = 0; r < n; ++r) {
+      if (r == c) continue;
+      const double f = a[size_t(r) * n + c];
+      if (f == 0.0) continue;
+      for (int k = 0; k < n; ++k) {
+        a[size_t(r) * n + k] -= f * a[size_t(c) * n + k];
+        inv[size_t(r) * n + k] -= f * inv[size_t(c) * n + k];
+      }
+    }
+  }
+  a.swap(inv);
+  return true;
+}
+
+// k_i = alpha_{m,i} / R, R = nr dr: mode m's spectral grid
+std::vector<double> spectral_kr(int m, int nr, double dr) {
+  std::vector<double> k = bessel_zeros(m, nr);
+  for (double &v : k) v /= nr * dr;
+  return k;
+}
+
+// The backward matrix of Hankel order p on the grid k: M[j][i] = J_p(k_i r_j)
+// (row-major nr x nr, r_j = (j + 1/2) dr).
+std::vector<double> backward_hankel(int p, const std::vector<double> &k, int nr, double dr) {
+  std::vector<double> M(size_t(nr) * nr);
+  for (int j = 0; j < nr; ++j)
+    for (int i = 0; i < nr; ++i) M[size_t(j) * nr + i] = bessel_j(p, k[i] * (j + 0.5) * dr);
+  return M;
+}
+
+}  // namespace
+}  // namespace galpic
+
+using namespace galpic;
+
+enum {
+  kQReal = 10,  // E_r E_t E_z B_r B_t B_z J_r J_t J_z rho
+  kQSpec = 11,  // E_+ E_- E_z B_+ B_- B_z J_+ J_- J_z rho (two buffers)
+  kQScr = 6
+};
+
+struct gp_qc_ctx {
+  gp_qc_desc d{};
+  size_t real_size = 8;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::vector<void *> allocs;
+  void *real[kQReal] = {};
+  void *spec[kQSpec] = {};
+  void *scr[kQScr] = {};
+  void *coef[6] = {};
+  double *kr_d = nullptr;  // [mode][k_r], double
+  void *kr_t = nullptr;    // the same in the real type
+  void *fmat = nullptr, *bmat = nullptr;
+  void *tw = nullptr;
+  void *tab = nullptr;     // device tables (FieldSet, QcSet)
+  int rho_old = 9;         // spec slot of rho^n (the other holds rho^{n+1})
+  double vgal = 0.0;
+  bool coef_ready = false;
+};
+
+namespace {
+
+// device table layout (byte offsets)
+enum { kFsFwdEB = 0, kFsFwdSrc, kFsInvEB, kNFs };
+enum { kQsEB = 0, kQsJ = 2, kQsRho0 = 3, kQsRho1 = 4, kQsBwdEB = 5, kNQs = 7 };
+
+size_t field_bytes(const gp_qc_ctx *c) {
+  return size_t(c->d.nmodes) * c->d.nz * c->d.nr * 2 * c->real_size;
+}
+
+gp_status qalloc(gp_qc_ctx *c, size_t bytes, void **out) {
+  void *p = nullptr;
+  if (hipMalloc(&p, std::max<size_t>(bytes, 256)) != hipSuccess) {
+    (void)hipGetLastError();
+    return qfail(GP_ERR_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+  }
+  c->allocs.push_back(p);
+  *out = p;
+  return GP_OK;
+}
+
+#define QTRY(expr)                \
+  do {                            \
+    gp_status st_ = (expr);       \
+    if (st_ != GP_OK) return st_; \
+  } while (0)
+
+gp_status qcheck(const char *what) {
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return qfail(GP_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+  return GP_OK;
+}
+
+template <typename T>
+const FieldSet *fs_at(gp_qc_ctx *c, int k) {
+  return reinterpret_cast<const FieldSet *>(c->tab) + k;
+}
+template <typename T>
+const QcSet *qs_at(gp_qc_ctx *c, int k) {
+  return reinterpret_cast<const QcSet *>(static_cast<char *>(c->tab) + kNFs * sizeof(FieldSet)) +
+         k;
+}
+
+template <typename T>
+void z_transform(gp_qc_ctx *c, int fs, int nf, bool inverse) {
+  int lz = 0;
+  while ((1 << lz) < c->d.nz) ++lz;
+  launch_c2c_lines<T>(fs_at<T>(c, fs), 1, nf, lz, c->d.nr, c->d.nr,
+                      int64_t(c->d.nz) * c->d.nr, c->d.nmodes, inverse,
+                      static_cast<const Cx<T> *>(c->tw), c->stream);
+}
+
+template <typename T, int KIND>
+void hankel(gp_qc_ctx *c, int qs, int nsets, const void *mats) {
+  const dim3 grid(unsigned((c->d.nz + kRows - 1) / kRows), unsigned(c->d.nmodes),
+                  unsigned(nsets));
+  // at most kRows * 512 * 16 bytes = 64 KiB, the default dynamic LDS limit
+  const size_t lds = size_t(kRows) * c->d.nr * sizeof(Cx<T>);
+  hipLaunchKernelGGL((k_qc_hankel<T, KIND>), grid, dim3(kQThreads), lds, c->stream,
+                     qs_at<T>(c, qs), static_cast<const T *>(mats), c->d.nz, c->d.nr);
+}
+
+template <typename T>
+void enqueue_sources_fwd(gp_qc_ctx *c) {
+  z_transform<T>(c, kFsFwdSrc, 4, false);
+  hankel<T, kVecFwd>(c, kQsJ, 1, c->fmat);
+  hankel<T, kScalarFwd>(c, c->rho_old == 9 ? kQsRho1 : kQsRho0, 1, c->fmat);
+}
+
+template <typename T>
+void enqueue_update(gp_qc_ctx *c) {
+  QcUpd<T> p;
+  for (int a = 0; a < 3; ++a) {
+    p.E[a] = static_cast<Cx<T> *>(c->spec[a]);
+    p.B[a] = static_cast<Cx<T> *>(c->spec[3 + a]);
+    p.J[a] = static_cast<const Cx<T> *>(c->spec[6 + a]);
+  }
+  p.rho_old = static_cast<const Cx<T> *>(c->spec[c->rho_old]);
+  p.rho_new = static_cast<const Cx<T> *>(c->spec[c->rho_old == 9 ? 10 : 9]);
+  for (int k = 0; k < 6; ++k) p.coef[k] = static_cast<const Cx<T> *>(c->coef[k]);
+  p.kr = static_cast<const T *>(c->kr_t);
+  const int64_t n = int64_t(c->d.nmodes) * c->d.nz * c->d.nr;
+  hipLaunchKernelGGL((k_qc_update<T>), dim3(unsigned((n + 255) / 256)), dim3(256), 0, c->stream,
+                     p, c->d.nmodes, c->d.nz, c->d.nr, T(2.0 * kPi / (c->d.nz * c->d.dz)));
+  c->rho_old = c->rho_old == 9 ? 10 : 9;
+}
+
+template <typename T>
+void enqueue_fields_inv(gp_qc_ctx *c) {
+  hankel<T, kVecBwd>(c, kQsBwdEB, 2, c->bmat);
+  z_transform<T>(c, kFsInvEB, 6, true);
+}
+
+template <typename T>
+void enqueue_fields_fwd(gp_qc_ctx *c) {
+  z_transform<T>(c, kFsFwdEB, 6, false);
+  hankel<T, kVecFwd>(c, kQsEB, 2, c->fmat);
+}
+
+template <typename F>
+gp_status qdispatch(gp_qc_ctx *c, F &&f) {
+  if (c->d.precision == GP_FP64)
+    f(double{});
+  else
+    f(float{});
+  return qcheck("kernel launch");
+}
+
+gp_status qcheck_ctx(gp_qc_ctx *c) {
+  if (!c) return qfail(GP_ERR_ARG, "context is NULL");
+  return GP_OK;
+}
+
+// transform matrices (transposed, real type) and k_r of every mode
+template <typename T>
+gp_status build_transforms(gp_qc_ctx *c) {
+  const int nr = c->d.nr, nm = c->d.nmodes;
+  const size_t mat = size_t(nr) * nr;
+  std::vector<T> fh(size_t(nm) * 3 * mat), bh(size_t(nm) * 3 * mat), kt(size_t(nm) * nr);
+  std::vector<double> kd(size_t(nm) * nr);
+  for (int m = 0; m < nm; ++m) {
+    const std::vector<double> k = spectral_kr(m, nr, c->d.dr);
+    for (int i = 0; i < nr; ++i) {
+      kd[size_t(m) * nr + i] = k[i];
+      kt[size_t(m) * nr + i] = T(k[i]);
+    }
+    for (int slot = 0; slot < 3; ++slot) {
+      const int p = m - 1 + slot;
+      const std::vector<double> M = backward_hankel(p, k, nr, c->d.dr);
+      std::vector<double> Minv = M;
+      if (!invert(Minv, nr))
+        return qfail(GP_ERR_ARG, "the Hankel matrix of order " + std::to_string(p) +
+                                     " is singular for this nr");
+      T *F = fh.data() + (size_t(m) * 3 + slot) * mat;
+      T *Bk = bh.data() + (size_t(m) * 3 + slot) * mat;
+      // forward A = Minv (spectral i <- radial j): AT[j][i] = Minv[i][j]
+      // backward A = M / nz (radial j <- spectral i): AT[i][j] = M[j][i] / nz
+      for (int j = 0; j < nr; ++j)
+        for (int i = 0; i < nr; ++i) {
+          F[size_t(j) * nr + i] = T(Minv[size_t(i) * nr + j]);
+          Bk[size_t(i) * nr + j] = T(M[size_t(j) * nr + i] / c->d.nz);
+        }
+    }
+  }
+  const size_t mbytes = fh.size() * sizeof(T);
+  QTRY(qalloc(c, mbytes, &c->fmat));
+  QTRY(qalloc(c, mbytes, &c->bmat));
+  void *p = nullptr;
+  QTRY(qalloc(c, kd.size() * sizeof(double), &p));
+  c->kr_d = static_cast<double *>(p);
+  QTRY(qalloc(c, kt.size() * sizeof(T), &c->kr_t));
+  if (hipMemcpyAsync(c->fmat, fh.data(), mbytes, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+      hipMemcpyAsync(c->bmat, bh.data(), mbytes, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+      hipMemcpyAsync(c->kr_d, kd.data(), kd.size() * sizeof(double), hipMemcpyHostToDevice,
+                     c->stream) != hipSuccess ||
+      hipMemcpyAsync(c->kr_t, kt.data(), kt.size() * sizeof(T), hipMemcpyHostToDevice,
+                     c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess)
+    return qfail(GP_ERR_HIP, "transform upload failed");
+  return GP_OK;
+}
+
+gp_status build_tables(gp_qc_ctx *c) {
+  std::vector<unsigned char> host(kNFs * sizeof(FieldSet) + kNQs * sizeof(QcSet), 0);
+  FieldSet *fs = reinterpret_cast<FieldSet *>(host.data());
+  QcSet *qs = reinterpret_cast<QcSet *>(host.data() + kNFs * sizeof(FieldSet));
+  for (int f = 0; f < 6; ++f) {
+    fs[kFsFwdEB].in[f] = c->real[f];
+    fs[kFsFwdEB].out[f] = c->scr[f];
+    fs[kFsInvEB].in[f] = c->scr[f];
+    fs[kFsInvEB].out[f] = c->real[f];
+  }
+  for (int f = 0; f < 4; ++f) {
+    fs[kFsFwdSrc].in[f] = c->real[6 + f];
+    fs[kFsFwdSrc].out[f] = c->scr[f];
+  }
+  for (int v = 0; v < 2; ++v)
+    for (int a = 0; a < 3; ++a) {
+      qs[kQsEB + v].in[a] = c->scr[3 * v + a];
+      qs[kQsEB + v].out[a] = c->spec[3 * v + a];
+      qs[kQsBwdEB + v].in[a] = c->spec[3 * v + a];
+      qs[kQsBwdEB + v].out[a] = c->scr[3 * v + a];
+    }
+  for (int a = 0; a < 3; ++a) {
+    qs[kQsJ].in[a] = c->scr[a];
+    qs[kQsJ].out[a] = c->spec[6 + a];
+  }
+  // rho^{n+1} into slot 9 (parity 0) or 10 (parity 1)
+  qs[kQsRho0].in[0] = c->scr[3];
+  qs[kQsRho0].out[0] = c->spec[9];
+  qs[kQsRho1].in[0] = c->scr[3];
+  qs[kQsRho1].out[0] = c->spec[10];
+  QTRY(qalloc(c, host.size(), &c->tab));
+  if (hipMemcpyAsync(c->tab, host.data(), host.size(), hipMemcpyHostToDevice, c->stream) !=
+          hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess)
+    return qfail(GP_ERR_HIP, "table upload failed");
+  return GP_OK;
+}
+
+// which -> buffer
+void *slot_of(gp_qc_ctx *c, int which) {
+  if (which >= GP_QC_ER && which <= GP_QC_RHO) return c->real[which - GP_QC_ER];
+  if (which >= GP_QC_E_PLUS && which <= GP_QC_J_Z_HAT) return c->spec[which - GP_QC_E_PLUS];
+  if (which == GP_QC_RHO_HAT_OLD) return c->spec[c->rho_old];
+  if (which == GP_QC_RHO_HAT_NEW) return c->spec[c->rho_old == 9 ? 10 : 9];
+  if (which >= GP_QC_COEF0 && which <= GP_QC_COEF5) return c->coef[which - GP_QC_COEF0];
+  return nullptr;
+}
+
+bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
+
+}  // namespace
+
+gp_status gp_qc_init(const gp_qc_desc *d, void *hip_stream, gp_qc_ctx **out) {
+  if (!d || !out) return qfail(GP_ERR_ARG, "NULL argument");
+  *out = nullptr;
+  if (!is_pow2(d->nz) || d->nz < 8 || d->nz > 1024)
+    return qfail(GP_ERR_ARG, "nz must be a power of two in [8, 1024]");
+  if (d->nr < 4 || d->nr > 2 * kQThreads)
+    return qfail(GP_ERR_ARG, "nr must lie in [4, 512]");
+  if (d->nmodes < 1 || d->nmodes > 8) return qfail(GP_ERR_ARG, "nmodes must lie in [1, 8]");
+  if (!(d->dz > 0) || !(d->dr > 0) || !(d->dt > 0) || !std::isfinite(d->dz) ||
+      !std::isfinite(d->dr) || !std::isfinite(d->dt))
+    return qfail(GP_ERR_ARG, "dz, dr, dt must be positive and finite");
+  if (d->precision != GP_FP64 && d->precision != GP_MIXED)
+    return qfail(GP_ERR_ARG, "precision must be GP_FP64 or GP_MIXED");
+  gp_qc_ctx *c = new gp_qc_ctx();
+  c->d = *d;
+  c->real_size = d->precision == GP_FP64 ? 8 : 4;
+  auto bail = [&](gp_status st) {
+    std::string keep = gp_last_error();
+    gp_qc_destroy(c);
+    set_last_error(keep);
+    return st;
+  };
+  if (hip_stream) {
+    c->stream = static_cast<hipStream_t>(hip_stream);
+  } else {
+    if (hipStreamCreate(&c->stream) != hipSuccess)
+      return bail(qfail(GP_ERR_HIP, "hipStreamCreate failed"));
+    c->own_stream = true;
+  }
+  const size_t fb = field_bytes(c);
+  for (auto &p : c->real) {
+    gp_status st = qalloc(c, fb, &p);
+    if (st) return bail(st);
+    if (hipMemsetAsync(p, 0, fb, c->stream) != hipSuccess)
+      return bail(qfail(GP_ERR_HIP, "clear failed"));
+  }
+  for (auto &p : c->spec) {
+    gp_status st = qalloc(c, fb, &p);
+    if (st) return bail(st);
+    if (hipMemsetAsync(p, 0, fb, c->stream) != hipSuccess)
+      return bail(qfail(GP_ERR_HIP, "clear failed"));
+  }
+  for (auto &p : c->scr) {
+    gp_status st = qalloc(c, fb, &p);
+    if (st) return bail(st);
+  }
+  for (auto &p : c->coef) {
+    gp_status st = qalloc(c, fb, &p);
+    if (st) return bail(st);
+  }
+  {
+    const size_t twb = 1024 * 2 * c->real_size;
+    gp_status st = qalloc(c, twb, &c->tw);
+    if (st) return bail(st);
+    std::vector<char> host(twb);
+    if (d->precision == GP_FP64)
+      fill_twiddles<double>(reinterpret_cast<Cx<double> *>(host.data()));
+    else
+      fill_twiddles<float>(reinterpret_cast<Cx<float> *>(host.data()));
+    if (hipMemcpyAsync(c->tw, host.data(), twb, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
+      return bail(qfail(GP_ERR_HIP, "twiddle upload failed"));
+  }
+  gp_status st = d->precision == GP_FP64 ? build_transforms<double>(c)
+                                         : build_transforms<float>(c);
+  if (st) return bail(st);
+  st = build_tables(c);
+  if (st) return bail(st);
+  st = gp_qc_set_v_gal(c, 0.0);
+  if (st) return bail(st);
+  *out = c;
+  return GP_OK;
+}
+
+gp_status gp_qc_set_v_gal(gp_qc_ctx *c, double vz) {
+  QTRY(qcheck_ctx(c));
+  if (!std::isfinite(vz) || std::fabs(vz) >= 1.0)
+    return qfail(GP_ERR_ARG, "|v_gal| must be finite and below c");
+  // largest |k_z v_gal| dt over the non-Nyquist planes
+  const double kzmax = 2.0 * kPi * double(c->d.nz / 2 - 1) / (c->d.nz * c->d.dz);
+  if (std::fabs(vz) * kzmax * c->d.dt >= 2.0 * kPi * (1.0 - 1e-6))
+    return qfail(GP_ERR_UNSTABLE, "some mode has |k_z v_gal| dt >= 2 pi");
+  c->vgal = vz;
+  // per mode: the Cartesian coefficient kernel with k_z on its "y" axis and
+  // this mode's k_r on its "z" axis (v_gal along "y")
+  std::vector<double> kt(1 + c->d.nz + c->d.nr);
+  kt[0] = 0.0;
+  for (int i = 0; i < c->d.nz; ++i) {
+    const int s = i < c->d.nz / 2 ? i : i - c->d.nz;
+    kt[1 + i] = 2.0 * kPi * double(s) / (c->d.nz * c->d.dz);
+  }
+  void *ktab = nullptr;
+  QTRY(qalloc(c, kt.size() * sizeof(double) * c->d.nmodes, &ktab));
+  std::vector<double> all(kt.size() * c->d.nmodes);
+  std::vector<double> krh(size_t(c->d.nmodes) * c->d.nr);
+  if (hipMemcpy(krh.data(), c->kr_d, krh.size() * sizeof(double), hipMemcpyDeviceToHost) !=
+      hipSuccess)
+    return qfail(GP_ERR_HIP, "k_r download failed");
+  for (int m = 0; m < c->d.nmodes; ++m) {
+    std::copy(kt.begin(), kt.end(), all.begin() + m * kt.size());
+    for (int i = 0; i < c->d.nr; ++i)
+      all[m * kt.size() + 1 + c->d.nz + i] = krh[size_t(m) * c->d.nr + i];
+  }
+  if (hipMemcpyAsync(ktab, all.data(), all.size() * sizeof(double), hipMemcpyHostToDevice,
+                     c->stream) != hipSuccess)
+    return qfail(GP_ERR_HIP, "k table upload failed");
+  const int64_t per = int64_t(c->d.nz) * c->d.nr;
+  for (int m = 0; m < c->d.nmodes; ++m) {
+    RunGeom g{};
+    g.nx = 1;
+    g.ny = c->d.nz;
+    g.nz = 2 * (c->d.nr - 1);  // unused by the kernel beyond nzh
+    g.nzh = c->d.nr;
+    g.dt = c->d.dt;
+    g.vgal[0] = 0.0;
+    g.vgal[1] = vz;
+    g.vgal[2] = 0.0;
+    g.nmode = per;
+    CoefPtrs cp;
+    for (int k = 0; k < 6; ++k)
+      cp.c[k] = static_cast<char *>(c->coef[k]) + size_t(m) * per * 2 * c->real_size;
+    const double *kd = static_cast<const double *>(ktab) + m * kt.size();
+    if (c->d.precision == GP_FP64)
+      launch_coefficients<double>(g, kd, cp, c->stream);
+    else
+      launch_coefficients<float>(g, kd, cp, c->stream);
+  }
+  QTRY(qcheck("coefficients"));
+  if (hipStreamSynchronize(c->stream) != hipSuccess)
+    return qfail(GP_ERR_HIP, "stream synchronize failed");
+  // the k table is not needed after the coefficients
+  (void)hipFree(ktab);
+  c->allocs.erase(std::remove(c->allocs.begin(), c->allocs.end(), ktab), c->allocs.end());
+  c->coef_ready = true;
+  return GP_OK;
+}
+
+gp_status gp_qc_write(gp_qc_ctx *c, int which, const void *src) {
+  QTRY(qcheck_ctx(c));
+  void *dst = slot_of(c, which);
+  if (!dst || which >= GP_QC_COEF0) return qfail(GP_ERR_ARG, "bad field selector");
+  if (!src) return qfail(GP_ERR_ARG, "source is NULL");
+  if (hipMemcpyAsync(dst, src, field_bytes(c), hipMemcpyDefault, c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess)
+    return qfail(GP_ERR_HIP, "write failed");
+  return GP_OK;
+}
+
+gp_status gp_qc_read(gp_qc_ctx *c, int which, void *dst) {
+  QTRY(qcheck_ctx(c));
+  void *src = slot_of(c, which);
+  if (!src) return qfail(GP_ERR_ARG, "bad field selector");
+  if (!dst) return qfail(GP_ERR_ARG, "destination is NULL");
+  if (hipMemcpyAsync(dst, src, field_bytes(c), hipMemcpyDefault, c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess)
+    return qfail(GP_ERR_HIP, "read failed");
+  return GP_OK;
+}
+
+gp_status gp_qc_fields_fwd(gp_qc_ctx *c) {
+  QTRY(qcheck_ctx(c));
+  return qdispatch(c, [&](auto t) { enqueue_fields_fwd<decltype(t)>(c); });
+}
+
+gp_status gp_qc_sources_fwd(gp_qc_ctx *c) {
+  QTRY(qcheck_ctx(c));
+  return qdispatch(c, [&](auto t) { enqueue_sources_fwd<decltype(t)>(c); });
+}
+
+gp_status gp_qc_init_rho(gp_qc_ctx *c) {
+  QTRY(qcheck_ctx(c));
+  // transform rho into rho^{n+1}, then make it rho^n
+  QTRY(qdispatch(c, [&](auto t) {
+    using T = decltype(t);
+    z_transform<T>(c, kFsFwdSrc, 4, false);
+    hankel<T, kScalarFwd>(c, c->rho_old == 9 ? kQsRho1 : kQsRho0, 1, c->fmat);
+  }));
+  c->rho_old = c->rho_old == 9 ? 10 : 9;
+  return GP_OK;
+}
+
+gp_status gp_qc_update(gp_qc_ctx *c) {
+  QTRY(qcheck_ctx(c));
+  return qdispatch(c, [&](auto t) { enqueue_update<decltype(t)>(c); });
+}
+
+gp_status gp_qc_fields_inv(gp_qc_ctx *c) {
+  QTRY(qcheck_ctx(c));
+  return qdispatch(c, [&](auto t) { enqueue_fields_inv<decltype(t)>(c); });
+}
+
+gp_status gp_qc_step(gp_qc_ctx *c, int nsteps) {
+  QTRY(qcheck_ctx(c));
+  if (nsteps < 0) return qfail(GP_ERR_ARG, "nsteps must be >= 0");
+  return qdispatch(c, [&](auto t) {
+    using T = decltype(t);
+    for (int s = 0; s < nsteps; ++s) {
+      enqueue_sources_fwd<T>(c);
+      enqueue_update<T>(c);
+      enqueue_fields_inv<T>(c);
+    }
+  });
+}
+
+gp_status gp_qc_synchronize(gp_qc_ctx *c) {
+  QTRY(qcheck_ctx(c));
+  if (hipStreamSynchronize(c->stream) != hipSuccess)
+    return qfail(GP_ERR_HIP, "stream synchronize failed");
+  return GP_OK;
+}
+
+gp_status gp_qc_destroy(gp_qc_ctx *c) {
+  if (!c) return GP_OK;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  for (void *p : c->allocs) (void)hipFree(p);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+  return GP_OK;
+}
+
+gp_status gp_qc_wavenumbers(int m, int nr, double dr, double *kr) {
+  if (!kr) return qfail(GP_ERR_ARG, "kr is NULL");
+  if (m < 0 || m > 63 || nr < 1 || nr > 512 || !(dr > 0) || !std::isfinite(dr))
+    return qfail(GP_ERR_ARG, "m must lie in [0, 63], nr in [1, 512], dr positive and finite");
+  const std::vector<double> k = spectral_kr(m, nr, dr);
+  std::copy(k.begin(), k.end(), kr);
+  return GP_OK;
+}
+
+gp_status gp_qc_hankel_matrix(int p, int m, int nr, double dr, int forward, double *out) {
+  if (!out) return qfail(GP_ERR_ARG, "out is NULL");
+  if (m < 0 || m > 63 || p < -64 || p > 64 || nr < 1 || nr > 512 || !(dr > 0) ||
+      !std::isfinite(dr))
+    return qfail(GP_ERR_ARG,
+                 "m must lie in [0, 63], p in [-64, 64], nr in [1, 512], dr positive and finite");
+  std::vector<double> M = backward_hankel(p, spectral_kr(m, nr, dr), nr, dr);
+  if (forward && !invert(M, nr))
+    return qfail(GP_ERR_ARG, "the Hankel matrix of order " + std::to_string(p) +
+                                 " is singular for this nr");
+  std::copy(M.begin(), M.end(), out);
+  return GP_OK;
+}

@@ -31,7 +31,15 @@ EXPORTS = ["gp_init_grid", "gp_set_v_gal", "gp_set_current_correction", "gp_bind
            "gp_write_field", "gp_field_energy", "gp_last_graph_ms", "gp_synchronize",
            "gp_stage_timing", "gp_stage_times", "gp_stage_name", "gp_sort_count",
            "gp_run", "gp_destroy", "gp_last_error", "gp_btd_configure", "gp_btd_record",
-           "gp_btd_particles"]
+           "gp_btd_particles", "gp_qc_init", "gp_qc_set_v_gal", "gp_qc_write", "gp_qc_read",
+           "gp_qc_fields_fwd", "gp_qc_sources_fwd", "gp_qc_init_rho", "gp_qc_update",
+           "gp_qc_fields_inv", "gp_qc_step", "gp_qc_synchronize", "gp_qc_destroy",
+           "gp_qc_wavenumbers", "gp_qc_hankel_matrix"]
+QC_FIELDS = ["ER", "ET", "EZ", "BR", "BT", "BZ", "JR", "JT", "JZ", "RHO",
+             "E_PLUS", "E_MINUS", "E_Z_HAT", "B_PLUS", "B_MINUS", "B_Z_HAT",
+             "J_PLUS", "J_MINUS", "J_Z_HAT", "RHO_HAT_OLD", "RHO_HAT_NEW",
+             "COEF0", "COEF1", "COEF2", "COEF3", "COEF4", "COEF5"]
+QC_FIELD = {name: i for i, name in enumerate(QC_FIELDS)}
 GP_N_STAGES = 13
 
 
@@ -41,6 +49,12 @@ class GridDesc(ctypes.Structure):
                 ("dt", ctypes.c_double), ("shape_order", ctypes.c_int),
                 ("precision", ctypes.c_int), ("tile", ctypes.c_int * 3),
                 ("resort_div", ctypes.c_int), ("stencil", ctypes.c_int * 3)]
+
+
+class QcDesc(ctypes.Structure):
+    _fields_ = [("nz", ctypes.c_int), ("nr", ctypes.c_int), ("nmodes", ctypes.c_int),
+                ("dz", ctypes.c_double), ("dr", ctypes.c_double), ("dt", ctypes.c_double),
+                ("precision", ctypes.c_int)]
 
 
 class ParticlesC(ctypes.Structure):
@@ -99,6 +113,20 @@ def load(path=LIB_PATH):
         "gp_btd_configure": [vp, i32, i32, dbl, dbl, dbl, vp],
         "gp_btd_record": [vp],
         "gp_btd_particles": [vp, i32, i32, vp, vp, vp],
+        "gp_qc_init": [ctypes.POINTER(QcDesc), vp, ctypes.POINTER(vp)],
+        "gp_qc_set_v_gal": [vp, dbl],
+        "gp_qc_write": [vp, i32, vp],
+        "gp_qc_read": [vp, i32, vp],
+        "gp_qc_fields_fwd": [vp],
+        "gp_qc_sources_fwd": [vp],
+        "gp_qc_init_rho": [vp],
+        "gp_qc_update": [vp],
+        "gp_qc_fields_inv": [vp],
+        "gp_qc_step": [vp, i32],
+        "gp_qc_synchronize": [vp],
+        "gp_qc_destroy": [vp],
+        "gp_qc_wavenumbers": [i32, i32, dbl, vp],
+        "gp_qc_hankel_matrix": [i32, i32, i32, dbl, i32, vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -420,3 +448,85 @@ def particles_from_inputs(inputs, cfg, precision, with_ids=True, device="cuda"):
                          device=device)
     return Particles(GP_MIXED, cfg.q, cfg.m, cfg.w, inputs["u"], cell=inputs["cell"],
                      offset=inputs["offset"], ids=ids, device=device)
+
+
+def qc_wavenumbers(m, nr, dr):
+    """Spectral k_r of azimuthal mode m (host only, no GPU)."""
+    lib = load()
+    out = np.empty(nr, dtype=np.float64)
+    _check(lib, lib.gp_qc_wavenumbers(int(m), int(nr), float(dr), out.ctypes.data))
+    return out
+
+
+def qc_hankel_matrix(p, m, nr, dr, forward=False):
+    """Backward matrix M[j][i] = J_p(k_i r_j) of mode m's grid, or its
+    inverse (host only, no GPU)."""
+    lib = load()
+    out = np.empty((nr, nr), dtype=np.float64)
+    _check(lib, lib.gp_qc_hankel_matrix(int(p), int(m), int(nr), float(dr), int(bool(forward)),
+                                        out.ctypes.data))
+    return out
+
+
+class QcContext:
+    """One gp_qc_ctx: the quasi-cylindrical field solve of nmodes azimuthal
+    modes on an nz x nr (z, r) grid.  Fields are complex numpy arrays
+    [mode][z][r]."""
+
+    def __init__(self, nz, nr, nmodes, dz, dr, dt, precision, stream=None):
+        self.lib = load()
+        _init_torch_first()
+        d = QcDesc(nz, nr, nmodes, dz, dr, dt, precision)
+        self.shape = (nmodes, nz, nr)
+        self.precision = precision
+        self.cplx = np.complex128 if precision == GP_FP64 else np.complex64
+        handle = ctypes.c_void_p()
+        _check(self.lib, self.lib.gp_qc_init(ctypes.byref(d), stream, ctypes.byref(handle)))
+        self.h = handle
+
+    def close(self):
+        if self.h:
+            self.lib.gp_qc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _call(self, name, *args):
+        _check(self.lib, getattr(self.lib, name)(self.h, *args))
+
+    def set_v_gal(self, vz):
+        self._call("gp_qc_set_v_gal", float(vz))
+
+    def write(self, name, arr):
+        a = np.ascontiguousarray(np.broadcast_to(arr, self.shape), dtype=self.cplx)
+        self._call("gp_qc_write", QC_FIELD[name], a.ctypes.data)
+
+    def read(self, name):
+        out = np.empty(self.shape, dtype=self.cplx)
+        self._call("gp_qc_read", QC_FIELD[name], out.ctypes.data)
+        return out
+
+    def fields_fwd(self):
+        self._call("gp_qc_fields_fwd")
+
+    def sources_fwd(self):
+        self._call("gp_qc_sources_fwd")
+
+    def init_rho(self):
+        self._call("gp_qc_init_rho")
+
+    def update(self):
+        self._call("gp_qc_update")
+
+    def fields_inv(self):
+        self._call("gp_qc_fields_inv")
+
+    def step(self, nsteps=1):
+        self._call("gp_qc_step", int(nsteps))
+
+    def synchronize(self):
+        self._call("gp_qc_synchronize")

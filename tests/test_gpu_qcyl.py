@@ -1,0 +1,238 @@
+"""GPU parity of the quasi-cylindrical (azimuthal-mode) field solve against
+the oracle: the forward and backward mode transforms, the source
+transforms, the update coefficients, the mode update and a short history.
+
+Tolerances.  The backward transforms, the coefficients and the update are
+plain products and sums: relative L2 1e-12 (FP64) and 1e-5 (mixed).  The
+forward Hankel transform is the inverse of the backward matrix, whose
+condition number kappa reaches 1e4..1e7 for the order m-1 (and m+1) matrices
+on the J_m zero grid; two correctly rounded FP64 inverses (the library's
+Gauss-Jordan and the oracle's LAPACK one) differ there by about kappa * eps.
+The FP64 bar of anything that passes through a forward transform is
+therefore max(1e-12, 8 kappa eps), with kappa of the orders involved; the
+mixed bar stays 1e-5 (float rounding of the matrix and the data dominates).
+"""
+
+import numpy as np
+import pytest
+
+from oracle import cylindrical as cy
+from oracle.coefficients import galilean_psatd_coefficients
+from paper_1608_00215_amd import galpic as gp
+from tests.gpu_common import rel_l2, tol_for
+
+pytestmark = pytest.mark.gpu
+
+EPS64 = 2.0 ** -52
+PRECISIONS = [gp.GP_FP64, gp.GP_MIXED]
+# (nz, nr, nmodes, dz, dr, dt): "small" fits one workgroup row of outputs;
+# "wide" has nr above the 256 threads of a transform workgroup (two outputs
+# per thread, a ragged second half) and four z row groups per mode
+CASES = {"small": (16, 24, 3, 0.7, 0.5, 0.3), "wide": (32, 300, 2, 0.4, 0.25, 0.2)}
+
+
+def _ctx(case, precision):
+    nz, nr, nm, dz, dr, dt = CASES[case]
+    return gp.QcContext(nz, nr, nm, dz, dr, dt, precision), (nz, nr, nm, dz, dr, dt)
+
+
+def _cplx(rng, shape):
+    return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
+def _fwd_tol(precision, m, orders, nr, dr):
+    base = tol_for(precision)
+    if precision != gp.GP_FP64:
+        return base
+    kappa = max(np.linalg.cond(cy.backward_matrix(p, m, nr, dr)) for p in orders)
+    return max(base, 8.0 * kappa * EPS64)
+
+
+def _as_input(a, precision):
+    """The values the library actually holds (float in mixed precision)."""
+    return a.astype(np.complex64).astype(np.complex128) if precision == gp.GP_MIXED else a
+
+
+@pytest.mark.parametrize("case", list(CASES))
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_fields_forward(gpu_lib, case, precision):
+    ctx, (nz, nr, nm, dz, dr, dt) = _ctx(case, precision)
+    rng = np.random.default_rng(300)
+    names = ["ER", "ET", "EZ", "BR", "BT", "BZ"]
+    F = {n: _as_input(_cplx(rng, (nm, nz, nr)), precision) for n in names}
+    for n in names:
+        ctx.write(n, F[n])
+    ctx.fields_fwd()
+    got = {n: ctx.read(n) for n in ["E_PLUS", "E_MINUS", "E_Z_HAT", "B_PLUS", "B_MINUS",
+                                    "B_Z_HAT"]}
+    for m in range(nm):
+        for v, pre in (("E", 0), ("B", 3)):
+            ref = cy.to_spectral(tuple(F[names[pre + a]][m] for a in range(3)), m, dr, dz)
+            for a, (suf, p) in enumerate((("_PLUS", m + 1), ("_MINUS", m - 1),
+                                           ("_Z_HAT", m))):
+                tol = _fwd_tol(precision, m, [p], nr, dr)
+                err = rel_l2(got[v + suf][m], ref[a])
+                assert err <= tol, (v + suf, m, err, tol)
+    ctx.close()
+
+
+@pytest.mark.parametrize("case", list(CASES))
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_fields_inverse(gpu_lib, case, precision):
+    ctx, (nz, nr, nm, dz, dr, dt) = _ctx(case, precision)
+    rng = np.random.default_rng(301)
+    spec = ["E_PLUS", "E_MINUS", "E_Z_HAT", "B_PLUS", "B_MINUS", "B_Z_HAT"]
+    G = {n: _as_input(_cplx(rng, (nm, nz, nr)), precision) for n in spec}
+    for n in spec:
+        ctx.write(n, G[n])
+    ctx.fields_inv()
+    tol = tol_for(precision)
+    real = ["ER", "ET", "EZ", "BR", "BT", "BZ"]
+    got = {n: ctx.read(n) for n in real}
+    for m in range(nm):
+        for v in (0, 3):
+            ref = cy.from_spectral(tuple(G[spec[v + a]][m] for a in range(3)), m, dr, dz)
+            for a in range(3):
+                err = rel_l2(got[real[v + a]][m], ref[a])
+                assert err <= tol, (real[v + a], m, err)
+    ctx.close()
+
+
+@pytest.mark.parametrize("case", list(CASES))
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_sources_forward(gpu_lib, case, precision):
+    ctx, (nz, nr, nm, dz, dr, dt) = _ctx(case, precision)
+    rng = np.random.default_rng(302)
+    J = [_as_input(_cplx(rng, (nm, nz, nr)), precision) for _ in range(3)]
+    rho0 = _as_input(_cplx(rng, (nm, nz, nr)), precision)
+    rho1 = _as_input(_cplx(rng, (nm, nz, nr)), precision)
+    ctx.write("RHO", rho0)
+    ctx.init_rho()
+    for n, a in zip(("JR", "JT", "JZ"), J):
+        ctx.write(n, a)
+    ctx.write("RHO", rho1)
+    ctx.sources_fwd()
+    got = [ctx.read(n) for n in ("J_PLUS", "J_MINUS", "J_Z_HAT")]
+    old, new = ctx.read("RHO_HAT_OLD"), ctx.read("RHO_HAT_NEW")
+    for m in range(nm):
+        ref = cy.to_spectral(tuple(a[m] for a in J), m, dr, dz)
+        for a, p in enumerate((m + 1, m - 1, m)):
+            tol = _fwd_tol(precision, m, [p], nr, dr)
+            assert rel_l2(got[a][m], ref[a]) <= tol, ("J", a, m)
+        tol = _fwd_tol(precision, m, [m], nr, dr)
+        assert rel_l2(old[m], cy.scalar_to_spectral(rho0[m], m, dr, dz)) <= tol, ("rho^n", m)
+        assert rel_l2(new[m], cy.scalar_to_spectral(rho1[m], m, dr, dz)) <= tol, ("rho^n+1", m)
+    ctx.close()
+
+
+@pytest.mark.parametrize("vz", [0.0, -0.866])
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_coefficients(gpu_lib, precision, vz):
+    ctx, (nz, nr, nm, dz, dr, dt) = _ctx("small", precision)
+    ctx.set_v_gal(vz)
+    tol = tol_for(precision)
+    live = ~cy.held_mask(nz, nr)
+    for m in range(nm):
+        kz = cy.axis_kz(nz, dz)[:, None] * np.ones((1, nr))
+        kr = np.ones((nz, 1)) * cy.spectral_kr(m, nr, dr)[None, :]
+        coef = galilean_psatd_coefficients((kr, np.zeros_like(kr), kz), (0.0, 0.0, vz), dt)
+        for i, key in enumerate(("c_EE", "s", "c_BJ", "c_EJ", "c_R1", "c_R0")):
+            got = ctx.read(f"COEF{i}")[m]
+            assert rel_l2(got[live], coef[key][live]) <= tol, (key, m)
+    ctx.close()
+
+
+@pytest.mark.parametrize("case", list(CASES))
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_mode_update(gpu_lib, case, precision):
+    ctx, (nz, nr, nm, dz, dr, dt) = _ctx(case, precision)
+    vz = -0.9
+    ctx.set_v_gal(vz)
+    rng = np.random.default_rng(303)
+    names = ["E_PLUS", "E_MINUS", "E_Z_HAT", "B_PLUS", "B_MINUS", "B_Z_HAT",
+             "J_PLUS", "J_MINUS", "J_Z_HAT", "RHO_HAT_OLD", "RHO_HAT_NEW"]
+    X = {n: _as_input(_cplx(rng, (nm, nz, nr)), precision) for n in names}
+    for n in names:
+        ctx.write(n, X[n])
+    ctx.update()
+    tol = tol_for(precision)
+    got = [ctx.read(n) for n in names[:6]]
+    for m in range(nm):
+        sel = lambda i: tuple(X[names[i + a]][m] for a in range(3))
+        En, Bn = cy.mode_update(sel(0), sel(3), sel(6), X["RHO_HAT_OLD"][m],
+                                X["RHO_HAT_NEW"][m], m, nr, dr, nz, dz, vz, dt)
+        for a in range(3):
+            assert rel_l2(got[a][m], En[a]) <= tol, ("E", a, m)
+            assert rel_l2(got[3 + a][m], Bn[a]) <= tol, ("B", a, m)
+    # rho^{n+1} has become rho^n
+    assert np.array_equal(ctx.read("RHO_HAT_OLD"), X["RHO_HAT_NEW"].astype(ctx.cplx))
+    ctx.close()
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_history(gpu_lib, precision):
+    """Eight steps from real fields and sources: forward transforms, then
+    step() (sources forward, update, fields back) against the oracle's
+    transforms and mode update."""
+    nz, nr, nm, dz, dr, dt = 16, 24, 2, 0.7, 0.5, 0.3
+    vz, steps = -0.8, 8
+    ctx = gp.QcContext(nz, nr, nm, dz, dr, dt, precision)
+    ctx.set_v_gal(vz)
+    rng = np.random.default_rng(304)
+    shp = (nm, nz, nr)
+    E = [_as_input(_cplx(rng, shp), precision) for _ in range(3)]
+    B = [_as_input(_cplx(rng, shp), precision) for _ in range(3)]
+    J = [_as_input(0.1 * _cplx(rng, shp), precision) for _ in range(3)]
+    rho = _as_input(0.1 * _cplx(rng, shp), precision)
+    for n, a in zip(("ER", "ET", "EZ", "BR", "BT", "BZ", "JR", "JT", "JZ", "RHO"),
+                    E + B + J + [rho]):
+        ctx.write(n, a)
+    ctx.fields_fwd()
+    ctx.init_rho()
+    ctx.step(steps)
+    ctx.synchronize()
+    real = [ctx.read(n) for n in ("ER", "ET", "EZ", "BR", "BT", "BZ")]
+    spec = [ctx.read(n) for n in ("E_PLUS", "E_MINUS", "E_Z_HAT", "B_PLUS", "B_MINUS",
+                                  "B_Z_HAT")]
+    for m in range(nm):
+        Eh = cy.to_spectral(tuple(a[m] for a in E), m, dr, dz)
+        Bh = cy.to_spectral(tuple(a[m] for a in B), m, dr, dz)
+        Jh = cy.to_spectral(tuple(a[m] for a in J), m, dr, dz)
+        rh = cy.scalar_to_spectral(rho[m], m, dr, dz)
+        for _ in range(steps):
+            Eh, Bh = cy.mode_update(Eh, Bh, Jh, rh, rh, m, nr, dr, nz, dz, vz, dt)
+        Er = cy.from_spectral(Eh, m, dr, dz)
+        Br = cy.from_spectral(Bh, m, dr, dz)
+        tol = 4 * _fwd_tol(precision, m, [m - 1, m, m + 1], nr, dr)
+        for a in range(3):
+            assert rel_l2(spec[a][m], Eh[a]) <= tol, ("E^", a, m)
+            assert rel_l2(spec[3 + a][m], Bh[a]) <= tol, ("B^", a, m)
+            assert rel_l2(real[a][m], Er[a]) <= tol, ("E", a, m)
+            assert rel_l2(real[3 + a][m], Br[a]) <= tol, ("B", a, m)
+    ctx.close()
+
+
+def test_rejects_bad_arguments(gpu_lib):
+    bad = [(12, 24, 1), (4, 24, 1), (2048, 24, 1), (16, 3, 1), (16, 513, 1), (16, 24, 0),
+           (16, 24, 9)]
+    for nz, nr, nm in bad:
+        with pytest.raises(gp.GalpicError) as e:
+            gp.QcContext(nz, nr, nm, 0.5, 0.5, 0.3, gp.GP_FP64)
+        assert e.value.status == gp.GP_ERR_ARG, (nz, nr, nm)
+    with pytest.raises(gp.GalpicError):
+        gp.QcContext(16, 24, 1, -0.5, 0.5, 0.3, gp.GP_FP64)
+    ctx = gp.QcContext(16, 24, 1, 0.5, 0.5, 0.3, gp.GP_FP64)
+    with pytest.raises(gp.GalpicError) as e:
+        ctx.set_v_gal(1.0)
+    assert e.value.status == gp.GP_ERR_ARG
+    # |k_z v| dt reaches 2 pi on the highest live k_z plane
+    kzmax = 2 * np.pi * (16 // 2 - 1) / (16 * 0.5)
+    with pytest.raises(gp.GalpicError) as e:
+        gp.QcContext(16, 24, 1, 0.5, 0.5, 2 * np.pi / (0.9 * kzmax) + 1e-3,
+                     gp.GP_FP64).set_v_gal(-0.9)
+    assert e.value.status == gp.GP_ERR_UNSTABLE
+    with pytest.raises(gp.GalpicError):
+        ctx.write("COEF0", np.zeros((1, 16, 24)))
+    with pytest.raises(KeyError):
+        ctx.read("NOPE")
+    ctx.close()
