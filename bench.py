@@ -281,6 +281,196 @@ def workload_text(cfg):
             f"v_gal = drift{laser}, order-{cfg.order} shape, {prec}")
 
 
+QC_WORKLOADS = {
+    # the cylindrical counterpart of the 256x256x512 boosted-laser grid:
+    # 512 z nodes, 128 radial nodes (the box half-width), modes 0 (wake) and
+    # 1 (linearly polarised laser), gamma_boost 20, dz = dr = 1, dt = dz / c
+    "qc_boosted": dict(nz=512, nr=128, nmodes=2, dz=1.0, dr=1.0, dt=1.0, gamma=20.0,
+                       steps=1000),
+    # the largest grid a context takes, two modes
+    "qc_wide": dict(nz=1024, nr=512, nmodes=2, dz=1.0, dr=1.0, dt=1.0, gamma=20.0,
+                    steps=200),
+}
+
+
+def qc_flops(w, stage):
+    """Algorithmic flops of one launch of a Hankel-transform stage: a real
+    nr x nr matrix times complex rows, 4 flops per (input, output) pair per
+    row, over nz rows, nmodes modes and the launch's components (forward: the
+    vector launch's 3 plus the scalar launch's 1, summed per step; backward:
+    E and B, 6)."""
+    comps = {"hankel_fwd": 4, "hankel_bwd": 6}[stage]
+    return 4.0 * w["nz"] * w["nr"] ** 2 * w["nmodes"] * comps
+
+
+def qc_bytes(w, stage, real_size):
+    """Algorithmic HBM bytes of one step's launches of a stage (complex
+    fields of nmodes * nz * nr values read and written once; the update reads
+    E, B, J (9), rho twice and 6 coefficients and writes E, B (6))."""
+    field = w["nmodes"] * w["nz"] * w["nr"] * 2 * real_size
+    per = {"z_fwd": 4 * 2, "hankel_fwd": 5 + 4, "update": 9 + 2 + 6 + 6,
+           "hankel_bwd": 6 + 6, "z_inv": 6 * 2}[stage]
+    return per * field
+
+
+def run_qc(name, precision, steps, warmup):
+    import torch
+
+    from paper_1608_00215_amd import galpic as gp
+
+    w = QC_WORKLOADS[name]
+    beta = np.sqrt(1.0 - 1.0 / w["gamma"] ** 2)
+    stream = torch.cuda.current_stream()
+    ctx = gp.QcContext(w["nz"], w["nr"], w["nmodes"], w["dz"], w["dr"], w["dt"], precision,
+                       stream=ctypes_stream(stream))
+    ctx.set_v_gal(-beta)
+    rng = np.random.Generator(np.random.PCG64(7000))
+    shp = (w["nmodes"], w["nz"], w["nr"])
+    for f in ("ER", "ET", "EZ", "BR", "BT", "BZ", "JR", "JT", "JZ", "RHO"):
+        ctx.write(f, rng.standard_normal(shp) + 1j * rng.standard_normal(shp))
+    ctx.fields_fwd()
+    ctx.init_rho()
+    ctx.step(warmup)
+    ctx.synchronize()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.step(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    # per-launch kernel times from events, in a separate pass
+    ctx.stage_timing(True)
+    ctx.step(min(steps, 50))
+    times = ctx.stage_times()
+    ctx.stage_timing(False)
+    ctx.close()
+    return {"wall_s": wall, "stages": times}
+
+
+def ctypes_stream(stream):
+    import ctypes
+
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def qc_cpu_baseline(name, budget_s=10.0):
+    """The oracle's mode transforms and update, as they stand, on the
+    workload's grid, for as many whole steps (all modes) as fit the budget."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import cylindrical as cy
+
+    w = QC_WORKLOADS[name]
+    beta = np.sqrt(1.0 - 1.0 / w["gamma"] ** 2)
+    rng = np.random.Generator(np.random.PCG64(7001))
+    shp = (w["nz"], w["nr"])
+    c = lambda: rng.standard_normal(shp) + 1j * rng.standard_normal(shp)
+    nz, nr, dz, dr, dt = w["nz"], w["nr"], w["dz"], w["dr"], w["dt"]
+    state = {m: (cy.to_spectral((c(), c(), c()), m, dr, dz),
+                 cy.to_spectral((c(), c(), c()), m, dr, dz)) for m in range(w["nmodes"])}
+    J = (c(), c(), c())
+    rho = c()
+    steps = 0
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < budget_s or steps == 0:
+            for m in range(w["nmodes"]):
+                E, B = state[m]
+                Jh = cy.to_spectral(J, m, dr, dz)
+                rh = cy.scalar_to_spectral(rho, m, dr, dz)
+                E, B = cy.mode_update(E, B, Jh, rh, rh, m, nr, dr, nz, dz, -beta, dt)
+                cy.from_spectral(E, m, dr, dz)
+                cy.from_spectral(B, m, dr, dz)
+                state[m] = (E, B)
+            steps += 1
+        t = time.perf_counter() - t0
+    cells = w["nmodes"] * nz * nr
+    return {"value": cells * steps / t, "unit": "mode-cell-updates/s", "cores": 1,
+            "kind": "oracle",
+            "sample": (f"{steps} whole oracle steps (sources forward, update, fields back, "
+                       f"every mode; numpy, single thread) on the full {nz}x{nr} grid, "
+                       f"{w['nmodes']} modes, {t:.1f} s; transform matrices rebuilt "
+                       f"per call as the oracle does")}
+
+
+def qc_main(args):
+    from paper_1608_00215_amd import galpic as gp
+
+    w = QC_WORKLOADS[args.qc]
+    steps = w["steps"] if args.steps is None else args.steps
+    print(f"[bench] {args.qc}: nz {w['nz']} nr {w['nr']} modes {w['nmodes']}, {steps} steps",
+          file=sys.stderr, flush=True)
+    mixed = run_qc(args.qc, gp.GP_MIXED, steps, args.warmup)
+    print(f"[bench] mixed: {mixed['wall_s'] / steps * 1e3:.4f} ms/step", file=sys.stderr,
+          flush=True)
+    fp64 = None
+    if not args.no_fp64:
+        fp64 = run_qc(args.qc, gp.GP_FP64, steps, args.warmup)
+        print(f"[bench] fp64: {fp64['wall_s'] / steps * 1e3:.4f} ms/step", file=sys.stderr,
+              flush=True)
+    cells = w["nmodes"] * w["nz"] * w["nr"]
+
+    def summary(res, real_size, peak):
+        st = {k: v for k, v in res["stages"].items() if v[1] > 0}
+        per = {k: v[0] / v[1] for k, v in st.items()}
+        # per-step time of a stage = its summed time / timed steps
+        nsteps = max(v[1] for v in st.values()) if st else 1
+        share = {k: v[0] for k, v in st.items()}
+        dominant = max(share, key=share.get)
+        if dominant.startswith("hankel"):
+            # ms per step of the stage (the forward stage has two launches a step)
+            ms_step = st[dominant][0] / (st["update"][1])
+            achieved = qc_flops(w, dominant) / (ms_step * 1e-3) / 1e12
+            roof = {"kernel": dominant, "bound": "alu", "achieved": achieved, "peak": peak,
+                    "unit": "TFLOP/s", "frac": achieved / peak,
+                    "ms_per_launch": per[dominant], "traffic": None}
+        else:
+            ms_step = st[dominant][0] / st["update"][1]
+            achieved = qc_bytes(w, dominant, real_size) / (ms_step * 1e-3) / 1e9
+            roof = {"kernel": dominant, "bound": "hbm", "achieved": achieved,
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                    "ms_per_launch": per[dominant], "traffic": None}
+        stages = {}
+        for k, v in st.items():
+            ms_s = v[0] / st["update"][1]
+            d = {"ms_per_step": round(ms_s, 5), "launches_per_step": v[1] // st["update"][1],
+                 "gbs": round(qc_bytes(w, k, real_size) / (ms_s * 1e-3) / 1e9, 1)}
+            if k.startswith("hankel"):
+                d["tflops"] = round(qc_flops(w, k) / (ms_s * 1e-3) / 1e12, 2)
+            stages[k] = d
+        return roof, stages
+
+    roof, stages = summary(mixed, 4, FP32_PEAK_TFLOPS)
+    line = {
+        "metric": "mode-cell updates/s of the quasi-cylindrical Galilean-PSATD field solve",
+        "value": cells * steps / mixed["wall_s"],
+        "unit": "mode-cell-updates/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": mixed["wall_s"] / steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.qc}: quasi-cylindrical field solve, nz {w['nz']}, "
+                               f"nr {w['nr']}, modes 0..{w['nmodes'] - 1}, gamma_boost "
+                               f"{w['gamma']}, v_gal = -beta c, seeded random mode fields "
+                               "and sources (kernel cost does not depend on the values)",
+                   "precision": "mixed"},
+        "stages": stages,
+        "roofline": roof,
+    }
+    if fp64 is not None:
+        roof64, stages64 = summary(fp64, 8, FP64_PEAK_TFLOPS)
+        line["fp64_gpu"] = {"value": cells * steps / fp64["wall_s"],
+                            "ms_per_step": fp64["wall_s"] / steps * 1e3,
+                            "stages": stages64, "roofline": roof64}
+    if not args.no_cpu:
+        line["cpu_baseline"] = qc_cpu_baseline(args.qc)
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -305,12 +495,18 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device three times (a plain copy "
                          "kernel of known size for scaling HBM byte counters)")
+    ap.add_argument("--qc", default=None, choices=sorted(QC_WORKLOADS),
+                    help="instead, time the quasi-cylindrical (azimuthal-mode) field solve "
+                         "on the named grid and print its own line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); the "
               "multi-GPU decomposition is a design, not an implementation", file=sys.stderr)
         sys.exit(2)
     rank = int(os.environ.get("RANK", "0"))
+    if args.qc:
+        qc_main(args)
+        return
 
     from paper_1608_00215_amd import galpic as gp
     from workload import get_config, particles_for

@@ -404,6 +404,15 @@ gp_status gp_qc_fields_inv(gp_qc_ctx *ctx);
  * real J and rho as they stand. */
 gp_status gp_qc_step(gp_qc_ctx *ctx, int nsteps);
 gp_status gp_qc_synchronize(gp_qc_ctx *ctx);
+/* With timing on, every launch records HIP events on the context stream,
+ * by stage: 0 z transforms forward, 1 Hankel transforms forward, 2 mode
+ * update, 3 Hankel transforms backward, 4 z transforms inverse.
+ * gp_qc_stage_times returns the summed milliseconds and launch counts per
+ * stage, then clears them (synchronising). */
+#define GP_QC_N_STAGES 5
+gp_status gp_qc_stage_timing(gp_qc_ctx *ctx, int enable);
+gp_status gp_qc_stage_times(gp_qc_ctx *ctx, double ms[GP_QC_N_STAGES],
+                            int count[GP_QC_N_STAGES]);
 gp_status gp_qc_destroy(gp_qc_ctx *ctx);
 /* Host-only (no GPU, no context): the spectral grid and transform matrices
  * a context builds, for callers that prepare or read spectral fields.

@@ -275,11 +275,12 @@ struct StridedGeom {
   int half_row, half_outer, half_col;
 };
 
-template <typename T, int LOGL>
+// CW columns per workgroup: TileCols<T> by default; fewer where that would
+// leave the chip short of workgroups (few, long lines).
+template <typename T, int LOGL, int CW = TileCols<T>::value>
 __global__ __launch_bounds__(kThreads) void k_c2c_strided(const FieldSet *__restrict__ sets,
                                                           int nf, StridedGeom sg, int inverse,
                                                           const Cx<T> *__restrict__ tw) {
-  constexpr int CW = TileCols<T>::value;
   constexpr int S = CW + 1;
   constexpr int L = 1 << LOGL;
   __shared__ Cx<T> lds[L * S];
@@ -334,11 +335,11 @@ void dispatch_c2r(const FieldSet *sets, int nsets, int nf, int64_t nlines, T sca
                      tw);
 }
 
-template <typename T, int LOG>
+template <typename T, int LOG, int CW = TileCols<T>::value>
 void dispatch_c2c(const FieldSet *sets, int nsets, int nf, const StridedGeom &sg, int n_outer,
                   int inverse, const Cx<T> *tw, hipStream_t s) {
   dim3 grid(unsigned(n_outer * sg.col_tiles), unsigned(nf * nsets));
-  hipLaunchKernelGGL((k_c2c_strided<T, LOG>), grid, dim3(kThreads), 0, s, sets, nf, sg,
+  hipLaunchKernelGGL((k_c2c_strided<T, LOG, CW>), grid, dim3(kThreads), 0, s, sets, nf, sg,
                      inverse, tw);
 }
 
@@ -427,28 +428,42 @@ void launch_c2c(const FieldSet *sets, int nsets, int nf, const RunGeom &g, int a
   }
 }
 
+template <typename T, int CW>
+void lines_cw(const FieldSet *sets, int nsets, int nf, int log_len, const StridedGeom &sg,
+              int n_outer, int inv, const Cx<T> *tw, hipStream_t s) {
+  switch (log_len) {
+    case 3: dispatch_c2c<T, 3, CW>(sets, nsets, nf, sg, n_outer, inv, tw, s); break;
+    case 4: dispatch_c2c<T, 4, CW>(sets, nsets, nf, sg, n_outer, inv, tw, s); break;
+    case 5: dispatch_c2c<T, 5, CW>(sets, nsets, nf, sg, n_outer, inv, tw, s); break;
+    case 6: dispatch_c2c<T, 6, CW>(sets, nsets, nf, sg, n_outer, inv, tw, s); break;
+    case 7: dispatch_c2c<T, 7, CW>(sets, nsets, nf, sg, n_outer, inv, tw, s); break;
+    case 8: dispatch_c2c<T, 8, CW>(sets, nsets, nf, sg, n_outer, inv, tw, s); break;
+    case 9: dispatch_c2c<T, 9, CW>(sets, nsets, nf, sg, n_outer, inv, tw, s); break;
+    case 10: dispatch_c2c<T, 10, CW>(sets, nsets, nf, sg, n_outer, inv, tw, s); break;
+    default: break;
+  }
+}
+
 template <typename T>
 void launch_c2c_lines(const FieldSet *sets, int nsets, int nf, int log_len, int ncols,
                       int64_t row_stride, int64_t outer_stride, int n_outer, bool inverse,
                       const Cx<T> *tw, hipStream_t s) {
   constexpr int CW = TileCols<T>::value;
+  constexpr int kNarrow = 4;
   StridedGeom sg{};
   sg.ncols = ncols;
-  sg.col_tiles = (ncols + CW - 1) / CW;
   sg.row_stride = row_stride;
   sg.outer_stride = outer_stride;
   sg.mask = 0;
   const int inv = inverse ? 1 : 0;
-  switch (log_len) {
-    case 3: dispatch_c2c<T, 3>(sets, nsets, nf, sg, n_outer, inv, tw, s); break;
-    case 4: dispatch_c2c<T, 4>(sets, nsets, nf, sg, n_outer, inv, tw, s); break;
-    case 5: dispatch_c2c<T, 5>(sets, nsets, nf, sg, n_outer, inv, tw, s); break;
-    case 6: dispatch_c2c<T, 6>(sets, nsets, nf, sg, n_outer, inv, tw, s); break;
-    case 7: dispatch_c2c<T, 7>(sets, nsets, nf, sg, n_outer, inv, tw, s); break;
-    case 8: dispatch_c2c<T, 8>(sets, nsets, nf, sg, n_outer, inv, tw, s); break;
-    case 9: dispatch_c2c<T, 9>(sets, nsets, nf, sg, n_outer, inv, tw, s); break;
-    case 10: dispatch_c2c<T, 10>(sets, nsets, nf, sg, n_outer, inv, tw, s); break;
-    default: break;
+  // Narrow tiles when the default width gives fewer than two workgroups per CU.
+  const int64_t wide = int64_t(n_outer) * ((ncols + CW - 1) / CW) * nf * nsets;
+  if (wide < 512) {
+    sg.col_tiles = (ncols + kNarrow - 1) / kNarrow;
+    lines_cw<T, kNarrow>(sets, nsets, nf, log_len, sg, n_outer, inv, tw, s);
+  } else {
+    sg.col_tiles = (ncols + CW - 1) / CW;
+    lines_cw<T, CW>(sets, nsets, nf, log_len, sg, n_outer, inv, tw, s);
   }
 }
 

@@ -20,11 +20,9 @@
 //
 // Layout: every field is complex [mode][z][r] (r contiguous).  A step:
 //  z transforms of J, rho (strided complex lines, the Cartesian c2c tile
-//  kernel) -> forward Hankel transforms (a real matrix times complex rows,
-//  matrices transposed so that a workgroup's threads read a matrix row
-//  together and reuse it over kRows z rows staged in LDS) -> the mode
-//  update (one streaming pass per mode) -> backward Hankel transforms of E, B
-//  -> inverse z transforms.
+//  kernel) -> forward Hankel transforms (a real matrix times complex rows: a
+//  batched GEMM on the matrix cores) -> the mode update (one streaming pass
+//  per mode) -> backward Hankel transforms of E, B -> inverse z transforms.
 #include "galpic.h"
 
 #include <algorithm>
@@ -38,9 +36,8 @@
 namespace galpic {
 namespace {
 
-constexpr int kQThreads = 256;
-constexpr int kRows = 8;     // z rows per Hankel-transform workgroup
-constexpr int kMaxOut = 2;   // radial outputs per thread: nr <= 2 * kQThreads
+constexpr int kQWaves = 4;  // waves per Hankel-transform workgroup, one z-row tile each
+constexpr int kTC = 4;      // 16-column MFMA tiles per wave (64 output radial nodes)
 
 enum { kVecFwd = 0, kVecBwd = 1, kScalarFwd = 2 };
 
@@ -50,92 +47,217 @@ struct QcSet {
   void *out[3];
 };
 
+typedef float qf32x4 __attribute__((ext_vector_type(4)));
+typedef double qf64x4 __attribute__((ext_vector_type(4)));
+template <typename T>
+struct MfmaAcc;
+template <>
+struct MfmaAcc<float> {
+  using type = qf32x4;
+};
+template <>
+struct MfmaAcc<double> {
+  using type = qf64x4;
+};
+
+// D += A B for a 16 x 4 A and a 4 x 16 B over one wave: lane l supplies
+// A[l % 16][l / 16] and B[l / 16][l % 16]; element r of its accumulator is
+// D[4 (l / 16) + r][l % 16] for the f32 instruction but D[l / 16 + 4 r][l % 16]
+// for the f64 one (both checked on gfx950).
+__device__ __forceinline__ qf32x4 mfma16(float a, float b, qf32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ qf64x4 mfma16(double a, double b, qf64x4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// The Hankel transforms along r as batched real GEMMs on the matrix cores.
+// Per (mode m, transform) the complex rows of a field ([z][r], r contiguous)
+// are multiplied by a real nr x nr matrix stored as [k][i] (input radial or
+// spectral index k, output index i).  A workgroup takes a tile of 8 z rows --
+// 16 GEMM rows holding their real and imaginary parts -- against kTC
+// 16-column tiles of outputs; its kQWaves waves split K (4 k per MFMA) and
+// sum their partial tiles through LDS at the end, which keeps each wave's
+// chain of dependent loads short on small grids.  Operands come straight
+// from global memory (a row piece is 32 contiguous bytes per z, a matrix
+// row piece 16 contiguous values, reused from L1/L2 by every workgroup of
+// the mode).
+//
 // Matrix slots per mode: 0 = order m-1, 1 = order m, 2 = order m+1.
-//  kVecFwd:    in = F_r, F_theta, F_z (z-transformed) -> out = G^_+, G^_-, G^_z
-//  kVecBwd:    in = G^_+, G^_-, G^_z -> out = F_r, F_theta, F_z (before the
-//              inverse z transform; the backward matrices carry its 1/nz)
-//  kScalarFwd: in[0] -> out[0], order m
-// Workgroup (z row group, mode, field).  mats: [mode][slot][j][i], the
-// transpose of the transform (out_i = sum_j A_ij in_j).
-template <typename T, int KIND>
-__global__ __launch_bounds__(kQThreads) void k_qc_hankel(const QcSet *__restrict__ sets,
-                                                         const T *__restrict__ mats, int nz,
-                                                         int nr) {
-  extern __shared__ __align__(16) unsigned char qsm[];
-  Cx<T> *x = reinterpret_cast<Cx<T> *>(qsm);  // [kRows][nr]
-  const QcSet st = sets[blockIdx.z];
-  const int m = blockIdx.y;
-  const int z0 = blockIdx.x * kRows;
-  const int rows = min(kRows, nz - z0);
-  const int64_t base = int64_t(m) * nz * nr + int64_t(z0) * nr;
-  const Cx<T> *in[3] = {global_ptr(static_cast<const Cx<T> *>(st.in[0])),
-                        global_ptr(static_cast<const Cx<T> *>(st.in[1])),
-                        global_ptr(static_cast<const Cx<T> *>(st.in[2]))};
-  Cx<T> *out[3] = {global_ptr(static_cast<Cx<T> *>(st.out[0])),
-                   global_ptr(static_cast<Cx<T> *>(st.out[1])),
-                   global_ptr(static_cast<Cx<T> *>(st.out[2]))};
-  constexpr int ncomp = KIND == kScalarFwd ? 1 : 3;
-  Cx<T> keep[kRows][kMaxOut];  // kVecBwd: the backward G_+ until G_- is ready
-  for (int c = 0; c < ncomp; ++c) {
-    for (int t = threadIdx.x; t < rows * nr; t += kQThreads) {
-      const int64_t at = base + t;
-      Cx<T> v;
-      if (KIND == kVecFwd && c < 2) {
-        const Cx<T> ib = mul_i(in[1][at]);
-        const Cx<T> a = in[0][at];
-        v = c == 0 ? T(0.5) * (a + ib) : T(0.5) * (a - ib);
+//  kVecFwd:    part 0: G^_+ (slot 2) and G^_- (slot 0) of (F_r +- i F_theta) / 2,
+//              part 1: G^_z (slot 1) of F_z (all z-transformed)
+//  kVecBwd:    part 0: F_r = G_+ + G_-, F_theta = -i (G_+ - G_-) from G^_+
+//              (slot 2) and G^_- (slot 0); part 1: F_z (slot 1).  The inverse z
+//              transform follows; the backward matrices carry its 1/nz.
+//  kScalarFwd: in[0] -> out[0], slot 1.
+// Grid: x = z-row tiles, y = column blocks, z = (set, mode, part).
+template <typename T, int KIND, bool PAIR>
+__device__ __forceinline__ void hankel_tile(const QcSet &st, const T *__restrict__ mats, int nz,
+                                            int nr, int m, int rt, int col0, int lane, int wave,
+                                            T *__restrict__ red) {
+  using V = typename MfmaAcc<T>::type;
+  const int l16 = lane & 15, g = lane >> 4;
+  const int64_t plane = int64_t(m) * nz * nr;
+  // GEMM row rho of the 16-row tile <-> z row 8 rt + zr(rho), real (c = 0)
+  // or imaginary (c = 1) part, chosen per instruction so that the four
+  // accumulator elements of a lane are two whole complex values: f32 rows
+  // 4 g + r give zr = 2 g + r / 2, c = r & 1; f64 rows g + 4 r give
+  // zr = g + 4 (r / 2), c = r & 1.
+  constexpr bool kF32 = sizeof(T) == 4;
+  const int zr = kF32 ? (l16 >> 1) : ((l16 & 3) + ((l16 >> 3) << 2));
+  const int ca = kF32 ? (l16 & 1) : ((l16 >> 2) & 1);
+  const int64_t arow = 2 * (plane + int64_t(rt * 8 + zr) * nr) + ca;  // in T units
+  const int64_t msz = int64_t(nr) * nr;
+  const T *__restrict__ M = global_ptr(mats) + int64_t(m) * 3 * msz;
+  const T *__restrict__ B0 = M + (PAIR ? 2 : 1) * msz;
+  const T *__restrict__ B1 = M;  // slot 0 (pair only)
+  const T *__restrict__ in0 =
+      global_ptr(static_cast<const T *>(st.in[KIND == kScalarFwd ? 0 : (PAIR ? 0 : 2)]));
+  const T *__restrict__ in1 = global_ptr(static_cast<const T *>(st.in[PAIR ? 1 : 0]));
+
+  V acc0[kTC], acc1[kTC];
+#pragma unroll
+  for (int t = 0; t < kTC; ++t) {
+    acc0[t] = V{0, 0, 0, 0};
+    acc1[t] = V{0, 0, 0, 0};
+  }
+  // Operands of kKU consecutive k-steps.  Every index is clamped into range,
+  // so the loads need no branches; the K padding (k >= nr) is zeroed by
+  // multiplying the matrix operand by 0 (matrix entries are finite, so this
+  // is exact, and the padded products then vanish), and columns i >= nr are
+  // computed from clamped values but never stored.
+  constexpr int kKU = 2;
+  struct Ops {
+    T a0[kKU], a1[kKU], b0[kKU][kTC], b1[kKU][kTC];
+  };
+  int icl[kTC];
+#pragma unroll
+  for (int t = 0; t < kTC; ++t) icl[t] = min(col0 + 16 * t + l16, nr - 1);
+  auto load = [&](int s0, Ops &o) {
+#pragma unroll
+    for (int u = 0; u < kKU; ++u) {
+      const int k = 4 * (s0 + u) + g;
+      const int kc = min(k, nr - 1);
+      const T kmask = k < nr ? T(1) : T(0);
+      const int64_t at = arow + 2 * int64_t(kc);
+      if (KIND == kVecFwd && PAIR) {
+        // (F_r +- i F_theta) / 2: the real part takes F_r.re -+ F_theta.im,
+        // the imaginary part F_r.im +- F_theta.re
+        const T fr = in0[at];
+        const T ft = in1[at + (ca ? -1 : 1)];
+        const T sft = ca ? ft : -ft;
+        o.a0[u] = T(0.5) * (fr + sft);
+        o.a1[u] = T(0.5) * (fr - sft);
       } else {
-        v = in[c][at];
+        o.a0[u] = in0[at];
+        if (PAIR) o.a1[u] = in1[at];
       }
-      x[t] = v;
-    }
-    __syncthreads();
-    const int slot = KIND == kScalarFwd ? 1 : (c == 0 ? 2 : (c == 1 ? 0 : 1));
-    const T *__restrict__ AT = global_ptr(mats) + (int64_t(m) * 3 + slot) * nr * nr;
-    Cx<T> acc[kRows][kMaxOut];
+      const int64_t row = int64_t(kc) * nr;
 #pragma unroll
-    for (int r = 0; r < kRows; ++r)
-#pragma unroll
-      for (int o = 0; o < kMaxOut; ++o) acc[r][o] = cx(T(0), T(0));
-    for (int j = 0; j < nr; ++j) {
-      T a[kMaxOut];
-#pragma unroll
-      for (int o = 0; o < kMaxOut; ++o) {
-        const int i = threadIdx.x + o * kQThreads;
-        a[o] = i < nr ? AT[int64_t(j) * nr + i] : T(0);
-      }
-#pragma unroll
-      for (int r = 0; r < kRows; ++r) {
-        if (r < rows) {
-          const Cx<T> xv = x[r * nr + j];
-#pragma unroll
-          for (int o = 0; o < kMaxOut; ++o) {
-            acc[r][o].re += a[o] * xv.re;
-            acc[r][o].im += a[o] * xv.im;
-          }
-        }
+      for (int t = 0; t < kTC; ++t) {
+        o.b0[u][t] = B0[row + icl[t]] * kmask;
+        if (PAIR) o.b1[u][t] = B1[row + icl[t]] * kmask;
       }
     }
-    __syncthreads();  // x is restaged for the next component
+  };
+  auto mma = [&](const Ops &o) {
 #pragma unroll
-    for (int r = 0; r < kRows; ++r) {
+    for (int u = 0; u < kKU; ++u) {
 #pragma unroll
-      for (int o = 0; o < kMaxOut; ++o) {
-        const int i = threadIdx.x + o * kQThreads;
-        if (r >= rows || i >= nr) continue;
-        const int64_t at = base + int64_t(r) * nr + i;
-        if (KIND == kVecBwd && c == 0) {
-          keep[r][o] = acc[r][o];
-        } else if (KIND == kVecBwd && c == 1) {
-          const Cx<T> gp = keep[r][o], gm = acc[r][o];
-          out[0][at] = gp + gm;                    // F_r
-          out[1][at] = T(-1) * mul_i(gp - gm);     // F_theta = -i (G_+ - G_-)
-        } else {
-          out[c][at] = acc[r][o];
-        }
+      for (int t = 0; t < kTC; ++t) acc0[t] = mfma16(o.a0[u], o.b0[u][t], acc0[t]);
+      if (PAIR) {
+#pragma unroll
+        for (int t = 0; t < kTC; ++t) acc1[t] = mfma16(o.a1[u], o.b1[u][t], acc1[t]);
+      }
+    }
+  };
+  // Groups of kKU k-steps; wave w of the workgroup takes groups w, w + W,
+  // w + 2W, ... (W = kQWaves), two at a time through two operand sets, so
+  // the loads of one group are in flight during the other's MFMAs.  A group
+  // past nr has a zero matrix operand and adds nothing, so each wave's count
+  // is rounded up to even; the last prefetch rereads a group in range.
+  const int ngroups = (nr + 4 * kKU - 1) / (4 * kKU);
+  const int mine = (ngroups - wave + kQWaves - 1) / kQWaves;  // may be 0
+  const int npairs = (mine + 1) / 2;
+  auto group = [&](int j) { return kKU * min(wave + kQWaves * j, ngroups); };
+  Ops X, Y;
+  if (npairs > 0) load(group(0), X);
+  for (int s = 0; s < npairs; ++s) {
+    load(group(2 * s + 1), Y);
+    mma(X);
+    load(group(min(2 * s + 2, 2 * npairs - 1)), X);
+    mma(Y);
+  }
+  // Sum the waves' partial tiles through LDS: red holds [wave][acc][t][4][64];
+  // wave w then finishes the column tiles t = w, w + W, ...
+  constexpr int kNA = PAIR ? 2 : 1;
+#pragma unroll
+  for (int t = 0; t < kTC; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      red[(((wave * kNA + 0) * kTC + t) * 4 + r) * 64 + lane] = acc0[t][r];
+      if (PAIR) red[(((wave * kNA + 1) * kTC + t) * 4 + r) * 64 + lane] = acc1[t][r];
+    }
+  __syncthreads();
+  // accumulator elements 2 h, 2 h + 1 of a lane: the real and imaginary
+  // parts at z row 8 rt + (2 g + h) (f32) or 8 rt + (g + 4 h) (f64)
+#pragma unroll
+  for (int t = 0; t < kTC; ++t) {
+    if (t % kQWaves != wave) continue;
+    const int i = col0 + 16 * t + l16;
+    if (i >= nr) continue;
+    T s0[4], s1[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      s0[r] = T(0);
+      s1[r] = T(0);
+#pragma unroll
+      for (int w = 0; w < kQWaves; ++w) {
+        s0[r] += red[(((w * kNA + 0) * kTC + t) * 4 + r) * 64 + lane];
+        if (PAIR) s1[r] += red[(((w * kNA + 1) * kTC + t) * 4 + r) * 64 + lane];
+      }
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int zo = rt * 8 + (kF32 ? 2 * g + h : g + 4 * h);
+      const int64_t at = plane + int64_t(zo) * nr + i;
+      const Cx<T> p = cx(s0[2 * h], s0[2 * h + 1]);
+      if (!PAIR) {
+        Cx<T> *o = global_ptr(static_cast<Cx<T> *>(st.out[KIND == kScalarFwd ? 0 : 2]));
+        o[at] = p;
+        continue;
+      }
+      const Cx<T> q = cx(s1[2 * h], s1[2 * h + 1]);
+      Cx<T> *o0 = global_ptr(static_cast<Cx<T> *>(st.out[0]));
+      Cx<T> *o1 = global_ptr(static_cast<Cx<T> *>(st.out[1]));
+      if (KIND == kVecBwd) {
+        o0[at] = p + q;                  // F_r
+        o1[at] = T(-1) * mul_i(p - q);   // F_theta = -i (G_+ - G_-)
+      } else {
+        o0[at] = p;                      // G^_+
+        o1[at] = q;                      // G^_-
       }
     }
   }
+}
+
+template <typename T, int KIND>
+__global__ __launch_bounds__(64 * kQWaves) void k_qc_hankel(const QcSet *__restrict__ sets,
+                                                            const T *__restrict__ mats, int nz,
+                                                            int nr, int nmodes, int nparts) {
+  // partial tiles of the waves: [wave][pair][kTC][4][64]
+  __shared__ T red[kQWaves * 2 * kTC * 4 * 64];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int rt = blockIdx.x;  // z rows 8 rt .. 8 rt + 7 (nz is a multiple of 8)
+  const int part = blockIdx.z % nparts;
+  const int m = (blockIdx.z / nparts) % nmodes;
+  const QcSet st = sets[blockIdx.z / (nparts * nmodes)];
+  const int col0 = blockIdx.y * 16 * kTC;
+  if (KIND != kScalarFwd && part == 0)
+    hankel_tile<T, KIND, true>(st, mats, nz, nr, m, rt, col0, lane, wave, red);
+  else
+    hankel_tile<T, KIND, false>(st, mats, nz, nr, m, rt, col0, lane, wave, red);
 }
 
 // The mode update's arrays.
@@ -412,6 +534,12 @@ struct gp_qc_ctx {
   int rho_old = 9;         // spec slot of rho^n (the other holds rho^{n+1})
   double vgal = 0.0;
   bool coef_ready = false;
+  bool timing = false;
+  struct Rec {
+    int stage;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;  // events of timed launches, until gp_qc_stage_times
 };
 
 namespace {
@@ -447,6 +575,33 @@ gp_status qcheck(const char *what) {
   return GP_OK;
 }
 
+// Device events around one launch when timing is on (stages as in the header:
+// 0 z forward, 1 Hankel forward, 2 update, 3 Hankel backward, 4 z inverse).
+struct QStamp {
+  gp_qc_ctx *c;
+  gp_qc_ctx::Rec rec{};
+  bool on;
+  QStamp(gp_qc_ctx *ctx, int stage) : c(ctx), on(ctx->timing) {
+    if (!on) return;
+    rec.stage = stage;
+    if (hipEventCreate(&rec.a) != hipSuccess) {
+      on = false;
+      return;
+    }
+    if (hipEventCreate(&rec.b) != hipSuccess) {
+      (void)hipEventDestroy(rec.a);
+      on = false;
+      return;
+    }
+    (void)hipEventRecord(rec.a, c->stream);
+  }
+  ~QStamp() {
+    if (!on) return;
+    (void)hipEventRecord(rec.b, c->stream);
+    c->recs.push_back(rec);
+  }
+};
+
 template <typename T>
 const FieldSet *fs_at(gp_qc_ctx *c, int k) {
   return reinterpret_cast<const FieldSet *>(c->tab) + k;
@@ -461,6 +616,7 @@ template <typename T>
 void z_transform(gp_qc_ctx *c, int fs, int nf, bool inverse) {
   int lz = 0;
   while ((1 << lz) < c->d.nz) ++lz;
+  QStamp stamp(c, inverse ? 4 : 0);
   launch_c2c_lines<T>(fs_at<T>(c, fs), 1, nf, lz, c->d.nr, c->d.nr,
                       int64_t(c->d.nz) * c->d.nr, c->d.nmodes, inverse,
                       static_cast<const Cx<T> *>(c->tw), c->stream);
@@ -468,12 +624,14 @@ void z_transform(gp_qc_ctx *c, int fs, int nf, bool inverse) {
 
 template <typename T, int KIND>
 void hankel(gp_qc_ctx *c, int qs, int nsets, const void *mats) {
-  const dim3 grid(unsigned((c->d.nz + kRows - 1) / kRows), unsigned(c->d.nmodes),
-                  unsigned(nsets));
-  // at most kRows * 512 * 16 bytes = 64 KiB, the default dynamic LDS limit
-  const size_t lds = size_t(kRows) * c->d.nr * sizeof(Cx<T>);
-  hipLaunchKernelGGL((k_qc_hankel<T, KIND>), grid, dim3(kQThreads), lds, c->stream,
-                     qs_at<T>(c, qs), static_cast<const T *>(mats), c->d.nz, c->d.nr);
+  const int nparts = KIND == kScalarFwd ? 1 : 2;
+  const dim3 grid(unsigned(c->d.nz / 8),
+                  unsigned((c->d.nr + 16 * kTC - 1) / (16 * kTC)),
+                  unsigned(nsets * c->d.nmodes * nparts));
+  QStamp stamp(c, KIND == kVecBwd ? 3 : 1);
+  hipLaunchKernelGGL((k_qc_hankel<T, KIND>), grid, dim3(64 * kQWaves), 0, c->stream,
+                     qs_at<T>(c, qs), static_cast<const T *>(mats), c->d.nz, c->d.nr,
+                     c->d.nmodes, nparts);
 }
 
 template <typename T>
@@ -496,6 +654,7 @@ void enqueue_update(gp_qc_ctx *c) {
   for (int k = 0; k < 6; ++k) p.coef[k] = static_cast<const Cx<T> *>(c->coef[k]);
   p.kr = static_cast<const T *>(c->kr_t);
   const int64_t n = int64_t(c->d.nmodes) * c->d.nz * c->d.nr;
+  QStamp stamp(c, 2);
   hipLaunchKernelGGL((k_qc_update<T>), dim3(unsigned((n + 255) / 256)), dim3(256), 0, c->stream,
                      p, c->d.nmodes, c->d.nz, c->d.nr, T(2.0 * kPi / (c->d.nz * c->d.dz)));
   c->rho_old = c->rho_old == 9 ? 10 : 9;
@@ -633,7 +792,7 @@ gp_status gp_qc_init(const gp_qc_desc *d, void *hip_stream, gp_qc_ctx **out) {
   *out = nullptr;
   if (!is_pow2(d->nz) || d->nz < 8 || d->nz > 1024)
     return qfail(GP_ERR_ARG, "nz must be a power of two in [8, 1024]");
-  if (d->nr < 4 || d->nr > 2 * kQThreads)
+  if (d->nr < 4 || d->nr > 512)
     return qfail(GP_ERR_ARG, "nr must lie in [4, 512]");
   if (d->nmodes < 1 || d->nmodes > 8) return qfail(GP_ERR_ARG, "nmodes must lie in [1, 8]");
   if (!(d->dz > 0) || !(d->dr > 0) || !(d->dt > 0) || !std::isfinite(d->dz) ||
@@ -839,9 +998,44 @@ gp_status gp_qc_synchronize(gp_qc_ctx *c) {
   return GP_OK;
 }
 
+gp_status gp_qc_stage_timing(gp_qc_ctx *c, int enable) {
+  QTRY(qcheck_ctx(c));
+  c->timing = enable != 0;
+  return GP_OK;
+}
+
+gp_status gp_qc_stage_times(gp_qc_ctx *c, double *ms, int *count) {
+  QTRY(qcheck_ctx(c));
+  if (!ms || !count) return qfail(GP_ERR_ARG, "output pointer is NULL");
+  for (int i = 0; i < GP_QC_N_STAGES; ++i) {
+    ms[i] = 0.0;
+    count[i] = 0;
+  }
+  if (hipStreamSynchronize(c->stream) != hipSuccess)
+    return qfail(GP_ERR_HIP, "stream synchronize failed");
+  gp_status st = GP_OK;
+  for (const auto &rec : c->recs) {
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, rec.a, rec.b) == hipSuccess) {
+      ms[rec.stage] += t;
+      count[rec.stage] += 1;
+    } else {
+      st = qfail(GP_ERR_HIP, "hipEventElapsedTime failed");
+    }
+    (void)hipEventDestroy(rec.a);
+    (void)hipEventDestroy(rec.b);
+  }
+  c->recs.clear();
+  return st;
+}
+
 gp_status gp_qc_destroy(gp_qc_ctx *c) {
   if (!c) return GP_OK;
   if (c->stream) (void)hipStreamSynchronize(c->stream);
+  for (const auto &rec : c->recs) {
+    (void)hipEventDestroy(rec.a);
+    (void)hipEventDestroy(rec.b);
+  }
   for (void *p : c->allocs) (void)hipFree(p);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;

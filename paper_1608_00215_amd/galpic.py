@@ -34,12 +34,14 @@ EXPORTS = ["gp_init_grid", "gp_set_v_gal", "gp_set_current_correction", "gp_bind
            "gp_btd_particles", "gp_qc_init", "gp_qc_set_v_gal", "gp_qc_write", "gp_qc_read",
            "gp_qc_fields_fwd", "gp_qc_sources_fwd", "gp_qc_init_rho", "gp_qc_update",
            "gp_qc_fields_inv", "gp_qc_step", "gp_qc_synchronize", "gp_qc_destroy",
-           "gp_qc_wavenumbers", "gp_qc_hankel_matrix"]
+           "gp_qc_wavenumbers", "gp_qc_hankel_matrix", "gp_qc_stage_timing",
+           "gp_qc_stage_times"]
 QC_FIELDS = ["ER", "ET", "EZ", "BR", "BT", "BZ", "JR", "JT", "JZ", "RHO",
              "E_PLUS", "E_MINUS", "E_Z_HAT", "B_PLUS", "B_MINUS", "B_Z_HAT",
              "J_PLUS", "J_MINUS", "J_Z_HAT", "RHO_HAT_OLD", "RHO_HAT_NEW",
              "COEF0", "COEF1", "COEF2", "COEF3", "COEF4", "COEF5"]
 QC_FIELD = {name: i for i, name in enumerate(QC_FIELDS)}
+QC_STAGES = ["z_fwd", "hankel_fwd", "update", "hankel_bwd", "z_inv"]
 GP_N_STAGES = 13
 
 
@@ -126,6 +128,8 @@ def load(path=LIB_PATH):
         "gp_qc_synchronize": [vp],
         "gp_qc_destroy": [vp],
         "gp_qc_wavenumbers": [i32, i32, dbl, vp],
+        "gp_qc_stage_timing": [vp, i32],
+        "gp_qc_stage_times": [vp, vp, vp],
         "gp_qc_hankel_matrix": [i32, i32, i32, dbl, i32, vp],
     }
     for name, args in sig.items():
@@ -530,3 +534,13 @@ class QcContext:
 
     def synchronize(self):
         self._call("gp_qc_synchronize")
+
+    def stage_timing(self, enable=True):
+        self._call("gp_qc_stage_timing", int(bool(enable)))
+
+    def stage_times(self):
+        """{stage: (summed ms, launches)} of the launches timed so far."""
+        ms = np.zeros(len(QC_STAGES), dtype=np.float64)
+        cnt = np.zeros(len(QC_STAGES), dtype=np.int32)
+        self._call("gp_qc_stage_times", ms.ctypes.data, cnt.ctypes.data)
+        return {name: (float(ms[i]), int(cnt[i])) for i, name in enumerate(QC_STAGES)}
