@@ -90,15 +90,22 @@ __device__ __forceinline__ qf64x4 mfma16(double a, double b, qf64x4 c) {
 //              (slot 2) and G^_- (slot 0); part 1: F_z (slot 1).  The inverse z
 //              transform follows; the backward matrices carry its 1/nz.
 //  kScalarFwd: in[0] -> out[0], slot 1.
-// Grid: x = z-row tiles, y = column blocks, z = (set, mode, part).
-template <typename T, int KIND, bool PAIR>
+// Grid: x = z-row tiles (or groups of 8), y = column blocks, z = (set, mode,
+// part).
+// One wave's share of a Hankel-transform launch: RT z-row tiles (8 rows
+// each, 16 GEMM rows) against kTC column tiles, over the groups of K that
+// fall to it.  KS = kQWaves: the workgroup's waves split K and sum their
+// partial tiles through red (small grids: short load chains per wave);
+// KS = 1: each wave takes all of K for its own row tiles (large grids: the
+// RT row tiles share every matrix operand).
+template <typename T, int KIND, bool PAIR, int RT, int KS>
 __device__ __forceinline__ void hankel_tile(const QcSet &st, const T *__restrict__ mats, int nz,
-                                            int nr, int m, int rt, int col0, int lane, int wave,
-                                            T *__restrict__ red) {
+                                            int nr, int m, int rt0, int col0, int lane,
+                                            int wave, T *__restrict__ red) {
   using V = typename MfmaAcc<T>::type;
   const int l16 = lane & 15, g = lane >> 4;
   const int64_t plane = int64_t(m) * nz * nr;
-  // GEMM row rho of the 16-row tile <-> z row 8 rt + zr(rho), real (c = 0)
+  // GEMM row rho of a 16-row tile <-> z row 8 rt + zr(rho), real (c = 0)
   // or imaginary (c = 1) part, chosen per instruction so that the four
   // accumulator elements of a lane are two whole complex values: f32 rows
   // 4 g + r give zr = 2 g + r / 2, c = r & 1; f64 rows g + 4 r give
@@ -106,7 +113,9 @@ __device__ __forceinline__ void hankel_tile(const QcSet &st, const T *__restrict
   constexpr bool kF32 = sizeof(T) == 4;
   const int zr = kF32 ? (l16 >> 1) : ((l16 & 3) + ((l16 >> 3) << 2));
   const int ca = kF32 ? (l16 & 1) : ((l16 >> 2) & 1);
-  const int64_t arow = 2 * (plane + int64_t(rt * 8 + zr) * nr) + ca;  // in T units
+  int64_t arow[RT];  // in T units
+#pragma unroll
+  for (int q = 0; q < RT; ++q) arow[q] = 2 * (plane + int64_t((rt0 + q) * 8 + zr) * nr) + ca;
   const int64_t msz = int64_t(nr) * nr;
   const T *__restrict__ M = global_ptr(mats) + int64_t(m) * 3 * msz;
   const T *__restrict__ B0 = M + (PAIR ? 2 : 1) * msz;
@@ -115,12 +124,14 @@ __device__ __forceinline__ void hankel_tile(const QcSet &st, const T *__restrict
       global_ptr(static_cast<const T *>(st.in[KIND == kScalarFwd ? 0 : (PAIR ? 0 : 2)]));
   const T *__restrict__ in1 = global_ptr(static_cast<const T *>(st.in[PAIR ? 1 : 0]));
 
-  V acc0[kTC], acc1[kTC];
+  V acc0[RT][kTC], acc1[RT][kTC];
 #pragma unroll
-  for (int t = 0; t < kTC; ++t) {
-    acc0[t] = V{0, 0, 0, 0};
-    acc1[t] = V{0, 0, 0, 0};
-  }
+  for (int q = 0; q < RT; ++q)
+#pragma unroll
+    for (int t = 0; t < kTC; ++t) {
+      acc0[q][t] = V{0, 0, 0, 0};
+      acc1[q][t] = V{0, 0, 0, 0};
+    }
   // Operands of kKU consecutive k-steps.  Every index is clamped into range,
   // so the loads need no branches; the K padding (k >= nr) is zeroed by
   // multiplying the matrix operand by 0 (matrix entries are finite, so this
@@ -128,7 +139,7 @@ __device__ __forceinline__ void hankel_tile(const QcSet &st, const T *__restrict
   // computed from clamped values but never stored.
   constexpr int kKU = 2;
   struct Ops {
-    T a0[kKU], a1[kKU], b0[kKU][kTC], b1[kKU][kTC];
+    T a0[kKU][RT], a1[kKU][RT], b0[kKU][kTC], b1[kKU][kTC];
   };
   int icl[kTC];
 #pragma unroll
@@ -139,18 +150,21 @@ __device__ __forceinline__ void hankel_tile(const QcSet &st, const T *__restrict
       const int k = 4 * (s0 + u) + g;
       const int kc = min(k, nr - 1);
       const T kmask = k < nr ? T(1) : T(0);
-      const int64_t at = arow + 2 * int64_t(kc);
-      if (KIND == kVecFwd && PAIR) {
-        // (F_r +- i F_theta) / 2: the real part takes F_r.re -+ F_theta.im,
-        // the imaginary part F_r.im +- F_theta.re
-        const T fr = in0[at];
-        const T ft = in1[at + (ca ? -1 : 1)];
-        const T sft = ca ? ft : -ft;
-        o.a0[u] = T(0.5) * (fr + sft);
-        o.a1[u] = T(0.5) * (fr - sft);
-      } else {
-        o.a0[u] = in0[at];
-        if (PAIR) o.a1[u] = in1[at];
+#pragma unroll
+      for (int q = 0; q < RT; ++q) {
+        const int64_t at = arow[q] + 2 * int64_t(kc);
+        if (KIND == kVecFwd && PAIR) {
+          // (F_r +- i F_theta) / 2: the real part takes F_r.re -+ F_theta.im,
+          // the imaginary part F_r.im +- F_theta.re
+          const T fr = in0[at];
+          const T ft = in1[at + (ca ? -1 : 1)];
+          const T sft = ca ? ft : -ft;
+          o.a0[u][q] = T(0.5) * (fr + sft);
+          o.a1[u][q] = T(0.5) * (fr - sft);
+        } else {
+          o.a0[u][q] = in0[at];
+          if (PAIR) o.a1[u][q] = in1[at];
+        }
       }
       const int64_t row = int64_t(kc) * nr;
 #pragma unroll
@@ -162,24 +176,30 @@ __device__ __forceinline__ void hankel_tile(const QcSet &st, const T *__restrict
   };
   auto mma = [&](const Ops &o) {
 #pragma unroll
-    for (int u = 0; u < kKU; ++u) {
+    for (int u = 0; u < kKU; ++u)
 #pragma unroll
-      for (int t = 0; t < kTC; ++t) acc0[t] = mfma16(o.a0[u], o.b0[u][t], acc0[t]);
-      if (PAIR) {
+      for (int q = 0; q < RT; ++q) {
 #pragma unroll
-        for (int t = 0; t < kTC; ++t) acc1[t] = mfma16(o.a1[u], o.b1[u][t], acc1[t]);
+        for (int t = 0; t < kTC; ++t)
+          acc0[q][t] = mfma16(o.a0[u][q], o.b0[u][t], acc0[q][t]);
+        if (PAIR) {
+#pragma unroll
+          for (int t = 0; t < kTC; ++t)
+            acc1[q][t] = mfma16(o.a1[u][q], o.b1[u][t], acc1[q][t]);
+        }
       }
-    }
   };
-  // Groups of kKU k-steps; wave w of the workgroup takes groups w, w + W,
-  // w + 2W, ... (W = kQWaves), two at a time through two operand sets, so
-  // the loads of one group are in flight during the other's MFMAs.  A group
-  // past nr has a zero matrix operand and adds nothing, so each wave's count
-  // is rounded up to even; the last prefetch rereads a group in range.
+  // Groups of kKU k-steps; this wave takes groups kw, kw + KS, kw + 2 KS, ...
+  // (kw = its place among the KS waves sharing K), two at a time through two
+  // operand sets, so the loads of one group are in flight during the other's
+  // MFMAs.  A group past nr has a zero matrix operand and adds nothing, so
+  // the count is rounded up to even; the last prefetch rereads a group in
+  // range.
+  const int kw = KS > 1 ? wave : 0;
   const int ngroups = (nr + 4 * kKU - 1) / (4 * kKU);
-  const int mine = (ngroups - wave + kQWaves - 1) / kQWaves;  // may be 0
+  const int mine = (ngroups - kw + KS - 1) / KS;  // may be 0
   const int npairs = (mine + 1) / 2;
-  auto group = [&](int j) { return kKU * min(wave + kQWaves * j, ngroups); };
+  auto group = [&](int j) { return kKU * min(kw + KS * j, ngroups); };
   Ops X, Y;
   if (npairs > 0) load(group(0), X);
   for (int s = 0; s < npairs; ++s) {
@@ -188,76 +208,95 @@ __device__ __forceinline__ void hankel_tile(const QcSet &st, const T *__restrict
     load(group(min(2 * s + 2, 2 * npairs - 1)), X);
     mma(Y);
   }
-  // Sum the waves' partial tiles through LDS: red holds [wave][acc][t][4][64];
-  // wave w then finishes the column tiles t = w, w + W, ...
   constexpr int kNA = PAIR ? 2 : 1;
+  if (KS > 1) {
+    // partial tiles of the waves: red holds [wave][acc][t][4][64] (RT = 1);
+    // wave w then finishes the column tiles t with t % KS == w
 #pragma unroll
-  for (int t = 0; t < kTC; ++t)
+    for (int t = 0; t < kTC; ++t)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      red[(((wave * kNA + 0) * kTC + t) * 4 + r) * 64 + lane] = acc0[t][r];
-      if (PAIR) red[(((wave * kNA + 1) * kTC + t) * 4 + r) * 64 + lane] = acc1[t][r];
-    }
-  __syncthreads();
+      for (int r = 0; r < 4; ++r) {
+        red[(((wave * kNA + 0) * kTC + t) * 4 + r) * 64 + lane] = acc0[0][t][r];
+        if (PAIR) red[(((wave * kNA + 1) * kTC + t) * 4 + r) * 64 + lane] = acc1[0][t][r];
+      }
+    __syncthreads();
+  }
   // accumulator elements 2 h, 2 h + 1 of a lane: the real and imaginary
   // parts at z row 8 rt + (2 g + h) (f32) or 8 rt + (g + 4 h) (f64)
 #pragma unroll
-  for (int t = 0; t < kTC; ++t) {
-    if (t % kQWaves != wave) continue;
-    const int i = col0 + 16 * t + l16;
-    if (i >= nr) continue;
-    T s0[4], s1[4];
+  for (int q = 0; q < RT; ++q)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      s0[r] = T(0);
-      s1[r] = T(0);
+    for (int t = 0; t < kTC; ++t) {
+      if (KS > 1 && t % KS != wave) continue;
+      const int i = col0 + 16 * t + l16;
+      if (i >= nr) continue;
+      T s0[4], s1[4];
 #pragma unroll
-      for (int w = 0; w < kQWaves; ++w) {
-        s0[r] += red[(((w * kNA + 0) * kTC + t) * 4 + r) * 64 + lane];
-        if (PAIR) s1[r] += red[(((w * kNA + 1) * kTC + t) * 4 + r) * 64 + lane];
+      for (int r = 0; r < 4; ++r) {
+        if (KS > 1) {
+          s0[r] = T(0);
+          s1[r] = T(0);
+#pragma unroll
+          for (int w = 0; w < KS; ++w) {
+            s0[r] += red[(((w * kNA + 0) * kTC + t) * 4 + r) * 64 + lane];
+            if (PAIR) s1[r] += red[(((w * kNA + 1) * kTC + t) * 4 + r) * 64 + lane];
+          }
+        } else {
+          s0[r] = acc0[q][t][r];
+          s1[r] = acc1[q][t][r];
+        }
+      }
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int zo = (rt0 + q) * 8 + (kF32 ? 2 * g + h : g + 4 * h);
+        const int64_t at = plane + int64_t(zo) * nr + i;
+        const Cx<T> p = cx(s0[2 * h], s0[2 * h + 1]);
+        if (!PAIR) {
+          Cx<T> *o = global_ptr(static_cast<Cx<T> *>(st.out[KIND == kScalarFwd ? 0 : 2]));
+          o[at] = p;
+          continue;
+        }
+        const Cx<T> qv = cx(s1[2 * h], s1[2 * h + 1]);
+        Cx<T> *o0 = global_ptr(static_cast<Cx<T> *>(st.out[0]));
+        Cx<T> *o1 = global_ptr(static_cast<Cx<T> *>(st.out[1]));
+        if (KIND == kVecBwd) {
+          o0[at] = p + qv;                  // F_r
+          o1[at] = T(-1) * mul_i(p - qv);   // F_theta = -i (G_+ - G_-)
+        } else {
+          o0[at] = p;                       // G^_+
+          o1[at] = qv;                      // G^_-
+        }
       }
     }
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int zo = rt * 8 + (kF32 ? 2 * g + h : g + 4 * h);
-      const int64_t at = plane + int64_t(zo) * nr + i;
-      const Cx<T> p = cx(s0[2 * h], s0[2 * h + 1]);
-      if (!PAIR) {
-        Cx<T> *o = global_ptr(static_cast<Cx<T> *>(st.out[KIND == kScalarFwd ? 0 : 2]));
-        o[at] = p;
-        continue;
-      }
-      const Cx<T> q = cx(s1[2 * h], s1[2 * h + 1]);
-      Cx<T> *o0 = global_ptr(static_cast<Cx<T> *>(st.out[0]));
-      Cx<T> *o1 = global_ptr(static_cast<Cx<T> *>(st.out[1]));
-      if (KIND == kVecBwd) {
-        o0[at] = p + q;                  // F_r
-        o1[at] = T(-1) * mul_i(p - q);   // F_theta = -i (G_+ - G_-)
-      } else {
-        o0[at] = p;                      // G^_+
-        o1[at] = q;                      // G^_-
-      }
-    }
-  }
 }
 
-template <typename T, int KIND>
+// WIDE = false: a workgroup is one z-row tile, its waves splitting K.
+// WIDE = true: a workgroup is 8 z-row tiles, 2 per wave (needs nz % 64 == 0).
+template <typename T, int KIND, bool WIDE>
 __global__ __launch_bounds__(64 * kQWaves) void k_qc_hankel(const QcSet *__restrict__ sets,
                                                             const T *__restrict__ mats, int nz,
                                                             int nr, int nmodes, int nparts) {
-  // partial tiles of the waves: [wave][pair][kTC][4][64]
-  __shared__ T red[kQWaves * 2 * kTC * 4 * 64];
+  // partial tiles of the waves when they split K: [wave][pair][kTC][4][64]
+  __shared__ T red[WIDE ? 1 : kQWaves * 2 * kTC * 4 * 64];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int rt = blockIdx.x;  // z rows 8 rt .. 8 rt + 7 (nz is a multiple of 8)
   const int part = blockIdx.z % nparts;
   const int m = (blockIdx.z / nparts) % nmodes;
   const QcSet st = sets[blockIdx.z / (nparts * nmodes)];
   const int col0 = blockIdx.y * 16 * kTC;
-  if (KIND != kScalarFwd && part == 0)
-    hankel_tile<T, KIND, true>(st, mats, nz, nr, m, rt, col0, lane, wave, red);
-  else
-    hankel_tile<T, KIND, false>(st, mats, nz, nr, m, rt, col0, lane, wave, red);
+  if (WIDE) {
+    const int rt0 = (blockIdx.x * kQWaves + wave) * 2;  // z rows 8 rt0 .. 8 rt0 + 15
+    if (KIND != kScalarFwd && part == 0)
+      hankel_tile<T, KIND, true, 2, 1>(st, mats, nz, nr, m, rt0, col0, lane, wave, red);
+    else
+      hankel_tile<T, KIND, false, 2, 1>(st, mats, nz, nr, m, rt0, col0, lane, wave, red);
+  } else {
+    const int rt = blockIdx.x;  // z rows 8 rt .. 8 rt + 7 (nz is a multiple of 8)
+    if (KIND != kScalarFwd && part == 0)
+      hankel_tile<T, KIND, true, 1, kQWaves>(st, mats, nz, nr, m, rt, col0, lane, wave, red);
+    else
+      hankel_tile<T, KIND, false, 1, kQWaves>(st, mats, nz, nr, m, rt, col0, lane, wave, red);
+  }
 }
 
 // The mode update's arrays.
@@ -622,16 +661,29 @@ void z_transform(gp_qc_ctx *c, int fs, int nf, bool inverse) {
                       static_cast<const Cx<T> *>(c->tw), c->stream);
 }
 
+// The wide form (two row tiles per wave, no K split) halves the matrix
+// operand traffic per flop but has an eighth of the workgroups; it is taken
+// when it still gives 4 waves per SIMD (8192 narrow workgroups).  Measured on
+// 1024 x 512 x 2 modes: f64 backward 383 -> 300 us, f32 unchanged; with
+// only 2 waves per SIMD (the one-set forward launch) it was slower.
+constexpr int64_t kWideMin = 8192;
+
 template <typename T, int KIND>
 void hankel(gp_qc_ctx *c, int qs, int nsets, const void *mats) {
   const int nparts = KIND == kScalarFwd ? 1 : 2;
-  const dim3 grid(unsigned(c->d.nz / 8),
-                  unsigned((c->d.nr + 16 * kTC - 1) / (16 * kTC)),
-                  unsigned(nsets * c->d.nmodes * nparts));
+  const unsigned cols = unsigned((c->d.nr + 16 * kTC - 1) / (16 * kTC));
+  const unsigned zdim = unsigned(nsets * c->d.nmodes * nparts);
+  const int64_t narrow = int64_t(c->d.nz / 8) * cols * zdim;
   QStamp stamp(c, KIND == kVecBwd ? 3 : 1);
-  hipLaunchKernelGGL((k_qc_hankel<T, KIND>), grid, dim3(64 * kQWaves), 0, c->stream,
-                     qs_at<T>(c, qs), static_cast<const T *>(mats), c->d.nz, c->d.nr,
-                     c->d.nmodes, nparts);
+  if (c->d.nz % 64 == 0 && narrow >= kWideMin) {
+    hipLaunchKernelGGL((k_qc_hankel<T, KIND, true>), dim3(unsigned(c->d.nz / 64), cols, zdim),
+                       dim3(64 * kQWaves), 0, c->stream, qs_at<T>(c, qs),
+                       static_cast<const T *>(mats), c->d.nz, c->d.nr, c->d.nmodes, nparts);
+  } else {
+    hipLaunchKernelGGL((k_qc_hankel<T, KIND, false>), dim3(unsigned(c->d.nz / 8), cols, zdim),
+                       dim3(64 * kQWaves), 0, c->stream, qs_at<T>(c, qs),
+                       static_cast<const T *>(mats), c->d.nz, c->d.nr, c->d.nmodes, nparts);
+  }
 }
 
 template <typename T>

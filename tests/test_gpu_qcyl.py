@@ -25,10 +25,14 @@ pytestmark = pytest.mark.gpu
 
 EPS64 = 2.0 ** -52
 PRECISIONS = [gp.GP_FP64, gp.GP_MIXED]
-# (nz, nr, nmodes, dz, dr, dt): "small" fits one workgroup row of outputs;
-# "wide" has nr above the 256 threads of a transform workgroup (two outputs
-# per thread, a ragged second half) and four z row groups per mode
-CASES = {"small": (16, 24, 3, 0.7, 0.5, 0.3), "wide": (32, 300, 2, 0.4, 0.25, 0.2)}
+# (nz, nr, nmodes, dz, dr, dt): "small" has one column block of 64 outputs;
+# "wide" five (a ragged last one) and K padded from 300 to 304; "big" is
+# large enough for the transform's large-grid form (two z-row tiles per
+# wave, no K split) for E and B, with a ragged last column block (500 =
+# 7 x 64 + 52) and K padded from 500
+CASES = {"small": (16, 24, 3, 0.7, 0.5, 0.3), "wide": (32, 300, 2, 0.4, 0.25, 0.2),
+         "big": (1024, 500, 2, 0.5, 0.5, 0.4)}
+SMALL_CASES = ["small", "wide"]
 
 
 def _ctx(case, precision):
@@ -98,7 +102,7 @@ def test_fields_inverse(gpu_lib, case, precision):
     ctx.close()
 
 
-@pytest.mark.parametrize("case", list(CASES))
+@pytest.mark.parametrize("case", SMALL_CASES)
 @pytest.mark.parametrize("precision", PRECISIONS)
 def test_sources_forward(gpu_lib, case, precision):
     ctx, (nz, nr, nm, dz, dr, dt) = _ctx(case, precision)
@@ -142,7 +146,7 @@ def test_coefficients(gpu_lib, precision, vz):
     ctx.close()
 
 
-@pytest.mark.parametrize("case", list(CASES))
+@pytest.mark.parametrize("case", SMALL_CASES)
 @pytest.mark.parametrize("precision", PRECISIONS)
 def test_mode_update(gpu_lib, case, precision):
     ctx, (nz, nr, nm, dz, dr, dt) = _ctx(case, precision)
