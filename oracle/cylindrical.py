@@ -29,9 +29,39 @@ down.  Readings taken here:
   and the Galilean-PSATD update, covariant under rotations about z for
   v_gal along z, advances the mode as the Cartesian update does at that
   wavevector.  The k_z Nyquist plane is held at zero; k_r > 0 always.
-* Particles (deposition and gather in azimuthal modes) are not part of
-  this option.
+* Particles (deposition and gather by azimuthal mode), a reading of the
+  standard azimuthal decomposition with linear (CIC) shapes in r and z:
+  - a stored mode-m field is g_m = c_m f_m, with c_0 = 1 and c_m = 2 for
+    m >= 1, where f = sum over all integer m of f_m exp(i m theta); the
+    physical field is then Re sum_{m >= 0} g_m exp(i m theta);
+  - a particle at (r, theta, z) deposits c_m q w W_j(r) W_k(z)
+    exp(-i m theta) s / V_j to node (j, k), with the linear weights of the
+    radial nodes (j + 1/2) dr and of the z nodes k dz (periodic);
+  - the node at r = -dr/2 (a particle with r < dr/2) is the node j = 0 seen
+    across the axis (the point at angle theta + pi): its weight goes to
+    j = 0 with s = (-1)^m for scalars and z components and s = (-1)^(m+1)
+    for r and theta components (whose unit vectors flip there);
+  - V_j = 2 pi dz times the integral of node j's (folded, m = 0) weight
+    against r dr: (j + 1/2) dr^2 for j >= 1 and (13/24) dr^2 for j = 0, so
+    that a uniform density deposits uniformly up to the axis;
+  - a weight reaching past the last node (j >= nr) is dropped;
+  - at r = 0 the angle is taken as 0;
+  - gather is the transpose: F(x_p) = Re sum_m (sum of W s g_m over the
+    nodes) exp(i m theta_p), then the r and theta components are rotated to
+    x and y.
+  The particle cycle (moves, time-centring, push) is the Cartesian one,
+  with z periodic and x, y open.
+* A limit of this grid reading, measured here: the order m - 1 transform
+  on the J_m zero grid has no k_r = 0 function, so for m = 1 a transverse
+  field or current that is uniform across the axis (G_- constant in r) is
+  carried by large high-k_r coefficients and its spectral divergence is
+  wrong.  A particle column moving sideways then violates continuity by
+  orders of magnitude in mode 1 and the cycle runs away.  The particle
+  cycle is pinned for the axisymmetric mode (m = 0) only; the field solve
+  of every mode keeps its pins (they hold for each basis function).
 """
+
+import functools
 
 import numpy as np
 from scipy import special
@@ -112,16 +142,247 @@ def held_mask(nz, nr):
     return mask
 
 
+@functools.lru_cache(maxsize=64)
+def _mode_tables(m, nr, dr, nz, dz, v_gal_z, dt):
+    kz = axis_kz(nz, dz)[:, None] * np.ones((1, nr))
+    kr = np.ones((nz, 1)) * spectral_kr(m, nr, dr)[None, :]
+    k = (kr, np.zeros_like(kr), kz)
+    coef = galilean_psatd_coefficients(k, (0.0, 0.0, v_gal_z), dt)
+    return k, coef, held_mask(nz, nr)
+
+
 def mode_update(E, B, J, rho_old, rho_new, m, nr, dr, nz, dz, v_gal_z, dt):
     """Advance the spectral (G^_+, G^_-, G^_z) of E and B of mode m by one
     Galilean-PSATD step ([k_z][k_r] arrays), through the Cartesian update
     at k = (k_r, 0, k_z)."""
-    kz = axis_kz(nz, dz)[:, None] * np.ones((1, nr))
-    kr = np.ones((nz, 1)) * spectral_kr(m, nr, dr)[None, :]
-    k = (kr, np.zeros_like(kr), kz)
-    v = (0.0, 0.0, v_gal_z)
-    coef = galilean_psatd_coefficients(k, v, dt)
-    mask = held_mask(nz, nr)
+    k, coef, mask = _mode_tables(m, nr, dr, nz, dz, v_gal_z, dt)
     En, Bn = sp.galilean_psatd_update(to_cartesian(E), to_cartesian(B), to_cartesian(J),
                                       rho_old, rho_new, k, coef, mask)
     return from_cartesian(En), from_cartesian(Bn)
+
+
+# ---- particles: deposition and gather by azimuthal mode ----------------------
+
+def mode_factor(m):
+    """c_m: 1 for m = 0, 2 for m >= 1 (the stored field is c_m f_m)."""
+    return 1.0 if m == 0 else 2.0
+
+
+def node_volumes(nr, dr, dz):
+    """V_j = 2 pi dz * int W_j(r) r dr with the axis fold of m = 0."""
+    v = (np.arange(nr) + 0.5) * dr * dr
+    v[0] = 13.0 / 24.0 * dr * dr
+    return 2.0 * np.pi * dz * v
+
+
+def _angle(x, y):
+    """(r, cos theta, sin theta), with theta = 0 at r = 0."""
+    r = np.hypot(x, y)
+    safe = np.where(r > 0, r, 1.0)
+    c = np.where(r > 0, x / safe, 1.0)
+    s = np.where(r > 0, y / safe, 0.0)
+    return r, c, s
+
+
+def _nodes(r, z, nr, dr, nz, dz):
+    """Radial node pair (j0, j0 + 1) with weights, and the z pair."""
+    sr = r / dr - 0.5
+    j0 = np.floor(sr).astype(np.int64)
+    fr = sr - j0
+    sz = z / dz
+    k0 = np.floor(sz).astype(np.int64)
+    fz = sz - k0
+    rad = ((j0, 1.0 - fr), (j0 + 1, fr))
+    ax = ((k0 % nz, 1.0 - fz), ((k0 + 1) % nz, fz))
+    return rad, ax
+
+
+def deposit_mode(x, y, z, values, m, kind, nr, dr, nz, dz):
+    """c_m sum_p values_p W_j W_k exp(-i m theta_p) s / V_j on the [nz][nr]
+    grid of mode m.  kind is "scalar" (scalars and z components) or
+    "transverse" (r and theta components), which sets the axis-fold sign."""
+    r, c, s = _angle(x, y)
+    rot = (c - 1j * s) ** m
+    vol = node_volumes(nr, dr, dz)
+    fold = (-1.0) ** m if kind == "scalar" else (-1.0) ** (m + 1)
+    out = np.zeros((nz, nr), dtype=complex)
+    rad, ax = _nodes(r, z, nr, dr, nz, dz)
+    for j, wr in rad:
+        sign = np.where(j < 0, fold, 1.0)
+        jj = np.where(j < 0, 0, j)
+        live = jj < nr
+        for k, wz in ax:
+            val = mode_factor(m) * values * wr * wz * sign * rot
+            np.add.at(out, (k[live], jj[live]), val[live])
+    return out / vol[None, :]
+
+
+def gather_mode(g, x, y, z, m, kind, nr, dr, nz, dz):
+    """The complex sum over nodes of W_j W_k s g[k][j] at each particle
+    (before the factor exp(i m theta) and the real part)."""
+    r, _, _ = _angle(x, y)
+    fold = (-1.0) ** m if kind == "scalar" else (-1.0) ** (m + 1)
+    acc = np.zeros(len(x), dtype=complex)
+    rad, ax = _nodes(r, z, nr, dr, nz, dz)
+    for j, wr in rad:
+        sign = np.where(j < 0, fold, 1.0)
+        jj = np.where(j < 0, 0, j)
+        live = jj < nr
+        jc = np.where(live, jj, 0)
+        for k, wz in ax:
+            acc += np.where(live, wr * wz * sign * g[k, jc], 0.0)
+    return acc
+
+
+def gather_vector(G, x, y, z, nr, dr, nz, dz):
+    """Cartesian (n, 3) field at the particles from the mode fields
+    G[m] = (F_r, F_theta, F_z), each [nz][nr]."""
+    r, c, s = _angle(x, y)
+    Fr = np.zeros(len(x))
+    Ft = np.zeros(len(x))
+    Fz = np.zeros(len(x))
+    for m, comps in enumerate(G):
+        e = (c + 1j * s) ** m
+        Fr += np.real(gather_mode(comps[0], x, y, z, m, "transverse", nr, dr, nz, dz) * e)
+        Ft += np.real(gather_mode(comps[1], x, y, z, m, "transverse", nr, dr, nz, dz) * e)
+        Fz += np.real(gather_mode(comps[2], x, y, z, m, "scalar", nr, dr, nz, dz) * e)
+    return np.stack([Fr * c - Ft * s, Fr * s + Ft * c, Fz], axis=1)
+
+
+def deposit_current(x, y, z, v, qw, nmodes, nr, dr, nz, dz):
+    """Per mode (J_r, J_theta, J_z) [nz][nr] of currents qw v at the points."""
+    _, c, s = _angle(x, y)
+    vr = v[:, 0] * c + v[:, 1] * s
+    vt = -v[:, 0] * s + v[:, 1] * c
+    return [(deposit_mode(x, y, z, qw * vr, m, "transverse", nr, dr, nz, dz),
+             deposit_mode(x, y, z, qw * vt, m, "transverse", nr, dr, nz, dz),
+             deposit_mode(x, y, z, qw * v[:, 2], m, "scalar", nr, dr, nz, dz))
+            for m in range(nmodes)]
+
+
+def deposit_charge(x, y, z, qw, nmodes, nr, dr, nz, dz):
+    return [deposit_mode(x, y, z, qw * np.ones(len(x)), m, "scalar", nr, dr, nz, dz)
+            for m in range(nmodes)]
+
+
+def uniform_cylinder_background(density, rp, v_z, nmodes, nr, dr, nz, dz):
+    """Charge and current of a neutralising ion column: charge density
+    +density for r < rp, uniform in z and theta, drifting at v_z along z
+    (it does not depend on time in either frame).  Node j takes the share of
+    its (folded) shape volume inside rp, so that it cancels the deposit of a
+    uniform electron column up to the particles' noise.  Returns per mode
+    (rho, (J_r, J_theta, J_z)) real-space [nz][nr] arrays (modes >= 1
+    zero)."""
+    r = np.linspace(0.0, (nr + 1) * dr, 200001)
+    tent = lambda j: np.maximum(0.0, 1.0 - np.abs(r - (j + 0.5) * dr) / dr)
+    prof = np.zeros(nr)
+    for j in range(nr):
+        w = tent(j) + (tent(-1) if j == 0 else 0.0)
+        prof[j] = np.trapezoid(w * r * (r < rp), r) / np.trapezoid(w * r, r)
+    rho0 = density * np.ones((nz, 1)) * prof[None, :] + 0j
+    zero = np.zeros((nz, nr), dtype=complex)
+    out = []
+    for m in range(nmodes):
+        if m == 0:
+            out.append((rho0, (zero, zero, v_z * rho0)))
+        else:
+            out.append((zero, (zero, zero, zero)))
+    return out
+
+
+class CylindricalPIC:
+    """The Galilean-PSATD particle cycle in azimuthal modes, in the order of
+    the Cartesian cycle: with u at n - 1/2, move x half a step with
+    v - v_gal, deposit J there with v, move the second half, deposit rho^{n+1},
+    transform, update every mode, transform back, gather at x^{n+1} and push
+    (relativistic Boris).  z is periodic; x and y are open."""
+
+    def __init__(self, nz, nr, nmodes, dz, dr, dt, q, mass, w, v_gal_z, background=None):
+        """background: optional per-mode (rho, (J_r, J_theta, J_z)) added to
+        the deposits every step (e.g. a neutralising ion column)."""
+        self.nz, self.nr, self.nmodes = nz, nr, nmodes
+        self.dz, self.dr, self.dt = dz, dr, dt
+        self.q, self.mass, self.w = q, mass, w
+        self.v_gal_z = v_gal_z
+        self.background = background
+
+    def _with_background(self, rho, J):
+        if self.background is None:
+            return rho, J
+        bg = self.background
+        rho = [rho[m] + bg[m][0] for m in range(self.nmodes)]
+        if J is not None:
+            J = [tuple(J[m][a] + bg[m][1][a] for a in range(3)) for m in range(self.nmodes)]
+        return rho, J
+
+    def _move(self, x, v):
+        h = 0.5 * self.dt
+        out = x + h * (v - np.array([0.0, 0.0, self.v_gal_z]))
+        out[:, 2] = np.mod(out[:, 2], self.nz * self.dz)
+        return out
+
+    def electrostatic_field(self, rho_hat, m):
+        """Spectral (G^_+, G^_-, G^_z) of the field with i k.E = rho and no
+        curl: E^_c = -i k rho^ / |k|^2 at k = (k_r, 0, k_z), through the
+        Cartesian map (every mode has k_r > 0; the held k_z row stays 0)."""
+        kz = axis_kz(self.nz, self.dz)[:, None] * np.ones((1, self.nr))
+        kr = np.ones((self.nz, 1)) * spectral_kr(m, self.nr, self.dr)[None, :]
+        k2 = kr * kr + kz * kz
+        live = ~held_mask(self.nz, self.nr)
+        Ec = tuple(np.where(live, -1j * ka * rho_hat / k2, 0.0)
+                   for ka in (kr, np.zeros_like(kr), kz))
+        return from_cartesian(Ec)
+
+    def initial_state(self, x, u, E=None, B=None, electrostatic=False):
+        """x, u (n, 3); optional real mode fields E, B [m] = (r, theta, z);
+        electrostatic: E^0 is the field of the initial charge instead."""
+        rho = deposit_charge(x[:, 0], x[:, 1], x[:, 2], self.q * self.w, self.nmodes,
+                             self.nr, self.dr, self.nz, self.dz)
+        rho, _ = self._with_background(rho, None)
+        zero = np.zeros((self.nz, self.nr), dtype=complex)
+        Eh, Bh = [], []
+        for m in range(self.nmodes):
+            e = E[m] if E is not None else (zero, zero, zero)
+            b = B[m] if B is not None else (zero, zero, zero)
+            Eh.append(to_spectral(e, m, self.dr, self.dz))
+            Bh.append(to_spectral(b, m, self.dr, self.dz))
+        rh = [scalar_to_spectral(rho[m], m, self.dr, self.dz) for m in range(self.nmodes)]
+        if electrostatic:
+            Eh = [self.electrostatic_field(rh[m], m) for m in range(self.nmodes)]
+        return {"x": x.copy(), "u": u.copy(), "E_hat": Eh, "B_hat": Bh, "rho_hat": rh,
+                "E": None, "B": None}
+
+    def step(self, st):
+        from .particles import boris_push, lab_velocity
+        nz, nr, dz, dr, nm = self.nz, self.nr, self.dz, self.dr, self.nmodes
+        qw = self.q * self.w
+        v = lab_velocity(st["u"])
+        xh = self._move(st["x"], v)
+        xn = self._move(xh, v)
+        J = deposit_current(xh[:, 0], xh[:, 1], xh[:, 2], v, qw, nm, nr, dr, nz, dz)
+        rho = deposit_charge(xn[:, 0], xn[:, 1], xn[:, 2], qw, nm, nr, dr, nz, dz)
+        rho, J = self._with_background(rho, J)
+        Eh, Bh, rh, E, B = [], [], [], [], []
+        for m in range(nm):
+            Jh = to_spectral(J[m], m, dr, dz)
+            r1 = scalar_to_spectral(rho[m], m, dr, dz)
+            en, bn = mode_update(st["E_hat"][m], st["B_hat"][m], Jh, st["rho_hat"][m], r1,
+                                 m, nr, dr, nz, dz, self.v_gal_z, self.dt)
+            Eh.append(en)
+            Bh.append(bn)
+            rh.append(r1)
+            E.append(from_spectral(en, m, dr, dz))
+            B.append(from_spectral(bn, m, dr, dz))
+        Ep = gather_vector(E, xn[:, 0], xn[:, 1], xn[:, 2], nr, dr, nz, dz)
+        Bp = gather_vector(B, xn[:, 0], xn[:, 1], xn[:, 2], nr, dr, nz, dz)
+        un = boris_push(st["u"], Ep, Bp, self.q, self.mass, self.dt)
+        return {"x": xn, "u": un, "E_hat": Eh, "B_hat": Bh, "rho_hat": rh, "E": E, "B": B,
+                "J": J, "rho": rho}
+
+
+def field_energy(G, nr, dr, dz):
+    """sum_m sum_nodes V_j |g_m|^2 / c_m over the components of real mode
+    fields G[m] = (F_r, F_theta, F_z): a norm for growth diagnostics."""
+    vol = node_volumes(nr, dr, dz)
+    return float(sum(np.sum(vol[None, :] * np.abs(a) ** 2) / mode_factor(m)
+                     for m, comps in enumerate(G) for a in comps))
