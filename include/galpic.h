@@ -404,12 +404,56 @@ gp_status gp_qc_fields_inv(gp_qc_ctx *ctx);
  * real J and rho as they stand. */
 gp_status gp_qc_step(gp_qc_ctx *ctx, int nsteps);
 gp_status gp_qc_synchronize(gp_qc_ctx *ctx);
+/* Particles of a quasi-cylindrical context: caller-owned device arrays of
+ * the context's real type (double for GP_FP64, float for GP_MIXED):
+ * Cartesian positions x, y (open) and z in [0, nz dz) (periodic), and
+ * u = p / (m c).  q, m, w as for gp_particles. */
+typedef struct {
+  int64_t n;
+  double q, m, w;
+  void *x, *y, *z;
+  void *ux, *uy, *uz;
+} gp_qc_particles;
+
+/* Deposition and gather by azimuthal mode (the paper's runs use a
+ * quasi-cylindrical code; it does not print the scheme).  Linear weights in
+ * r (nodes (j + 1/2) dr) and z; a stored mode-m field is c_m f_m (c_0 = 1,
+ * c_m = 2), so the physical field is Re sum_m F_m exp(i m theta); a particle
+ * inside dr/2 folds its inner weight onto node 0 with (-1)^m (scalars, z
+ * components) or (-1)^(m+1) (r, theta components); node j's volume is its
+ * folded weight's integral against 2 pi r dr dz; weights past the last node
+ * are dropped.  Caution: the order m-1 transform on the J_m zero grid has no
+ * k_r = 0 function, so mode-1 fields and currents that are uniform across
+ * the axis are carried by large high-k_r coefficients with a wrong spectral
+ * divergence; a plasma column moving sideways then runs away.  Runs with
+ * particles are sound for nmodes = 1 (axisymmetric) only.
+ *
+ * gp_qc_set_background: a fixed source added to every deposit (e.g. a
+ * neutralising ion column), complex [mode][z][r] host or device arrays of rho,
+ * J_r, J_theta, J_z (a NULL one is zero; all NULL clears it).  Synchronising.
+ * gp_qc_bind_particles: keeps the pointers (the caller keeps the arrays
+ * alive), deposits rho^n (with the background) and makes it the spectral
+ * rho^n.  Synchronising.  Errors: GP_ERR_ARG.
+ * gp_qc_electrostatic_fields: E^ = the curl-free field with i k.E^ = rho^n
+ * (k_z Nyquist row zero), then the real E, B from E^, B^.
+ * gp_qc_particle_step: nsteps of the Galilean-PSATD particle cycle (with u
+ * at n - 1/2: move half a step with v - v_gal, deposit J with v = u / gamma,
+ * move the other half, deposit rho^{n+1}, transform, update every mode,
+ * transform back, gather E, B at x^{n+1}, relativistic Boris push).
+ * Errors: GP_ERR_STATE (no particles bound). */
+gp_status gp_qc_set_background(gp_qc_ctx *ctx, const void *rho, const void *j_r,
+                               const void *j_theta, const void *j_z);
+gp_status gp_qc_bind_particles(gp_qc_ctx *ctx, const gp_qc_particles *p);
+gp_status gp_qc_electrostatic_fields(gp_qc_ctx *ctx);
+gp_status gp_qc_particle_step(gp_qc_ctx *ctx, int nsteps);
+
 /* With timing on, every launch records HIP events on the context stream,
  * by stage: 0 z transforms forward, 1 Hankel transforms forward, 2 mode
- * update, 3 Hankel transforms backward, 4 z transforms inverse.
- * gp_qc_stage_times returns the summed milliseconds and launch counts per
- * stage, then clears them (synchronising). */
-#define GP_QC_N_STAGES 5
+ * update, 3 Hankel transforms backward, 4 z transforms inverse, 5 particle
+ * moves and deposits, 6 gather and push.  gp_qc_stage_times returns the
+ * summed milliseconds and launch counts per stage, then clears them
+ * (synchronising). */
+#define GP_QC_N_STAGES 7
 gp_status gp_qc_stage_timing(gp_qc_ctx *ctx, int enable);
 gp_status gp_qc_stage_times(gp_qc_ctx *ctx, double ms[GP_QC_N_STAGES],
                             int count[GP_QC_N_STAGES]);

@@ -379,6 +379,242 @@ __global__ __launch_bounds__(256) void k_qc_update(QcUpd<T> p, int nmodes, int n
   from_cart(Bn, p.B, idx);
 }
 
+// ---- particles: deposition and gather by azimuthal mode --------------------
+// Linear (CIC) shapes in r (nodes (j + 1/2) dr) and z (nodes k dz,
+// periodic).  A stored mode-m field is c_m f_m (c_0 = 1, c_m = 2), so the
+// physical field is Re sum_m g_m exp(i m theta).  A particle with r < dr/2
+// has its inner node at r = -dr/2, which is node 0 seen across the axis: its
+// weight goes to node 0 with (-1)^m for scalars and z components and
+// (-1)^(m+1) for r and theta components.  Node j's volume is the integral of
+// its (folded) weight against 2 pi r dr dz.  Weights past the last node are
+// dropped.  At r = 0 the angle is taken as 0.
+
+template <typename T>
+struct QcPart {
+  T *x, *y, *z, *ux, *uy, *uz;
+  int64_t n;
+};
+
+template <typename T>
+struct QcGeo {
+  int nmodes, nz, nr;
+  T inv_dz, inv_dr, lz;
+  const T *inv_vol;  // [nr]
+};
+
+template <typename T>
+struct QcNodes {
+  int j0;        // inner radial node (-1: folded onto 0)
+  T fr;          // weight of j0 + 1
+  int k0, k1;
+  T fz;          // weight of k1
+};
+
+template <typename T>
+__device__ __forceinline__ QcNodes<T> qc_nodes(const QcGeo<T> &g, T r, T z) {
+  QcNodes<T> o;
+  const T sr = r * g.inv_dr - T(0.5);
+  const T fj = floor(sr);
+  o.j0 = int(fj);
+  o.fr = sr - fj;
+  const T sz = z * g.inv_dz;
+  const T fk = floor(sz);
+  o.fz = sz - fk;
+  int k = int(fk) % g.nz;
+  if (k < 0) k += g.nz;
+  o.k0 = k;
+  o.k1 = k + 1 == g.nz ? 0 : k + 1;
+  return o;
+}
+
+// cos, sin of the particle's angle (1, 0 at r = 0) and r
+template <typename T>
+__device__ __forceinline__ void qc_angle(T x, T y, T &r, T &c, T &s) {
+  r = sqrt(x * x + y * y);
+  if (r > T(0)) {
+    c = x / r;
+    s = y / r;
+  } else {
+    c = T(1);
+    s = T(0);
+  }
+}
+
+// Add c_m val exp(-i m theta) W s / V to the four nodes of every mode.
+template <typename T>
+__device__ __forceinline__ void qc_deposit(const QcGeo<T> &g, T *__restrict__ arr,
+                                           const QcNodes<T> &nd, T c, T s, T val,
+                                           bool transverse) {
+  const int64_t plane = int64_t(g.nz) * g.nr;
+  T er = T(1), ei = T(0);  // exp(-i m theta), advanced per mode
+  for (int m = 0; m < g.nmodes; ++m) {
+    const T cm = m == 0 ? T(1) : T(2);
+    const T fold = ((m + (transverse ? 1 : 0)) & 1) ? T(-1) : T(1);
+    const T vr = cm * val * er, vi = cm * val * ei;
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const int j = nd.j0 + a;
+      const int jj = j < 0 ? 0 : j;
+      if (jj >= g.nr) continue;
+      const T wr = (a ? nd.fr : T(1) - nd.fr) * (j < 0 ? fold : T(1)) * g.inv_vol[jj];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const int k = b ? nd.k1 : nd.k0;
+        const T w = wr * (b ? nd.fz : T(1) - nd.fz);
+        const int64_t at = 2 * (int64_t(m) * plane + int64_t(k) * g.nr + jj);
+        atomicAdd(arr + at, w * vr);
+        atomicAdd(arr + at + 1, w * vi);
+      }
+    }
+    // exp(-i (m+1) theta) = exp(-i m theta) (c - i s)
+    const T nr_ = er * c + ei * s, ni = ei * c - er * s;
+    er = nr_;
+    ei = ni;
+  }
+}
+
+// Re sum_m (sum over nodes of W s g_m) exp(i m theta) for one component.
+template <typename T>
+__device__ __forceinline__ T qc_gather(const QcGeo<T> &g, const T *__restrict__ arr,
+                                       const QcNodes<T> &nd, T c, T s, bool transverse) {
+  const int64_t plane = int64_t(g.nz) * g.nr;
+  T er = T(1), ei = T(0);  // exp(i m theta)
+  T out = T(0);
+  for (int m = 0; m < g.nmodes; ++m) {
+    const T fold = ((m + (transverse ? 1 : 0)) & 1) ? T(-1) : T(1);
+    T ar = T(0), ai = T(0);
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const int j = nd.j0 + a;
+      const int jj = j < 0 ? 0 : j;
+      if (jj >= g.nr) continue;
+      const T wr = (a ? nd.fr : T(1) - nd.fr) * (j < 0 ? fold : T(1));
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const int k = b ? nd.k1 : nd.k0;
+        const T w = wr * (b ? nd.fz : T(1) - nd.fz);
+        const int64_t at = 2 * (int64_t(m) * plane + int64_t(k) * g.nr + jj);
+        ar += w * arr[at];
+        ai += w * arr[at + 1];
+      }
+    }
+    out += ar * er - ai * ei;
+    const T nr_ = er * c - ei * s, ni = ei * c + er * s;
+    er = nr_;
+    ei = ni;
+  }
+  return out;
+}
+
+template <typename T>
+struct QcSrc {
+  T *jr, *jt, *jz, *rho;
+};
+
+// move = 1: x^n -> x_h (deposit J with v = u / gamma) -> x^{n+1} (deposit
+// rho); move = 0: deposit rho at x only.  Moves use v - v_gal (v_gal along
+// z); z wraps, x and y are open.
+template <typename T>
+__global__ __launch_bounds__(256) void k_qc_move_deposit(QcPart<T> p, QcGeo<T> g, QcSrc<T> src,
+                                                         T dt, T vgal, T qw, int move) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= p.n) return;
+  T x = p.x[i], y = p.y[i], z = p.z[i];
+  if (move) {
+    const T ux = p.ux[i], uy = p.uy[i], uz = p.uz[i];
+    const T ig = T(1) / sqrt(T(1) + ux * ux + uy * uy + uz * uz);
+    const T vx = ux * ig, vy = uy * ig, vz = uz * ig;
+    const T h = T(0.5) * dt;
+    auto wrap = [&](T zz) {
+      zz -= g.lz * floor(zz / g.lz);
+      return zz >= g.lz ? zz - g.lz : zz;
+    };
+    x += h * vx;
+    y += h * vy;
+    z = wrap(z + h * (vz - vgal));
+    T r, c, s;
+    qc_angle(x, y, r, c, s);
+    const QcNodes<T> nd = qc_nodes(g, r, z);
+    const T vr = vx * c + vy * s, vt = -vx * s + vy * c;
+    qc_deposit(g, src.jr, nd, c, s, qw * vr, true);
+    qc_deposit(g, src.jt, nd, c, s, qw * vt, true);
+    qc_deposit(g, src.jz, nd, c, s, qw * vz, false);
+    x += h * vx;
+    y += h * vy;
+    z = wrap(z + h * (vz - vgal));
+    p.x[i] = x;
+    p.y[i] = y;
+    p.z[i] = z;
+  }
+  T r, c, s;
+  qc_angle(x, y, r, c, s);
+  qc_deposit(g, src.rho, qc_nodes(g, r, z), c, s, qw, false);
+}
+
+// Gather E, B at x (the mode fields [m][z][r]: r, theta, z components), then
+// the relativistic Boris push of u over dt (c = 1).
+template <typename T>
+__global__ __launch_bounds__(256) void k_qc_gather_push(QcPart<T> p, QcGeo<T> g,
+                                                        const T *__restrict__ E0,
+                                                        const T *__restrict__ E1,
+                                                        const T *__restrict__ E2,
+                                                        const T *__restrict__ B0,
+                                                        const T *__restrict__ B1,
+                                                        const T *__restrict__ B2, T h) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= p.n) return;
+  T r, c, s;
+  qc_angle(p.x[i], p.y[i], r, c, s);
+  const QcNodes<T> nd = qc_nodes(g, r, p.z[i]);
+  const T er = qc_gather(g, E0, nd, c, s, true), et = qc_gather(g, E1, nd, c, s, true);
+  const T ez = qc_gather(g, E2, nd, c, s, false);
+  const T br = qc_gather(g, B0, nd, c, s, true), bt = qc_gather(g, B1, nd, c, s, true);
+  const T bz = qc_gather(g, B2, nd, c, s, false);
+  const T Ex = er * c - et * s, Ey = er * s + et * c, Ez = ez;
+  const T Bx = br * c - bt * s, By = br * s + bt * c, Bz = bz;
+  // h = q dt / (2 m c)
+  const T mx = p.ux[i] + h * Ex, my = p.uy[i] + h * Ey, mz = p.uz[i] + h * Ez;
+  const T ig = T(1) / sqrt(T(1) + mx * mx + my * my + mz * mz);
+  const T tx = h * Bx * ig, ty = h * By * ig, tz = h * Bz * ig;
+  const T sf = T(2) / (T(1) + tx * tx + ty * ty + tz * tz);
+  const T sx = sf * tx, sy = sf * ty, sz = sf * tz;
+  const T px = mx + (my * tz - mz * ty), py = my + (mz * tx - mx * tz), pz = mz + (mx * ty - my * tx);
+  const T ax = mx + (py * sz - pz * sy), ay = my + (pz * sx - px * sz), az = mz + (px * sy - py * sx);
+  p.ux[i] = ax + h * Ex;
+  p.uy[i] = ay + h * Ey;
+  p.uz[i] = az + h * Ez;
+}
+
+// E^ of the initial charge: i k.E = rho^n with no curl, at k = (k_r, 0, k_z)
+// through the Cartesian map (E^_x = -i k_r rho / k^2, E^_z = -i k_z rho / k^2;
+// G_+ = (i/2) E_x, G_- = -(i/2) E_x, G_z = E_z); the held k_z row is zero.
+template <typename T>
+__global__ __launch_bounds__(256) void k_qc_electrostatic(Cx<T> *Ep, Cx<T> *Em, Cx<T> *Ez,
+                                                          const Cx<T> *__restrict__ rho,
+                                                          const T *__restrict__ kr, int nmodes,
+                                                          int nz, int nr, T kzfac) {
+  const int64_t n = int64_t(nmodes) * nz * nr;
+  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= n) return;
+  const int i = int(idx % nr);
+  const int iz = int((idx / nr) % nz);
+  const int m = int(idx / (int64_t(nz) * nr));
+  if (iz == nz / 2) {
+    Ep[idx] = Em[idx] = Ez[idx] = cx(T(0), T(0));
+    return;
+  }
+  const T k_r = kr[int64_t(m) * nr + i];
+  const T k_z = T(iz < nz / 2 ? iz : iz - nz) * kzfac;
+  const T k2 = k_r * k_r + k_z * k_z;
+  const Cx<T> q = rho[idx];
+  // -i k rho / k^2
+  const Cx<T> ex = cx(q.im * k_r / k2, -q.re * k_r / k2);
+  const Cx<T> ez = cx(q.im * k_z / k2, -q.re * k_z / k2);
+  Ep[idx] = T(0.5) * mul_i(ex);
+  Em[idx] = T(-0.5) * mul_i(ex);
+  Ez[idx] = ez;
+}
+
 // ---- host -------------------------------------------------------------------
 
 gp_status qfail(gp_status st, const std::string &msg) {
@@ -579,6 +815,12 @@ struct gp_qc_ctx {
     hipEvent_t a, b;
   };
   std::vector<Rec> recs;  // events of timed launches, until gp_qc_stage_times
+  // particles (caller-owned device arrays of the real type) and sources
+  gp_qc_particles part{};
+  bool bound = false;
+  void *bg[4] = {};        // background rho, J_r, J_theta, J_z (allocated once)
+  bool has_bg = false;
+  void *inv_vol = nullptr; // [nr] 1 / V_j in the real type
 };
 
 namespace {
@@ -776,6 +1018,17 @@ gp_status build_transforms(gp_qc_ctx *c) {
   QTRY(qalloc(c, kd.size() * sizeof(double), &p));
   c->kr_d = static_cast<double *>(p);
   QTRY(qalloc(c, kt.size() * sizeof(T), &c->kr_t));
+  // 1 / V_j, V_j = 2 pi dz dr^2 (j + 1/2), and (13/24) 2 pi dz dr^2 for the
+  // axis node (the integral of its folded linear weight against r dr)
+  std::vector<T> iv(nr);
+  for (int j = 0; j < nr; ++j) {
+    const double v = 2.0 * kPi * c->d.dz * c->d.dr * c->d.dr * (j == 0 ? 13.0 / 24.0 : j + 0.5);
+    iv[j] = T(1.0 / v);
+  }
+  QTRY(qalloc(c, iv.size() * sizeof(T), &c->inv_vol));
+  if (hipMemcpyAsync(c->inv_vol, iv.data(), iv.size() * sizeof(T), hipMemcpyHostToDevice,
+                     c->stream) != hipSuccess)
+    return qfail(GP_ERR_HIP, "volume upload failed");
   if (hipMemcpyAsync(c->fmat, fh.data(), mbytes, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
       hipMemcpyAsync(c->bmat, bh.data(), mbytes, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
       hipMemcpyAsync(c->kr_d, kd.data(), kd.size() * sizeof(double), hipMemcpyHostToDevice,
@@ -836,6 +1089,71 @@ void *slot_of(gp_qc_ctx *c, int which) {
 }
 
 bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
+
+template <typename T>
+QcGeo<T> qc_geo(gp_qc_ctx *c) {
+  QcGeo<T> g;
+  g.nmodes = c->d.nmodes;
+  g.nz = c->d.nz;
+  g.nr = c->d.nr;
+  g.inv_dz = T(1.0 / c->d.dz);
+  g.inv_dr = T(1.0 / c->d.dr);
+  g.lz = T(c->d.nz * c->d.dz);
+  g.inv_vol = static_cast<const T *>(c->inv_vol);
+  return g;
+}
+
+template <typename T>
+QcPart<T> qc_part(gp_qc_ctx *c) {
+  QcPart<T> q;
+  q.x = static_cast<T *>(c->part.x);
+  q.y = static_cast<T *>(c->part.y);
+  q.z = static_cast<T *>(c->part.z);
+  q.ux = static_cast<T *>(c->part.ux);
+  q.uy = static_cast<T *>(c->part.uy);
+  q.uz = static_cast<T *>(c->part.uz);
+  q.n = c->part.n;
+  return q;
+}
+
+// the real-space sources start each deposit as the background (or zero)
+gp_status fill_sources(gp_qc_ctx *c) {
+  const size_t fb = field_bytes(c);
+  for (int a = 0; a < 4; ++a) {
+    void *dst = c->real[a == 0 ? 9 : 5 + a];  // RHO, then J_r, J_theta, J_z
+    const hipError_t e = c->has_bg ? hipMemcpyAsync(dst, c->bg[a], fb, hipMemcpyDeviceToDevice,
+                                                    c->stream)
+                                   : hipMemsetAsync(dst, 0, fb, c->stream);
+    if (e != hipSuccess) return qfail(GP_ERR_HIP, "source reset failed");
+  }
+  return GP_OK;
+}
+
+template <typename T>
+void launch_move_deposit(gp_qc_ctx *c, int move) {
+  if (c->part.n == 0) return;
+  QcSrc<T> src;
+  src.jr = static_cast<T *>(c->real[6]);
+  src.jt = static_cast<T *>(c->real[7]);
+  src.jz = static_cast<T *>(c->real[8]);
+  src.rho = static_cast<T *>(c->real[9]);
+  QStamp stamp(c, 5);
+  hipLaunchKernelGGL((k_qc_move_deposit<T>), dim3(unsigned((c->part.n + 255) / 256)), dim3(256),
+                     0, c->stream, qc_part<T>(c), qc_geo<T>(c), src, T(c->d.dt), T(c->vgal),
+                     T(c->part.q * c->part.w), move);
+}
+
+template <typename T>
+void launch_gather_push(gp_qc_ctx *c) {
+  if (c->part.n == 0) return;
+  const T h = T(c->part.q * c->d.dt / (2.0 * c->part.m));
+  QStamp stamp(c, 6);
+  hipLaunchKernelGGL((k_qc_gather_push<T>), dim3(unsigned((c->part.n + 255) / 256)), dim3(256),
+                     0, c->stream, qc_part<T>(c), qc_geo<T>(c),
+                     static_cast<const T *>(c->real[0]), static_cast<const T *>(c->real[1]),
+                     static_cast<const T *>(c->real[2]), static_cast<const T *>(c->real[3]),
+                     static_cast<const T *>(c->real[4]), static_cast<const T *>(c->real[5]), h);
+}
 
 }  // namespace
 
@@ -1047,6 +1365,86 @@ gp_status gp_qc_synchronize(gp_qc_ctx *c) {
   QTRY(qcheck_ctx(c));
   if (hipStreamSynchronize(c->stream) != hipSuccess)
     return qfail(GP_ERR_HIP, "stream synchronize failed");
+  return GP_OK;
+}
+
+gp_status gp_qc_set_background(gp_qc_ctx *c, const void *rho, const void *jr, const void *jt,
+                               const void *jz) {
+  QTRY(qcheck_ctx(c));
+  const void *src[4] = {rho, jr, jt, jz};
+  if (!rho && !jr && !jt && !jz) {
+    c->has_bg = false;  // the arrays stay allocated for a later call
+    return GP_OK;
+  }
+  const size_t fb = field_bytes(c);
+  for (int a = 0; a < 4; ++a)
+    if (!c->bg[a]) QTRY(qalloc(c, fb, &c->bg[a]));
+  for (int a = 0; a < 4; ++a) {
+    const hipError_t e = src[a] ? hipMemcpyAsync(c->bg[a], src[a], fb, hipMemcpyDefault, c->stream)
+                                : hipMemsetAsync(c->bg[a], 0, fb, c->stream);
+    if (e != hipSuccess) return qfail(GP_ERR_HIP, "background upload failed");
+  }
+  if (hipStreamSynchronize(c->stream) != hipSuccess)
+    return qfail(GP_ERR_HIP, "stream synchronize failed");
+  c->has_bg = true;
+  return GP_OK;
+}
+
+gp_status gp_qc_bind_particles(gp_qc_ctx *c, const gp_qc_particles *p) {
+  QTRY(qcheck_ctx(c));
+  if (!p) return qfail(GP_ERR_ARG, "particles are NULL");
+  if (p->n < 0 || p->n > (int64_t(1) << 40)) return qfail(GP_ERR_ARG, "bad particle count");
+  if (!std::isfinite(p->q) || !std::isfinite(p->w) || !(p->m > 0) || !std::isfinite(p->m))
+    return qfail(GP_ERR_ARG, "q, w must be finite and m positive");
+  if (p->n > 0 && (!p->x || !p->y || !p->z || !p->ux || !p->uy || !p->uz))
+    return qfail(GP_ERR_ARG, "a particle array is NULL");
+  c->part = *p;
+  c->bound = true;
+  QTRY(fill_sources(c));
+  // rho^n of the particles (and the background), transformed into the
+  // rho^{n+1} slot, which then becomes rho^n
+  QTRY(qdispatch(c, [&](auto t) {
+    using T = decltype(t);
+    launch_move_deposit<T>(c, 0);
+    z_transform<T>(c, kFsFwdSrc, 4, false);
+    hankel<T, kScalarFwd>(c, c->rho_old == 9 ? kQsRho1 : kQsRho0, 1, c->fmat);
+  }));
+  c->rho_old = c->rho_old == 9 ? 10 : 9;
+  if (hipStreamSynchronize(c->stream) != hipSuccess)
+    return qfail(GP_ERR_HIP, "stream synchronize failed");
+  return GP_OK;
+}
+
+gp_status gp_qc_electrostatic_fields(gp_qc_ctx *c) {
+  QTRY(qcheck_ctx(c));
+  return qdispatch(c, [&](auto t) {
+    using T = decltype(t);
+    const int64_t n = int64_t(c->d.nmodes) * c->d.nz * c->d.nr;
+    hipLaunchKernelGGL((k_qc_electrostatic<T>), dim3(unsigned((n + 255) / 256)), dim3(256), 0,
+                       c->stream, static_cast<Cx<T> *>(c->spec[0]),
+                       static_cast<Cx<T> *>(c->spec[1]), static_cast<Cx<T> *>(c->spec[2]),
+                       static_cast<const Cx<T> *>(c->spec[c->rho_old]),
+                       static_cast<const T *>(c->kr_t), c->d.nmodes, c->d.nz, c->d.nr,
+                       T(2.0 * kPi / (c->d.nz * c->d.dz)));
+    enqueue_fields_inv<T>(c);
+  });
+}
+
+gp_status gp_qc_particle_step(gp_qc_ctx *c, int nsteps) {
+  QTRY(qcheck_ctx(c));
+  if (!c->bound) return qfail(GP_ERR_STATE, "no particles bound");
+  if (nsteps < 0) return qfail(GP_ERR_ARG, "nsteps must be >= 0");
+  for (int s = 0; s < nsteps; ++s) {
+    QTRY(fill_sources(c));
+    QTRY(qdispatch(c, [&](auto t) {
+      using T = decltype(t);
+      launch_move_deposit<T>(c, 1);
+      enqueue_sources_fwd<T>(c);
+      enqueue_update<T>(c);
+      enqueue_fields_inv<T>(c);
+      launch_gather_push<T>(c);
+    }));
+  }
   return GP_OK;
 }
 

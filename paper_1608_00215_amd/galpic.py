@@ -35,13 +35,15 @@ EXPORTS = ["gp_init_grid", "gp_set_v_gal", "gp_set_current_correction", "gp_bind
            "gp_qc_fields_fwd", "gp_qc_sources_fwd", "gp_qc_init_rho", "gp_qc_update",
            "gp_qc_fields_inv", "gp_qc_step", "gp_qc_synchronize", "gp_qc_destroy",
            "gp_qc_wavenumbers", "gp_qc_hankel_matrix", "gp_qc_stage_timing",
-           "gp_qc_stage_times"]
+           "gp_qc_stage_times", "gp_qc_set_background", "gp_qc_bind_particles",
+           "gp_qc_electrostatic_fields", "gp_qc_particle_step"]
 QC_FIELDS = ["ER", "ET", "EZ", "BR", "BT", "BZ", "JR", "JT", "JZ", "RHO",
              "E_PLUS", "E_MINUS", "E_Z_HAT", "B_PLUS", "B_MINUS", "B_Z_HAT",
              "J_PLUS", "J_MINUS", "J_Z_HAT", "RHO_HAT_OLD", "RHO_HAT_NEW",
              "COEF0", "COEF1", "COEF2", "COEF3", "COEF4", "COEF5"]
 QC_FIELD = {name: i for i, name in enumerate(QC_FIELDS)}
-QC_STAGES = ["z_fwd", "hankel_fwd", "update", "hankel_bwd", "z_inv"]
+QC_STAGES = ["z_fwd", "hankel_fwd", "update", "hankel_bwd", "z_inv", "deposit",
+             "gather_push"]
 GP_N_STAGES = 13
 
 
@@ -51,6 +53,13 @@ class GridDesc(ctypes.Structure):
                 ("dt", ctypes.c_double), ("shape_order", ctypes.c_int),
                 ("precision", ctypes.c_int), ("tile", ctypes.c_int * 3),
                 ("resort_div", ctypes.c_int), ("stencil", ctypes.c_int * 3)]
+
+
+class QcParticlesC(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("q", ctypes.c_double), ("m", ctypes.c_double),
+                ("w", ctypes.c_double),
+                ("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("z", ctypes.c_void_p),
+                ("ux", ctypes.c_void_p), ("uy", ctypes.c_void_p), ("uz", ctypes.c_void_p)]
 
 
 class QcDesc(ctypes.Structure):
@@ -129,6 +138,10 @@ def load(path=LIB_PATH):
         "gp_qc_destroy": [vp],
         "gp_qc_wavenumbers": [i32, i32, dbl, vp],
         "gp_qc_stage_timing": [vp, i32],
+        "gp_qc_set_background": [vp, vp, vp, vp, vp],
+        "gp_qc_bind_particles": [vp, ctypes.POINTER(QcParticlesC)],
+        "gp_qc_electrostatic_fields": [vp],
+        "gp_qc_particle_step": [vp, i32],
         "gp_qc_stage_times": [vp, vp, vp],
         "gp_qc_hankel_matrix": [i32, i32, i32, dbl, i32, vp],
     }
@@ -534,6 +547,39 @@ class QcContext:
 
     def synchronize(self):
         self._call("gp_qc_synchronize")
+
+    def set_background(self, rho=None, j_r=None, j_theta=None, j_z=None):
+        """Fixed sources added to every deposit (complex [mode][z][r])."""
+        keep = []
+
+        def ptr(a):
+            if a is None:
+                return None
+            b = np.ascontiguousarray(np.broadcast_to(a, self.shape), dtype=self.cplx)
+            keep.append(b)
+            return b.ctypes.data
+
+        self._call("gp_qc_set_background", ptr(rho), ptr(j_r), ptr(j_theta), ptr(j_z))
+
+    def bind_particles(self, q, m, w, x, y, z, ux, uy, uz):
+        """x ... uz: device tensors of the context's real type (kept by the
+        caller while bound); deposits rho^n."""
+        arrs = (x, y, z, ux, uy, uz)
+        n = int(x.numel())
+        for a in arrs:
+            if a.numel() != n or not a.is_contiguous() or not a.is_cuda:
+                raise ValueError("particle arrays must be contiguous device tensors of one size")
+            if a.element_size() != (8 if self.precision == GP_FP64 else 4):
+                raise ValueError("particle arrays must have the context's real type")
+        self._parts = arrs
+        pc = QcParticlesC(n, float(q), float(m), float(w), *[a.data_ptr() for a in arrs])
+        self._call("gp_qc_bind_particles", ctypes.byref(pc))
+
+    def electrostatic_fields(self):
+        self._call("gp_qc_electrostatic_fields")
+
+    def particle_step(self, nsteps=1):
+        self._call("gp_qc_particle_step", int(nsteps))
 
     def stage_timing(self, enable=True):
         self._call("gp_qc_stage_timing", int(bool(enable)))
