@@ -290,6 +290,12 @@ QC_WORKLOADS = {
     # the largest grid a context takes, two modes
     "qc_wide": dict(nz=1024, nr=512, nmodes=2, dz=1.0, dr=1.0, dt=1.0, gamma=20.0,
                     steps=200),
+    # the particle cycle: an electron column of radius 96 (density 1, 24
+    # particles per (r, z) cell, drifting at gamma 20 along -z) on its
+    # neutralising ion column, axisymmetric (mode 0), Galilean frame,
+    # electrostatic start
+    "qc_column": dict(nz=512, nr=128, nmodes=1, dz=1.0, dr=1.0, dt=1.0, gamma=20.0,
+                      steps=200, ppc=24, rp=96.0),
 }
 
 
@@ -303,10 +309,15 @@ def qc_flops(w, stage):
     return 4.0 * w["nz"] * w["nr"] ** 2 * w["nmodes"] * comps
 
 
-def qc_bytes(w, stage, real_size):
+def qc_bytes(w, stage, real_size, n_part=0):
     """Algorithmic HBM bytes of one step's launches of a stage (complex
     fields of nmodes * nz * nr values read and written once; the update reads
-    E, B, J (9), rho twice and 6 coefficients and writes E, B (6))."""
+    E, B, J (9), rho twice and 6 coefficients and writes E, B (6)).  The
+    particle stages read positions and momenta (6 values) and write
+    positions (deposit) or momenta (gather-push) (3 values); their grid
+    accesses (atomics and gathers) resolve in L2 and are not counted."""
+    if stage in ("deposit", "gather_push"):
+        return n_part * 9 * real_size
     field = w["nmodes"] * w["nz"] * w["nr"] * 2 * real_size
     per = {"z_fwd": 4 * 2, "hankel_fwd": 5 + 4, "update": 9 + 2 + 6 + 6,
            "hankel_bwd": 6 + 6, "z_inv": 6 * 2}[stage]
@@ -326,24 +337,69 @@ def run_qc(name, precision, steps, warmup):
     ctx.set_v_gal(-beta)
     rng = np.random.Generator(np.random.PCG64(7000))
     shp = (w["nmodes"], w["nz"], w["nr"])
-    for f in ("ER", "ET", "EZ", "BR", "BT", "BZ", "JR", "JT", "JZ", "RHO"):
-        ctx.write(f, rng.standard_normal(shp) + 1j * rng.standard_normal(shp))
-    ctx.fields_fwd()
-    ctx.init_rho()
-    ctx.step(warmup)
+    n_part = 0
+    if "ppc" in w:
+        x, u, qw_w = qc_column_inputs(w)
+        n_part = len(x)
+        dt_t = torch.float64 if precision == gp.GP_FP64 else torch.float32
+        parts = [torch.tensor(np.ascontiguousarray(a), dtype=dt_t, device="cuda")
+                 for a in (x[:, 0], x[:, 1], x[:, 2], u[:, 0], u[:, 1], u[:, 2])]
+        rho_bg = np.zeros(shp, dtype=complex)
+        rho_bg[0] = qc_ion_profile(w)[None, :]
+        zero = np.zeros(shp, dtype=complex)
+        ctx.set_background(rho_bg, zero, zero, -beta * rho_bg)
+        ctx.bind_particles(-1.0, 1.0, qw_w, *parts)
+        ctx.electrostatic_fields()
+        advance = ctx.particle_step
+    else:
+        for f in ("ER", "ET", "EZ", "BR", "BT", "BZ", "JR", "JT", "JZ", "RHO"):
+            ctx.write(f, rng.standard_normal(shp) + 1j * rng.standard_normal(shp))
+        ctx.fields_fwd()
+        ctx.init_rho()
+        advance = ctx.step
+    advance(warmup)
     ctx.synchronize()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ctx.step(steps)
+    advance(steps)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     # per-launch kernel times from events, in a separate pass
     ctx.stage_timing(True)
-    ctx.step(min(steps, 50))
+    advance(min(steps, 50))
     times = ctx.stage_times()
     ctx.stage_timing(False)
     ctx.close()
-    return {"wall_s": wall, "stages": times}
+    return {"wall_s": wall, "stages": times, "particles": n_part}
+
+
+def qc_column_inputs(w):
+    """Seeded electron column: 8 particles per (r, z) cell inside rp, r drawn
+    with density proportional to r, angle and z uniform; cold drift at
+    gamma along -z.  Returns x, u (n, 3) and the weight of density 1."""
+    rng = np.random.Generator(np.random.PCG64(7002))
+    n = int(w["ppc"] * w["nz"] * w["rp"] / w["dr"])
+    r = w["rp"] * np.sqrt(rng.uniform(0.0, 1.0, n))
+    th = rng.uniform(0.0, 2.0 * np.pi, n)
+    x = np.stack([r * np.cos(th), r * np.sin(th), rng.uniform(0.0, w["nz"] * w["dz"], n)], 1)
+    u = np.zeros((n, 3))
+    u[:, 2] = -np.sqrt(w["gamma"] ** 2 - 1.0)
+    weight = np.pi * w["rp"] ** 2 * w["nz"] * w["dz"] / n
+    return x, u, weight
+
+
+def qc_ion_profile(w):
+    """Per radial node, the share of the node's (folded, linear) shape
+    volume inside rp: the charge density of a uniform ion column of
+    density 1 as the deposit sees it."""
+    dr, nr, rp = w["dr"], w["nr"], w["rp"]
+    r = np.linspace(0.0, (nr + 1) * dr, 400001)
+    tent = lambda j: np.maximum(0.0, 1.0 - np.abs(r - (j + 0.5) * dr) / dr)
+    prof = np.zeros(nr)
+    for j in range(nr):
+        wt = tent(j) + (tent(-1) if j == 0 else 0.0)
+        prof[j] = np.trapezoid(wt * r * (r < rp), r) / np.trapezoid(wt * r, r)
+    return prof
 
 
 def ctypes_stream(stream):
@@ -409,28 +465,47 @@ def qc_main(args):
               flush=True)
     cells = w["nmodes"] * w["nz"] * w["nr"]
 
-    def summary(res, real_size, peak):
-        st = {k: v for k, v in res["stages"].items() if v[1] > 0}
-        per = {k: v[0] / v[1] for k, v in st.items()}
-        # the dominant kernel: the largest single launch of the step, the
-        # backward Hankel transform of E and B (one k_qc_hankel<T, kVecBwd>
-        # launch; the forward stage is two different launches); it runs on
-        # the matrix cores, so its roof is the dense MFMA peak of its type
-        dominant = "hankel_bwd"
-        ms_launch = per[dominant]
-        achieved = qc_flops(w, dominant) / (ms_launch * 1e-3) / 1e12
-        roof = {"kernel": "k_qc_hankel (backward, E and B)", "bound": "mfma",
-                "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                "frac": achieved / peak, "ms_per_launch": ms_launch, "traffic": None}
+    def stages_of(st, res, real_size):
         stages = {}
         for k, v in st.items():
             ms_s = v[0] / st["update"][1]
             d = {"ms_per_step": round(ms_s, 5), "launches_per_step": v[1] // st["update"][1],
-                 "gbs": round(qc_bytes(w, k, real_size) / (ms_s * 1e-3) / 1e9, 1)}
+                 "gbs": round(qc_bytes(w, k, real_size, res["particles"]) / (ms_s * 1e-3) / 1e9,
+                              1)}
+            if k in ("deposit", "gather_push"):
+                d["ns_per_particle"] = round(ms_s * 1e6 / res["particles"], 3)
             if k.startswith("hankel"):
                 d["tflops"] = round(qc_flops(w, k) / (ms_s * 1e-3) / 1e12, 2)
             stages[k] = d
-        return roof, stages
+        return stages
+
+    def summary(res, real_size, peak):
+        st = {k: v for k, v in res["stages"].items() if v[1] > 0}
+        per = {k: v[0] / v[1] for k, v in st.items()}
+        if res["particles"]:
+            # with particles the move-and-deposit kernel dominates; its
+            # algorithmic HBM bytes are the particle arrays (read 6, write 3
+            # values) and the four source grids written once; its atomics
+            # resolve in L2 and bound it
+            ms_launch = per["deposit"]
+            byt = qc_bytes(w, "deposit", real_size, res["particles"]) + \
+                4 * w["nmodes"] * w["nz"] * w["nr"] * 2 * real_size
+            achieved = byt / (ms_launch * 1e-3) / 1e9
+            roof = {"kernel": "k_qc_move_deposit", "bound": "hbm", "achieved": achieved,
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                    "ms_per_launch": ms_launch, "traffic": None,
+                    "note": "bound by global atomics to the source grids (resolved in L2)"}
+        else:
+            # the largest single launch of the field step: the backward
+            # Hankel transform of E and B (one k_qc_hankel<T, kVecBwd> launch;
+            # the forward stage is two different launches); it runs on the
+            # matrix cores, so its roof is the dense MFMA peak of its type
+            ms_launch = per["hankel_bwd"]
+            achieved = qc_flops(w, "hankel_bwd") / (ms_launch * 1e-3) / 1e12
+            roof = {"kernel": "k_qc_hankel (backward, E and B)", "bound": "mfma",
+                    "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                    "frac": achieved / peak, "ms_per_launch": ms_launch, "traffic": None}
+        return roof, stages_of(st, res, real_size)
 
     # dense MFMA peaks of MI355X: fp32 157.3, fp64 78.6 TFLOP/s
     roof, stages = summary(mixed, 4, FP32_PEAK_TFLOPS)
@@ -455,12 +530,20 @@ def qc_main(args):
         "stages": stages,
         "roofline": roof,
     }
+    if mixed["particles"]:
+        line["particles"] = mixed["particles"]
+        line["particle_steps_per_s"] = mixed["particles"] * steps / mixed["wall_s"]
+        line["config"]["workload"] = (f"{args.qc}: quasi-cylindrical particle cycle, nz "
+                                      f"{w['nz']}, nr {w['nr']}, mode 0, an electron column of "
+                                      f"radius {w['rp']:g} ({w['ppc']} particles per (r, z) "
+                                      f"cell, {mixed['particles']} particles) drifting at "
+                                      f"gamma {w['gamma']:g} on its ion column, Galilean frame")
     if fp64 is not None:
         roof64, stages64 = summary(fp64, 8, FP64_PEAK_TFLOPS)
         line["fp64_gpu"] = {"value": cells * steps / fp64["wall_s"],
                             "ms_per_step": fp64["wall_s"] / steps * 1e3,
                             "stages": stages64, "roofline": roof64}
-    if not args.no_cpu:
+    if not args.no_cpu and not mixed["particles"]:
         line["cpu_baseline"] = qc_cpu_baseline(args.qc)
     print(json.dumps(line), flush=True)
 

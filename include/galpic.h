@@ -432,8 +432,10 @@ typedef struct {
  * neutralising ion column), complex [mode][z][r] host or device arrays of rho,
  * J_r, J_theta, J_z (a NULL one is zero; all NULL clears it).  Synchronising.
  * gp_qc_bind_particles: keeps the pointers (the caller keeps the arrays
- * alive), deposits rho^n (with the background) and makes it the spectral
- * rho^n.  Synchronising.  Errors: GP_ERR_ARG.
+ * alive), reorders the particles along z in place (a stable sort of all six
+ * arrays together, so that the deposit's chunks of consecutive particles
+ * cover few z planes), deposits rho^n (with the background) and makes it
+ * the spectral rho^n.  Synchronising.  Errors: GP_ERR_ARG.
  * gp_qc_electrostatic_fields: E^ = the curl-free field with i k.E^ = rho^n
  * (k_z Nyquist row zero), then the real E, B from E^, B^.
  * gp_qc_particle_step: nsteps of the Galilean-PSATD particle cycle (with u

@@ -440,12 +440,11 @@ __device__ __forceinline__ void qc_angle(T x, T y, T &r, T &c, T &s) {
   }
 }
 
-// Add c_m val exp(-i m theta) W s / V to the four nodes of every mode.
-template <typename T>
-__device__ __forceinline__ void qc_deposit(const QcGeo<T> &g, T *__restrict__ arr,
-                                           const QcNodes<T> &nd, T c, T s, T val,
-                                           bool transverse) {
-  const int64_t plane = int64_t(g.nz) * g.nr;
+// Add c_m val exp(-i m theta) W s / V to the four nodes of every mode,
+// through add(m, k, j, re, im).
+template <typename T, typename Add>
+__device__ __forceinline__ void qc_deposit(const QcGeo<T> &g, const QcNodes<T> &nd, T c, T s,
+                                           T val, bool transverse, Add &&add) {
   T er = T(1), ei = T(0);  // exp(-i m theta), advanced per mode
   for (int m = 0; m < g.nmodes; ++m) {
     const T cm = m == 0 ? T(1) : T(2);
@@ -461,9 +460,7 @@ __device__ __forceinline__ void qc_deposit(const QcGeo<T> &g, T *__restrict__ ar
       for (int b = 0; b < 2; ++b) {
         const int k = b ? nd.k1 : nd.k0;
         const T w = wr * (b ? nd.fz : T(1) - nd.fz);
-        const int64_t at = 2 * (int64_t(m) * plane + int64_t(k) * g.nr + jj);
-        atomicAdd(arr + at, w * vr);
-        atomicAdd(arr + at + 1, w * vi);
+        add(m, k, jj, w * vr, w * vi);
       }
     }
     // exp(-i (m+1) theta) = exp(-i m theta) (c - i s)
@@ -472,6 +469,19 @@ __device__ __forceinline__ void qc_deposit(const QcGeo<T> &g, T *__restrict__ ar
     ei = ni;
   }
 }
+
+// global atomics into a [mode][z][r] complex array (mode 0 adds no
+// imaginary parts: they are exact zeros)
+template <typename T>
+struct GlobalSink {
+  T *arr;
+  int nz, nr;
+  __device__ __forceinline__ void operator()(int m, int k, int j, T re, T im) const {
+    const int64_t at = 2 * ((int64_t(m) * nz + k) * nr + j);
+    atomicAdd(arr + at, re);
+    if (m > 0) atomicAdd(arr + at + 1, im);
+  }
+};
 
 // Re sum_m (sum over nodes of W s g_m) exp(i m theta) for one component.
 template <typename T>
@@ -511,14 +521,15 @@ struct QcSrc {
   T *jr, *jt, *jz, *rho;
 };
 
-// move = 1: x^n -> x_h (deposit J with v = u / gamma) -> x^{n+1} (deposit
-// rho); move = 0: deposit rho at x only.  Moves use v - v_gal (v_gal along
-// z); z wraps, x and y are open.
-template <typename T>
-__global__ __launch_bounds__(256) void k_qc_move_deposit(QcPart<T> p, QcGeo<T> g, QcSrc<T> src,
-                                                         T dt, T vgal, T qw, int move) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= p.n) return;
+// One particle's part of a move-and-deposit: with move, x^n -> x_h (J
+// deposited with v = u / gamma) -> x^{n+1} (stored; rho deposited there);
+// without, rho at x.  Moves use v - v_gal (v_gal along z); z wraps, x and y
+// are open.  sink(s) gives the sink of source s (0 J_r, 1 J_theta, 2 J_z,
+// 3 rho).
+template <typename T, typename SinkOf>
+__device__ __forceinline__ void qc_particle_deposit(const QcPart<T> &p, const QcGeo<T> &g,
+                                                    int64_t i, T dt, T vgal, T qw, int move,
+                                                    SinkOf &&sink) {
   T x = p.x[i], y = p.y[i], z = p.z[i];
   if (move) {
     const T ux = p.ux[i], uy = p.uy[i], uz = p.uz[i];
@@ -536,9 +547,9 @@ __global__ __launch_bounds__(256) void k_qc_move_deposit(QcPart<T> p, QcGeo<T> g
     qc_angle(x, y, r, c, s);
     const QcNodes<T> nd = qc_nodes(g, r, z);
     const T vr = vx * c + vy * s, vt = -vx * s + vy * c;
-    qc_deposit(g, src.jr, nd, c, s, qw * vr, true);
-    qc_deposit(g, src.jt, nd, c, s, qw * vt, true);
-    qc_deposit(g, src.jz, nd, c, s, qw * vz, false);
+    qc_deposit(g, nd, c, s, qw * vr, true, sink(0));
+    qc_deposit(g, nd, c, s, qw * vt, true, sink(1));
+    qc_deposit(g, nd, c, s, qw * vz, false, sink(2));
     x += h * vx;
     y += h * vy;
     z = wrap(z + h * (vz - vgal));
@@ -548,7 +559,100 @@ __global__ __launch_bounds__(256) void k_qc_move_deposit(QcPart<T> p, QcGeo<T> g
   }
   T r, c, s;
   qc_angle(x, y, r, c, s);
-  qc_deposit(g, src.rho, qc_nodes(g, r, z), c, s, qw, false);
+  qc_deposit(g, qc_nodes(g, r, z), c, s, qw, false, sink(3));
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_qc_move_deposit(QcPart<T> p, QcGeo<T> g, QcSrc<T> src,
+                                                         T dt, T vgal, T qw, int move) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= p.n) return;
+  T *arrs[4] = {global_ptr(src.jr), global_ptr(src.jt), global_ptr(src.jz),
+                global_ptr(src.rho)};
+  qc_particle_deposit(p, g, i, dt, vgal, qw, move, [=](int si) {
+    return GlobalSink<T>{arrs[si], g.nz, g.nr};
+  });
+}
+
+// The same with an LDS window: a workgroup takes kQcChunk consecutive
+// particles (sorted along z at binding, so a chunk covers few z nodes),
+// accumulates the nodes of kQcWin z planes from one plane below its first
+// particle in LDS ([source][mode][plane][r] complex), sends every other node
+// straight to global atomics, and flushes the window's nonzero entries with
+// global atomics at the end.
+constexpr int kQcDepThreads = 256;
+constexpr int kQcDepPer = 8;
+constexpr int kQcChunk = kQcDepThreads * kQcDepPer;
+constexpr int kQcWin = 4;
+
+template <typename T>
+__global__ __launch_bounds__(kQcDepThreads) void k_qc_move_deposit_tiled(QcPart<T> p, QcGeo<T> g,
+                                                                         QcSrc<T> src, T dt,
+                                                                         T vgal, T qw, int move) {
+  extern __shared__ __align__(16) unsigned char qdsm[];
+  T *win = reinterpret_cast<T *>(qdsm);
+  __shared__ int zs_sh;
+  const int64_t first = int64_t(blockIdx.x) * kQcChunk;
+  const int plane = g.nr * 2;                            // T values per z plane
+  const int per_src = g.nmodes * kQcWin * plane;
+  const int total = 4 * per_src;
+  if (threadIdx.x == 0) {
+    // one plane below the first particle's z after its first half move
+    T z = p.z[first];
+    if (move) {
+      const T ux = p.ux[first], uy = p.uy[first], uz = p.uz[first];
+      const T vz = uz / sqrt(T(1) + ux * ux + uy * uy + uz * uz);
+      z += T(0.5) * dt * (vz - vgal);
+    }
+    int k = int(floor(z * g.inv_dz)) % g.nz;
+    if (k < 0) k += g.nz;
+    zs_sh = (k - 1 + g.nz) % g.nz;
+  }
+  for (int t = threadIdx.x; t < total; t += kQcDepThreads) win[t] = T(0);
+  __syncthreads();
+  const int zs = zs_sh;
+  T *arrs[4] = {global_ptr(src.jr), global_ptr(src.jt), global_ptr(src.jz),
+                global_ptr(src.rho)};
+  const int nz = g.nz, nr = g.nr;
+  for (int q = 0; q < kQcDepPer; ++q) {
+    const int64_t i = first + int64_t(q) * kQcDepThreads + threadIdx.x;
+    if (i >= p.n) break;
+    qc_particle_deposit(p, g, i, dt, vgal, qw, move, [=](int si) {
+      T *garr = arrs[si];
+      T *warr = win + si * per_src;
+      return [=](int m, int k, int j, T re, T im) {
+        int slot = k - zs;
+        if (slot < 0) slot += nz;
+        // workgroup-scope adds for the window, device-scope ones for the
+        // grid (distinct scopes also keep the two from being merged into
+        // one flat atomic on a selected address)
+        if (slot < kQcWin) {
+          T *w = warr + (m * kQcWin + slot) * plane + 2 * j;
+          __hip_atomic_fetch_add(w, re, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          if (m > 0)
+            __hip_atomic_fetch_add(w + 1, im, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        } else {
+          const int64_t at = 2 * ((int64_t(m) * nz + k) * nr + j);
+          __hip_atomic_fetch_add(garr + at, re, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (m > 0)
+            __hip_atomic_fetch_add(garr + at + 1, im, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+      };
+    });
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < total; t += kQcDepThreads) {
+    const T v = win[t];
+    if (v == T(0)) continue;
+    const int si = t / per_src;
+    const int r1 = t % per_src;
+    const int m = r1 / (kQcWin * plane);
+    const int r2 = r1 % (kQcWin * plane);
+    const int slot = r2 / plane;
+    const int e = r2 % plane;  // 2 j + part
+    const int k = (zs + slot) % g.nz;
+    atomicAdd(global_ptr(arrs[si] + 2 * ((int64_t(m) * g.nz + k) * g.nr) + e), v);
+  }
 }
 
 // Gather E, B at x (the mode fields [m][z][r]: r, theta, z components), then
@@ -1129,6 +1233,39 @@ gp_status fill_sources(gp_qc_ctx *c) {
   return GP_OK;
 }
 
+// Reorder the particles along z (stable, in the caller's arrays), so that
+// the deposit's chunks of consecutive particles cover few z planes.  On the
+// host, at binding only.
+template <typename T>
+gp_status sort_particles_by_z(gp_qc_ctx *c) {
+  const int64_t n = c->part.n;
+  if (n < 2) return GP_OK;
+  void *dev[6] = {c->part.x, c->part.y, c->part.z, c->part.ux, c->part.uy, c->part.uz};
+  std::vector<std::vector<T>> h(6, std::vector<T>(static_cast<size_t>(n)));
+  for (int a = 0; a < 6; ++a)
+    if (hipMemcpyAsync(h[a].data(), dev[a], size_t(n) * sizeof(T), hipMemcpyDeviceToHost,
+                       c->stream) != hipSuccess)
+      return qfail(GP_ERR_HIP, "particle download failed");
+  if (hipStreamSynchronize(c->stream) != hipSuccess)
+    return qfail(GP_ERR_HIP, "stream synchronize failed");
+  std::vector<int64_t> idx(static_cast<size_t>(n));
+  for (int64_t i = 0; i < n; ++i) idx[size_t(i)] = i;
+  const std::vector<T> &z = h[2];
+  std::stable_sort(idx.begin(), idx.end(),
+                   [&](int64_t a, int64_t b) { return z[size_t(a)] < z[size_t(b)]; });
+  std::vector<T> tmp(static_cast<size_t>(n));
+  for (int a = 0; a < 6; ++a) {
+    for (int64_t i = 0; i < n; ++i) tmp[size_t(i)] = h[a][size_t(idx[size_t(i)])];
+    h[a].swap(tmp);
+    if (hipMemcpyAsync(dev[a], h[a].data(), size_t(n) * sizeof(T), hipMemcpyHostToDevice,
+                       c->stream) != hipSuccess)
+      return qfail(GP_ERR_HIP, "particle upload failed");
+    if (hipStreamSynchronize(c->stream) != hipSuccess)  // before tmp is reused
+      return qfail(GP_ERR_HIP, "stream synchronize failed");
+  }
+  return GP_OK;
+}
+
 template <typename T>
 void launch_move_deposit(gp_qc_ctx *c, int move) {
   if (c->part.n == 0) return;
@@ -1138,9 +1275,17 @@ void launch_move_deposit(gp_qc_ctx *c, int move) {
   src.jz = static_cast<T *>(c->real[8]);
   src.rho = static_cast<T *>(c->real[9]);
   QStamp stamp(c, 5);
-  hipLaunchKernelGGL((k_qc_move_deposit<T>), dim3(unsigned((c->part.n + 255) / 256)), dim3(256),
-                     0, c->stream, qc_part<T>(c), qc_geo<T>(c), src, T(c->d.dt), T(c->vgal),
-                     T(c->part.q * c->part.w), move);
+  const size_t lds = size_t(4) * c->d.nmodes * kQcWin * c->d.nr * 2 * sizeof(T);
+  if (lds <= 65536) {
+    hipLaunchKernelGGL((k_qc_move_deposit_tiled<T>),
+                       dim3(unsigned((c->part.n + kQcChunk - 1) / kQcChunk)), dim3(kQcDepThreads),
+                       lds, c->stream, qc_part<T>(c), qc_geo<T>(c), src, T(c->d.dt), T(c->vgal),
+                       T(c->part.q * c->part.w), move);
+  } else {
+    hipLaunchKernelGGL((k_qc_move_deposit<T>), dim3(unsigned((c->part.n + 255) / 256)),
+                       dim3(256), 0, c->stream, qc_part<T>(c), qc_geo<T>(c), src, T(c->d.dt),
+                       T(c->vgal), T(c->part.q * c->part.w), move);
+  }
 }
 
 template <typename T>
@@ -1400,6 +1545,7 @@ gp_status gp_qc_bind_particles(gp_qc_ctx *c, const gp_qc_particles *p) {
     return qfail(GP_ERR_ARG, "a particle array is NULL");
   c->part = *p;
   c->bound = true;
+  QTRY(c->d.precision == GP_FP64 ? sort_particles_by_z<double>(c) : sort_particles_by_z<float>(c));
   QTRY(fill_sources(c));
   // rho^n of the particles (and the background), transformed into the
   // rho^{n+1} slot, which then becomes rho^n

@@ -46,7 +46,10 @@ def _column(rng, n, rp, lz, precision, gamma=None, u_th=0.0):
     u = u_th * rng.standard_normal((n, 3))
     if gamma is not None:
         u[:, 2] += -np.sqrt(gamma * gamma - 1.0)
-    return _round(x, precision), _round(u, precision)
+    x, u = _round(x, precision), _round(u, precision)
+    # in the order the library keeps them: stably sorted along z
+    order = np.argsort(x[:, 2], kind="stable")
+    return x[order], u[order]
 
 
 def _gpu_particles(x, u, precision):
@@ -244,3 +247,31 @@ def test_particle_errors(gpu_lib):
     ctx.particle_step(2)
     ctx.synchronize()
     ctx.close()
+
+
+@pytest.mark.parametrize("precision", [gp.GP_FP64, gp.GP_MIXED])
+def test_binding_sorts_along_z(gpu_lib, precision):
+    """The library reorders the particles along z at binding (all six
+    arrays together); the deposit does not depend on the input order."""
+    nz, nr, nm, dz, dr = 32, 12, 1, 1.0, 1.0
+    rng = np.random.default_rng(404)
+    x, u = _column(rng, 6000, 9.0, nz * dz, precision, gamma=3.0, u_th=0.1)
+    perm = rng.permutation(len(x))
+    xs, us = x[perm], u[perm]
+    out = []
+    for xin, uin in ((x, u), (xs, us)):
+        ctx = gp.QcContext(nz, nr, nm, dz, dr, 0.5, precision)
+        parts = _gpu_particles(xin, uin, precision)
+        ctx.bind_particles(-1.0, 1.0, 0.2, *parts)
+        xb, ub = _particles_back(parts)
+        assert np.all(np.diff(xb[:, 2]) >= 0)
+        # the same particles, moved together
+        key = lambda a, b: np.lexsort((b[:, 2], a[:, 1], a[:, 0], a[:, 2]))
+        ref = key(xin, uin)
+        got = key(xb, ub)
+        assert np.array_equal(xb[got], xin[ref]) and np.array_equal(ub[got], uin[ref])
+        ctx.particle_step(2)
+        ctx.synchronize()
+        out.append(ctx.read("RHO"))
+        ctx.close()
+    assert rel_l2(out[1], out[0]) <= tol_for(precision)
