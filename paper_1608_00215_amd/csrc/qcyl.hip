@@ -655,6 +655,20 @@ __global__ __launch_bounds__(kQcDepThreads) void k_qc_move_deposit_tiled(QcPart<
   }
 }
 
+// Reset the four real-space sources before a deposit: each takes the
+// background's values, or zero (n values of the real type per array).
+template <typename T>
+__global__ __launch_bounds__(256) void k_qc_reset_sources(QcSrc<T> dst, QcSrc<T> bg, int has_bg,
+                                                          int64_t n) {
+  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= 4 * n) return;
+  const int a = int(idx / n);
+  const int64_t i = idx % n;
+  T *d = a == 0 ? dst.rho : (a == 1 ? dst.jr : (a == 2 ? dst.jt : dst.jz));
+  const T *b = a == 0 ? bg.rho : (a == 1 ? bg.jr : (a == 2 ? bg.jt : bg.jz));
+  d[i] = has_bg ? b[i] : T(0);
+}
+
 // Gather E, B at x (the mode fields [m][z][r]: r, theta, z components), then
 // the relativistic Boris push of u over dt (c = 1).
 template <typename T>
@@ -1220,17 +1234,25 @@ QcPart<T> qc_part(gp_qc_ctx *c) {
   return q;
 }
 
-// the real-space sources start each deposit as the background (or zero)
+// the real-space sources start each deposit as the background (or zero),
+// in one launch
 gp_status fill_sources(gp_qc_ctx *c) {
-  const size_t fb = field_bytes(c);
-  for (int a = 0; a < 4; ++a) {
-    void *dst = c->real[a == 0 ? 9 : 5 + a];  // RHO, then J_r, J_theta, J_z
-    const hipError_t e = c->has_bg ? hipMemcpyAsync(dst, c->bg[a], fb, hipMemcpyDeviceToDevice,
-                                                    c->stream)
-                                   : hipMemsetAsync(dst, 0, fb, c->stream);
-    if (e != hipSuccess) return qfail(GP_ERR_HIP, "source reset failed");
-  }
-  return GP_OK;
+  return qdispatch(c, [&](auto t) {
+    using T = decltype(t);
+    QcSrc<T> dst, bg;
+    dst.rho = static_cast<T *>(c->real[9]);
+    dst.jr = static_cast<T *>(c->real[6]);
+    dst.jt = static_cast<T *>(c->real[7]);
+    dst.jz = static_cast<T *>(c->real[8]);
+    // without a background the kernel never reads these
+    bg.rho = static_cast<T *>(c->has_bg ? c->bg[0] : c->real[9]);
+    bg.jr = static_cast<T *>(c->has_bg ? c->bg[1] : c->real[6]);
+    bg.jt = static_cast<T *>(c->has_bg ? c->bg[2] : c->real[7]);
+    bg.jz = static_cast<T *>(c->has_bg ? c->bg[3] : c->real[8]);
+    const int64_t n = int64_t(c->d.nmodes) * c->d.nz * c->d.nr * 2;  // real values per array
+    hipLaunchKernelGGL((k_qc_reset_sources<T>), dim3(unsigned((4 * n + 255) / 256)), dim3(256), 0,
+                       c->stream, dst, bg, c->has_bg ? 1 : 0, n);
+  });
 }
 
 // Reorder the particles along z (stable, in the caller's arrays), so that
