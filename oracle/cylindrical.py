@@ -20,6 +20,18 @@ down.  Readings taken here:
   zeros of J_m.  Backward (spectral -> radial) transform of order p:
   F(r_j) = sum_i F^_i J_p(k_i r_j); the forward transform is its matrix
   inverse.
+* Completing the order m - 1 set (m >= 1): on the zeros of J_m the
+  functions J_{m-1}(k_i r) form a Dini series (x J'_{m-1} - (m-1) J_{m-1} =
+  0 there), which is complete only with the extra eigenfunction r^{m-1}
+  (k_r = 0).  Without it a G_- that does not vanish on average (for m = 1
+  a transverse field or current uniform across the axis) is carried by
+  large high-k_r coefficients with a wrong divergence, and a particle
+  column moving sideways runs away.  So for m >= 1 the last G_- function is
+  (r / R)^{m-1} at k_r = 0, and the last k_r column of G_+, G_z and the
+  scalars (order m + 1 and m, k = alpha_{m,N_r} / R) is held at zero, like
+  a Nyquist plane; at k_r = 0 the Cartesian update keeps G_+ at zero by
+  itself (F^_x = i G^_-, F^_y = -G^_-).  The orders m and m + 1 on these
+  zeros, and order -1 for m = 0, are complete already.
 * The update: the 2D Fourier transform of f(r) exp(i p theta) is
   2 pi (-i)^p exp(i p phi) times the Hankel transform of order p.  At
   azimuth phi = 0 of the wavevector k = (k_r, 0, k_z) the Cartesian
@@ -51,14 +63,6 @@ down.  Readings taken here:
     x and y.
   The particle cycle (moves, time-centring, push) is the Cartesian one,
   with z periodic and x, y open.
-* A limit of this grid reading, measured here: the order m - 1 transform
-  on the J_m zero grid has no k_r = 0 function, so for m = 1 a transverse
-  field or current that is uniform across the axis (G_- constant in r) is
-  carried by large high-k_r coefficients and its spectral divergence is
-  wrong.  A particle column moving sideways then violates continuity by
-  orders of magnitude in mode 1 and the cycle runs away.  The particle
-  cycle is pinned for the axisymmetric mode (m = 0) only; the field solve
-  of every mode keeps its pins (they hold for each basis function).
 """
 
 import functools
@@ -79,11 +83,30 @@ def spectral_kr(m, nr, dr):
     return special.jn_zeros(m, nr) / (nr * dr)
 
 
+def held_column(m):
+    """True if mode m holds its last k_r column (of G_+, G_z and scalars)
+    at zero and carries the k_r = 0 function of G_- there."""
+    return m >= 1
+
+
+def update_kr(m, nr, dr):
+    """k_r of each spectral column in the update: the zeros of J_m, with 0
+    in the last column of modes that hold it."""
+    k = spectral_kr(m, nr, dr)
+    if held_column(m):
+        k[-1] = 0.0
+    return k
+
+
 def backward_matrix(p, m, nr, dr):
-    """M[j, i] = J_p(k_i r_j) on mode m's spectral grid."""
+    """M[j, i] = J_p(k_i r_j) on mode m's spectral grid; for p = m - 1 of a
+    mode that holds its last column, that column is (r_j / R)^{m-1}."""
     r = radial_grid(nr, dr)
     k = spectral_kr(m, nr, dr)
-    return special.jv(p, np.outer(r, k))
+    M = special.jv(p, np.outer(r, k))
+    if held_column(m) and p == m - 1:
+        M[:, -1] = (r / (nr * dr)) ** (m - 1)
+    return M
 
 
 def forward_matrix(p, m, nr, dr):
@@ -145,20 +168,38 @@ def held_mask(nz, nr):
 @functools.lru_cache(maxsize=64)
 def _mode_tables(m, nr, dr, nz, dz, v_gal_z, dt):
     kz = axis_kz(nz, dz)[:, None] * np.ones((1, nr))
-    kr = np.ones((nz, 1)) * spectral_kr(m, nr, dr)[None, :]
+    kr = np.ones((nz, 1)) * update_kr(m, nr, dr)[None, :]
     k = (kr, np.zeros_like(kr), kz)
     coef = galilean_psatd_coefficients(k, (0.0, 0.0, v_gal_z), dt)
     return k, coef, held_mask(nz, nr)
 
 
+def hold(G, m):
+    """(G_+, G_-, G_z) with the held column of G_+ and G_z zeroed."""
+    G = tuple(np.array(a, dtype=complex) for a in G)
+    if held_column(m):
+        G[0][:, -1] = 0.0
+        G[2][:, -1] = 0.0
+    return G
+
+
+def hold_scalar(f, m):
+    f = np.array(f, dtype=complex)
+    if held_column(m):
+        f[:, -1] = 0.0
+    return f
+
+
 def mode_update(E, B, J, rho_old, rho_new, m, nr, dr, nz, dz, v_gal_z, dt):
     """Advance the spectral (G^_+, G^_-, G^_z) of E and B of mode m by one
     Galilean-PSATD step ([k_z][k_r] arrays), through the Cartesian update
-    at k = (k_r, 0, k_z)."""
+    at k = (k_r, 0, k_z) (k_r = 0 in a held column, whose G_+, G_z and
+    scalar entries are taken as zero and stay zero)."""
     k, coef, mask = _mode_tables(m, nr, dr, nz, dz, v_gal_z, dt)
-    En, Bn = sp.galilean_psatd_update(to_cartesian(E), to_cartesian(B), to_cartesian(J),
-                                      rho_old, rho_new, k, coef, mask)
-    return from_cartesian(En), from_cartesian(Bn)
+    En, Bn = sp.galilean_psatd_update(to_cartesian(hold(E, m)), to_cartesian(hold(B, m)),
+                                      to_cartesian(hold(J, m)), hold_scalar(rho_old, m),
+                                      hold_scalar(rho_new, m), k, coef, mask)
+    return hold(from_cartesian(En), m), hold(from_cartesian(Bn), m)
 
 
 # ---- particles: deposition and gather by azimuthal mode ----------------------
@@ -326,12 +367,14 @@ class CylindricalPIC:
         curl: E^_c = -i k rho^ / |k|^2 at k = (k_r, 0, k_z), through the
         Cartesian map (every mode has k_r > 0; the held k_z row stays 0)."""
         kz = axis_kz(self.nz, self.dz)[:, None] * np.ones((1, self.nr))
-        kr = np.ones((self.nz, 1)) * spectral_kr(m, self.nr, self.dr)[None, :]
+        kr = np.ones((self.nz, 1)) * update_kr(m, self.nr, self.dr)[None, :]
         k2 = kr * kr + kz * kz
-        live = ~held_mask(self.nz, self.nr)
-        Ec = tuple(np.where(live, -1j * ka * rho_hat / k2, 0.0)
+        rho = hold_scalar(rho_hat, m)
+        live = ~held_mask(self.nz, self.nr) & (k2 > 0)
+        safe = np.where(k2 > 0, k2, 1.0)
+        Ec = tuple(np.where(live, -1j * ka * rho / safe, 0.0)
                    for ka in (kr, np.zeros_like(kr), kz))
-        return from_cartesian(Ec)
+        return hold(from_cartesian(Ec), m)
 
     def initial_state(self, x, u, E=None, B=None, electrostatic=False):
         """x, u (n, 3); optional real mode fields E, B [m] = (r, theta, z);

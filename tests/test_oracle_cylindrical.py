@@ -102,11 +102,11 @@ def test_mode_update_keeps_gauss_law():
     rng = np.random.default_rng(90)
     m, nz, nr, dr, dz, dt, v = 1, 8, 12, 0.5, 0.5, 0.4, -0.9
     kz = cy.axis_kz(nz, dz)[:, None] * np.ones((1, nr))
-    kr = np.ones((nz, 1)) * cy.spectral_kr(m, nr, dr)[None, :]
+    kr = np.ones((nz, 1)) * cy.update_kr(m, nr, dr)[None, :]
     cplx = lambda: rng.standard_normal((nz, nr)) + 1j * rng.standard_normal((nz, nr))
-    E = tuple(cplx() for _ in range(3))
-    B = tuple(cplx() for _ in range(3))
-    J = tuple(cplx() for _ in range(3))
+    E = cy.hold(tuple(cplx() for _ in range(3)), m)
+    B = cy.hold(tuple(cplx() for _ in range(3)), m)
+    J = cy.hold(tuple(cplx() for _ in range(3)), m)
     Ec, Jc = cy.to_cartesian(E), cy.to_cartesian(J)
     rho0 = 1j * (kr * Ec[0] + kz * Ec[2])
     kJ = kr * Jc[0] + kz * Jc[2]
@@ -224,7 +224,8 @@ def test_angular_density_modulation_is_its_mode_one_content():
     assert np.allclose(g1[live] / g0[live], a * np.exp(-1j * phi), rtol=0, atol=1e-14)
 
 
-def _drifting_column(galilean, steps, seed=1, nz=64, nr=12, n=20000, gamma=10.0, rp=8.0):
+def _drifting_column(galilean, steps, seed=1, nz=64, nr=12, n=20000, gamma=10.0, rp=8.0,
+                     nmodes=2):
     rng = np.random.default_rng(seed)
     r = rp * np.sqrt(rng.uniform(0, 1, n))
     th = rng.uniform(0, 2 * np.pi, n)
@@ -234,9 +235,9 @@ def _drifting_column(galilean, steps, seed=1, nz=64, nr=12, n=20000, gamma=10.0,
     u[:, 2] = uz
     vz = uz / np.sqrt(1.0 + uz * uz)
     w = np.pi * rp * rp * nz / n
-    bg = cy.uniform_cylinder_background(1.0, rp, vz, 1, nr, 1.0, nz, 1.0)
-    sim = cy.CylindricalPIC(nz, nr, 1, 1.0, 1.0, 1.0, -1.0, 1.0, w, vz if galilean else 0.0,
-                            background=bg)
+    bg = cy.uniform_cylinder_background(1.0, rp, vz, nmodes, nr, 1.0, nz, 1.0)
+    sim = cy.CylindricalPIC(nz, nr, nmodes, 1.0, 1.0, 1.0, -1.0, 1.0, w,
+                            vz if galilean else 0.0, background=bg)
     st = sim.initial_state(x, u, electrostatic=True)
     W = []
     for _ in range(steps):
@@ -245,18 +246,19 @@ def _drifting_column(galilean, steps, seed=1, nz=64, nr=12, n=20000, gamma=10.0,
     return np.array(W)
 
 
-def test_nci_pair_in_the_axisymmetric_geometry():
-    """The paper's contrast in its own (quasi-cylindrical) geometry, mode 0:
-    an electron column (gamma 10, density 1, radius 8, on a neutralising ion
-    column) drifting along -z stays quiet on the Galilean grid and grows
-    under standard PSATD.  Calibrated on this oracle (80 steps, dt = dz / c):
-    Galilean max W = 11.3 W(1), standard W(80) = 329 W(1), 52 times the
-    Galilean W(80); the bars leave a factor of about 2 to 3."""
+def test_nci_pair_in_the_quasi_cylindrical_geometry():
+    """The paper's contrast in its own (quasi-cylindrical) geometry, modes 0
+    and 1: an electron column (gamma 10, density 1, radius 8, on a
+    neutralising ion column) drifting along -z stays quiet on the Galilean
+    grid and grows under standard PSATD.  Calibrated on this oracle (80
+    steps, dt = dz / c): Galilean max W = 8.8 W(1), standard W(80) = 120 W(1),
+    18 times the Galilean W(80); the bars leave a factor of about 2 to 3.
+    (With mode 0 alone: 11.3, 329 and 52.)"""
     gal = _drifting_column(True, 80)
     std = _drifting_column(False, 80)
     assert gal.max() <= 25.0 * gal[0]
-    assert std[-1] >= 100.0 * std[0]
-    assert std[-1] >= 20.0 * gal[-1]
+    assert std[-1] >= 50.0 * std[0]
+    assert std[-1] >= 8.0 * gal[-1]
 
 
 def test_electrostatic_start_satisfies_gauss():
@@ -268,9 +270,64 @@ def test_electrostatic_start_satisfies_gauss():
     live = ~cy.held_mask(nz, nr)
     for m in range(2):
         kz = cy.axis_kz(nz, dz)[:, None] * np.ones((1, nr))
-        kr = np.ones((nz, 1)) * cy.spectral_kr(m, nr, dr)[None, :]
+        kr = np.ones((nz, 1)) * cy.update_kr(m, nr, dr)[None, :]
         Ec = cy.to_cartesian(st["E_hat"][m])
-        gauss = 1j * (kr * Ec[0] + kz * Ec[2]) - st["rho_hat"][m]
-        assert np.max(np.abs(gauss[live])) <= 1e-12 * np.max(np.abs(st["rho_hat"][m]))
+        gauss = 1j * (kr * Ec[0] + kz * Ec[2]) - cy.hold_scalar(st["rho_hat"][m], m)
+        keep = live & ((kr * kr + kz * kz) > 0)
+        assert np.max(np.abs(gauss[keep])) <= 1e-12 * np.max(np.abs(st["rho_hat"][m]))
         # and curl-free: k x E = 0
         assert np.max(np.abs((kz * Ec[0] - kr * Ec[2])[live])) <= 1e-12 * np.max(np.abs(Ec[0]))
+
+
+@pytest.mark.parametrize("m", [1, 2, 3])
+def test_order_m_minus_1_set_is_complete(m):
+    """On the zeros of J_m the functions J_{m-1}(k_i r) are a Dini series
+    that needs r^{m-1} (k_r = 0) to be complete.  With it, G_- = (r/R)^{m-1}
+    is one coefficient; the mode's field (F_r, F_theta) = (G_-, i G_-)
+    (for m = 1: the uniform field E_x = 1) then has zero divergence
+    spectrally, and the transforms still invert."""
+    nz, nr, dz, dr = 8, 16, 0.5, 0.4
+    r = cy.radial_grid(nr, dr)
+    gm = np.ones((nz, 1)) * (r / (nr * dr))[None, :] ** (m - 1) + 0j
+    F = (gm, 1j * gm, np.zeros_like(gm))     # G_- = (F_r - i F_theta) / 2 = gm, G_+ = 0
+    G = cy.to_spectral(F, m, dr, dz)
+    assert np.max(np.abs(G[1][0, :-1])) <= 1e-10 * nz  # only the k_r = 0 column
+    assert abs(G[1][0, -1] - nz) <= 1e-10 * nz          # (the z transform's factor nz)
+    kz = cy.axis_kz(nz, dz)[:, None] * np.ones((1, nr))
+    kr = np.ones((nz, 1)) * cy.update_kr(m, nr, dr)[None, :]
+    Ec = cy.to_cartesian(G)
+    assert np.max(np.abs(1j * (kr * Ec[0] + kz * Ec[2]))) <= 1e-10 * nz
+    back = cy.from_spectral(G, m, dr, dz)
+    for a, b in zip(back, F):
+        assert np.max(np.abs(a - b)) <= 1e-10
+
+
+def test_sideways_current_keeps_continuity_in_mode_one():
+    """A uniform column moving along x: its mode-1 charge change and the
+    spectral divergence of its mode-1 current agree as well as in mode 0
+    (direct deposition is not charge-conserving, so neither is exact).
+    Without the k_r = 0 function the mode-1 mismatch was about 8000 times
+    the charge change."""
+    rng = np.random.default_rng(105)
+    nz, nr, dz, dr, dt = 8, 12, 1.0, 1.0, 0.05
+    n, rp = 20000, 6.0
+    r = rp * np.sqrt(rng.uniform(0, 1, n))
+    th = rng.uniform(0, 2 * np.pi, n)
+    x = np.stack([r * np.cos(th), r * np.sin(th), rng.uniform(0, nz * dz, n)], 1)
+    v = np.tile([0.5, 0.0, 0.0], (n, 1))
+    xh, xn = x + v * dt / 2, x + v * dt
+    res = []
+    for m in (0, 1):
+        r0 = cy.deposit_mode(x[:, 0], x[:, 1], x[:, 2], np.ones(n), m, "scalar", nr, dr, nz, dz)
+        r1 = cy.deposit_mode(xn[:, 0], xn[:, 1], xn[:, 2], np.ones(n), m, "scalar", nr, dr, nz,
+                             dz)
+        J = cy.deposit_current(xh[:, 0], xh[:, 1], xh[:, 2], v, 1.0, 2, nr, dr, nz, dz)[m]
+        dr_dt = cy.hold_scalar((cy.scalar_to_spectral(r1, m, dr, dz)
+                                - cy.scalar_to_spectral(r0, m, dr, dz)) / dt, m)
+        Ec = cy.to_cartesian(cy.hold(cy.to_spectral(J, m, dr, dz), m))
+        kz = cy.axis_kz(nz, dz)[:, None] * np.ones((1, nr))
+        kr = np.ones((nz, 1)) * cy.update_kr(m, nr, dr)[None, :]
+        live = ~cy.held_mask(nz, nr)
+        div = 1j * (kr * Ec[0] + kz * Ec[2])
+        res.append(np.linalg.norm((dr_dt + div)[live]) / np.linalg.norm(dr_dt[live]))
+    assert res[1] <= 3.0 * max(res[0], 1.0)
