@@ -340,8 +340,8 @@ const char *gp_last_error(void);
  * azimuthal modes m, discrete Hankel transforms along r in place of the
  * transverse Fourier transforms; the Galilean scheme does not depend on the
  * geometry.  This context advances the fields of nmodes modes with the
- * Galilean-PSATD update for given sources (particles in azimuthal modes are
- * not part of it).  Readings (the paper does not print the scheme):
+ * Galilean-PSATD update for given sources, and (below) particles deposited
+ * and gathered by mode.  Readings (the paper does not print the scheme):
  *  - a mode m field is F_m(r, z) exp(i m theta); G_+ = (F_r + i F_theta)/2
  *    carries Hankel order m+1, G_- = (F_r - i F_theta)/2 order m-1, F_z
  *    and rho order m;
@@ -350,6 +350,11 @@ const char *gp_last_error(void);
  *    backward transform F(r_j) = sum_i F^_i J_p(k_i r_j), forward its
  *    matrix inverse; z periodic with the Cartesian Fourier convention, the
  *    k_z Nyquist plane held at zero;
+ *  - for m >= 1 the order m-1 functions on the zeros of J_m are a Dini
+ *    series that needs r^{m-1} (k_r = 0) to be complete: the last G_-
+ *    function is (r / R)^{m-1} at k_r = 0, and the last k_r column of G_+,
+ *    G_z and the scalars is held at zero (without this a G_- with nonzero
+ *    mean, e.g. a uniform transverse mode-1 field, has a wrong divergence);
  *  - the update is the Cartesian Galilean-PSATD update at k = (k_r, 0, k_z)
  *    applied to F^_x = i (G^_- - G^_+), F^_y = -(G^_+ + G^_-), F^_z = G^_z;
  *    v_gal is along z.
@@ -422,11 +427,7 @@ typedef struct {
  * inside dr/2 folds its inner weight onto node 0 with (-1)^m (scalars, z
  * components) or (-1)^(m+1) (r, theta components); node j's volume is its
  * folded weight's integral against 2 pi r dr dz; weights past the last node
- * are dropped.  Caution: the order m-1 transform on the J_m zero grid has no
- * k_r = 0 function, so mode-1 fields and currents that are uniform across
- * the axis are carried by large high-k_r coefficients with a wrong spectral
- * divergence; a plasma column moving sideways then runs away.  Runs with
- * particles are sound for nmodes = 1 (axisymmetric) only.
+ * are dropped.
  *
  * gp_qc_set_background: a fixed source added to every deposit (e.g. a
  * neutralising ion column), complex [mode][z][r] host or device arrays of rho,
@@ -463,10 +464,12 @@ gp_status gp_qc_destroy(gp_qc_ctx *ctx);
 /* Host-only (no GPU, no context): the spectral grid and transform matrices
  * a context builds, for callers that prepare or read spectral fields.
  * gp_qc_wavenumbers writes k_i = alpha_{m,i} / (nr dr), i < nr, the first nr
- * positive zeros of J_m over R.  gp_qc_hankel_matrix writes, row-major
- * nr x nr, the backward matrix of Hankel order p on mode m's grid,
- * M[j][i] = J_p(k_i r_j) with r_j = (j + 1/2) dr (radial j <- spectral i),
- * or, with forward != 0, its inverse A[i][j] (spectral i <- radial j).  A
+ * positive zeros of J_m over R (for m >= 1 the update takes k_r = 0 in the
+ * last column, see above).  gp_qc_hankel_matrix writes, row-major nr x nr,
+ * the backward matrix of Hankel order p on mode m's grid, M[j][i] =
+ * J_p(k_i r_j) with r_j = (j + 1/2) dr (radial j <- spectral i), its last
+ * column (r_j / R)^{m-1} for p = m - 1, m >= 1; or, with forward != 0, its
+ * inverse A[i][j] (spectral i <- radial j).  A
  * context applies these (the backward one divided by nz, in the run's real
  * type) along r.  Errors: GP_ERR_ARG (NULL output, m outside [0, 63], p
  * outside [-64, 64], nr outside [1, 512], dr not positive and finite, a

@@ -335,8 +335,11 @@ __global__ __launch_bounds__(256) void k_qc_update(QcUpd<T> p, int nmodes, int n
     }
     return;
   }
-  const T kr = p.kr[int64_t(m) * nr + i];
+  const T kr = p.kr[int64_t(m) * nr + i];  // 0 in a held column
   const T kz = T(iz < nz / 2 ? iz : iz - nz) * kzfac;
+  // modes m >= 1 hold the last k_r column of G_+, G_z and the scalars at
+  // zero; G_- carries its k_r = 0 function there
+  const bool held = m >= 1 && i == nr - 1;
   // azimuth-0 Cartesian components: x = i (G_- - G_+), y = -(G_+ + G_-), z
   auto to_cart = [](const Cx<T> g[3], Cx<T> f[3]) {
     f[0] = mul_i(g[1] - g[0]);
@@ -346,15 +349,17 @@ __global__ __launch_bounds__(256) void k_qc_update(QcUpd<T> p, int nmodes, int n
   Cx<T> Eg[3], Bg[3], Jg[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    Eg[a] = p.E[a][idx];
-    Bg[a] = p.B[a][idx];
-    Jg[a] = p.J[a][idx];
+    const bool zero = held && a != 1;
+    Eg[a] = zero ? cx(T(0), T(0)) : p.E[a][idx];
+    Bg[a] = zero ? cx(T(0), T(0)) : p.B[a][idx];
+    Jg[a] = zero ? cx(T(0), T(0)) : p.J[a][idx];
   }
   Cx<T> E[3], B[3], J[3];
   to_cart(Eg, E);
   to_cart(Bg, B);
   to_cart(Jg, J);
-  const Cx<T> r0 = p.rho_old[idx], r1 = p.rho_new[idx];
+  const Cx<T> r0 = held ? cx(T(0), T(0)) : p.rho_old[idx];
+  const Cx<T> r1 = held ? cx(T(0), T(0)) : p.rho_new[idx];
   const Cx<T> c0 = p.coef[0][idx], c1 = p.coef[1][idx], c2 = p.coef[2][idx];
   const Cx<T> c3 = p.coef[3][idx], c4 = p.coef[4][idx], c5 = p.coef[5][idx];
   Cx<T> kE[3], kB[3], kJ[3];
@@ -370,10 +375,11 @@ __global__ __launch_bounds__(256) void k_qc_update(QcUpd<T> p, int nmodes, int n
     En[a] = c0 * E[a] + c1 * kB[a] + c3 * J[a] + kk[a] * rho_i;
   }
   // back: G_+ = (i / 2)(x + i y), G_- = -(i / 2)(x - i y)
-  auto from_cart = [](const Cx<T> f[3], Cx<T> *const g[3], int64_t at) {
-    g[0][at] = T(0.5) * mul_i(f[0] + mul_i(f[1]));
+  auto from_cart = [held](const Cx<T> f[3], Cx<T> *const g[3], int64_t at) {
+    const Cx<T> z = cx(T(0), T(0));
+    g[0][at] = held ? z : T(0.5) * mul_i(f[0] + mul_i(f[1]));
     g[1][at] = T(-0.5) * mul_i(f[0] - mul_i(f[1]));
-    g[2][at] = f[2];
+    g[2][at] = held ? z : f[2];
   };
   from_cart(En, p.E, idx);
   from_cart(Bn, p.B, idx);
@@ -717,7 +723,9 @@ __global__ __launch_bounds__(256) void k_qc_electrostatic(Cx<T> *Ep, Cx<T> *Em, 
   const int i = int(idx % nr);
   const int iz = int((idx / nr) % nz);
   const int m = int(idx / (int64_t(nz) * nr));
-  if (iz == nz / 2) {
+  // the held k_z row, and the held last k_r column of modes m >= 1 (its
+  // charge is held at zero)
+  if (iz == nz / 2 || (m >= 1 && i == nr - 1)) {
     Ep[idx] = Em[idx] = Ez[idx] = cx(T(0), T(0));
     return;
   }
@@ -889,12 +897,20 @@ std::vector<double> spectral_kr(int m, int nr, double dr) {
   return k;
 }
 
-// The backward matrix of Hankel order p on the grid k: M[j][i] = J_p(k_i r_j)
-// (row-major nr x nr, r_j = (j + 1/2) dr).
-std::vector<double> backward_hankel(int p, const std::vector<double> &k, int nr, double dr) {
+// The backward matrix of Hankel order p on mode m's grid k: M[j][i] =
+// J_p(k_i r_j) (row-major nr x nr, r_j = (j + 1/2) dr).  For p = m - 1,
+// m >= 1, the last column is (r_j / R)^{m-1}: on the zeros of J_m the
+// functions J_{m-1}(k_i r) form a Dini series (x J'_{m-1} = (m-1) J_{m-1}
+// there) that is complete only with that k_r = 0 eigenfunction; it takes
+// the place of the last J_{m-1}, whose column of the other orders is held.
+std::vector<double> backward_hankel(int p, int m, const std::vector<double> &k, int nr,
+                                    double dr) {
   std::vector<double> M(size_t(nr) * nr);
   for (int j = 0; j < nr; ++j)
     for (int i = 0; i < nr; ++i) M[size_t(j) * nr + i] = bessel_j(p, k[i] * (j + 0.5) * dr);
+  if (m >= 1 && p == m - 1)
+    for (int j = 0; j < nr; ++j)
+      M[size_t(j) * nr + nr - 1] = std::pow((j + 0.5) / nr, double(m - 1));
   return M;
 }
 
@@ -1107,13 +1123,16 @@ gp_status build_transforms(gp_qc_ctx *c) {
   std::vector<double> kd(size_t(nm) * nr);
   for (int m = 0; m < nm; ++m) {
     const std::vector<double> k = spectral_kr(m, nr, c->d.dr);
+    // k_r of the update and the coefficients: the zeros, with 0 in the last
+    // column of modes m >= 1 (G_-'s k_r = 0 function; the others held)
     for (int i = 0; i < nr; ++i) {
-      kd[size_t(m) * nr + i] = k[i];
-      kt[size_t(m) * nr + i] = T(k[i]);
+      const double ku = (m >= 1 && i == nr - 1) ? 0.0 : k[i];
+      kd[size_t(m) * nr + i] = ku;
+      kt[size_t(m) * nr + i] = T(ku);
     }
     for (int slot = 0; slot < 3; ++slot) {
       const int p = m - 1 + slot;
-      const std::vector<double> M = backward_hankel(p, k, nr, c->d.dr);
+      const std::vector<double> M = backward_hankel(p, m, k, nr, c->d.dr);
       std::vector<double> Minv = M;
       if (!invert(Minv, nr))
         return qfail(GP_ERR_ARG, "the Hankel matrix of order " + std::to_string(p) +
@@ -1675,7 +1694,7 @@ gp_status gp_qc_hankel_matrix(int p, int m, int nr, double dr, int forward, doub
       !std::isfinite(dr))
     return qfail(GP_ERR_ARG,
                  "m must lie in [0, 63], p in [-64, 64], nr in [1, 512], dr positive and finite");
-  std::vector<double> M = backward_hankel(p, spectral_kr(m, nr, dr), nr, dr);
+  std::vector<double> M = backward_hankel(p, m, spectral_kr(m, nr, dr), nr, dr);
   if (forward && !invert(M, nr))
     return qfail(GP_ERR_ARG, "the Hankel matrix of order " + std::to_string(p) +
                                  " is singular for this nr");

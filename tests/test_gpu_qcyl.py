@@ -5,8 +5,8 @@ transforms, the update coefficients, the mode update and a short history.
 Tolerances.  The backward transforms, the coefficients and the update are
 plain products and sums: relative L2 1e-12 (FP64) and 1e-5 (mixed).  The
 forward Hankel transform is the inverse of the backward matrix, whose
-condition number kappa reaches 1e4..1e7 for the order m-1 (and m+1) matrices
-on the J_m zero grid; two correctly rounded FP64 inverses (the library's
+condition number kappa reaches 1e4..1e7 for the order m+1 matrices of the
+higher modes on the J_m zero grid; two correctly rounded FP64 inverses (the library's
 Gauss-Jordan and the oracle's LAPACK one) differ there by about kappa * eps.
 The FP64 bar of anything that passes through a forward transform is
 therefore max(1e-12, 8 kappa eps), with kappa of the orders involved; the
@@ -138,7 +138,7 @@ def test_coefficients(gpu_lib, precision, vz):
     live = ~cy.held_mask(nz, nr)
     for m in range(nm):
         kz = cy.axis_kz(nz, dz)[:, None] * np.ones((1, nr))
-        kr = np.ones((nz, 1)) * cy.spectral_kr(m, nr, dr)[None, :]
+        kr = np.ones((nz, 1)) * cy.update_kr(m, nr, dr)[None, :]
         coef = galilean_psatd_coefficients((kr, np.zeros_like(kr), kz), (0.0, 0.0, vz), dt)
         for i, key in enumerate(("c_EE", "s", "c_BJ", "c_EJ", "c_R1", "c_R0")):
             got = ctx.read(f"COEF{i}")[m]

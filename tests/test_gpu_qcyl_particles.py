@@ -6,11 +6,8 @@ Bars: one call or step from an identical state, relative L2 per field 1e-12
 (FP64) and 1e-5 (mixed), particle positions and momenta within 1e-12 / 1e-5
 of their scale; a 10-step axisymmetric history 1e-10 (FP64) and 1e-4 (mixed).
 The forward Hankel transforms inside a step carry the derived FP64 bar of
-the field-solve tests, max(1e-12, 8 kappa eps) (kappa <= 3e3 on these
-grids), which stays below 1e-12 here except for mode 1, whose bar is
-applied to it.  Runs with mode 1 are kept to one step: the cycle is not
-sound for m >= 1 under this grid reading (the k_r = 0 gap of the order
-m - 1 transform), which the oracle documents.
+the field-solve tests, max(1e-12, 8 kappa eps) (kappa of these grids is
+small, so the bar is 1e-12).
 """
 
 import numpy as np
@@ -182,18 +179,20 @@ def test_one_step_two_modes(gpu_lib, precision):
     ctx.close()
 
 
+@pytest.mark.parametrize("nm", [1, 2])
 @pytest.mark.parametrize("galilean", [True, False])
 @pytest.mark.parametrize("precision", [gp.GP_FP64, gp.GP_MIXED])
-def test_axisymmetric_history(gpu_lib, precision, galilean):
-    """Ten steps of a drifting electron column (gamma 5) on its ion column,
-    mode 0, electrostatic start, Galilean or standard frame."""
-    nz, nr, nm, dz, dr, dt = 32, 12, 1, 1.0, 1.0, 1.0
+def test_column_history(gpu_lib, precision, galilean, nm):
+    """Ten steps of a drifting electron column (gamma 5, a small thermal
+    spread) on its ion column, modes 0 (and 1), electrostatic start,
+    Galilean or standard frame."""
+    nz, nr, dz, dr, dt = 32, 12, 1.0, 1.0, 1.0
     gamma = 5.0
     uz = np.float32(-np.sqrt(gamma * gamma - 1.0))
     vz = float(uz / np.sqrt(1.0 + uz * uz)) if galilean else 0.0
     rp = 8.0
     rng = np.random.default_rng(403)
-    x, u = _column(rng, 5000, rp, nz * dz, precision, gamma)
+    x, u = _column(rng, 5000, rp, nz * dz, precision, gamma, u_th=0.02)
     n = len(x)
     w = np.pi * rp * rp * nz * dz / n
     v_ion = float(uz / np.sqrt(1.0 + uz * uz))
@@ -213,11 +212,12 @@ def test_axisymmetric_history(gpu_lib, precision, galilean):
     for _ in range(steps):
         st = sim.step(st)
     tol = 1e-10 if precision == gp.GP_FP64 else 1e-4
-    # E and B as vectors (pure drift leaves E_theta, B_r, B_z at zero in mode 0)
+    # E and B of each mode as vectors
     for names, F in ((("ER", "ET", "EZ"), st["E"]), (("BR", "BT", "BZ"), st["B"])):
-        got = np.stack([ctx.read(nme)[0] for nme in names])
-        ref = np.stack([F[0][a] for a in range(3)])
-        assert rel_l2(got, ref) <= tol, names
+        for m in range(nm):
+            got = np.stack([ctx.read(nme)[m] for nme in names])
+            ref = np.stack([F[m][a] for a in range(3)])
+            assert rel_l2(got, ref) <= tol, (names, m)
     xg, ug = _particles_back(parts)
     lz = nz * dz
     dzp = np.abs(xg[:, 2] - st["x"][:, 2])

@@ -1,5 +1,6 @@
 """The quasi-cylindrical solver's host logic (no GPU): its spectral grid
-(zeros of J_m) and its Hankel transform matrices, against mpmath's
+(zeros of J_m) and its Hankel transform matrices (with the k_r = 0 function
+(r/R)^{m-1} as the last order m - 1 column for m >= 1), against mpmath's
 arbitrary-precision Bessel functions and zeros and against scipy."""
 
 import mpmath
@@ -35,8 +36,14 @@ def test_backward_matrix_is_bessel_values(m):
     rng = np.random.default_rng(500 + m)
     for p in (m - 1, m, m + 1):
         M = gp.qc_hankel_matrix(p, m, nr, dr)
+        # for p = m - 1, m >= 1, the last column is the k_r = 0 function
+        # (r_j / R)^{m-1} that completes the order m - 1 set
+        cols = nr - 1 if (m >= 1 and p == m - 1) else nr
+        if cols < nr:
+            r = (np.arange(nr) + 0.5) / nr
+            assert np.max(np.abs(M[:, -1] - r ** (m - 1))) <= 1e-15
         for _ in range(40):
-            j, i = (int(v) for v in rng.integers(0, nr, 2))
+            j, i = int(rng.integers(0, nr)), int(rng.integers(0, cols))
             x = k[i] * (j + 0.5) * dr
             ref = float(mpmath.besselj(p, x))
             assert abs(M[j, i] - ref) <= 4e-15, (p, j, i, x)
@@ -53,6 +60,8 @@ def test_backward_matrix_matches_scipy():
         k = gp.qc_wavenumbers(m, nr, dr)
         for p in (m - 1, m, m + 1):
             ref = special.jv(p, np.outer(r, k))
+            if m >= 1 and p == m - 1:
+                ref[:, -1] = (r / (nr * dr)) ** (m - 1)
             assert np.max(np.abs(gp.qc_hankel_matrix(p, m, nr, dr) - ref)) <= 1e-14
 
 
