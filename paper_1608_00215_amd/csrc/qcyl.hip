@@ -583,9 +583,9 @@ __global__ __launch_bounds__(256) void k_qc_move_deposit(QcPart<T> p, QcGeo<T> g
 // The same with an LDS window: a workgroup takes kQcChunk consecutive
 // particles (sorted along z at binding, so a chunk covers few z nodes),
 // accumulates the nodes of kQcWin z planes from one plane below its first
-// particle in LDS ([source][mode][plane][r] complex), sends every other node
-// straight to global atomics, and flushes the window's nonzero entries with
-// global atomics at the end.
+// particle in LDS ([source][mode][plane][r] complex, in double for either
+// precision), sends every other node straight to global atomics, and
+// flushes the window's nonzero entries with global atomics at the end.
 constexpr int kQcDepThreads = 256;
 constexpr int kQcDepPer = 8;
 constexpr int kQcChunk = kQcDepThreads * kQcDepPer;
@@ -595,11 +595,12 @@ template <typename T>
 __global__ __launch_bounds__(kQcDepThreads) void k_qc_move_deposit_tiled(QcPart<T> p, QcGeo<T> g,
                                                                          QcSrc<T> src, T dt,
                                                                          T vgal, T qw, int move) {
+  // the window accumulates in double whatever T is (as the Cartesian tiles do)
   extern __shared__ __align__(16) unsigned char qdsm[];
-  T *win = reinterpret_cast<T *>(qdsm);
+  double *win = reinterpret_cast<double *>(qdsm);
   __shared__ int zs_sh;
   const int64_t first = int64_t(blockIdx.x) * kQcChunk;
-  const int plane = g.nr * 2;                            // T values per z plane
+  const int plane = g.nr * 2;                            // values per z plane
   const int per_src = g.nmodes * kQcWin * plane;
   const int total = 4 * per_src;
   if (threadIdx.x == 0) {
@@ -614,7 +615,7 @@ __global__ __launch_bounds__(kQcDepThreads) void k_qc_move_deposit_tiled(QcPart<
     if (k < 0) k += g.nz;
     zs_sh = (k - 1 + g.nz) % g.nz;
   }
-  for (int t = threadIdx.x; t < total; t += kQcDepThreads) win[t] = T(0);
+  for (int t = threadIdx.x; t < total; t += kQcDepThreads) win[t] = 0.0;
   __syncthreads();
   const int zs = zs_sh;
   T *arrs[4] = {global_ptr(src.jr), global_ptr(src.jt), global_ptr(src.jz),
@@ -625,7 +626,7 @@ __global__ __launch_bounds__(kQcDepThreads) void k_qc_move_deposit_tiled(QcPart<
     if (i >= p.n) break;
     qc_particle_deposit(p, g, i, dt, vgal, qw, move, [=](int si) {
       T *garr = arrs[si];
-      T *warr = win + si * per_src;
+      double *warr = win + si * per_src;
       return [=](int m, int k, int j, T re, T im) {
         int slot = k - zs;
         if (slot < 0) slot += nz;
@@ -633,10 +634,11 @@ __global__ __launch_bounds__(kQcDepThreads) void k_qc_move_deposit_tiled(QcPart<
         // grid (distinct scopes also keep the two from being merged into
         // one flat atomic on a selected address)
         if (slot < kQcWin) {
-          T *w = warr + (m * kQcWin + slot) * plane + 2 * j;
-          __hip_atomic_fetch_add(w, re, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          double *w = warr + (m * kQcWin + slot) * plane + 2 * j;
+          __hip_atomic_fetch_add(w, double(re), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
           if (m > 0)
-            __hip_atomic_fetch_add(w + 1, im, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            __hip_atomic_fetch_add(w + 1, double(im), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
         } else {
           const int64_t at = 2 * ((int64_t(m) * nz + k) * nr + j);
           __hip_atomic_fetch_add(garr + at, re, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -648,7 +650,7 @@ __global__ __launch_bounds__(kQcDepThreads) void k_qc_move_deposit_tiled(QcPart<
   }
   __syncthreads();
   for (int t = threadIdx.x; t < total; t += kQcDepThreads) {
-    const T v = win[t];
+    const T v = T(win[t]);
     if (v == T(0)) continue;
     const int si = t / per_src;
     const int r1 = t % per_src;
@@ -1316,7 +1318,7 @@ void launch_move_deposit(gp_qc_ctx *c, int move) {
   src.jz = static_cast<T *>(c->real[8]);
   src.rho = static_cast<T *>(c->real[9]);
   QStamp stamp(c, 5);
-  const size_t lds = size_t(4) * c->d.nmodes * kQcWin * c->d.nr * 2 * sizeof(T);
+  const size_t lds = size_t(4) * c->d.nmodes * kQcWin * c->d.nr * 2 * sizeof(double);
   if (lds <= 65536) {
     hipLaunchKernelGGL((k_qc_move_deposit_tiled<T>),
                        dim3(unsigned((c->part.n + kQcChunk - 1) / kQcChunk)), dim3(kQcDepThreads),
