@@ -292,9 +292,9 @@ QC_WORKLOADS = {
                     steps=200),
     # the particle cycle: an electron column of radius 96 (density 1, 24
     # particles per (r, z) cell, drifting at gamma 20 along -z) on its
-    # neutralising ion column, axisymmetric (mode 0), Galilean frame,
-    # electrostatic start
-    "qc_column": dict(nz=512, nr=128, nmodes=1, dz=1.0, dr=1.0, dt=1.0, gamma=20.0,
+    # neutralising ion column, modes 0 and 1, Galilean frame, electrostatic
+    # start
+    "qc_column": dict(nz=512, nr=128, nmodes=2, dz=1.0, dr=1.0, dt=1.0, gamma=20.0,
                       steps=200, ppc=24, rp=96.0),
 }
 
@@ -534,7 +534,8 @@ def qc_main(args):
         line["particles"] = mixed["particles"]
         line["particle_steps_per_s"] = mixed["particles"] * steps / mixed["wall_s"]
         line["config"]["workload"] = (f"{args.qc}: quasi-cylindrical particle cycle, nz "
-                                      f"{w['nz']}, nr {w['nr']}, mode 0, an electron column of "
+                                      f"{w['nz']}, nr {w['nr']}, modes 0..{w['nmodes'] - 1}, "
+                                      "an electron column of "
                                       f"radius {w['rp']:g} ({w['ppc']} particles per (r, z) "
                                       f"cell, {mixed['particles']} particles) drifting at "
                                       f"gamma {w['gamma']:g} on its ion column, Galilean frame")

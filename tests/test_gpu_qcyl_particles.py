@@ -275,3 +275,47 @@ def test_binding_sorts_along_z(gpu_lib, precision):
         out.append(ctx.read("RHO"))
         ctx.close()
     assert rel_l2(out[1], out[0]) <= tol_for(precision)
+
+
+@pytest.mark.parametrize("precision", [gp.GP_FP64, gp.GP_MIXED])
+def test_nci_pair_on_the_gpu(gpu_lib, precision):
+    """The paper's contrast in its quasi-cylindrical geometry, run by the
+    library: an electron column (gamma 10, density 1, radius 8, 20000
+    particles, modes 0 and 1) drifting along -z on its ion column stays
+    quiet on the Galilean grid and grows under standard PSATD; the bars of
+    the oracle's pin (Galilean max W <= 25 W(1); standard W(80) >= 50 W(1)
+    and >= 8 times the Galilean W(80))."""
+    nz, nr, nm, n, gamma, rp = 64, 12, 2, 20000, 10.0, 8.0
+    energies = {}
+    for galilean in (True, False):
+        rng = np.random.default_rng(1)
+        r = rp * np.sqrt(rng.uniform(0, 1, n))
+        th = rng.uniform(0, 2 * np.pi, n)
+        x = np.stack([r * np.cos(th), r * np.sin(th), rng.uniform(0, nz, n)], 1)
+        u = np.zeros((n, 3))
+        u[:, 2] = -np.sqrt(gamma * gamma - 1.0)
+        x, u = _round(x, precision), _round(u, precision)
+        vz = float(u[0, 2] / np.sqrt(1.0 + u[0, 2] ** 2))
+        w = np.pi * rp * rp * nz / n
+        bg = cy.uniform_cylinder_background(1.0, rp, vz, nm, nr, 1.0, nz, 1.0)
+        ctx = gp.QcContext(nz, nr, nm, 1.0, 1.0, 1.0, precision)
+        ctx.set_v_gal(vz if galilean else 0.0)
+        rho_bg, J_bg = _bg_arrays(bg, nm)
+        ctx.set_background(rho_bg, *J_bg)
+        parts = _gpu_particles(x, u, precision)
+        ctx.bind_particles(-1.0, 1.0, w, *parts)
+        ctx.electrostatic_fields()
+        W = []
+        for s in range(80):
+            ctx.particle_step(1)
+            if s == 0 or s % 10 == 9:
+                G = lambda names: [tuple(ctx.read(nme)[m].astype(np.complex128) for nme in names)
+                                   for m in range(nm)]
+                W.append(cy.field_energy(G(("ER", "ET", "EZ")), nr, 1.0, 1.0)
+                         + cy.field_energy(G(("BR", "BT", "BZ")), nr, 1.0, 1.0))
+        energies[galilean] = np.array(W)
+        ctx.close()
+    gal, std = energies[True], energies[False]
+    assert gal.max() <= 25.0 * gal[0], gal / gal[0]
+    assert std[-1] >= 50.0 * std[0], std / std[0]
+    assert std[-1] >= 8.0 * gal[-1], (std[-1], gal[-1])
