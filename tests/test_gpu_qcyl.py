@@ -240,3 +240,45 @@ def test_rejects_bad_arguments(gpu_lib):
     with pytest.raises(KeyError):
         ctx.read("NOPE")
     ctx.close()
+
+
+@pytest.mark.parametrize("vz, dt, n", [(0.0, 2.1, 3), (-0.95, 0.3, 4)])
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_vacuum_steps_compose(gpu_lib, precision, vz, dt, n):
+    """Without sources, n library steps of dt equal one step of n dt (every
+    spectral mode evolves exactly), modes 0..2 including the k_r = 0
+    function of G_-."""
+    nz, nr, nm, dz, dr = 16, 12, 3, 0.7, 0.5
+    rng = np.random.default_rng(310)
+    spec = ["E_PLUS", "E_MINUS", "E_Z_HAT", "B_PLUS", "B_MINUS", "B_Z_HAT"]
+    kz = cy.axis_kz(nz, dz)[:, None] * np.ones((1, nr))
+
+    def transverse(F, m):
+        # divergence-free part (a longitudinal field without charge evolves
+        # as theta^2 C under the update, which does not compose)
+        kr = np.ones((nz, 1)) * cy.update_kr(m, nr, dr)[None, :]
+        k2 = np.where(kr * kr + kz * kz > 0, kr * kr + kz * kz, 1.0)
+        Fc = list(cy.to_cartesian(cy.hold(F, m)))
+        kd = (kr * Fc[0] + kz * Fc[2]) / k2
+        Fc[0], Fc[2] = Fc[0] - kr * kd, Fc[2] - kz * kd
+        return cy.hold(cy.from_cartesian(tuple(Fc)), m)
+
+    G = {nme: np.zeros((nm, nz, nr), dtype=complex) for nme in spec}
+    for m in range(nm):
+        for v in (0, 3):
+            F = transverse(tuple(_cplx(rng, (nz, nr)) for _ in range(3)), m)
+            for a in range(3):
+                G[spec[v + a]][m] = F[a]
+    G = {nme: _as_input(a, precision) for nme, a in G.items()}
+    out = []
+    for step_dt, steps in ((dt, n), (n * dt, 1)):
+        ctx = gp.QcContext(nz, nr, nm, dz, dr, step_dt, precision)
+        ctx.set_v_gal(vz)
+        for nme in spec:
+            ctx.write(nme, G[nme])
+        ctx.step(steps)   # real J and rho are zero
+        ctx.synchronize()
+        out.append(np.stack([ctx.read(nme) for nme in spec]))
+        ctx.close()
+    tol = 1e-11 if precision == gp.GP_FP64 else 1e-5
+    assert rel_l2(out[0], out[1]) <= tol

@@ -331,3 +331,39 @@ def test_sideways_current_keeps_continuity_in_mode_one():
         div = 1j * (kr * Ec[0] + kz * Ec[2])
         res.append(np.linalg.norm((dr_dt + div)[live]) / np.linalg.norm(dr_dt[live]))
     assert res[1] <= 3.0 * max(res[0], 1.0)
+
+
+@pytest.mark.parametrize("m", [0, 1, 2])
+def test_vacuum_propagation_is_exact_for_any_dt(m):
+    """Without sources every spectral mode evolves exactly, so N steps of dt
+    equal one step of N dt, for any dt (the cylindrical counterpart of the
+    Cartesian plane-wave pin), with v_gal = 0 and relativistic."""
+    rng = np.random.default_rng(110 + m)
+    nz, nr, dz, dr = 16, 12, 0.7, 0.5
+    cplx = lambda: rng.standard_normal((nz, nr)) + 1j * rng.standard_normal((nz, nr))
+    E = cy.hold(tuple(cplx() for _ in range(3)), m)
+    B = cy.hold(tuple(cplx() for _ in range(3)), m)
+    zero = np.zeros((nz, nr), dtype=complex)
+    # a vacuum field: divergence-free (project out the longitudinal part)
+    kz = cy.axis_kz(nz, dz)[:, None] * np.ones((1, nr))
+    kr = np.ones((nz, 1)) * cy.update_kr(m, nr, dr)[None, :]
+    k2 = np.where(kr * kr + kz * kz > 0, kr * kr + kz * kz, 1.0)
+
+    def transverse(G):
+        Fc = list(cy.to_cartesian(G))
+        kd = (kr * Fc[0] + kz * Fc[2]) / k2
+        Fc[0] = Fc[0] - kr * kd
+        Fc[2] = Fc[2] - kz * kd
+        return cy.hold(cy.from_cartesian(tuple(Fc)), m)
+
+    E, B = transverse(E), transverse(B)
+    for v in (0.0, -0.95):
+        for dt, n in ((0.3, 7), (2.1, 3)):
+            a, b = E, B
+            for _ in range(n):
+                a, b = cy.mode_update(a, b, (zero, zero, zero), zero, zero, m, nr, dr, nz, dz,
+                                      v, dt)
+            c, d = cy.mode_update(E, B, (zero, zero, zero), zero, zero, m, nr, dr, nz, dz, v,
+                                  n * dt)
+            for x, y in zip(a + b, c + d):
+                assert np.max(np.abs(x - y)) <= 1e-11 * np.max(np.abs(np.stack(E))), (v, dt)
