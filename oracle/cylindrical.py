@@ -42,20 +42,24 @@ down.  Readings taken here:
   v_gal along z, advances the mode as the Cartesian update does at that
   wavevector.  The k_z Nyquist plane is held at zero; k_r > 0 always.
 * Particles (deposition and gather by azimuthal mode), a reading of the
-  standard azimuthal decomposition with linear (CIC) shapes in r and z:
+  standard azimuthal decomposition with B-spline shapes (linear or cubic)
+  in r and z:
   - a stored mode-m field is g_m = c_m f_m, with c_0 = 1 and c_m = 2 for
     m >= 1, where f = sum over all integer m of f_m exp(i m theta); the
     physical field is then Re sum_{m >= 0} g_m exp(i m theta);
   - a particle at (r, theta, z) deposits c_m q w W_j(r) W_k(z)
-    exp(-i m theta) s / V_j to node (j, k), with the linear weights of the
-    radial nodes (j + 1/2) dr and of the z nodes k dz (periodic);
-  - the node at r = -dr/2 (a particle with r < dr/2) is the node j = 0 seen
-    across the axis (the point at angle theta + pi): its weight goes to
-    j = 0 with s = (-1)^m for scalars and z components and s = (-1)^(m+1)
-    for r and theta components (whose unit vectors flip there);
+    exp(-i m theta) s / V_j to node (j, k), with the B-spline weights
+    (order 1 or 3) of the radial nodes (j + 1/2) dr and of the z nodes k dz
+    (periodic);
+  - a node j < 0 (at r = (j + 1/2) dr < 0) is node -j-1 seen across the
+    axis (the point at angle theta + pi): its weight goes there with
+    s = (-1)^m for scalars and z components and s = (-1)^(m+1) for r and
+    theta components (whose unit vectors flip there);
   - V_j = 2 pi dz times the integral of node j's (folded, m = 0) weight
-    against r dr: (j + 1/2) dr^2 for j >= 1 and (13/24) dr^2 for j = 0, so
-    that a uniform density deposits uniformly up to the axis;
+    against r dr: (j + 1/2) dr^2 where the support stays off the axis; for
+    linear weights (13/24) dr^2 at j = 0, for cubic ones the integral over
+    the folded kernel; so a uniform density deposits uniformly up to the
+    axis;
   - a weight reaching past the last node (j >= nr) is dropped;
   - at r = 0 the angle is taken as 0;
   - gather is the transpose: F(x_p) = Re sum_m (sum of W s g_m over the
@@ -209,10 +213,40 @@ def mode_factor(m):
     return 1.0 if m == 0 else 2.0
 
 
-def node_volumes(nr, dr, dz):
-    """V_j = 2 pi dz * int W_j(r) r dr with the axis fold of m = 0."""
+def shape_kernel(x, order):
+    """The centred B-spline of the given order (1: tent, 3: cubic) at x, in
+    units of the node spacing."""
+    a = np.abs(np.asarray(x, dtype=np.float64))
+    if order == 1:
+        return np.maximum(0.0, 1.0 - a)
+    if order == 3:
+        return np.where(a < 1.0, (4.0 - 6.0 * a * a + 3.0 * a ** 3) / 6.0,
+                        np.where(a < 2.0, (2.0 - a) ** 3 / 6.0, 0.0))
+    raise ValueError("shape order must be 1 or 3")
+
+
+def folded_weight(r, j, dr, order):
+    """Node j's weight at radius r >= 0 with the axis fold of m = 0: its
+    own kernel plus that of the mirrored node -j-1 (at -(j + 1/2) dr)."""
+    return (shape_kernel(r / dr - (j + 0.5), order)
+            + shape_kernel(r / dr + (j + 0.5), order))
+
+
+def node_volumes(nr, dr, dz, order=1):
+    """V_j = 2 pi dz * int W_j(r) r dr with the axis fold of m = 0.  Nodes
+    whose support stays off the axis give (j + 1/2) dr^2; the others are
+    integrated exactly (the folded weight times r is a polynomial between the
+    breakpoints (n + 1/2) dr, so 3-point Gauss-Legendre per interval)."""
     v = (np.arange(nr) + 0.5) * dr * dr
-    v[0] = 13.0 / 24.0 * dr * dr
+    t, wq = np.polynomial.legendre.leggauss(3)
+    reach = (order + 1) // 2          # support half-width in nodes
+    for j in range(min(reach, nr)):
+        edges = np.concatenate([[0.0], (np.arange(j + reach + 1) + 0.5) * dr])
+        tot = 0.0
+        for a, b in zip(edges[:-1], edges[1:]):
+            rr = 0.5 * (b - a) * t + 0.5 * (a + b)
+            tot += 0.5 * (b - a) * np.sum(wq * folded_weight(rr, j, dr, order) * rr)
+        v[j] = tot
     return 2.0 * np.pi * dz * v
 
 
@@ -225,32 +259,35 @@ def _angle(x, y):
     return r, c, s
 
 
-def _nodes(r, z, nr, dr, nz, dz):
-    """Radial node pair (j0, j0 + 1) with weights, and the z pair."""
+def _nodes(r, z, nr, dr, nz, dz, order=1):
+    """Radial nodes (j, may be negative: folded) with weights, and the z
+    nodes (periodic), of the B-spline shape of the given order."""
+    from .particles import bspline_weights
     sr = r / dr - 0.5
     j0 = np.floor(sr).astype(np.int64)
-    fr = sr - j0
+    wr, rel = bspline_weights(sr - j0, order)
     sz = z / dz
     k0 = np.floor(sz).astype(np.int64)
-    fz = sz - k0
-    rad = ((j0, 1.0 - fr), (j0 + 1, fr))
-    ax = ((k0 % nz, 1.0 - fz), ((k0 + 1) % nz, fz))
+    wz, relz = bspline_weights(sz - k0, order)
+    rad = tuple((j0 + d, wr[:, i]) for i, d in enumerate(rel))
+    ax = tuple(((k0 + d) % nz, wz[:, i]) for i, d in enumerate(relz))
     return rad, ax
 
 
-def deposit_mode(x, y, z, values, m, kind, nr, dr, nz, dz):
+def deposit_mode(x, y, z, values, m, kind, nr, dr, nz, dz, order=1):
     """c_m sum_p values_p W_j W_k exp(-i m theta_p) s / V_j on the [nz][nr]
     grid of mode m.  kind is "scalar" (scalars and z components) or
-    "transverse" (r and theta components), which sets the axis-fold sign."""
+    "transverse" (r and theta components), which sets the axis-fold sign;
+    a node j < 0 is node -j-1 seen across the axis."""
     r, c, s = _angle(x, y)
     rot = (c - 1j * s) ** m
-    vol = node_volumes(nr, dr, dz)
+    vol = node_volumes(nr, dr, dz, order)
     fold = (-1.0) ** m if kind == "scalar" else (-1.0) ** (m + 1)
     out = np.zeros((nz, nr), dtype=complex)
-    rad, ax = _nodes(r, z, nr, dr, nz, dz)
+    rad, ax = _nodes(r, z, nr, dr, nz, dz, order)
     for j, wr in rad:
         sign = np.where(j < 0, fold, 1.0)
-        jj = np.where(j < 0, 0, j)
+        jj = np.where(j < 0, -j - 1, j)
         live = jj < nr
         for k, wz in ax:
             val = mode_factor(m) * values * wr * wz * sign * rot
@@ -258,16 +295,16 @@ def deposit_mode(x, y, z, values, m, kind, nr, dr, nz, dz):
     return out / vol[None, :]
 
 
-def gather_mode(g, x, y, z, m, kind, nr, dr, nz, dz):
+def gather_mode(g, x, y, z, m, kind, nr, dr, nz, dz, order=1):
     """The complex sum over nodes of W_j W_k s g[k][j] at each particle
     (before the factor exp(i m theta) and the real part)."""
     r, _, _ = _angle(x, y)
     fold = (-1.0) ** m if kind == "scalar" else (-1.0) ** (m + 1)
     acc = np.zeros(len(x), dtype=complex)
-    rad, ax = _nodes(r, z, nr, dr, nz, dz)
+    rad, ax = _nodes(r, z, nr, dr, nz, dz, order)
     for j, wr in rad:
         sign = np.where(j < 0, fold, 1.0)
-        jj = np.where(j < 0, 0, j)
+        jj = np.where(j < 0, -j - 1, j)
         live = jj < nr
         jc = np.where(live, jj, 0)
         for k, wz in ax:
@@ -275,7 +312,7 @@ def gather_mode(g, x, y, z, m, kind, nr, dr, nz, dz):
     return acc
 
 
-def gather_vector(G, x, y, z, nr, dr, nz, dz):
+def gather_vector(G, x, y, z, nr, dr, nz, dz, order=1):
     """Cartesian (n, 3) field at the particles from the mode fields
     G[m] = (F_r, F_theta, F_z), each [nz][nr]."""
     r, c, s = _angle(x, y)
@@ -284,29 +321,29 @@ def gather_vector(G, x, y, z, nr, dr, nz, dz):
     Fz = np.zeros(len(x))
     for m, comps in enumerate(G):
         e = (c + 1j * s) ** m
-        Fr += np.real(gather_mode(comps[0], x, y, z, m, "transverse", nr, dr, nz, dz) * e)
-        Ft += np.real(gather_mode(comps[1], x, y, z, m, "transverse", nr, dr, nz, dz) * e)
-        Fz += np.real(gather_mode(comps[2], x, y, z, m, "scalar", nr, dr, nz, dz) * e)
+        Fr += np.real(gather_mode(comps[0], x, y, z, m, "transverse", nr, dr, nz, dz, order) * e)
+        Ft += np.real(gather_mode(comps[1], x, y, z, m, "transverse", nr, dr, nz, dz, order) * e)
+        Fz += np.real(gather_mode(comps[2], x, y, z, m, "scalar", nr, dr, nz, dz, order) * e)
     return np.stack([Fr * c - Ft * s, Fr * s + Ft * c, Fz], axis=1)
 
 
-def deposit_current(x, y, z, v, qw, nmodes, nr, dr, nz, dz):
+def deposit_current(x, y, z, v, qw, nmodes, nr, dr, nz, dz, order=1):
     """Per mode (J_r, J_theta, J_z) [nz][nr] of currents qw v at the points."""
     _, c, s = _angle(x, y)
     vr = v[:, 0] * c + v[:, 1] * s
     vt = -v[:, 0] * s + v[:, 1] * c
-    return [(deposit_mode(x, y, z, qw * vr, m, "transverse", nr, dr, nz, dz),
-             deposit_mode(x, y, z, qw * vt, m, "transverse", nr, dr, nz, dz),
-             deposit_mode(x, y, z, qw * v[:, 2], m, "scalar", nr, dr, nz, dz))
+    return [(deposit_mode(x, y, z, qw * vr, m, "transverse", nr, dr, nz, dz, order),
+             deposit_mode(x, y, z, qw * vt, m, "transverse", nr, dr, nz, dz, order),
+             deposit_mode(x, y, z, qw * v[:, 2], m, "scalar", nr, dr, nz, dz, order))
             for m in range(nmodes)]
 
 
-def deposit_charge(x, y, z, qw, nmodes, nr, dr, nz, dz):
-    return [deposit_mode(x, y, z, qw * np.ones(len(x)), m, "scalar", nr, dr, nz, dz)
+def deposit_charge(x, y, z, qw, nmodes, nr, dr, nz, dz, order=1):
+    return [deposit_mode(x, y, z, qw * np.ones(len(x)), m, "scalar", nr, dr, nz, dz, order)
             for m in range(nmodes)]
 
 
-def uniform_cylinder_background(density, rp, v_z, nmodes, nr, dr, nz, dz):
+def uniform_cylinder_background(density, rp, v_z, nmodes, nr, dr, nz, dz, order=1):
     """Charge and current of a neutralising ion column: charge density
     +density for r < rp, uniform in z and theta, drifting at v_z along z
     (it does not depend on time in either frame).  Node j takes the share of
@@ -314,11 +351,10 @@ def uniform_cylinder_background(density, rp, v_z, nmodes, nr, dr, nz, dz):
     uniform electron column up to the particles' noise.  Returns per mode
     (rho, (J_r, J_theta, J_z)) real-space [nz][nr] arrays (modes >= 1
     zero)."""
-    r = np.linspace(0.0, (nr + 1) * dr, 200001)
-    tent = lambda j: np.maximum(0.0, 1.0 - np.abs(r - (j + 0.5) * dr) / dr)
+    r = np.linspace(0.0, (nr + 2) * dr, 400001)
     prof = np.zeros(nr)
     for j in range(nr):
-        w = tent(j) + (tent(-1) if j == 0 else 0.0)
+        w = folded_weight(r, j, dr, order)
         prof[j] = np.trapezoid(w * r * (r < rp), r) / np.trapezoid(w * r, r)
     rho0 = density * np.ones((nz, 1)) * prof[None, :] + 0j
     zero = np.zeros((nz, nr), dtype=complex)
@@ -338,9 +374,12 @@ class CylindricalPIC:
     transform, update every mode, transform back, gather at x^{n+1} and push
     (relativistic Boris).  z is periodic; x and y are open."""
 
-    def __init__(self, nz, nr, nmodes, dz, dr, dt, q, mass, w, v_gal_z, background=None):
+    def __init__(self, nz, nr, nmodes, dz, dr, dt, q, mass, w, v_gal_z, background=None,
+                 order=1):
         """background: optional per-mode (rho, (J_r, J_theta, J_z)) added to
-        the deposits every step (e.g. a neutralising ion column)."""
+        the deposits every step (e.g. a neutralising ion column); order: the
+        particle shape (1 linear, 3 cubic) in r and z."""
+        self.order = order
         self.nz, self.nr, self.nmodes = nz, nr, nmodes
         self.dz, self.dr, self.dt = dz, dr, dt
         self.q, self.mass, self.w = q, mass, w
@@ -380,7 +419,7 @@ class CylindricalPIC:
         """x, u (n, 3); optional real mode fields E, B [m] = (r, theta, z);
         electrostatic: E^0 is the field of the initial charge instead."""
         rho = deposit_charge(x[:, 0], x[:, 1], x[:, 2], self.q * self.w, self.nmodes,
-                             self.nr, self.dr, self.nz, self.dz)
+                             self.nr, self.dr, self.nz, self.dz, self.order)
         rho, _ = self._with_background(rho, None)
         zero = np.zeros((self.nz, self.nr), dtype=complex)
         Eh, Bh = [], []
@@ -402,8 +441,9 @@ class CylindricalPIC:
         v = lab_velocity(st["u"])
         xh = self._move(st["x"], v)
         xn = self._move(xh, v)
-        J = deposit_current(xh[:, 0], xh[:, 1], xh[:, 2], v, qw, nm, nr, dr, nz, dz)
-        rho = deposit_charge(xn[:, 0], xn[:, 1], xn[:, 2], qw, nm, nr, dr, nz, dz)
+        o = self.order
+        J = deposit_current(xh[:, 0], xh[:, 1], xh[:, 2], v, qw, nm, nr, dr, nz, dz, o)
+        rho = deposit_charge(xn[:, 0], xn[:, 1], xn[:, 2], qw, nm, nr, dr, nz, dz, o)
         rho, J = self._with_background(rho, J)
         Eh, Bh, rh, E, B = [], [], [], [], []
         for m in range(nm):
@@ -416,8 +456,8 @@ class CylindricalPIC:
             rh.append(r1)
             E.append(from_spectral(en, m, dr, dz))
             B.append(from_spectral(bn, m, dr, dz))
-        Ep = gather_vector(E, xn[:, 0], xn[:, 1], xn[:, 2], nr, dr, nz, dz)
-        Bp = gather_vector(B, xn[:, 0], xn[:, 1], xn[:, 2], nr, dr, nz, dz)
+        Ep = gather_vector(E, xn[:, 0], xn[:, 1], xn[:, 2], nr, dr, nz, dz, o)
+        Bp = gather_vector(B, xn[:, 0], xn[:, 1], xn[:, 2], nr, dr, nz, dz, o)
         un = boris_push(st["u"], Ep, Bp, self.q, self.mass, self.dt)
         return {"x": xn, "u": un, "E_hat": Eh, "B_hat": Bh, "rho_hat": rh, "E": E, "B": B,
                 "J": J, "rho": rho}

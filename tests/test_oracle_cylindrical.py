@@ -122,18 +122,23 @@ def test_mode_update_keeps_gauss_law():
 
 # ---- particles: deposition and gather by azimuthal mode ----------------------
 
-def _tent(r, j, dr):
-    """Linear weight of the radial node at (j + 1/2) dr."""
-    return np.maximum(0.0, 1.0 - np.abs(r - (j + 0.5) * dr) / dr)
+def _spline(order):
+    """scipy's centred cardinal B-spline of the order (node spacing 1)."""
+    from scipy.interpolate import BSpline
+    b = BSpline.basis_element(np.arange(order + 2) - (order + 1) / 2, extrapolate=False)
+    return lambda x: np.nan_to_num(b(x))
 
 
-def test_node_volumes_are_the_folded_shape_integrals():
+@pytest.mark.parametrize("order", [1, 3])
+def test_node_volumes_are_the_folded_shape_integrals(order):
     nr, dr, dz = 6, 0.7, 0.9
-    r = np.linspace(0.0, (nr + 1) * dr, 400001)
+    B = _spline(order)
+    r = np.linspace(0.0, (nr + 2) * dr, 400001)
     for j in range(nr):
-        w = _tent(r, j, dr) + (_tent(r, -1, dr) if j == 0 else 0.0)
+        # node j's weight plus that of its mirror -j-1 across the axis
+        w = B(r / dr - (j + 0.5)) + B(r / dr + (j + 0.5))
         ref = 2 * np.pi * dz * np.trapezoid(w * r, r)
-        assert abs(cy.node_volumes(nr, dr, dz)[j] - ref) <= 1e-9 * ref, j
+        assert abs(cy.node_volumes(nr, dr, dz, order)[j] - ref) <= 1e-9 * ref, j
 
 
 def _cyl_particles(rng, n, rmax, lz):
@@ -143,34 +148,37 @@ def _cyl_particles(rng, n, rmax, lz):
     return r * np.cos(th), r * np.sin(th), rng.uniform(0, lz, n)
 
 
-def test_charge_sums_exactly_up_to_the_axis():
+@pytest.mark.parametrize("order", [1, 3])
+def test_charge_sums_exactly_up_to_the_axis(order):
     rng = np.random.default_rng(100)
     nz, nr, dz, dr = 8, 6, 0.5, 0.7
-    x, y, z = _cyl_particles(rng, 2000, (nr - 1) * dr, nz * dz)
+    x, y, z = _cyl_particles(rng, 2000, (nr - 2) * dr, nz * dz)
     qw = rng.uniform(0.5, 1.5, len(x))
-    g0 = cy.deposit_mode(x, y, z, qw, 0, "scalar", nr, dr, nz, dz)
-    vol = cy.node_volumes(nr, dr, dz)
+    g0 = cy.deposit_mode(x, y, z, qw, 0, "scalar", nr, dr, nz, dz, order)
+    vol = cy.node_volumes(nr, dr, dz, order)
     assert abs(np.sum(vol[None, :] * g0.real) - qw.sum()) <= 1e-12 * qw.sum()
     assert np.max(np.abs(g0.imag)) == 0.0
 
 
-def test_uniform_fields_are_gathered_exactly_everywhere():
+@pytest.mark.parametrize("order", [1, 3])
+def test_uniform_fields_are_gathered_exactly_everywhere(order):
     """A uniform Cartesian field is mode 0 (F_z) plus mode 1 with
     (F_r, F_theta) = (F_x - i F_y, F_y + i F_x); linear weights reproduce it
     exactly at every point, on and near the axis too, only if the axis fold
     signs, the sign of theta and the rotation back to x, y are right."""
     rng = np.random.default_rng(101)
     nz, nr, dz, dr = 8, 5, 0.5, 0.7
-    x, y, z = _cyl_particles(rng, 500, (nr - 1) * dr, nz * dz)
+    x, y, z = _cyl_particles(rng, 500, (nr - 2) * dr, nz * dz)
     F = np.array([0.3, -1.2, 0.7])
     one = np.ones((nz, nr))
     G = [(0 * one + 0j, 0 * one + 0j, F[2] * one + 0j),
          ((F[0] - 1j * F[1]) * one, (F[1] + 1j * F[0]) * one, 0 * one + 0j)]
-    got = cy.gather_vector(G, x, y, z, nr, dr, nz, dz)
+    got = cy.gather_vector(G, x, y, z, nr, dr, nz, dz, order)
     assert np.max(np.abs(got - F[None, :])) <= 1e-14
 
 
-def test_deposit_and_gather_are_adjoint():
+@pytest.mark.parametrize("order", [1, 3])
+def test_deposit_and_gather_are_adjoint(order):
     """sum_p q w v.E(x_p) = Re sum_m (1/c_m) sum_nodes V g_m conj(D_m) over
     the three components, for random mode fields g and the deposited
     currents D: ties the deposit's c_m, angle sign, volumes and fold to
@@ -182,27 +190,30 @@ def test_deposit_and_gather_are_adjoint():
     qw = 0.8
     cplx = lambda: rng.standard_normal((nz, nr)) + 1j * rng.standard_normal((nz, nr))
     G = [(cplx(), cplx(), cplx()) for _ in range(nm)]
-    lhs = qw * np.sum(v * cy.gather_vector(G, x, y, z, nr, dr, nz, dz))
-    D = cy.deposit_current(x, y, z, v, qw, nm, nr, dr, nz, dz)
-    vol = cy.node_volumes(nr, dr, dz)[None, :]
+    lhs = qw * np.sum(v * cy.gather_vector(G, x, y, z, nr, dr, nz, dz, order))
+    D = cy.deposit_current(x, y, z, v, qw, nm, nr, dr, nz, dz, order)
+    vol = cy.node_volumes(nr, dr, dz, order)[None, :]
     c = lambda m: 1.0 if m == 0 else 2.0
     rhs = sum(np.real(np.sum(vol * G[m][a] * np.conj(D[m][a]))) / c(m)
               for m in range(nm) for a in range(3))
     assert abs(lhs - rhs) <= 1e-12 * np.sum(np.abs(v)) * qw
 
 
-def test_mode_content_of_particles():
+@pytest.mark.parametrize("order", [1, 3])
+def test_mode_content_of_particles(order):
     nz, nr, dz, dr = 8, 6, 0.5, 0.7
     # one particle off the axis: g_m = c_m exp(-i m theta) g_0 node by node
     th = 0.9
     x, y, z = np.array([2.1 * np.cos(th)]), np.array([2.1 * np.sin(th)]), np.array([1.3])
-    g = [cy.deposit_mode(x, y, z, np.ones(1), m, "scalar", nr, dr, nz, dz) for m in range(4)]
+    g = [cy.deposit_mode(x, y, z, np.ones(1), m, "scalar", nr, dr, nz, dz, order)
+         for m in range(4)]
     for m in range(1, 4):
         assert np.allclose(g[m], 2.0 * np.exp(-1j * m * th) * g[0], rtol=0, atol=1e-15)
     # three particles at equal angles on a ring: modes 1 and 2 vanish
     ths = th + 2 * np.pi * np.arange(3) / 3
     x, y, z = 2.1 * np.cos(ths), 2.1 * np.sin(ths), np.full(3, 1.3)
-    g = [cy.deposit_mode(x, y, z, np.ones(3), m, "scalar", nr, dr, nz, dz) for m in range(4)]
+    g = [cy.deposit_mode(x, y, z, np.ones(3), m, "scalar", nr, dr, nz, dz, order)
+         for m in range(4)]
     for m in (1, 2):
         assert np.max(np.abs(g[m])) <= 1e-14 * np.max(np.abs(g[0]))
     assert np.max(np.abs(g[3])) >= 0.5 * np.max(np.abs(g[0]))
@@ -367,3 +378,26 @@ def test_vacuum_propagation_is_exact_for_any_dt(m):
                                   n * dt)
             for x, y in zip(a + b, c + d):
                 assert np.max(np.abs(x - y)) <= 1e-11 * np.max(np.abs(np.stack(E))), (v, dt)
+
+
+@pytest.mark.parametrize("order", [1, 3])
+def test_uniform_density_deposits_uniformly_up_to_the_axis(order):
+    """A column of density 1 sampled finely (equal-area radii, any angles,
+    a regular z lattice) deposits density 1 on every node whose support lies
+    inside the column, the axis nodes included: the axis fold (node j < 0
+    onto -j-1) and the node volumes must agree for that."""
+    nz, nr, dz, dr = 4, 10, 1.0, 0.5
+    R = 7 * dr
+    nrad, nzp = 6000, 8
+    r = R * np.sqrt((np.arange(nrad) + 0.5) / nrad)
+    th = 2.399963 * np.arange(nrad)              # any angles
+    zs = (np.arange(nz * nzp) + 0.5) * dz / nzp
+    rr = np.repeat(r, len(zs))
+    tt = np.repeat(th, len(zs))
+    zz = np.tile(zs, nrad)
+    w = np.pi * R * R * nz * dz / len(rr)
+    g0 = cy.deposit_mode(rr * np.cos(tt), rr * np.sin(tt), zz, np.full(len(rr), w), 0,
+                         "scalar", nr, dr, nz, dz, order)
+    reach = (order + 1) // 2
+    inside = [j for j in range(nr) if (j + 0.5 + reach) * dr <= R]
+    assert np.max(np.abs(g0[:, inside] - 1.0)) <= 2e-6, g0[0, inside]
