@@ -343,6 +343,25 @@ def deposit_charge(x, y, z, qw, nmodes, nr, dr, nz, dz, order=1):
             for m in range(nmodes)]
 
 
+def _folded_moment(j, dr, order, upper=np.inf):
+    """int_0^upper of node j's folded weight times r.  Between the breakpoints
+    (n + 1/2) dr (and the cut at upper) the integrand is a polynomial of
+    degree order + 1 <= 4, so 3-point Gauss-Legendre on each piece is exact."""
+    reach = (order + 1) // 2
+    lo = max(0.0, (j + 0.5 - reach) * dr)
+    hi = (j + 0.5 + reach) * dr
+    cuts = [(i + 0.5) * dr for i in range(j + reach)] + [upper]
+    edges = np.unique([lo, hi] + [c for c in cuts if lo < c < hi])
+    t, wq = np.polynomial.legendre.leggauss(3)
+    tot = 0.0
+    for a, b in zip(edges[:-1], edges[1:]):
+        if 0.5 * (a + b) >= upper:
+            break
+        rr = 0.5 * (b - a) * t + 0.5 * (a + b)
+        tot += 0.5 * (b - a) * np.sum(wq * folded_weight(rr, j, dr, order) * rr)
+    return tot
+
+
 def uniform_cylinder_background(density, rp, v_z, nmodes, nr, dr, nz, dz, order=1):
     """Charge and current of a neutralising ion column: charge density
     +density for r < rp, uniform in z and theta, drifting at v_z along z
@@ -351,11 +370,8 @@ def uniform_cylinder_background(density, rp, v_z, nmodes, nr, dr, nz, dz, order=
     uniform electron column up to the particles' noise.  Returns per mode
     (rho, (J_r, J_theta, J_z)) real-space [nz][nr] arrays (modes >= 1
     zero)."""
-    r = np.linspace(0.0, (nr + 2) * dr, 400001)
-    prof = np.zeros(nr)
-    for j in range(nr):
-        w = folded_weight(r, j, dr, order)
-        prof[j] = np.trapezoid(w * r * (r < rp), r) / np.trapezoid(w * r, r)
+    prof = np.array([_folded_moment(j, dr, order, rp) / _folded_moment(j, dr, order)
+                     for j in range(nr)])
     rho0 = density * np.ones((nz, 1)) * prof[None, :] + 0j
     zero = np.zeros((nz, nr), dtype=complex)
     out = []
@@ -463,9 +479,10 @@ class CylindricalPIC:
                 "J": J, "rho": rho}
 
 
-def field_energy(G, nr, dr, dz):
+def field_energy(G, nr, dr, dz, order=1):
     """sum_m sum_nodes V_j |g_m|^2 / c_m over the components of real mode
-    fields G[m] = (F_r, F_theta, F_z): a norm for growth diagnostics."""
-    vol = node_volumes(nr, dr, dz)
+    fields G[m] = (F_r, F_theta, F_z), with the node volumes of the shape
+    order: a norm for growth diagnostics."""
+    vol = node_volumes(nr, dr, dz, order)
     return float(sum(np.sum(vol[None, :] * np.abs(a) ** 2) / mode_factor(m)
                      for m, comps in enumerate(G) for a in comps))

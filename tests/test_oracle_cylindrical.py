@@ -385,7 +385,9 @@ def test_uniform_density_deposits_uniformly_up_to_the_axis(order):
     """A column of density 1 sampled finely (equal-area radii, any angles,
     a regular z lattice) deposits density 1 on every node whose support lies
     inside the column, the axis nodes included: the axis fold (node j < 0
-    onto -j-1) and the node volumes must agree for that."""
+    onto -j-1) and the node volumes must agree for that.  On the nodes that
+    straddle the column's edge it deposits the share of the node's shape
+    volume inside it, which is the neutralising background's profile."""
     nz, nr, dz, dr = 4, 10, 1.0, 0.5
     R = 7 * dr
     nrad, nzp = 6000, 8
@@ -401,3 +403,8 @@ def test_uniform_density_deposits_uniformly_up_to_the_axis(order):
     reach = (order + 1) // 2
     inside = [j for j in range(nr) if (j + 0.5 + reach) * dr <= R]
     assert np.max(np.abs(g0[:, inside] - 1.0)) <= 2e-6, g0[0, inside]
+    bg = cy.uniform_cylinder_background(1.0, R, 0.3, 1, nr, dr, nz, dz, order)[0]
+    edge = [j for j in range(nr) if (j + 0.5 - reach) * dr < R < (j + 0.5 + reach) * dr]
+    assert len(edge) == 2 * reach
+    assert np.max(np.abs(g0 - bg[0])) <= 2e-6, (g0[0], bg[0][0])
+    assert np.max(np.abs(bg[1][2] - 0.3 * bg[0])) == 0.0
