@@ -368,6 +368,7 @@ typedef struct {
   int nmodes;    /* azimuthal modes m = 0 .. nmodes-1: [1, 8]              */
   double dz, dr, dt;
   int precision; /* GP_FP64 or GP_MIXED (float fields, FP64-built tables)  */
+  int shape_order; /* particle shape in r and z: 0 or 1 linear, 3 cubic    */
 } gp_qc_desc;
 
 /* Selectors of gp_qc_read / gp_qc_write: real-space components, spectral
@@ -421,13 +422,14 @@ typedef struct {
 } gp_qc_particles;
 
 /* Deposition and gather by azimuthal mode (the paper's runs use a
- * quasi-cylindrical code; it does not print the scheme).  Linear weights in
- * r (nodes (j + 1/2) dr) and z; a stored mode-m field is c_m f_m (c_0 = 1,
- * c_m = 2), so the physical field is Re sum_m F_m exp(i m theta); a particle
- * inside dr/2 folds its inner weight onto node 0 with (-1)^m (scalars, z
- * components) or (-1)^(m+1) (r, theta components); node j's volume is its
- * folded weight's integral against 2 pi r dr dz; weights past the last node
- * are dropped.
+ * quasi-cylindrical code; it does not print the scheme).  B-spline weights
+ * of order shape_order (linear or cubic) in r (nodes (j + 1/2) dr) and z; a
+ * stored mode-m field is c_m f_m (c_0 = 1, c_m = 2), so the physical field
+ * is Re sum_m F_m exp(i m theta); a radial node j < 0 is node -j-1 seen
+ * across the axis and takes its weight with (-1)^m (scalars, z components)
+ * or (-1)^(m+1) (r, theta components); node j's volume is its folded
+ * weight's integral against 2 pi r dr dz; weights past the last node are
+ * dropped.
  *
  * gp_qc_set_background: a fixed source added to every deposit (e.g. a
  * neutralising ion column), complex [mode][z][r] host or device arrays of rho,

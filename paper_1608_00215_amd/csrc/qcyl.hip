@@ -386,13 +386,13 @@ __global__ __launch_bounds__(256) void k_qc_update(QcUpd<T> p, int nmodes, int n
 }
 
 // ---- particles: deposition and gather by azimuthal mode --------------------
-// Linear (CIC) shapes in r (nodes (j + 1/2) dr) and z (nodes k dz,
-// periodic).  A stored mode-m field is c_m f_m (c_0 = 1, c_m = 2), so the
-// physical field is Re sum_m g_m exp(i m theta).  A particle with r < dr/2
-// has its inner node at r = -dr/2, which is node 0 seen across the axis: its
-// weight goes to node 0 with (-1)^m for scalars and z components and
-// (-1)^(m+1) for r and theta components.  Node j's volume is the integral of
-// its (folded) weight against 2 pi r dr dz.  Weights past the last node are
+// B-spline shapes of order O (1 linear, 3 cubic) in r (nodes (j + 1/2) dr)
+// and z (nodes k dz, periodic).  A stored mode-m field is c_m f_m (c_0 = 1,
+// c_m = 2), so the physical field is Re sum_m g_m exp(i m theta).  A radial
+// node j < 0 (at r = (j + 1/2) dr < 0) is node -j-1 seen across the axis: its
+// weight goes there with (-1)^m for scalars and z components and (-1)^(m+1)
+// for r and theta components.  Node j's volume is the integral of its
+// (folded) weight against 2 pi r dr dz.  Weights past the last node are
 // dropped.  At r = 0 the angle is taken as 0.
 
 template <typename T>
@@ -408,28 +408,48 @@ struct QcGeo {
   const T *inv_vol;  // [nr]
 };
 
-template <typename T>
+// B-spline weights of the O + 1 nodes around an offset f in [0, 1): linear
+// {1 - f, f} on nodes 0, 1; cubic on nodes -1 .. 2.
+template <typename T, int O>
+__device__ __forceinline__ void qc_weights(T f, T *w) {
+  if (O == 1) {
+    w[0] = T(1) - f;
+    w[1] = f;
+  } else {
+    const T g = T(1) - f, f2 = f * f, f3 = f2 * f;
+    w[0] = g * g * g / T(6);
+    w[1] = (T(4) - T(6) * f2 + T(3) * f3) / T(6);
+    w[2] = (T(1) + T(3) * f + T(3) * f2 - T(3) * f3) / T(6);
+    w[3] = f3 / T(6);
+  }
+}
+
+template <typename T, int O>
 struct QcNodes {
-  int j0;        // inner radial node (-1: folded onto 0)
-  T fr;          // weight of j0 + 1
-  int k0, k1;
-  T fz;          // weight of k1
+  int j0;          // first radial node (may be negative: folded)
+  T wr[O + 1];
+  int k[O + 1];    // z nodes, wrapped
+  T wz[O + 1];
 };
 
-template <typename T>
-__device__ __forceinline__ QcNodes<T> qc_nodes(const QcGeo<T> &g, T r, T z) {
-  QcNodes<T> o;
+template <typename T, int O>
+__device__ __forceinline__ QcNodes<T, O> qc_nodes(const QcGeo<T> &g, T r, T z) {
+  QcNodes<T, O> o;
+  constexpr int lo = O == 1 ? 0 : -1;  // offset of the first node
   const T sr = r * g.inv_dr - T(0.5);
   const T fj = floor(sr);
-  o.j0 = int(fj);
-  o.fr = sr - fj;
+  o.j0 = int(fj) + lo;
+  qc_weights<T, O>(sr - fj, o.wr);
   const T sz = z * g.inv_dz;
   const T fk = floor(sz);
-  o.fz = sz - fk;
-  int k = int(fk) % g.nz;
+  qc_weights<T, O>(sz - fk, o.wz);
+  int k = (int(fk) + lo) % g.nz;
   if (k < 0) k += g.nz;
-  o.k0 = k;
-  o.k1 = k + 1 == g.nz ? 0 : k + 1;
+#pragma unroll
+  for (int b = 0; b <= O; ++b) {
+    o.k[b] = k;
+    k = k + 1 == g.nz ? 0 : k + 1;
+  }
   return o;
 }
 
@@ -448,8 +468,8 @@ __device__ __forceinline__ void qc_angle(T x, T y, T &r, T &c, T &s) {
 
 // Add c_m val exp(-i m theta) W s / V to the four nodes of every mode,
 // through add(m, k, j, re, im).
-template <typename T, typename Add>
-__device__ __forceinline__ void qc_deposit(const QcGeo<T> &g, const QcNodes<T> &nd, T c, T s,
+template <typename T, int O, typename Add>
+__device__ __forceinline__ void qc_deposit(const QcGeo<T> &g, const QcNodes<T, O> &nd, T c, T s,
                                            T val, bool transverse, Add &&add) {
   T er = T(1), ei = T(0);  // exp(-i m theta), advanced per mode
   for (int m = 0; m < g.nmodes; ++m) {
@@ -457,16 +477,15 @@ __device__ __forceinline__ void qc_deposit(const QcGeo<T> &g, const QcNodes<T> &
     const T fold = ((m + (transverse ? 1 : 0)) & 1) ? T(-1) : T(1);
     const T vr = cm * val * er, vi = cm * val * ei;
 #pragma unroll
-    for (int a = 0; a < 2; ++a) {
+    for (int a = 0; a <= O; ++a) {
       const int j = nd.j0 + a;
-      const int jj = j < 0 ? 0 : j;
+      const int jj = j < 0 ? -j - 1 : j;
       if (jj >= g.nr) continue;
-      const T wr = (a ? nd.fr : T(1) - nd.fr) * (j < 0 ? fold : T(1)) * g.inv_vol[jj];
+      const T wr = nd.wr[a] * (j < 0 ? fold : T(1)) * g.inv_vol[jj];
 #pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        const int k = b ? nd.k1 : nd.k0;
-        const T w = wr * (b ? nd.fz : T(1) - nd.fz);
-        add(m, k, jj, w * vr, w * vi);
+      for (int b = 0; b <= O; ++b) {
+        const T w = wr * nd.wz[b];
+        add(m, nd.k[b], jj, w * vr, w * vi);
       }
     }
     // exp(-i (m+1) theta) = exp(-i m theta) (c - i s)
@@ -490,9 +509,9 @@ struct GlobalSink {
 };
 
 // Re sum_m (sum over nodes of W s g_m) exp(i m theta) for one component.
-template <typename T>
+template <typename T, int O>
 __device__ __forceinline__ T qc_gather(const QcGeo<T> &g, const T *__restrict__ arr,
-                                       const QcNodes<T> &nd, T c, T s, bool transverse) {
+                                       const QcNodes<T, O> &nd, T c, T s, bool transverse) {
   const int64_t plane = int64_t(g.nz) * g.nr;
   T er = T(1), ei = T(0);  // exp(i m theta)
   T out = T(0);
@@ -500,15 +519,15 @@ __device__ __forceinline__ T qc_gather(const QcGeo<T> &g, const T *__restrict__ 
     const T fold = ((m + (transverse ? 1 : 0)) & 1) ? T(-1) : T(1);
     T ar = T(0), ai = T(0);
 #pragma unroll
-    for (int a = 0; a < 2; ++a) {
+    for (int a = 0; a <= O; ++a) {
       const int j = nd.j0 + a;
-      const int jj = j < 0 ? 0 : j;
+      const int jj = j < 0 ? -j - 1 : j;
       if (jj >= g.nr) continue;
-      const T wr = (a ? nd.fr : T(1) - nd.fr) * (j < 0 ? fold : T(1));
+      const T wr = nd.wr[a] * (j < 0 ? fold : T(1));
 #pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        const int k = b ? nd.k1 : nd.k0;
-        const T w = wr * (b ? nd.fz : T(1) - nd.fz);
+      for (int b = 0; b <= O; ++b) {
+        const int k = nd.k[b];
+        const T w = wr * nd.wz[b];
         const int64_t at = 2 * (int64_t(m) * plane + int64_t(k) * g.nr + jj);
         ar += w * arr[at];
         ai += w * arr[at + 1];
@@ -532,7 +551,7 @@ struct QcSrc {
 // without, rho at x.  Moves use v - v_gal (v_gal along z); z wraps, x and y
 // are open.  sink(s) gives the sink of source s (0 J_r, 1 J_theta, 2 J_z,
 // 3 rho).
-template <typename T, typename SinkOf>
+template <typename T, int O, typename SinkOf>
 __device__ __forceinline__ void qc_particle_deposit(const QcPart<T> &p, const QcGeo<T> &g,
                                                     int64_t i, T dt, T vgal, T qw, int move,
                                                     SinkOf &&sink) {
@@ -551,7 +570,7 @@ __device__ __forceinline__ void qc_particle_deposit(const QcPart<T> &p, const Qc
     z = wrap(z + h * (vz - vgal));
     T r, c, s;
     qc_angle(x, y, r, c, s);
-    const QcNodes<T> nd = qc_nodes(g, r, z);
+    const QcNodes<T, O> nd = qc_nodes<T, O>(g, r, z);
     const T vr = vx * c + vy * s, vt = -vx * s + vy * c;
     qc_deposit(g, nd, c, s, qw * vr, true, sink(0));
     qc_deposit(g, nd, c, s, qw * vt, true, sink(1));
@@ -565,33 +584,37 @@ __device__ __forceinline__ void qc_particle_deposit(const QcPart<T> &p, const Qc
   }
   T r, c, s;
   qc_angle(x, y, r, c, s);
-  qc_deposit(g, qc_nodes(g, r, z), c, s, qw, false, sink(3));
+  qc_deposit(g, qc_nodes<T, O>(g, r, z), c, s, qw, false, sink(3));
 }
 
-template <typename T>
+template <typename T, int O>
 __global__ __launch_bounds__(256) void k_qc_move_deposit(QcPart<T> p, QcGeo<T> g, QcSrc<T> src,
                                                          T dt, T vgal, T qw, int move) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= p.n) return;
   T *arrs[4] = {global_ptr(src.jr), global_ptr(src.jt), global_ptr(src.jz),
                 global_ptr(src.rho)};
-  qc_particle_deposit(p, g, i, dt, vgal, qw, move, [=](int si) {
+  qc_particle_deposit<T, O>(p, g, i, dt, vgal, qw, move, [=](int si) {
     return GlobalSink<T>{arrs[si], g.nz, g.nr};
   });
 }
 
 // The same with an LDS window: a workgroup takes kQcChunk consecutive
 // particles (sorted along z at binding, so a chunk covers few z nodes),
-// accumulates the nodes of kQcWin z planes from one plane below its first
-// particle in LDS ([source][mode][plane][r] complex, in double for either
-// precision), sends every other node straight to global atomics, and
-// flushes the window's nonzero entries with global atomics at the end.
+// accumulates the nodes of a window of z planes (4 for linear shapes from
+// one plane below its first particle, 6 for cubic ones from two below) in
+// LDS ([source][mode][plane][r] complex, in double for either precision),
+// sends every other node straight to global atomics, and flushes the
+// window's nonzero entries with global atomics at the end.
 constexpr int kQcDepThreads = 256;
 constexpr int kQcDepPer = 8;
 constexpr int kQcChunk = kQcDepThreads * kQcDepPer;
-constexpr int kQcWin = 4;
+template <int O>
+constexpr int qc_win() {
+  return O == 1 ? 4 : 6;
+}
 
-template <typename T>
+template <typename T, int O>
 __global__ __launch_bounds__(kQcDepThreads) void k_qc_move_deposit_tiled(QcPart<T> p, QcGeo<T> g,
                                                                          QcSrc<T> src, T dt,
                                                                          T vgal, T qw, int move) {
@@ -600,6 +623,7 @@ __global__ __launch_bounds__(kQcDepThreads) void k_qc_move_deposit_tiled(QcPart<
   double *win = reinterpret_cast<double *>(qdsm);
   __shared__ int zs_sh;
   const int64_t first = int64_t(blockIdx.x) * kQcChunk;
+  constexpr int kQcWin = qc_win<O>();
   const int plane = g.nr * 2;                            // values per z plane
   const int per_src = g.nmodes * kQcWin * plane;
   const int total = 4 * per_src;
@@ -613,7 +637,7 @@ __global__ __launch_bounds__(kQcDepThreads) void k_qc_move_deposit_tiled(QcPart<
     }
     int k = int(floor(z * g.inv_dz)) % g.nz;
     if (k < 0) k += g.nz;
-    zs_sh = (k - 1 + g.nz) % g.nz;
+    zs_sh = (k - (O == 1 ? 1 : 2) + 2 * g.nz) % g.nz;
   }
   for (int t = threadIdx.x; t < total; t += kQcDepThreads) win[t] = 0.0;
   __syncthreads();
@@ -624,7 +648,7 @@ __global__ __launch_bounds__(kQcDepThreads) void k_qc_move_deposit_tiled(QcPart<
   for (int q = 0; q < kQcDepPer; ++q) {
     const int64_t i = first + int64_t(q) * kQcDepThreads + threadIdx.x;
     if (i >= p.n) break;
-    qc_particle_deposit(p, g, i, dt, vgal, qw, move, [=](int si) {
+    qc_particle_deposit<T, O>(p, g, i, dt, vgal, qw, move, [=](int si) {
       T *garr = arrs[si];
       double *warr = win + si * per_src;
       return [=](int m, int k, int j, T re, T im) {
@@ -679,7 +703,7 @@ __global__ __launch_bounds__(256) void k_qc_reset_sources(QcSrc<T> dst, QcSrc<T>
 
 // Gather E, B at x (the mode fields [m][z][r]: r, theta, z components), then
 // the relativistic Boris push of u over dt (c = 1).
-template <typename T>
+template <typename T, int O>
 __global__ __launch_bounds__(256) void k_qc_gather_push(QcPart<T> p, QcGeo<T> g,
                                                         const T *__restrict__ E0,
                                                         const T *__restrict__ E1,
@@ -691,7 +715,7 @@ __global__ __launch_bounds__(256) void k_qc_gather_push(QcPart<T> p, QcGeo<T> g,
   if (i >= p.n) return;
   T r, c, s;
   qc_angle(p.x[i], p.y[i], r, c, s);
-  const QcNodes<T> nd = qc_nodes(g, r, p.z[i]);
+  const QcNodes<T, O> nd = qc_nodes<T, O>(g, r, p.z[i]);
   const T er = qc_gather(g, E0, nd, c, s, true), et = qc_gather(g, E1, nd, c, s, true);
   const T ez = qc_gather(g, E2, nd, c, s, false);
   const T br = qc_gather(g, B0, nd, c, s, true), bt = qc_gather(g, B1, nd, c, s, true);
@@ -957,6 +981,7 @@ struct gp_qc_ctx {
   void *bg[4] = {};        // background rho, J_r, J_theta, J_z (allocated once)
   bool has_bg = false;
   void *inv_vol = nullptr; // [nr] 1 / V_j in the real type
+  int order = 1;           // particle shape: 1 linear, 3 cubic
 };
 
 namespace {
@@ -1157,12 +1182,40 @@ gp_status build_transforms(gp_qc_ctx *c) {
   QTRY(qalloc(c, kd.size() * sizeof(double), &p));
   c->kr_d = static_cast<double *>(p);
   QTRY(qalloc(c, kt.size() * sizeof(T), &c->kr_t));
-  // 1 / V_j, V_j = 2 pi dz dr^2 (j + 1/2), and (13/24) 2 pi dz dr^2 for the
-  // axis node (the integral of its folded linear weight against r dr)
+  // 1 / V_j, V_j = 2 pi dz times the integral of node j's folded weight
+  // against r dr: dr^2 (j + 1/2) where the shape's support stays off the
+  // axis; (13/24) dr^2 for the linear axis node; for cubic shapes the axis
+  // nodes 0 and 1 are integrated exactly (the folded weight times r is a
+  // polynomial between the breakpoints (n + 1/2) dr: 4-point Gauss-Legendre
+  // per piece)
   std::vector<T> iv(nr);
+  const double dr2 = c->d.dr * c->d.dr;
   for (int j = 0; j < nr; ++j) {
-    const double v = 2.0 * kPi * c->d.dz * c->d.dr * c->d.dr * (j == 0 ? 13.0 / 24.0 : j + 0.5);
-    iv[j] = T(1.0 / v);
+    double v = (j + 0.5) * dr2;
+    if (c->order == 1 && j == 0) v = 13.0 / 24.0 * dr2;
+    if (c->order == 3 && j < 2) {
+      auto cubic = [](double x) {  // the centred cubic B-spline
+        const double a = std::fabs(x);
+        return a < 1.0 ? (4.0 - 6.0 * a * a + 3.0 * a * a * a) / 6.0
+                       : (a < 2.0 ? (2.0 - a) * (2.0 - a) * (2.0 - a) / 6.0 : 0.0);
+      };
+      // nodes and weights of 4-point Gauss-Legendre on [-1, 1]
+      const double gx[4] = {-0.8611363115940526, -0.3399810435848563, 0.3399810435848563,
+                            0.8611363115940526};
+      const double gw[4] = {0.3478548451374538, 0.6521451548625461, 0.6521451548625461,
+                            0.3478548451374538};
+      double acc = 0.0;  // in units of dr: int_0^{j+2.5} w(u) u du
+      for (int piece = 0; piece <= j + 2; ++piece) {
+        const double a = piece == 0 ? 0.0 : piece - 0.5, b = piece + 0.5;
+        for (int q = 0; q < 4; ++q) {
+          const double u = 0.5 * (b - a) * gx[q] + 0.5 * (a + b);
+          const double w = cubic(u - (j + 0.5)) + cubic(u + (j + 0.5));  // node + mirror
+          acc += 0.5 * (b - a) * gw[q] * w * u;
+        }
+      }
+      v = acc * dr2;
+    }
+    iv[j] = T(1.0 / (2.0 * kPi * c->d.dz * v));
   }
   QTRY(qalloc(c, iv.size() * sizeof(T), &c->inv_vol));
   if (hipMemcpyAsync(c->inv_vol, iv.data(), iv.size() * sizeof(T), hipMemcpyHostToDevice,
@@ -1309,6 +1362,31 @@ gp_status sort_particles_by_z(gp_qc_ctx *c) {
   return GP_OK;
 }
 
+// Windows above this take the plain kernel (gfx950 allows 160 KiB of LDS
+// per workgroup; the attribute below lifts the 64 KiB default).
+constexpr size_t kQcMaxWindow = 128 * 1024;
+
+template <typename T, int O>
+void launch_move_deposit_o(gp_qc_ctx *c, const QcSrc<T> &src, int move) {
+  const size_t lds = size_t(4) * c->d.nmodes * qc_win<O>() * c->d.nr * 2 * sizeof(double);
+  if (lds <= kQcMaxWindow) {
+    static bool attr_set = false;
+    if (!attr_set) {
+      (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_qc_move_deposit_tiled<T, O>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, int(kQcMaxWindow));
+      attr_set = true;
+    }
+    hipLaunchKernelGGL((k_qc_move_deposit_tiled<T, O>),
+                       dim3(unsigned((c->part.n + kQcChunk - 1) / kQcChunk)), dim3(kQcDepThreads),
+                       lds, c->stream, qc_part<T>(c), qc_geo<T>(c), src, T(c->d.dt), T(c->vgal),
+                       T(c->part.q * c->part.w), move);
+  } else {
+    hipLaunchKernelGGL((k_qc_move_deposit<T, O>), dim3(unsigned((c->part.n + 255) / 256)),
+                       dim3(256), 0, c->stream, qc_part<T>(c), qc_geo<T>(c), src, T(c->d.dt),
+                       T(c->vgal), T(c->part.q * c->part.w), move);
+  }
+}
+
 template <typename T>
 void launch_move_deposit(gp_qc_ctx *c, int move) {
   if (c->part.n == 0) return;
@@ -1318,17 +1396,10 @@ void launch_move_deposit(gp_qc_ctx *c, int move) {
   src.jz = static_cast<T *>(c->real[8]);
   src.rho = static_cast<T *>(c->real[9]);
   QStamp stamp(c, 5);
-  const size_t lds = size_t(4) * c->d.nmodes * kQcWin * c->d.nr * 2 * sizeof(double);
-  if (lds <= 65536) {
-    hipLaunchKernelGGL((k_qc_move_deposit_tiled<T>),
-                       dim3(unsigned((c->part.n + kQcChunk - 1) / kQcChunk)), dim3(kQcDepThreads),
-                       lds, c->stream, qc_part<T>(c), qc_geo<T>(c), src, T(c->d.dt), T(c->vgal),
-                       T(c->part.q * c->part.w), move);
-  } else {
-    hipLaunchKernelGGL((k_qc_move_deposit<T>), dim3(unsigned((c->part.n + 255) / 256)),
-                       dim3(256), 0, c->stream, qc_part<T>(c), qc_geo<T>(c), src, T(c->d.dt),
-                       T(c->vgal), T(c->part.q * c->part.w), move);
-  }
+  if (c->order == 3)
+    launch_move_deposit_o<T, 3>(c, src, move);
+  else
+    launch_move_deposit_o<T, 1>(c, src, move);
 }
 
 template <typename T>
@@ -1336,11 +1407,17 @@ void launch_gather_push(gp_qc_ctx *c) {
   if (c->part.n == 0) return;
   const T h = T(c->part.q * c->d.dt / (2.0 * c->part.m));
   QStamp stamp(c, 6);
-  hipLaunchKernelGGL((k_qc_gather_push<T>), dim3(unsigned((c->part.n + 255) / 256)), dim3(256),
-                     0, c->stream, qc_part<T>(c), qc_geo<T>(c),
-                     static_cast<const T *>(c->real[0]), static_cast<const T *>(c->real[1]),
-                     static_cast<const T *>(c->real[2]), static_cast<const T *>(c->real[3]),
-                     static_cast<const T *>(c->real[4]), static_cast<const T *>(c->real[5]), h);
+  auto go = [&](auto kern) {
+    hipLaunchKernelGGL(kern, dim3(unsigned((c->part.n + 255) / 256)), dim3(256), 0, c->stream,
+                       qc_part<T>(c), qc_geo<T>(c), static_cast<const T *>(c->real[0]),
+                       static_cast<const T *>(c->real[1]), static_cast<const T *>(c->real[2]),
+                       static_cast<const T *>(c->real[3]), static_cast<const T *>(c->real[4]),
+                       static_cast<const T *>(c->real[5]), h);
+  };
+  if (c->order == 3)
+    go(k_qc_gather_push<T, 3>);
+  else
+    go(k_qc_gather_push<T, 1>);
 }
 
 }  // namespace
@@ -1358,8 +1435,11 @@ gp_status gp_qc_init(const gp_qc_desc *d, void *hip_stream, gp_qc_ctx **out) {
     return qfail(GP_ERR_ARG, "dz, dr, dt must be positive and finite");
   if (d->precision != GP_FP64 && d->precision != GP_MIXED)
     return qfail(GP_ERR_ARG, "precision must be GP_FP64 or GP_MIXED");
+  if (d->shape_order != 0 && d->shape_order != 1 && d->shape_order != 3)
+    return qfail(GP_ERR_ARG, "shape_order must be 0 or 1 (linear) or 3 (cubic)");
   gp_qc_ctx *c = new gp_qc_ctx();
   c->d = *d;
+  c->order = d->shape_order == 3 ? 3 : 1;
   c->real_size = d->precision == GP_FP64 ? 8 : 4;
   auto bail = [&](gp_status st) {
     std::string keep = gp_last_error();

@@ -65,7 +65,7 @@ class QcParticlesC(ctypes.Structure):
 class QcDesc(ctypes.Structure):
     _fields_ = [("nz", ctypes.c_int), ("nr", ctypes.c_int), ("nmodes", ctypes.c_int),
                 ("dz", ctypes.c_double), ("dr", ctypes.c_double), ("dt", ctypes.c_double),
-                ("precision", ctypes.c_int)]
+                ("precision", ctypes.c_int), ("shape_order", ctypes.c_int)]
 
 
 class ParticlesC(ctypes.Structure):
@@ -490,10 +490,10 @@ class QcContext:
     modes on an nz x nr (z, r) grid.  Fields are complex numpy arrays
     [mode][z][r]."""
 
-    def __init__(self, nz, nr, nmodes, dz, dr, dt, precision, stream=None):
+    def __init__(self, nz, nr, nmodes, dz, dr, dt, precision, stream=None, shape_order=1):
         self.lib = load()
         _init_torch_first()
-        d = QcDesc(nz, nr, nmodes, dz, dr, dt, precision)
+        d = QcDesc(nz, nr, nmodes, dz, dr, dt, precision, shape_order)
         self.shape = (nmodes, nz, nr)
         self.precision = precision
         self.cplx = np.complex128 if precision == GP_FP64 else np.complex64

@@ -1,6 +1,7 @@
 """GPU parity of the quasi-cylindrical particle cycle (deposition and gather
 by azimuthal mode, Boris push, Galilean moves) against the oracle's
-CylindricalPIC, on the same seeded inputs.
+CylindricalPIC, on the same seeded inputs, with linear (order 1) and cubic
+(order 3) B-spline shapes.
 
 Bars: one call or step from an identical state, relative L2 per field 1e-12
 (FP64) and 1e-5 (mixed), particle positions and momenta within 1e-12 / 1e-5
@@ -64,13 +65,13 @@ def _bg_arrays(bg, nmodes):
 
 
 def _setup(precision, nz, nr, nmodes, dz, dr, dt, n, vz, seed, rp, gamma=None, u_th=0.0,
-           fields=True, background=True):
+           fields=True, background=True, order=1):
     rng = np.random.default_rng(seed)
     x, u = _column(rng, n, rp, nz * dz, precision, gamma, u_th)
     q, mass = -1.0, 1.0
     w = np.pi * rp * rp * nz * dz / n
-    bg = cy.uniform_cylinder_background(1.0, rp, vz, nmodes, nr, dr, nz, dz) if background \
-        else None
+    bg = cy.uniform_cylinder_background(1.0, rp, vz, nmodes, nr, dr, nz, dz, order) \
+        if background else None
     shp = (nz, nr)
     cplx = lambda: 0.05 * (rng.standard_normal(shp) + 1j * rng.standard_normal(shp))
     E0 = [tuple(cplx() for _ in range(3)) for _ in range(nmodes)] if fields else None
@@ -79,7 +80,7 @@ def _setup(precision, nz, nr, nmodes, dz, dr, dt, n, vz, seed, rp, gamma=None, u
         c64 = lambda a: a.astype(np.complex64).astype(np.complex128)
         E0 = [tuple(c64(a) for a in e) for e in E0]
         B0 = [tuple(c64(a) for a in b) for b in B0]
-    ctx = gp.QcContext(nz, nr, nmodes, dz, dr, dt, precision)
+    ctx = gp.QcContext(nz, nr, nmodes, dz, dr, dt, precision, shape_order=order)
     ctx.set_v_gal(vz)
     if background:
         rho_bg, J_bg = _bg_arrays(bg, nmodes)
@@ -92,7 +93,8 @@ def _setup(precision, nz, nr, nmodes, dz, dr, dt, n, vz, seed, rp, gamma=None, u
         ctx.fields_fwd()
     parts = _gpu_particles(x, u, precision)
     ctx.bind_particles(q, mass, w, *parts)
-    sim = cy.CylindricalPIC(nz, nr, nmodes, dz, dr, dt, q, mass, w, vz, background=bg)
+    sim = cy.CylindricalPIC(nz, nr, nmodes, dz, dr, dt, q, mass, w, vz, background=bg,
+                            order=order)
     st = sim.initial_state(x, u, E=E0, B=B0)
     return ctx, parts, sim, st
 
@@ -102,17 +104,20 @@ def _particles_back(parts):
     return np.stack(a[:3], 1), np.stack(a[3:], 1)
 
 
+@pytest.mark.parametrize("order", [1, 3])
 @pytest.mark.parametrize("background", [False, True])
 @pytest.mark.parametrize("precision", [gp.GP_FP64, gp.GP_MIXED])
-def test_bound_charge(gpu_lib, precision, background):
+def test_bound_charge(gpu_lib, precision, background, order):
     nz, nr, nm, dz, dr = 16, 14, 2, 0.9, 0.7
     ctx, parts, sim, st = _setup(precision, nz, nr, nm, dz, dr, 0.5, 3000, 0.0, 400,
-                                 rp=(nr - 2) * dr, fields=False, background=background)
+                                 rp=(nr - 2) * dr, fields=False, background=background,
+                                 order=order)
     tol = _tol(precision, nr, dr, nm)
     rho_real = ctx.read("RHO")
     rho_hat = ctx.read("RHO_HAT_OLD")
     x, _ = _particles_back(parts)
-    ref = cy.deposit_charge(x[:, 0], x[:, 1], x[:, 2], sim.q * sim.w, nm, nr, dr, nz, dz)
+    ref = cy.deposit_charge(x[:, 0], x[:, 1], x[:, 2], sim.q * sim.w, nm, nr, dr, nz, dz,
+                            order)
     if background:
         ref = [ref[m] + sim.background[m][0] for m in range(nm)]
     for m in range(nm):
@@ -121,11 +126,13 @@ def test_bound_charge(gpu_lib, precision, background):
     ctx.close()
 
 
+@pytest.mark.parametrize("order", [1, 3])
 @pytest.mark.parametrize("precision", [gp.GP_FP64, gp.GP_MIXED])
-def test_electrostatic_start(gpu_lib, precision):
+def test_electrostatic_start(gpu_lib, precision, order):
     nz, nr, nm, dz, dr = 16, 14, 2, 0.9, 0.7
     ctx, parts, sim, _ = _setup(precision, nz, nr, nm, dz, dr, 0.5, 3000, 0.0, 401,
-                                rp=(nr - 2) * dr, fields=False, background=True)
+                                rp=(nr - 2) * dr, fields=False, background=True,
+                                order=order)
     x, u = _particles_back(parts)
     st = sim.initial_state(x, u, electrostatic=True)
     ctx.electrostatic_fields()
@@ -140,14 +147,24 @@ def test_electrostatic_start(gpu_lib, precision):
     ctx.close()
 
 
+# (nz, nr, modes): the narrow grid deposits through the LDS window; the wide
+# one needs 4 sources x 3 modes x (4 or 6) planes x 180 nodes x 16 bytes =
+# 135 KiB (linear) or 203 KiB (cubic), above the 128 KiB the library gives the
+# window, and takes the plain deposit kernel
+GRIDS = {"narrow": (32, 16, 2), "wide": (8, 180, 3)}
+
+
+@pytest.mark.parametrize("grid", ["narrow", "wide"])
+@pytest.mark.parametrize("order", [1, 3])
 @pytest.mark.parametrize("precision", [gp.GP_FP64, gp.GP_MIXED])
-def test_one_step_two_modes(gpu_lib, precision):
-    """One whole step with modes 0 and 1, relativistic drift, thermal spread,
-    random initial fields, the ion background and Galilean moves."""
-    nz, nr, nm, dz, dr, dt = 32, 16, 2, 0.8, 0.6, 0.5
+def test_one_step(gpu_lib, precision, order, grid):
+    """One whole step with modes 0 and 1 (and 2), relativistic drift, thermal
+    spread, random initial fields, the ion background and Galilean moves."""
+    nz, nr, nm = GRIDS[grid]
+    dz, dr, dt = 0.8, 0.6, 0.5
     vz = -0.9
     ctx, parts, sim, st = _setup(precision, nz, nr, nm, dz, dr, dt, 4000, vz, 402,
-                                 rp=(nr - 2) * dr, gamma=2.0, u_th=0.05)
+                                 rp=(nr - 2) * dr, gamma=2.0, u_th=0.05, order=order)
     ctx.particle_step(1)
     ctx.synchronize()
     st1 = sim.step(st)
@@ -179,13 +196,14 @@ def test_one_step_two_modes(gpu_lib, precision):
     ctx.close()
 
 
+@pytest.mark.parametrize("order", [1, 3])
 @pytest.mark.parametrize("nm", [1, 2])
 @pytest.mark.parametrize("galilean", [True, False])
 @pytest.mark.parametrize("precision", [gp.GP_FP64, gp.GP_MIXED])
-def test_column_history(gpu_lib, precision, galilean, nm):
+def test_column_history(gpu_lib, precision, galilean, nm, order):
     """Ten steps of a drifting electron column (gamma 5, a small thermal
     spread) on its ion column, modes 0 (and 1), electrostatic start,
-    Galilean or standard frame."""
+    Galilean or standard frame, linear or cubic shapes."""
     nz, nr, dz, dr, dt = 32, 12, 1.0, 1.0, 1.0
     gamma = 5.0
     uz = np.float32(-np.sqrt(gamma * gamma - 1.0))
@@ -196,15 +214,16 @@ def test_column_history(gpu_lib, precision, galilean, nm):
     n = len(x)
     w = np.pi * rp * rp * nz * dz / n
     v_ion = float(uz / np.sqrt(1.0 + uz * uz))
-    bg = cy.uniform_cylinder_background(1.0, rp, v_ion, nm, nr, dr, nz, dz)
-    ctx = gp.QcContext(nz, nr, nm, dz, dr, dt, precision)
+    bg = cy.uniform_cylinder_background(1.0, rp, v_ion, nm, nr, dr, nz, dz, order)
+    ctx = gp.QcContext(nz, nr, nm, dz, dr, dt, precision, shape_order=order)
     ctx.set_v_gal(vz)
     rho_bg, J_bg = _bg_arrays(bg, nm)
     ctx.set_background(rho_bg, *J_bg)
     parts = _gpu_particles(x, u, precision)
     ctx.bind_particles(-1.0, 1.0, w, *parts)
     ctx.electrostatic_fields()
-    sim = cy.CylindricalPIC(nz, nr, nm, dz, dr, dt, -1.0, 1.0, w, vz, background=bg)
+    sim = cy.CylindricalPIC(nz, nr, nm, dz, dr, dt, -1.0, 1.0, w, vz, background=bg,
+                            order=order)
     st = sim.initial_state(x, u, electrostatic=True)
     steps = 10
     ctx.particle_step(steps)
@@ -231,6 +250,10 @@ def test_column_history(gpu_lib, precision, galilean, nm):
 def test_particle_errors(gpu_lib):
     import torch
 
+    for bad in (2, 4, -1):
+        with pytest.raises(gp.GalpicError) as e:
+            gp.QcContext(16, 8, 1, 1.0, 1.0, 0.5, gp.GP_FP64, shape_order=bad)
+        assert e.value.status == gp.GP_ERR_ARG, bad
     ctx = gp.QcContext(16, 8, 1, 1.0, 1.0, 0.5, gp.GP_FP64)
     with pytest.raises(gp.GalpicError) as e:
         ctx.particle_step(1)
