@@ -603,11 +603,17 @@ __global__ __launch_bounds__(256) void k_qc_move_deposit(QcPart<T> p, QcGeo<T> g
 // particles (sorted along z at binding, so a chunk covers few z nodes),
 // accumulates the nodes of a window of z planes (4 for linear shapes from
 // one plane below its first particle, 6 for cubic ones from two below) in
-// LDS ([source][mode][plane][r] complex, in double for either precision),
-// sends every other node straight to global atomics, and flushes the
-// window's nonzero entries with global atomics at the end.
-constexpr int kQcDepThreads = 256;
-constexpr int kQcDepPer = 8;
+// LDS, sends every other node straight to global atomics, and flushes the
+// window's nonzero entries with global atomics at the end.  The window is
+// [source][mode][plane][part][r] in double for either precision: real and
+// imaginary parts in separate rows, so that lanes adding to random radial
+// nodes spread over all LDS banks (interleaved, the real parts of a row
+// would fall on a quarter of them).  512 threads share one window (the
+// cubic window allows one workgroup per CU): eight waves per CU hide the
+// LDS atomics' conflicts better than four; measured against 256 x 8 and
+// 512 x 1 particles per workgroup, 512 x 2 was fastest.
+constexpr int kQcDepThreads = 512;
+constexpr int kQcDepPer = 2;
 constexpr int kQcChunk = kQcDepThreads * kQcDepPer;
 template <int O>
 constexpr int qc_win() {
@@ -628,7 +634,8 @@ __global__ __launch_bounds__(kQcDepThreads) void k_qc_move_deposit_tiled(QcPart<
   const int per_src = g.nmodes * kQcWin * plane;
   const int total = 4 * per_src;
   if (threadIdx.x == 0) {
-    // one plane below the first particle's z after its first half move
+    // one plane (linear) or two (cubic) below the first particle's z cell
+    // after its first half move
     T z = p.z[first];
     if (move) {
       const T ux = p.ux[first], uy = p.uy[first], uz = p.uz[first];
@@ -658,10 +665,10 @@ __global__ __launch_bounds__(kQcDepThreads) void k_qc_move_deposit_tiled(QcPart<
         // grid (distinct scopes also keep the two from being merged into
         // one flat atomic on a selected address)
         if (slot < kQcWin) {
-          double *w = warr + (m * kQcWin + slot) * plane + 2 * j;
+          double *w = warr + (m * kQcWin + slot) * plane + j;
           __hip_atomic_fetch_add(w, double(re), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
           if (m > 0)
-            __hip_atomic_fetch_add(w + 1, double(im), __ATOMIC_RELAXED,
+            __hip_atomic_fetch_add(w + nr, double(im), __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_WORKGROUP);
         } else {
           const int64_t at = 2 * ((int64_t(m) * nz + k) * nr + j);
@@ -681,7 +688,8 @@ __global__ __launch_bounds__(kQcDepThreads) void k_qc_move_deposit_tiled(QcPart<
     const int m = r1 / (kQcWin * plane);
     const int r2 = r1 % (kQcWin * plane);
     const int slot = r2 / plane;
-    const int e = r2 % plane;  // 2 j + part
+    const int e0 = r2 % plane;  // part * nr + j
+    const int e = 2 * (e0 % g.nr) + e0 / g.nr;
     const int k = (zs + slot) % g.nz;
     atomicAdd(global_ptr(arrs[si] + 2 * ((int64_t(m) * g.nz + k) * g.nr) + e), v);
   }
