@@ -296,6 +296,9 @@ QC_WORKLOADS = {
     # start
     "qc_column": dict(nz=512, nr=128, nmodes=2, dz=1.0, dr=1.0, dt=1.0, gamma=20.0,
                       steps=200, ppc=24, rp=96.0),
+    # the same with cubic shapes in r and z (as the paper's runs use)
+    "qc_column_cubic": dict(nz=512, nr=128, nmodes=2, dz=1.0, dr=1.0, dt=1.0, gamma=20.0,
+                            steps=200, ppc=24, rp=96.0, order=3),
 }
 
 
@@ -333,7 +336,7 @@ def run_qc(name, precision, steps, warmup):
     beta = np.sqrt(1.0 - 1.0 / w["gamma"] ** 2)
     stream = torch.cuda.current_stream()
     ctx = gp.QcContext(w["nz"], w["nr"], w["nmodes"], w["dz"], w["dr"], w["dt"], precision,
-                       stream=ctypes_stream(stream))
+                       stream=ctypes_stream(stream), shape_order=w.get("order", 1))
     ctx.set_v_gal(-beta)
     rng = np.random.Generator(np.random.PCG64(7000))
     shp = (w["nmodes"], w["nz"], w["nr"])
@@ -389,16 +392,39 @@ def qc_column_inputs(w):
 
 
 def qc_ion_profile(w):
-    """Per radial node, the share of the node's (folded, linear) shape
-    volume inside rp: the charge density of a uniform ion column of
-    density 1 as the deposit sees it."""
+    """Per radial node, the share of the node's shape volume (its B-spline
+    of the workload's order plus the mirror image across the axis, times r)
+    inside rp: the charge density of a uniform ion column of density 1 as
+    the deposit sees it.  In u = r / dr the integrand is a polynomial of
+    degree <= 4 between the half-integers, so 4-point Gauss-Legendre on
+    each unit piece (and the piece cut at rp) is exact."""
     dr, nr, rp = w["dr"], w["nr"], w["rp"]
-    r = np.linspace(0.0, (nr + 1) * dr, 400001)
-    tent = lambda j: np.maximum(0.0, 1.0 - np.abs(r - (j + 0.5) * dr) / dr)
+    order = w.get("order", 1)
+
+    def spline(t):
+        a = np.abs(t)
+        if order == 1:
+            return np.maximum(0.0, 1.0 - a)
+        return np.where(a < 1.0, 2.0 / 3.0 - a * a + 0.5 * a ** 3,
+                        np.where(a < 2.0, (2.0 - a) ** 3 / 6.0, 0.0))
+
+    gx, gw = np.polynomial.legendre.leggauss(4)
+    half = (order + 1) // 2
+    ucut = rp / dr
     prof = np.zeros(nr)
     for j in range(nr):
-        wt = tent(j) + (tent(-1) if j == 0 else 0.0)
-        prof[j] = np.trapezoid(wt * r * (r < rp), r) / np.trapezoid(wt * r, r)
+        c = j + 0.5
+        bounds = sorted({max(0.0, c - half), c + half, *[b + 0.5 for b in range(j + half)],
+                         *([ucut] if 0.0 < ucut < c + half else [])})
+        bounds = [b for b in bounds if max(0.0, c - half) <= b <= c + half]
+        inside = total = 0.0
+        for a, b in zip(bounds[:-1], bounds[1:]):
+            u = 0.5 * (a + b) + 0.5 * (b - a) * gx
+            part = 0.5 * (b - a) * np.sum(gw * (spline(u - c) + spline(u + c)) * u)
+            total += part
+            if 0.5 * (a + b) < ucut:
+                inside += part
+        prof[j] = inside / total
     return prof
 
 
@@ -538,7 +564,9 @@ def qc_main(args):
                                       "an electron column of "
                                       f"radius {w['rp']:g} ({w['ppc']} particles per (r, z) "
                                       f"cell, {mixed['particles']} particles) drifting at "
-                                      f"gamma {w['gamma']:g} on its ion column, Galilean frame")
+                                      f"gamma {w['gamma']:g} on its ion column, Galilean frame, "
+                                      f"{'cubic' if w.get('order', 1) == 3 else 'linear'} "
+                                      "shapes")
     if fp64 is not None:
         roof64, stages64 = summary(fp64, 8, FP64_PEAK_TFLOPS)
         line["fp64_gpu"] = {"value": cells * steps / fp64["wall_s"],
