@@ -84,7 +84,8 @@ def back_transform(levels, t0, dt, t_snap, dz, beta, c=C_LIGHT):
     return snaps, filled
 
 
-def particle_crossings(x_new, u_move, dt, t_new, v_gal_z, t_snap, length, c=C_LIGHT):
+def particle_crossings(x_new, u_move, dt, t_new, v_gal_z, t_snap, length, c=C_LIGHT,
+                       fractions=False):
     """Lab-frame records of the particles whose worldline over one step
     crosses a snapshot's lab time.
 
@@ -101,7 +102,8 @@ def particle_crossings(x_new, u_move, dt, t_new, v_gal_z, t_snap, length, c=C_LI
     position there (wrapped to the box; z scaled to the lab plane gamma z)
     and the lab momentum u_x, u_y, gamma (u_z + beta gamma_p).  Returns, per
     snapshot, (index, values) with values[:, 0:6] = x, y, z_lab, u_x, u_y,
-    u_z."""
+    u_z; with fractions, (index, values, s_j) (a crossing with s_j near 0 or
+    1 lies within rounding of the adjacent step's)."""
     beta = -v_gal_z / c
     g = 1.0 / np.sqrt(1.0 - beta * beta)
     gp = np.sqrt(1.0 + np.sum(u_move * u_move, axis=1))
@@ -119,5 +121,5 @@ def particle_crossings(x_new, u_move, dt, t_new, v_gal_z, t_snap, length, c=C_LI
         u = u_move[hit]
         vals = np.stack([pos[:, 0], pos[:, 1], g * pos[:, 2], u[:, 0], u[:, 1],
                          g * (u[:, 2] + beta * gp[hit])], axis=1)
-        out.append((hit, vals))
+        out.append((hit, vals, s) if fractions else (hit, vals))
     return out

@@ -154,6 +154,8 @@ def test_recording_errors_and_off(gpu_lib):
 
 
 def _oracle_particle_records(cfg, inp, E0, B0, t_snap, steps):
+    """Per snapshot (ids, values, s): the oracle's crossings of its own
+    history, with each crossing's fraction s along its step."""
     sim = oracle_sim(cfg)
     st = sim.initial_state(inp["x"], inp["u"], E0, B0, project_transverse=True)
     L = np.array(cfg.shape) * np.array(cfg.spacing)
@@ -162,15 +164,16 @@ def _oracle_particle_records(cfg, inp, E0, B0, t_snap, steps):
         u_move = st.u.copy()
         st = sim.step(st)
         hits = obtd.particle_crossings(st.x, u_move, cfg.dt, (n + 1) * cfg.dt, cfg.v_gal()[2],
-                                       t_snap, L)
-        for j, (idx, vals) in enumerate(hits):
-            recs[j].append((idx, vals))
+                                       t_snap, L, fractions=True)
+        for j, (idx, vals, s) in enumerate(hits):
+            recs[j].append((idx, vals, s))
     out = []
     for j in range(len(t_snap)):
         idx = np.concatenate([r[0] for r in recs[j]])
         vals = np.concatenate([r[1] for r in recs[j]])
+        s = np.concatenate([r[2] for r in recs[j]])
         order = np.argsort(idx)
-        out.append((idx[order], vals[order]))
+        out.append((idx[order], vals[order], s[order]))
     return out
 
 
@@ -187,7 +190,13 @@ def test_particle_records_match_the_oracle(gpu_lib, precision):
     """Thermal plasma with the laser, 30 steps: the particles recorded at two
     lab times and their lab positions and momenta match the oracle's
     crossings of its own history (FP64: the same set; mixed: the same set
-    but for particles within rounding of a crossing)."""
+    but for particles within rounding of a crossing).  A record holds the
+    momentum that moved the particle over its crossing step, so a mixed run
+    may record a particle whose crossing lies within rounding of a step
+    boundary one step apart from the oracle, with a momentum one push apart:
+    in mixed precision the values are compared for crossings with
+    1e-3 < s < 1 - 1e-3 along their step (the rest, about 0.2 %, are only
+    counted)."""
     cfg = CFG.with_(u_th=0.05)
     ctx, parts, inp, E0, B0 = _laser_start(cfg, precision)
     t_lab0, dt_lab, beta = _snap_times(cfg)
@@ -198,7 +207,7 @@ def test_particle_records_match_the_oracle(gpu_lib, precision):
     ref = _oracle_particle_records(cfg, inp, E0, B0, [t_lab0, t_lab0 + dt_lab], STEPS)
     for j in range(2):
         n, gid, gv = _gpu_records(vals, ids, counts, j)
-        rid, rv = ref[j]
+        rid, rv, rs = ref[j]
         assert len(rid) > 0.2 * inp["n"], j
         assert len(np.unique(gid)) == n, j                # once per particle
         if precision == gp.GP_FP64:
@@ -208,6 +217,9 @@ def test_particle_records_match_the_oracle(gpu_lib, precision):
             both, common_g, common_r = np.intersect1d(gid, rid, return_indices=True)
             assert len(rid) - len(both) <= max(20, 1e-4 * len(rid)), j
             assert n - len(both) <= max(20, 1e-4 * len(rid)), j
+            inner = (rs[common_r] > 1e-3) & (rs[common_r] < 1.0 - 1e-3)
+            assert np.sum(~inner) <= 0.005 * len(both), (j, int(np.sum(~inner)))
+            common_g, common_r = common_g[inner], common_r[inner]
         a, b = gv[common_g], rv[common_r]
         tol = 1e-9 if precision == gp.GP_FP64 else 2e-4
         for q in range(6):
