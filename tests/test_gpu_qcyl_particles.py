@@ -196,6 +196,63 @@ def test_one_step(gpu_lib, precision, order, grid):
 
 
 @pytest.mark.parametrize("order", [1, 3])
+@pytest.mark.parametrize("precision", [gp.GP_FP64, gp.GP_MIXED])
+def test_one_step_eight_modes(gpu_lib, precision, order):
+    """The largest mode count a context takes (modes 0..7), one whole step
+    with random initial fields, drift and thermal spread."""
+    nz, nr, nm, dz, dr, dt = 16, 12, 8, 0.9, 0.7, 0.5
+    ctx, parts, sim, st = _setup(precision, nz, nr, nm, dz, dr, dt, 3000, -0.8, 406,
+                                 rp=(nr - 2) * dr, gamma=1.8, u_th=0.05, order=order)
+    ctx.particle_step(1)
+    ctx.synchronize()
+    st1 = sim.step(st)
+    tol = _tol(precision, nr, dr, nm)
+    for a, name in enumerate(("JR", "JT", "JZ")):
+        got = ctx.read(name)
+        for m in range(nm):
+            assert rel_l2(got[m], st1["J"][m][a]) <= tol_for(precision), (name, m)
+    rho = ctx.read("RHO")
+    for m in range(nm):
+        assert rel_l2(rho[m], st1["rho"][m]) <= tol_for(precision), ("rho", m)
+    for names, F in ((("ER", "ET", "EZ"), st1["E"]), (("BR", "BT", "BZ"), st1["B"])):
+        for a, n in enumerate(names):
+            got = ctx.read(n)
+            for m in range(nm):
+                assert rel_l2(got[m], F[m][a]) <= tol, (n, m)
+    _, u = _particles_back(parts)
+    mom = 1e-12 if precision == gp.GP_FP64 else 1e-5
+    assert np.max(np.abs(u - st1["u"])) <= mom * np.max(np.abs(st1["u"]))
+    ctx.close()
+
+
+@pytest.mark.parametrize("order", [1, 3])
+@pytest.mark.parametrize("precision", [gp.GP_FP64, gp.GP_MIXED])
+def test_weights_past_the_last_node_are_dropped(gpu_lib, precision, order):
+    """Particles out to a cell beyond the grid's last node: the weights
+    that fall past node nr - 1 are dropped on both sides (deposit and
+    gather), the rest match the oracle."""
+    nz, nr, nm, dz, dr, dt = 16, 10, 2, 1.0, 1.0, 0.5
+    ctx, parts, sim, st = _setup(precision, nz, nr, nm, dz, dr, dt, 3000, 0.0, 407,
+                                 rp=(nr + 1) * dr, u_th=0.1, order=order, background=False)
+    x0, _ = _particles_back(parts)
+    assert np.max(np.hypot(x0[:, 0], x0[:, 1])) > (nr - 0.5) * dr   # some weights drop
+    ctx.particle_step(1)
+    ctx.synchronize()
+    st1 = sim.step(st)
+    for a, name in enumerate(("JR", "JT", "JZ")):
+        got = ctx.read(name)
+        for m in range(nm):
+            assert rel_l2(got[m], st1["J"][m][a]) <= tol_for(precision), (name, m)
+    rho = ctx.read("RHO")
+    for m in range(nm):
+        assert rel_l2(rho[m], st1["rho"][m]) <= tol_for(precision), ("rho", m)
+    _, u = _particles_back(parts)
+    mom = 1e-12 if precision == gp.GP_FP64 else 1e-5
+    assert np.max(np.abs(u - st1["u"])) <= mom * np.max(np.abs(st1["u"]))
+    ctx.close()
+
+
+@pytest.mark.parametrize("order", [1, 3])
 @pytest.mark.parametrize("nm", [1, 2])
 @pytest.mark.parametrize("galilean", [True, False])
 @pytest.mark.parametrize("precision", [gp.GP_FP64, gp.GP_MIXED])
