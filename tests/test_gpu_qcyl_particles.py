@@ -399,3 +399,77 @@ def test_nci_pair_on_the_gpu(gpu_lib, precision):
     assert gal.max() <= 25.0 * gal[0], gal / gal[0]
     assert std[-1] >= 50.0 * std[0], std / std[0]
     assert std[-1] >= 8.0 * gal[-1], (std[-1], gal[-1])
+
+
+@pytest.mark.parametrize("order", [1, 3])
+@pytest.mark.parametrize("precision", [gp.GP_FP64, gp.GP_MIXED])
+def test_column_workload_sampled(gpu_lib, precision, order):
+    """The benchmarked column at its full size and launch configuration (nz
+    512, nr 128, modes 0 and 1, an electron column of radius 96 with 24
+    particles per (r, z) cell: 1,179,648 particles, gamma 20 along -z,
+    Galilean frame), checked where the oracle can compute single outputs:
+    rho at 24 sampled nodes after binding (the oracle deposits only the
+    particles inside a node's support), and after one step the moved
+    positions and pushed momenta of 2000 sampled particles (the oracle
+    gathers from the library's own fields at the library's new positions)."""
+    nz, nr, nm, dz, dr, dt, gamma, rp = 512, 128, 2, 1.0, 1.0, 1.0, 20.0, 96.0
+    rng = np.random.default_rng(408)
+    n = int(24 * nz * rp / dr)
+    r = rp * np.sqrt(rng.uniform(0.0, 1.0, n))
+    th = rng.uniform(0.0, 2.0 * np.pi, n)
+    x = np.stack([r * np.cos(th), r * np.sin(th), rng.uniform(0.0, nz * dz, n)], 1)
+    u = np.zeros((n, 3))
+    u[:, 2] = -np.sqrt(gamma * gamma - 1.0)
+    x, u = _round(x, precision), _round(u, precision)
+    w = np.pi * rp * rp * nz * dz / n
+    vz = float(u[0, 2] / np.sqrt(1.0 + u[0, 2] ** 2))
+    ctx = gp.QcContext(nz, nr, nm, dz, dr, dt, precision, shape_order=order)
+    ctx.set_v_gal(vz)
+    parts = _gpu_particles(x, u, precision)
+    ctx.bind_particles(-1.0, 1.0, w, *parts)
+    x0, u0 = _particles_back(parts)
+    rho = ctx.read("RHO")
+    reach = (order + 1) // 2
+    r0 = np.hypot(x0[:, 0], x0[:, 1])
+    scale = np.max(np.abs(rho[0]))
+    tol = 1e-12 if precision == gp.GP_FP64 else 1e-5
+    for _ in range(24):
+        k, j = int(rng.integers(0, nz)), int(rng.integers(0, 100))
+        dzc = np.abs(x0[:, 2] / dz - k)
+        dzc = np.minimum(dzc, nz - dzc)
+        near = (dzc < reach + 1) & (r0 < (j + 1.5 + reach) * dr)
+        xs = x0[near]
+        for m in range(nm):
+            ref = cy.deposit_mode(xs[:, 0], xs[:, 1], xs[:, 2], np.full(len(xs), -w), m,
+                                  "scalar", nr, dr, nz, dz, order)[k, j]
+            assert abs(rho[m][k, j] - ref) <= tol * scale, (k, j, m, rho[m][k, j], ref)
+    ctx.electrostatic_fields()
+    ctx.particle_step(1)
+    ctx.synchronize()
+    x1, u1 = _particles_back(parts)
+    E = [tuple(ctx.read(nme)[m].astype(np.complex128) for nme in ("ER", "ET", "EZ"))
+         for m in range(nm)]
+    B = [tuple(ctx.read(nme)[m].astype(np.complex128) for nme in ("BR", "BT", "BZ"))
+         for m in range(nm)]
+    sim = cy.CylindricalPIC(nz, nr, nm, dz, dr, dt, -1.0, 1.0, w, vz, order=order)
+    idx = rng.choice(n, 2000, replace=False)
+    from oracle.particles import boris_push, lab_velocity
+    v = lab_velocity(u0[idx])
+    xr = sim._move(sim._move(x0[idx], v), v)
+    dzp = np.abs(x1[idx, 2] - xr[:, 2])
+    dzp = np.minimum(dzp, nz * dz - dzp)
+    pos = 1e-12 if precision == gp.GP_FP64 else 1e-6
+    assert np.max(np.abs(x1[idx, :2] - xr[:, :2])) <= pos * rp
+    assert np.max(dzp) <= pos * nz * dz
+    Ep = cy.gather_vector(E, x1[idx, 0], x1[idx, 1], x1[idx, 2], nr, dr, nz, dz, order)
+    Bp = cy.gather_vector(B, x1[idx, 0], x1[idx, 1], x1[idx, 2], nr, dr, nz, dz, order)
+    ur = boris_push(u0[idx], Ep, Bp, -1.0, 1.0, dt)
+    # compare the change of u: rounding of u itself (a few ulp of |u|, 20
+    # here) plus a relative error of the push
+    du_ref = ur - u0[idx]
+    du_gpu = u1[idx] - u0[idx]
+    c_u, c_du = (1e-13, 1e-10) if precision == gp.GP_FP64 else (2e-6, 1e-5)
+    err = np.max(np.abs(du_gpu - du_ref))
+    assert err <= c_u * np.max(np.abs(u0)) + c_du * np.max(np.abs(du_ref)), \
+        (err, np.max(np.abs(du_ref)))
+    ctx.close()
