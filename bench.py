@@ -474,6 +474,40 @@ def qc_cpu_baseline(name, budget_s=10.0):
                        f"per call as the oracle does")}
 
 
+def qc_particle_cpu_baseline(name, budget_s=15.0):
+    """The oracle's whole particle cycle (CylindricalPIC: moves, deposits,
+    transforms, mode update, gather and push), as it stands, on a sub-box
+    of the workload: 64 of its z cells with the same radius, particles per
+    cell, drift, modes and shape; single thread, as many steps as fit the
+    budget."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import cylindrical as cy
+
+    w = dict(QC_WORKLOADS[name])
+    w["nz"] = 64
+    beta = np.sqrt(1.0 - 1.0 / w["gamma"] ** 2)
+    order = w.get("order", 1)
+    x, u, qw_w = qc_column_inputs(w)
+    bg = cy.uniform_cylinder_background(1.0, w["rp"], -beta, w["nmodes"], w["nr"], w["dr"],
+                                        w["nz"], w["dz"], order)
+    sim = cy.CylindricalPIC(w["nz"], w["nr"], w["nmodes"], w["dz"], w["dr"], w["dt"], -1.0, 1.0,
+                            qw_w, -beta, background=bg, order=order)
+    steps = 0
+    with threadpool_limits(limits=1):
+        st = sim.initial_state(x, u, electrostatic=True)
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < budget_s or steps == 0:
+            st = sim.step(st)
+            steps += 1
+        t = time.perf_counter() - t0
+    return {"value": len(x) * steps / t, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": (f"{steps} whole oracle steps (numpy, single thread) on a {w['nz']}x"
+                       f"{w['nr']} sub-box of the workload ({len(x)} particles, same radius, "
+                       f"particles per cell, drift, modes and shape), {t:.1f} s; set-up and "
+                       "electrostatic start not timed")}
+
+
 def qc_main(args):
     from paper_1608_00215_amd import galpic as gp
 
@@ -572,8 +606,9 @@ def qc_main(args):
         line["fp64_gpu"] = {"value": cells * steps / fp64["wall_s"],
                             "ms_per_step": fp64["wall_s"] / steps * 1e3,
                             "stages": stages64, "roofline": roof64}
-    if not args.no_cpu and not mixed["particles"]:
-        line["cpu_baseline"] = qc_cpu_baseline(args.qc)
+    if not args.no_cpu:
+        line["cpu_baseline"] = (qc_particle_cpu_baseline(args.qc) if mixed["particles"]
+                                else qc_cpu_baseline(args.qc))
     print(json.dumps(line), flush=True)
 
 
