@@ -87,7 +87,7 @@ def btd_snapshot_times(c, nsnap, t_mid):
 
 
 def run_gpu(cfg, precision, steps, warmup, inputs, tile=(0, 0, 0), resort_div=0, btd=0,
-            btd_cap=0):
+            btd_cap=0, correction=False):
     """Time one run (cfg, inputs) or a batch of runs (lists of both)."""
     import torch
 
@@ -102,6 +102,8 @@ def run_gpu(cfg, precision, steps, warmup, inputs, tile=(0, 0, 0), resort_div=0,
     ctx = gp.Context(grids)
     for r, c in enumerate(cfgs):
         ctx.set_v_gal(r, c.v_gal())
+    if correction:
+        ctx.set_current_correction(True)
     parts = [gp.particles_from_inputs(i, c, precision, with_ids=False)
              for c, i in zip(cfgs, inps)]
     ctx.bind_particles(parts)
@@ -636,6 +638,11 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device three times (a plain copy "
                          "kernel of known size for scaling HBM byte counters)")
+    ap.add_argument("--stencil", type=int, default=0, metavar="P",
+                    help="field solve with the finite-order stencil of even order P on every "
+                         "axis (0: spectral, the default)")
+    ap.add_argument("--current-correction", action="store_true",
+                    help="field solve with the Galilean current correction")
     ap.add_argument("--qc", default=None, choices=sorted(QC_WORKLOADS),
                     help="instead, time the quasi-cylindrical (azimuthal-mode) field solve "
                          "on the named grid and print its own line")
@@ -674,6 +681,8 @@ def main():
         run_arg = runs
     else:
         cfg = get_config(args.workload)
+        if args.stencil:
+            cfg = cfg.with_(stencil=(args.stencil,) * 3)
         inputs = particles_for(cfg)
         run_arg = cfg
     if args.steps is None:
@@ -702,12 +711,13 @@ def main():
                   "candidates_ms_per_step": {f"{k[0][0]}x{k[0][1]}x{k[0][2]}/n{k[1]}": round(v, 4)
                                              for k, v in res.items()}}
     mixed = run_gpu(run_arg, gp.GP_MIXED, args.steps, args.warmup, inputs, btd=args.btd,
-                    btd_cap=args.btd_particles, **setting)
+                    btd_cap=args.btd_particles, correction=args.current_correction, **setting)
     print(f"[bench] mixed: {mixed['wall_s'] / args.steps * 1e3:.3f} ms/step", file=sys.stderr,
           flush=True)
     fp64 = None
     if not args.no_fp64:
-        fp64 = run_gpu(run_arg, gp.GP_FP64, args.steps, args.warmup, inputs)
+        fp64 = run_gpu(run_arg, gp.GP_FP64, args.steps, args.warmup, inputs,
+                       correction=args.current_correction)
         print(f"[bench] fp64: {fp64['wall_s'] / args.steps * 1e3:.3f} ms/step",
               file=sys.stderr, flush=True)
     del inputs
@@ -753,6 +763,8 @@ def main():
             "particles": cfg.n_particles,
             "cells": cfg.n_cells,
             "precision": "mixed",
+            "stencil": list(cfg.stencil) if not isinstance(cfg, BatchView) else None,
+            "current_correction": args.current_correction,
         },
         "grid_updates_per_s": cfg.n_cells * args.steps / mixed["wall_s"],
         "graph_ms_per_step": mixed["graph_ms_per_step"],
