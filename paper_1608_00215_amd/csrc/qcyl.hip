@@ -711,6 +711,16 @@ __global__ __launch_bounds__(256) void k_qc_reset_sources(QcSrc<T> dst, QcSrc<T>
 
 // Gather E, B at x (the mode fields [m][z][r]: r, theta, z components), then
 // the relativistic Boris push of u over dt (c = 1).
+// Gather and push over blocks of 256 particles.  The particles are sorted
+// along z only, so consecutive ones sit at random radii; a counting sort of
+// each block by radial cell in LDS hands lane l the block's particle of rank
+// l, so that neighbouring lanes read neighbouring nodes (the particles stay
+// where they are; each is still pushed exactly once).  Measured on the
+// 1.18 M-particle column: cubic gathers 5-9 % faster, linear double 11 %;
+// linear float, whose gather is cheapest, 7 % slower, so it keeps the plain
+// order.
+constexpr int kQcGatherBins = 512;  // radial cells (nr <= 512; larger radii clamp)
+
 template <typename T, int O>
 __global__ __launch_bounds__(256) void k_qc_gather_push(QcPart<T> p, QcGeo<T> g,
                                                         const T *__restrict__ E0,
@@ -719,8 +729,45 @@ __global__ __launch_bounds__(256) void k_qc_gather_push(QcPart<T> p, QcGeo<T> g,
                                                         const T *__restrict__ B0,
                                                         const T *__restrict__ B1,
                                                         const T *__restrict__ B2, T h) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= p.n) return;
+  const int tid = threadIdx.x;
+  const int64_t base = int64_t(blockIdx.x) * 256;
+  const int here = int(p.n - base < 256 ? p.n - base : 256);
+  constexpr bool kSort = !(O == 1 && sizeof(T) == 4);
+  int64_t i = base + tid;
+  if constexpr (kSort) {
+    __shared__ int hist[kQcGatherBins];
+    __shared__ int part[256];  // per-thread bin pair sums, then their exclusive scan
+    __shared__ int perm[256];
+    int key = 0;
+    if (tid < here) {
+      const T x = p.x[base + tid], y = p.y[base + tid];
+      const T rc = sqrt(x * x + y * y) * g.inv_dr;
+      key = rc < T(kQcGatherBins - 1) ? int(rc) : kQcGatherBins - 1;
+    }
+    for (int t = tid; t < kQcGatherBins; t += 256) hist[t] = 0;
+    __syncthreads();
+    const int within = tid < here ? atomicAdd(&hist[key], 1) : 0;
+    __syncthreads();
+    // exclusive scan of the 512 bins: thread t owns bins 2t and 2t + 1
+    const int h0 = hist[2 * tid], h1 = hist[2 * tid + 1];
+    part[tid] = h0 + h1;
+    __syncthreads();
+    for (int off = 1; off < 256; off *= 2) {
+      const int v = tid >= off ? part[tid - off] : 0;
+      __syncthreads();
+      part[tid] += v;
+      __syncthreads();
+    }
+    const int start0 = part[tid] - (h0 + h1);  // exclusive prefix of bin 2t
+    __syncthreads();
+    hist[2 * tid] = start0;
+    hist[2 * tid + 1] = start0 + h0;
+    __syncthreads();
+    if (tid < here) perm[hist[key] + within] = tid;
+    __syncthreads();
+    if (tid < here) i = base + perm[tid];
+  }
+  if (tid >= here) return;
   T r, c, s;
   qc_angle(p.x[i], p.y[i], r, c, s);
   const QcNodes<T, O> nd = qc_nodes<T, O>(g, r, p.z[i]);
