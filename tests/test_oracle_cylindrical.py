@@ -408,3 +408,21 @@ def test_uniform_density_deposits_uniformly_up_to_the_axis(order):
     assert len(edge) == 2 * reach
     assert np.max(np.abs(g0 - bg[0])) <= 2e-6, (g0[0], bg[0][0])
     assert np.max(np.abs(bg[1][2] - 0.3 * bg[0])) == 0.0
+
+
+@pytest.mark.parametrize("order", [1, 3])
+def test_field_energy_closed_form(order):
+    """A uniform mode-0 F_z = 1 and a uniform mode-1 F_r = a: the norm is
+    nz (1 + |a|^2 / c_1) times the summed node volumes, which are
+    2 pi dz dr^2 (nr^2 / 2 + e) with e the axis nodes' excess over (j + 1/2):
+    1/24 for linear shapes (13/24 on node 0) and 1/8 for cubic ones
+    ((1199 + 2881) / 1920 on nodes 0 and 1, against 2)."""
+    nz, nr, dz, dr = 8, 6, 0.5, 0.7
+    a = 0.3 - 0.4j
+    one = np.ones((nz, nr), dtype=complex)
+    zero = np.zeros((nz, nr), dtype=complex)
+    G = [(zero, zero, one), (a * one, zero, zero)]
+    excess = 1.0 / 24.0 if order == 1 else 1.0 / 8.0
+    vol = 2 * np.pi * dz * dr * dr * (nr * nr / 2.0 + excess)
+    expect = nz * vol * (1.0 + abs(a) ** 2 / 2.0)
+    assert abs(cy.field_energy(G, nr, dr, dz, order) - expect) <= 1e-12 * expect
