@@ -599,7 +599,7 @@ __global__ __launch_bounds__(256) void k_qc_move_deposit(QcPart<T> p, QcGeo<T> g
   });
 }
 
-// The same with an LDS window: a workgroup takes kQcChunk consecutive
+// The same with an LDS window: a workgroup takes per x kQcDepThreads consecutive
 // particles (sorted along z at binding, so a chunk covers few z nodes),
 // accumulates the nodes of a window of z planes (4 for linear shapes from
 // one plane below its first particle, 6 for cubic ones from two below) in
@@ -611,10 +611,10 @@ __global__ __launch_bounds__(256) void k_qc_move_deposit(QcPart<T> p, QcGeo<T> g
 // would fall on a quarter of them).  512 threads share one window (the
 // cubic window allows one workgroup per CU): eight waves per CU hide the
 // LDS atomics' conflicts better than four; measured against 256 x 8 and
-// 512 x 1 particles per workgroup, 512 x 2 was fastest.
+// 512 x 1 particles per workgroup, 512 x 2 or 3 were fastest.  The launch
+// picks per (2 to 4 particles per thread) to leave the smallest tail of
+// workgroup rounds on the device.
 constexpr int kQcDepThreads = 512;
-constexpr int kQcDepPer = 2;
-constexpr int kQcChunk = kQcDepThreads * kQcDepPer;
 template <int O>
 constexpr int qc_win() {
   return O == 1 ? 4 : 6;
@@ -623,12 +623,13 @@ constexpr int qc_win() {
 template <typename T, int O>
 __global__ __launch_bounds__(kQcDepThreads) void k_qc_move_deposit_tiled(QcPart<T> p, QcGeo<T> g,
                                                                          QcSrc<T> src, T dt,
-                                                                         T vgal, T qw, int move) {
+                                                                         T vgal, T qw, int move,
+                                                                         int per) {
   // the window accumulates in double whatever T is (as the Cartesian tiles do)
   extern __shared__ __align__(16) unsigned char qdsm[];
   double *win = reinterpret_cast<double *>(qdsm);
   __shared__ int zs_sh;
-  const int64_t first = int64_t(blockIdx.x) * kQcChunk;
+  const int64_t first = int64_t(blockIdx.x) * kQcDepThreads * per;
   constexpr int kQcWin = qc_win<O>();
   const int plane = g.nr * 2;                            // values per z plane
   const int per_src = g.nmodes * kQcWin * plane;
@@ -652,7 +653,7 @@ __global__ __launch_bounds__(kQcDepThreads) void k_qc_move_deposit_tiled(QcPart<
   T *arrs[4] = {global_ptr(src.jr), global_ptr(src.jt), global_ptr(src.jz),
                 global_ptr(src.rho)};
   const int nz = g.nz, nr = g.nr;
-  for (int q = 0; q < kQcDepPer; ++q) {
+  for (int q = 0; q < per; ++q) {
     const int64_t i = first + int64_t(q) * kQcDepThreads + threadIdx.x;
     if (i >= p.n) break;
     qc_particle_deposit<T, O>(p, g, i, dt, vgal, qw, move, [=](int si) {
@@ -1036,6 +1037,7 @@ struct gp_qc_ctx {
   void *bg[4] = {};        // background rho, J_r, J_theta, J_z (allocated once)
   bool has_bg = false;
   void *inv_vol = nullptr; // [nr] 1 / V_j in the real type
+  int dep_per = 0;         // deposit particles per thread (0: not chosen yet)
   int order = 1;           // particle shape: 1 linear, 3 cubic
 };
 
@@ -1431,10 +1433,40 @@ void launch_move_deposit_o(gp_qc_ctx *c, const QcSrc<T> &src, int move) {
                                 hipFuncAttributeMaxDynamicSharedMemorySize, int(kQcMaxWindow));
       attr_set = true;
     }
+    if (c->dep_per == 0) {
+      // particles per thread: the fewest of 2..4 whose workgroups fill the
+      // device's resident slots (CUs x workgroups per CU) with the least
+      // tail, i.e. the smallest ceil(workgroups / slots) x per
+      int cus = 0, per_cu = 0;
+      int dev = 0;
+      (void)hipGetDevice(&dev);
+      if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        cus = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+              &per_cu, reinterpret_cast<const void *>(&k_qc_move_deposit_tiled<T, O>),
+              kQcDepThreads, lds) != hipSuccess)
+        per_cu = 0;
+      (void)hipGetLastError();
+      c->dep_per = 2;
+      const int64_t slots = int64_t(cus) * per_cu;
+      if (slots > 0) {
+        int64_t best = -1;
+        for (int per = 2; per <= 4; ++per) {
+          const int64_t wgs = (c->part.n + int64_t(kQcDepThreads) * per - 1) /
+                              (int64_t(kQcDepThreads) * per);
+          const int64_t cost = (wgs + slots - 1) / slots * per;
+          if (best < 0 || cost < best) {
+            best = cost;
+            c->dep_per = per;
+          }
+        }
+      }
+    }
+    const int64_t chunk = int64_t(kQcDepThreads) * c->dep_per;
     hipLaunchKernelGGL((k_qc_move_deposit_tiled<T, O>),
-                       dim3(unsigned((c->part.n + kQcChunk - 1) / kQcChunk)), dim3(kQcDepThreads),
-                       lds, c->stream, qc_part<T>(c), qc_geo<T>(c), src, T(c->d.dt), T(c->vgal),
-                       T(c->part.q * c->part.w), move);
+                       dim3(unsigned((c->part.n + chunk - 1) / chunk)), dim3(kQcDepThreads), lds,
+                       c->stream, qc_part<T>(c), qc_geo<T>(c), src, T(c->d.dt), T(c->vgal),
+                       T(c->part.q * c->part.w), move, c->dep_per);
   } else {
     hipLaunchKernelGGL((k_qc_move_deposit<T, O>), dim3(unsigned((c->part.n + 255) / 256)),
                        dim3(256), 0, c->stream, qc_part<T>(c), qc_geo<T>(c), src, T(c->d.dt),
@@ -1723,6 +1755,7 @@ gp_status gp_qc_bind_particles(gp_qc_ctx *c, const gp_qc_particles *p) {
     return qfail(GP_ERR_ARG, "a particle array is NULL");
   c->part = *p;
   c->bound = true;
+  c->dep_per = 0;  // chosen again for the new particle count
   QTRY(c->d.precision == GP_FP64 ? sort_particles_by_z<double>(c) : sort_particles_by_z<float>(c));
   QTRY(fill_sources(c));
   // rho^n of the particles (and the background), transformed into the
