@@ -2,14 +2,19 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 
-Runs W untimed steps, then K timed steps (default: the workload's whole run,
-500 steps for the 128x128x256 plasma) of the whole hot path (deposit,
-forward FFT, k-space update, inverse FFT, gather + Boris push) on the
-workload's seeded synthetic plasma, inputs resident in HBM, and prints one
-JSON line: particle-steps/s (the whole job), the per-kernel device times
-measured with HIP events on the library's stream, the roofline of the
-dominant kernel, the FP64 GPU path on the same workload, and the CPU
-oracle timed on a bounded sample of the workload on this host.
+Runs W untimed steps, then K timed steps (default 200, or the workload's
+run if shorter) of the whole hot path (deposit, forward FFT, k-space update,
+inverse FFT, gather + Boris push) on the workload's seeded synthetic plasma,
+inputs resident in HBM, and prints one JSON line: particle-steps/s (the
+whole job), the per-kernel device times measured with HIP events on the
+library's stream, the roofline of the dominant kernel, the FP64 GPU path on
+the same workload, and the CPU oracle timed on a bounded sample of the
+workload on this host.  The default workload is the 256x256x512 boosted
+run with its laser (cubic shapes, dt = dz / c, v_gal = -beta c), the
+largest single-GPU configuration; the mixed-precision and FP64 GPU paths
+run it side by side.  After the timed steps (and their graph replay) the
+run continues to step 200 and times 20 more steps there, so that a short
+timed window early in the run is reported beside a later one.
 """
 
 import argparse
@@ -87,7 +92,7 @@ def btd_snapshot_times(c, nsnap, t_mid):
 
 
 def run_gpu(cfg, precision, steps, warmup, inputs, tile=(0, 0, 0), resort_div=0, btd=0,
-            btd_cap=0, correction=False):
+            btd_cap=0, correction=False, late_at=0, late_n=20):
     """Time one run (cfg, inputs) or a batch of runs (lists of both)."""
     import torch
 
@@ -139,26 +144,50 @@ def run_gpu(cfg, precision, steps, warmup, inputs, tile=(0, 0, 0), resort_div=0,
     ctx.step_graph(steps)
     graph_ms = ctx.last_graph_ms()
     we, wb = ctx.field_energy(0)
+    done = warmup + 2 * steps + 1
+    late = None
+    if late_at > 0:
+        # a later window of the same run: advance to step late_at (untimed),
+        # then time late_n eager steps
+        if done < late_at:
+            ctx.run(late_at - done)
+            done = late_at
+        ctx.synchronize()
+        ctx.stage_timing(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.run(late_n)
+        ctx.synchronize()
+        torch.cuda.synchronize()
+        late_wall = time.perf_counter() - t0
+        lst = ctx.stage_times()
+        ctx.stage_timing(False)
+        late = {"first_step": done + 1, "steps": late_n,
+                "ms_per_step": late_wall / late_n * 1e3,
+                "stage_ms": {k: ms / n for k, (ms, n) in lst.items() if n > 0}}
     ctx.close()
     del parts
     torch.cuda.empty_cache()
     return {"wall_s": wall,
             "stage_ms": {k: ms / n for k, (ms, n) in stage.items() if n > 0},
             "stage_launches": {k: n for k, (ms, n) in stage.items() if n > 0},
-            "graph_ms_per_step": graph_ms / steps, "field_energy": we + wb, "sorts": sorts}
+            "graph_ms_per_step": graph_ms / steps, "field_energy": we + wb, "sorts": sorts,
+            "late": late}
 
 
-def traffic_from_profiles(kernel_stage, fp64):
+def traffic_from_profiles(workload, kernel_stage, fp64):
     """HBM bytes per launch measured with rocprofv3 counters, if a summary for
-    this kernel exists and its source has not changed since."""
+    this kernel on this workload exists and its source has not changed
+    since."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     try:
-        rec = json.load(open(path)).get(("fp64:" if fp64 else "mixed:") + kernel_stage)
+        key = f"{workload}:{'fp64' if fp64 else 'mixed'}:{kernel_stage}"
+        rec = json.load(open(path)).get(key)
     except (OSError, ValueError):
         return None
-    if not rec:
+    if not rec or rec.get("workload") != workload:
         return None
     for rel, want in rec["sources"].items():
         src = os.path.join(ROOT, rel)
@@ -184,31 +213,55 @@ class BatchView:
         self.laser = None
 
 
+def host_cpu():
+    """(model name, logical CPUs) of this host."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return model, os.cpu_count()
+
+
 def cpu_baseline(cfg):
-    """The oracle, as it stands, on a sub-box of the workload (same
-    particles per cell, shape, drift and thermal spread; fewer cells)."""
+    """The oracle, as it stands, on a sub-box of the workload: the same
+    particles per cell, shape, drift and thermal spread (and laser pulse,
+    started the same way), on about two million particles; the coefficient
+    set-up, the laser start and the first step are not timed."""
     from threadpoolctl import threadpool_limits
 
     from oracle import pic
-    from workload import particles_for
+    from workload import laser_fields, particles_for
 
-    sub = cfg.with_(shape=(64, 64, 64))
+    nz = max(64, (1 << 21) // (64 * 64 * cfg.ppc))
+    sub = cfg.with_(shape=(64, 64, min(nz, cfg.shape[2])))
     inp = particles_for(sub)
     g = pic.Grid(sub.shape, sub.spacing, sub.dt, sub.order)
     sim = pic.Simulation(g, pic.Species(sub.q, sub.m, sub.w), sub.v_gal())
-    st = sim.initial_state(inp["x"], inp["u"])
+    lf = laser_fields(sub)
+    if lf is not None:
+        st = sim.initial_state(inp["x"], inp["u"], lf[0], lf[1], project_transverse=True)
+        st = sim.half_push(st)
+    else:
+        st = sim.initial_state(inp["x"], inp["u"])
     steps = 3
+    model, ncpu = host_cpu()
     with threadpool_limits(limits=1):     # any BLAS/OpenMP pool: one thread
+        st = sim.step(st)
         t0 = time.perf_counter()
         for _ in range(steps):
             st = sim.step(st)
         t = time.perf_counter() - t0
     return {"value": sub.n_particles * steps / t, "unit": "particle-steps/s", "cores": 1,
-            "kind": "oracle",
-            "sample": (f"{steps} oracle steps (numpy, single thread) on a {sub.shape[0]}x"
+            "kind": "oracle", "host_cpu": model, "host_logical_cpus": ncpu,
+            "sample": (f"{steps} oracle steps (numpy FP64, one thread) on a {sub.shape[0]}x"
                        f"{sub.shape[1]}x{sub.shape[2]} sub-box of the workload "
-                       f"({sub.n_particles} particles, same ppc/shape/drift), "
-                       f"{t:.1f} s; coefficient set-up not timed")}
+                       f"({sub.n_particles} particles, same ppc/shape/drift"
+                       f"{'/laser' if lf is not None else ''}), {t:.1f} s, after one "
+                       f"untimed step; host: {model}, {ncpu} logical CPUs")}
 
 
 def accuracy_run(cfg, steps, inputs, every=10):
@@ -618,9 +671,12 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None,
-                    help="timed steps (default: the workload's own run length)")
+                    help="timed steps (default: 200, or the workload's run if shorter)")
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c2_cubic_mixed")
+    ap.add_argument("--workload", default="c3_boosted_laser")
+    ap.add_argument("--late-at", type=int, default=200, metavar="STEP",
+                    help="after the timed steps, continue the run to this step and time 20 "
+                         "more steps there (0: skip)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--accuracy", action="store_true",
@@ -686,7 +742,7 @@ def main():
         inputs = particles_for(cfg)
         run_arg = cfg
     if args.steps is None:
-        args.steps = cfg.runs[0].steps if isinstance(cfg, BatchView) else cfg.steps
+        args.steps = min(200, cfg.runs[0].steps if isinstance(cfg, BatchView) else cfg.steps)
     print(f"[bench] {cfg.name}: grid {cfg.shape}, {cfg.n_particles} particles, "
           f"{args.steps} steps", file=sys.stderr, flush=True)
     if args.accuracy:
@@ -711,13 +767,14 @@ def main():
                   "candidates_ms_per_step": {f"{k[0][0]}x{k[0][1]}x{k[0][2]}/n{k[1]}": round(v, 4)
                                              for k, v in res.items()}}
     mixed = run_gpu(run_arg, gp.GP_MIXED, args.steps, args.warmup, inputs, btd=args.btd,
-                    btd_cap=args.btd_particles, correction=args.current_correction, **setting)
+                    btd_cap=args.btd_particles, correction=args.current_correction,
+                    late_at=args.late_at, **setting)
     print(f"[bench] mixed: {mixed['wall_s'] / args.steps * 1e3:.3f} ms/step", file=sys.stderr,
           flush=True)
     fp64 = None
     if not args.no_fp64:
         fp64 = run_gpu(run_arg, gp.GP_FP64, args.steps, args.warmup, inputs,
-                       correction=args.current_correction)
+                       correction=args.current_correction, late_at=args.late_at)
         print(f"[bench] fp64: {fp64['wall_s'] / args.steps * 1e3:.3f} ms/step",
               file=sys.stderr, flush=True)
     del inputs
@@ -740,7 +797,7 @@ def main():
         achieved = alg[dominant] / (dom_ms * 1e-3) / 1e9
         roof = {"kernel": dominant, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS}
-    roof["traffic"] = traffic_from_profiles(dominant, False)
+    roof["traffic"] = traffic_from_profiles(cfg.name, dominant, False)
     stages = {k: {"ms_per_launch": round(v, 5), "launches": mixed["stage_launches"][k],
                   "gbs": round(alg[k] / (v * 1e-3) / 1e9, 1) if (v > 0 and alg[k]) else None}
               for k, v in mixed["stage_ms"].items()}
@@ -769,6 +826,11 @@ def main():
         "grid_updates_per_s": cfg.n_cells * args.steps / mixed["wall_s"],
         "graph_ms_per_step": mixed["graph_ms_per_step"],
         "tile_sorts": mixed["sorts"],
+        "late_window": None if mixed["late"] is None else {
+            "first_step": mixed["late"]["first_step"], "steps": mixed["late"]["steps"],
+            "ms_per_step": mixed["late"]["ms_per_step"],
+            "particle_steps_per_s": cfg.n_particles / (mixed["late"]["ms_per_step"] * 1e-3),
+            "dominant_ms_per_launch": mixed["late"]["stage_ms"].get(dominant)},
         "stages": stages,
         "roofline": roof,
         "tuning": tuning,
@@ -791,6 +853,8 @@ def main():
             "stages_ms": {k: round(v, 5) for k, v in fp64["stage_ms"].items()},
             "field_energy_rel_diff_vs_mixed": abs(fp64["field_energy"] - mixed["field_energy"])
             / max(abs(fp64["field_energy"]), 1e-300),
+            "late_window_ms_per_step": None if fp64["late"] is None
+            else fp64["late"]["ms_per_step"],
         }
     if rank == 0 and not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(cfg.runs[0] if isinstance(cfg, BatchView) else cfg)

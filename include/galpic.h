@@ -12,6 +12,18 @@
  * (n+1) dt on the grid nodes, transforms back, interpolates to the
  * particles and advances them with dx'/dt = v - v_gal.
  *
+ * Passages of the paper cited below (it numbers no equations):
+ *  - "the transformed equations": the equations of motion and Maxwell's
+ *    equations written in x' = x - v_gal t, with the continuity equation;
+ *  - "the update display": the Galilean-PSATD update of E and B with its
+ *    coefficients C, S, nu, theta, chi_1..chi_3;
+ *  - "the deposition paragraph": the paragraph after the update display
+ *    (J deposited at (n+1/2) dt, rho at n dt and (n+1) dt, on the grid
+ *    nodes; transform to Fourier space; update; transform back; interpolate
+ *    to the particles; advance them with the transformed equations);
+ *  - "the simulation parameters": the boosted laser-plasma run's set-up
+ *    (cubic shapes, dt = dz / c).
+ *
  * One step is the sequence
  *     gp_deposit -> gp_fft_fwd -> gp_galilean_psatd_update -> gp_fft_inv
  *     -> gp_gather_push
@@ -146,6 +158,9 @@ typedef struct {
 } gp_particles;
 
 /* Create a context for n_runs independent runs advanced together.
+ * Paper: the deposition paragraph (fields and sources on the nodes of a
+ * periodic grid, advanced in Fourier space by the pseudo-spectral solver
+ * of the update display).
  * hip_stream: a hipStream_t, or NULL for a stream created and owned by
  * the context (default priority; graph capture needs a non-null stream).
  * Allocates all
@@ -156,8 +171,8 @@ gp_status gp_init_grid(const gp_grid_desc *runs, int n_runs, void *hip_stream,
                        gp_ctx **out);
 
 /* Set v_gal of one run and rebuild its coefficient table in double
- * precision on the device (paper's coefficient block: C, S, nu, theta,
- * chi_1..chi_3, evaluated through cancellation-free integral forms).
+ * precision on the device.  Paper: the update display (C, S, nu, theta,
+ * chi_1..chi_3, evaluated here through cancellation-free integral forms).
  * Errors: GP_ERR_ARG if run is out of range or |v_gal| >= c,
  * GP_ERR_UNSTABLE if some non-Nyquist mode has |k.v_gal| dt >=
  * 2 pi (1 - 1e-6). */
@@ -175,7 +190,8 @@ gp_status gp_set_current_correction(gp_ctx *ctx, int enable);
 
 /* Register the particle arrays p[0..n_runs-1] with the context, sort them
  * into deposition tiles (reordering them in place), deposit rho at the
- * current positions and transform it into rho^n.  Must precede
+ * current positions and transform it into rho^n.  Paper: the deposition
+ * paragraph (rho at n dt, the first of the two charge densities).  Must precede
  * gp_deposit / gp_gather_push / gp_step; call again after changing the
  * arrays from outside.  Errors: GP_ERR_ARG (NULL pointers, n < 0,
  * positions outside the layout contract are not checked). */
@@ -183,43 +199,61 @@ gp_status gp_bind_particles(gp_ctx *ctx, const gp_particles *p);
 
 /* Deposit J^{n+1/2} and rho^{n+1}: move every particle by (v - v_gal) dt/2,
  * deposit q w v S (lab velocity v = u / gamma) into J, move it by another
- * (v - v_gal) dt/2, deposit q w S into rho (paper: currents at
- * (n+1/2) dt, charge at (n+1) dt, on the grid nodes).  Positions are
+ * (v - v_gal) dt/2, deposit q w S into rho.  Paper: the deposition
+ * paragraph (currents at (n+1/2) dt, charge at (n+1) dt, on the grid
+ * nodes) and the transformed equations (dx'/dt = v - v_gal).  Positions are
  * written back.  p must be the bound arrays (else GP_ERR_STATE). */
 gp_status gp_deposit(gp_ctx *ctx, const gp_particles *p);
 
 /* Forward FFT of J (3 components) and rho^{n+1}; k = 0 and Nyquist planes
- * set to zero.  Requires a deposit (or written J/rho) since the last
- * forward transform. */
+ * set to zero.  Paper: the deposition paragraph (the deposited sources are
+ * transformed to Fourier space before the update).  Requires a deposit (or
+ * written J/rho) since the last forward transform. */
 gp_status gp_fft_fwd(gp_ctx *ctx);
 
 /* Galilean-PSATD update of spectral E and B from E^n, B^n, J^{n+1/2},
- * rho^n, rho^{n+1} (the paper's update equations); then rho^{n+1} becomes
- * rho^n.  Requires gp_fft_fwd (or written spectral J and rho^{n+1}). */
+ * rho^n, rho^{n+1}; then rho^{n+1} becomes rho^n.  Paper: the update
+ * display.  Requires gp_fft_fwd (or written spectral J and rho^{n+1}). */
 gp_status gp_galilean_psatd_update(gp_ctx *ctx);
 
 /* Inverse FFT of spectral E and B into the real E and B used by the
- * gather.  The spectral state is left unchanged. */
+ * gather.  Paper: the deposition paragraph (the updated fields are
+ * transformed back to real space and interpolated to the particles).  The
+ * spectral state is left unchanged. */
 gp_status gp_fft_inv(gp_ctx *ctx);
 
 /* Interpolate E and B to every particle (same shape as the deposit) and
- * advance u by dt with the relativistic Boris scheme (the paper's
- * momentum equation dp/dt = q (E + v x B)).  Positions are unchanged.
+ * advance u by dt with the relativistic Boris scheme.  Paper: the
+ * deposition paragraph (interpolation to the particles) and the
+ * transformed equations (dp/dt = q (E + v x B), unchanged by the
+ * transformation).  Positions are unchanged.
  * Requires real E and B produced by gp_fft_inv or gp_write_field. */
 gp_status gp_gather_push(gp_ctx *ctx, const gp_particles *p);
 
+/* gp_gather_push followed by gp_deposit in one particle pass: interpolate
+ * E and B at x^n, push u^{n-1/2} -> u^{n+1/2}, then move by (v - v_gal) dt/2,
+ * deposit J^{n+1/2}, move again and deposit rho^{n+1}.  This is the pass
+ * gp_run makes between two field cycles; callers that drive the stage calls
+ * themselves use it in place of the two calls.  Paper: the deposition
+ * paragraph (interpolation, push, then the next step's deposition) and the
+ * transformed equations.  Requires real E and B as for gp_gather_push. */
+gp_status gp_gather_push_deposit(gp_ctx *ctx, const gp_particles *p);
+
 /* One full step for every run (deposit, fft_fwd, update, fft_inv,
- * gather_push), equivalent to the five calls above. */
+ * gather_push), equivalent to the five calls above.  Paper: the deposition
+ * paragraph (the order of the cycle). */
 gp_status gp_step(gp_ctx *ctx, const gp_particles *p);
 
 /* nsteps full steps, equivalent to nsteps gp_step calls; the gather-push
  * of each step is fused with the deposit of the next into one particle
- * pass. */
+ * pass.  Paper: the deposition paragraph (the order of the cycle, which
+ * the fusion keeps: push with the fields at x^n, then move and deposit). */
 gp_status gp_run(gp_ctx *ctx, const gp_particles *p, int nsteps);
 
 /* As gp_run, replayed from HIP graphs captured on first use (recaptured
- * after gp_bind_particles or gp_set_v_gal).  The context stream must not
- * be the null stream. */
+ * after gp_bind_particles or gp_set_v_gal).  Paper: the deposition
+ * paragraph (the same cycle as gp_run).  The context stream must not be
+ * the null stream. */
 gp_status gp_step_graph(gp_ctx *ctx, const gp_particles *p, int nsteps);
 
 /* Lab-frame snapshots of a boosted run (back-transformed diagnostics): the
@@ -294,7 +328,9 @@ gp_status gp_set_fields(gp_ctx *ctx, int run, const void *const E[3],
                         const void *const B[3], int project_transverse);
 
 /* Boris half push u^0 -> u^{1/2} through dt/2 with the current real E and
- * B at the current positions (start-up of the leapfrog). */
+ * B at the current positions (start-up of the leapfrog).  Paper: the
+ * transformed equations (the momentum equation over half a step; the
+ * start-up itself is not printed). */
 gp_status gp_half_push(gp_ctx *ctx, const gp_particles *p);
 
 /* Copy one grid array of one run to dst / from src (host or device
@@ -302,6 +338,21 @@ gp_status gp_half_push(gp_ctx *ctx, const gp_particles *p);
  * the next call that consumes it.  Coefficient tables are read-only. */
 gp_status gp_read_field(gp_ctx *ctx, int run, int which, void *dst);
 gp_status gp_write_field(gp_ctx *ctx, int run, int which, const void *src);
+
+/* Device address of one grid array of one run (the array gp_read_field
+ * would copy), for callers that read or write the fields in place (e.g.
+ * through torch tensors on the context's stream).  Real arrays hold
+ * nx*ny*nz values of the run's real type, spectral ones nx*ny*(nz/2+1)
+ * interleaved complex values.  The address of a real array, of E^, B^, J^
+ * and of a coefficient table is fixed from gp_init_grid to gp_destroy; the
+ * two rho^ buffers swap roles at every update, so the address returned for
+ * GP_RHO_HAT_OLD / GP_RHO_HAT_NEW holds that role only until the next
+ * update.  Coefficient tables must not be written.  Writing through the
+ * address does not mark the array as a fresh input (gp_write_field does);
+ * the caller orders its accesses with the context's stream.  Paper: the
+ * deposition paragraph (the grids it names: J, rho, E, B and their
+ * transforms).  Errors: GP_ERR_ARG (bad run or selector, NULL out). */
+gp_status gp_field_ptr(gp_ctx *ctx, int run, int which, void **dev_ptr);
 
 /* Field energy W_E = 1/2 sum |E|^2 dV and W_B = 1/2 sum |B|^2 dV of the
  * real fields, reduced in double on the device (synchronising). */

@@ -1322,6 +1322,18 @@ gp_status gp_gather_push(gp_ctx *c, const gp_particles *p) {
   });
 }
 
+gp_status gp_gather_push_deposit(gp_ctx *c, const gp_particles *p) {
+  GP_TRY(check_ctx(c));
+  GP_TRY(require_bound(c, p));
+  GP_TRY(require_eb(c, "gp_gather_push_deposit"));
+  GP_TRY(dispatch(c, [&](auto t) {
+    using T = decltype(t);
+    enqueue_sources<T>(c, kPartFused);
+  }));
+  for (auto &r : c->runs) r.src_real_ready = true;
+  return GP_OK;
+}
+
 gp_status gp_half_push(gp_ctx *c, const gp_particles *p) {
   GP_TRY(check_ctx(c));
   GP_TRY(require_bound(c, p));
@@ -1454,6 +1466,16 @@ gp_status gp_write_field(gp_ctx *c, int run, int which, const void *src) {
   if ((which >= GP_JX_HAT && which <= GP_JZ_HAT) || which == GP_RHO_HAT_NEW)
     r.src_spec_ready = true;
   if (which >= GP_EX && which <= GP_BZ) r.eb_real_ready = true;
+  return GP_OK;
+}
+
+gp_status gp_field_ptr(gp_ctx *c, int run, int which, void **dev_ptr) {
+  GP_TRY(check_run(c, run));
+  if (!dev_ptr) return fail(GP_ERR_ARG, "dev_ptr is NULL");
+  size_t bytes = 0;
+  void *p = field_slot(c, c->runs[run], which, &bytes);
+  if (!p) return fail(GP_ERR_ARG, "unknown field selector");
+  *dev_ptr = p;
   return GP_OK;
 }
 

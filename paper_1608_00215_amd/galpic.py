@@ -26,9 +26,10 @@ FIELD = {name: i for i, name in enumerate(FIELDS)}
 
 #: every symbol the header declares
 EXPORTS = ["gp_init_grid", "gp_set_v_gal", "gp_set_current_correction", "gp_bind_particles", "gp_deposit", "gp_fft_fwd",
-           "gp_galilean_psatd_update", "gp_fft_inv", "gp_gather_push", "gp_step",
+           "gp_galilean_psatd_update", "gp_fft_inv", "gp_gather_push",
+           "gp_gather_push_deposit", "gp_step",
            "gp_step_graph", "gp_set_fields", "gp_half_push", "gp_read_field",
-           "gp_write_field", "gp_field_energy", "gp_last_graph_ms", "gp_synchronize",
+           "gp_write_field", "gp_field_ptr", "gp_field_energy", "gp_last_graph_ms", "gp_synchronize",
            "gp_stage_timing", "gp_stage_times", "gp_stage_name", "gp_sort_count",
            "gp_run", "gp_destroy", "gp_last_error", "gp_btd_configure", "gp_btd_record",
            "gp_btd_particles", "gp_qc_init", "gp_qc_set_v_gal", "gp_qc_write", "gp_qc_read",
@@ -107,12 +108,14 @@ def load(path=LIB_PATH):
         "gp_galilean_psatd_update": [vp],
         "gp_fft_inv": [vp],
         "gp_gather_push": [vp, vp],
+        "gp_gather_push_deposit": [vp, vp],
         "gp_step": [vp, vp],
         "gp_step_graph": [vp, vp, i32],
         "gp_set_fields": [vp, i32, vp, vp, i32],
         "gp_half_push": [vp, vp],
         "gp_read_field": [vp, i32, i32, vp],
         "gp_write_field": [vp, i32, i32, vp],
+        "gp_field_ptr": [vp, i32, i32, ctypes.POINTER(vp)],
         "gp_field_energy": [vp, i32, ctypes.POINTER(dbl), ctypes.POINTER(dbl)],
         "gp_last_graph_ms": [vp, ctypes.POINTER(dbl)],
         "gp_synchronize": [vp],
@@ -316,6 +319,9 @@ class Context:
     def gather_push(self):
         self._call("gp_gather_push", self._parts_c)
 
+    def gather_push_deposit(self):
+        self._call("gp_gather_push_deposit", self._parts_c)
+
     def half_push(self):
         self._call("gp_half_push", self._parts_c)
 
@@ -437,6 +443,36 @@ class Context:
         shape, dt = self._shape(run, which)
         arr = np.ascontiguousarray(np.broadcast_to(values, shape), dtype=dt)
         self._call("gp_write_field", int(run), which, arr.ctypes.data)
+
+    def field_ptr(self, run, name):
+        """Device address of one grid array of a run (gp_field_ptr)."""
+        p = ctypes.c_void_p()
+        self._call("gp_field_ptr", int(run), FIELD[name], ctypes.byref(p))
+        return p.value
+
+    def field_tensor(self, run, name):
+        """A torch tensor viewing one grid array in place (no copy): real
+        arrays as [nx][ny][nz] of the run's real type, spectral ones as
+        [nx][ny][nz/2+1] complex.  It aliases library memory, so it is valid
+        while the context lives (rho^ slots: until the next update)."""
+        import torch
+
+        which = FIELD[name]
+        shape, dt = self._shape(run, which)
+        tdt = {np.float64: torch.float64, np.float32: torch.float32,
+               np.complex128: torch.complex128, np.complex64: torch.complex64}[dt]
+        n = int(np.prod(shape))
+        addr = self.field_ptr(run, name)
+        elem = np.dtype(dt).itemsize
+
+        class _Iface:
+            __cuda_array_interface__ = {"shape": (n,), "typestr": np.dtype(dt).str,
+                                        "data": (addr, False), "version": 2,
+                                        "strides": None}
+
+        t = torch.as_tensor(_Iface(), device="cuda")
+        assert t.element_size() == elem and t.dtype == tdt
+        return t.view(shape)
 
     def field_energy(self, run=0):
         we, wb = ctypes.c_double(), ctypes.c_double()

@@ -1,0 +1,216 @@
+"""GPU parity at the shapes and launch configurations the benchmark times,
+on outputs the oracle computes one by one from the library's own inputs:
+
+* the fused particle pass (gather + Boris push of one step with the deposit
+  of the next, the kernel that dominates a step) on the 128 x 128 x 256
+  plasma, on its first step and after 30 steps, for the benchmarked plasma
+  and for a hot one whose particles cross cells and tiles;
+* the 256 x 256 x 512 boosted run with its laser: the laser start (Boris
+  half push through dt/2), the moves and deposit, the update on sampled
+  modes and the gather-push, in both precisions;
+* full-size forward and inverse transforms of that grid (256- and 512-point
+  lines, the instantiations the boosted run uses).
+"""
+
+import numpy as np
+import pytest
+
+from oracle import spectral as osp
+from paper_1608_00215_amd import galpic as gp
+from workload import get_config, laser_fields, particles_for
+from tests import sampled as sm
+from tests.gpu_common import rel_l2
+
+pytestmark = pytest.mark.gpu
+
+C2 = get_config("c2_cubic_mixed")
+C3 = get_config("c3_boosted_laser")
+
+# per particle: |u_gpu - u_ref| <= REL_U |u| + REL_DU |du| (a float rounding
+# of the stored momentum, and the kick's own rounding with margin)
+BARS = {gp.GP_MIXED: (2e-6, 1e-5), gp.GP_FP64: (1e-13, 1e-10)}
+XTOL = {gp.GP_MIXED: 2e-5, gp.GP_FP64: 1e-11}
+FTOL = {gp.GP_MIXED: 1e-5, gp.GP_FP64: 1e-12}
+
+
+@pytest.fixture(scope="module")
+def c2_inputs():
+    return particles_for(C2)
+
+
+@pytest.fixture(scope="module")
+def c3_inputs():
+    return particles_for(C3)
+
+
+def _ctx(cfg, precision, inp):
+    ctx = gp.Context([gp.grid_from_config(cfg, precision)])
+    ctx.set_v_gal(0, cfg.v_gal())
+    parts = gp.particles_from_inputs(inp, cfg, precision, with_ids=True)
+    ctx.bind_particles([parts])
+    return ctx, parts
+
+
+def _field_cycle(ctx):
+    ctx.fft_fwd()
+    ctx.galilean_psatd_update()
+    ctx.fft_inv()
+
+
+def _check_windows(ctx, cfg, corners, before, tol):
+    """J and rho of the last deposit against the oracle's deposit of the
+    particles that can reach each window, from their state `before` (dict
+    corner -> (x, u, u_new or None)); u_new None: the deposit moved them
+    with u; else the pass pushed u to u_new first (given)."""
+    J = [ctx.read_field(0, "J" + c) for c in "XYZ"]
+    rho = ctx.read_field(0, "RHO")
+    for corner in corners:
+        x, u_dep = before[corner]
+        v, xh, xn = sm.oracle_moves(cfg, x, u_dep)
+        Jref, rref = sm.window_reference(cfg, corner, xh, v, xn)
+        win = sm.window_index(cfg, corner)
+        for a in range(3):
+            assert rel_l2(J[a][win], Jref[a]) <= tol, (corner, a)
+        assert rel_l2(rho[win], rref) <= tol, corner
+
+
+@pytest.mark.parametrize("case,pre", [("bench", 0), ("bench", 30), ("hot", 30)])
+def test_fused_pass_c2_sampled(gpu_lib, c2_inputs, case, pre):
+    """After `pre` whole steps (gp_run) and one more deposit and field
+    cycle, one fused pass (gp_gather_push_deposit): sampled particles'
+    momenta and positions, and J and rho on node windows (at the periodic
+    seams, a tile edge and the interior), against the oracle's gather, Boris
+    push, moves and deposit from the state and fields the pass started
+    from."""
+    cfg = C2
+    inp = c2_inputs
+    if case == "hot":
+        rng = np.random.Generator(np.random.PCG64(40))
+        u = inp["u"].copy()
+        u[:, :2] = rng.standard_normal((u.shape[0], 2)).astype(np.float32)
+        inp = {**inp, "u": u}
+    ctx, parts = _ctx(cfg, gp.GP_MIXED, inp)
+    if pre:
+        ctx.run(pre)
+    ctx.deposit()
+    _field_cycle(ctx)
+    ctx.synchronize()
+    F = sm.read_fields(ctx, 0)
+    rng = np.random.Generator(np.random.PCG64(41 + pre))
+    pick = rng.choice(cfg.n_particles, 20000, replace=False)
+    x0, u0 = sm.state_of(parts, cfg, pick)
+    corners = [(0, 0, 0), (61, 17, 130), (127, 127, 255), (40, 100, 7)]
+    before = {}
+    for corner in corners:
+        lo, hi = sm.window_sources(cfg, corner)
+        ids = sm.ids_near(parts, cfg, lo, hi)
+        xw, uw = sm.state_of(parts, cfg, ids)
+        un, _, _, _ = sm.oracle_pass(cfg, xw, uw, F)
+        before[corner] = (xw, un)
+    ctx.gather_push_deposit()
+    ctx.synchronize()
+    x1, u1 = sm.state_of(parts, cfg, pick)
+    un, _, _, xn = sm.oracle_pass(cfg, x0, u0, F)
+    assert sm.momentum_bar(u1, un, u0, *BARS[gp.GP_MIXED]) <= 1.0
+    assert sm.periodic_max_diff(x1, xn, cfg) <= XTOL[gp.GP_MIXED]
+    _check_windows(ctx, cfg, corners, before, FTOL[gp.GP_MIXED])
+    rho = ctx.read_field(0, "RHO").astype(np.float64)
+    total = cfg.n_particles * cfg.q * cfg.w
+    assert abs(rho.sum() - total) <= 1e-6 * abs(total)
+    ctx.close()
+
+
+@pytest.mark.parametrize("precision", [gp.GP_MIXED, gp.GP_FP64])
+def test_c3_laser_start_and_step_sampled(gpu_lib, c3_inputs, precision):
+    """The 256 x 256 x 512 boosted run with its laser, as the benchmark
+    starts it: fields set and projected, the Boris half push u^0 -> u^{1/2}
+    (dt/2), then one step through the stage calls.  Checked against the
+    oracle from the library's inputs of each stage: sampled momenta after
+    the half push (half of them inside the pulse), positions after the
+    moves, J and rho on windows inside and outside the pulse, E^ and B^ at
+    sampled modes after the update, and momenta after the gather-push."""
+    cfg = C3
+    ctx, parts = _ctx(cfg, precision, c3_inputs)
+    lf = laser_fields(cfg)
+    ctx.set_fields(0, lf[0], lf[1], project_transverse=True)
+    F0 = sm.read_fields(ctx, 0)
+    rng = np.random.Generator(np.random.PCG64(51))
+    nx, ny, nz = cfg.shape
+    # half the sample inside the pulse (|x - nx/2|, |y - ny/2| < 16, z near nz/4)
+    ids_all = np.arange(cfg.n_particles)
+    cell = ids_all[:: 97] // cfg.ppc
+    ix, iy, iz = cell // (ny * nz), (cell // nz) % ny, cell % nz
+    inside = ids_all[:: 97][(np.abs(ix - nx // 2) < 16) & (np.abs(iy - ny // 2) < 16)
+                            & (np.abs(iz - nz // 4) < 40)]
+    pick = np.concatenate([rng.choice(inside, 10000, replace=False),
+                           rng.choice(cfg.n_particles, 10000, replace=False)])
+    x0, u0 = sm.state_of(parts, cfg, pick)
+    ctx.half_push()
+    ctx.synchronize()
+    _, uh = sm.state_of(parts, cfg, pick)
+    uref, _, _, _ = sm.oracle_pass(cfg, x0, u0, F0, dt_factor=0.5)
+    assert np.max(np.linalg.norm(uref - u0, axis=1)) > 1e-2   # the pulse kicks them
+    assert sm.momentum_bar(uh, uref, u0, *BARS[precision]) <= 1.0
+    corners = [(126, 126, 126), (0, 0, 0), (255, 200, 511)]
+    before = {}
+    for corner in corners:
+        lo, hi = sm.window_sources(cfg, corner)
+        ids = sm.ids_near(parts, cfg, lo, hi)
+        before[corner] = sm.state_of(parts, cfg, ids)
+    ctx.deposit()
+    ctx.synchronize()
+    x1, _ = sm.state_of(parts, cfg, pick)
+    _, _, xn = sm.oracle_moves(cfg, x0, uh)
+    assert sm.periodic_max_diff(x1, xn, cfg) <= XTOL[precision]
+    _check_windows(ctx, cfg, corners, before, FTOL[precision])
+    ctx.fft_fwd()
+    ctx.synchronize()
+    spectra = {n: ctx.read_field(0, n) for n in sm.SPECTRA}
+    ctx.galilean_psatd_update()
+    ctx.synchronize()
+    idx = sm.sample_modes(cfg.shape, 4000, 52)
+    En, Bn = sm.update_reference(cfg, spectra, idx)
+    del spectra
+    utol = 1e-6 if precision == gp.GP_MIXED else 1e-12
+    for a, c in enumerate("XYZ"):
+        assert rel_l2(ctx.read_field(0, "E" + c + "_HAT")[idx], En[a]) <= utol, c
+        assert rel_l2(ctx.read_field(0, "B" + c + "_HAT")[idx], Bn[a]) <= utol, c
+    ctx.fft_inv()
+    ctx.synchronize()
+    F1 = sm.read_fields(ctx, 0)
+    ctx.gather_push()
+    ctx.synchronize()
+    _, u2 = sm.state_of(parts, cfg, pick)
+    uref2, _, _, _ = sm.oracle_pass(cfg, x1, uh, F1)
+    assert sm.momentum_bar(u2, uref2, uh, *BARS[precision]) <= 1.0
+    ctx.close()
+
+
+@pytest.mark.parametrize("precision", [gp.GP_MIXED, gp.GP_FP64])
+def test_c3_transforms_full(gpu_lib, precision):
+    """Forward and inverse transforms of the 256 x 256 x 512 grid (the
+    boosted run's 256-point x and y lines and 512-point z lines, in the
+    launch configuration of its steps) against numpy's FFT in double."""
+    cfg = C3
+    g = gp.grid_from_config(cfg, precision)
+    ctx = gp.Context([g])
+    rng = np.random.Generator(np.random.PCG64(53))
+    real = np.float64 if precision == gp.GP_FP64 else np.float32
+    f = rng.standard_normal(cfg.shape).astype(real)
+    ctx.write_field(0, "RHO", f)
+    zero = np.zeros(cfg.shape, real)
+    for c in "XYZ":
+        ctx.write_field(0, "J" + c, zero)
+    ctx.fft_fwd()
+    ref = osp.forward(f.astype(np.float64))
+    ref[osp.held_zero_mask(cfg.shape)] = 0
+    nzh = cfg.shape[2] // 2 + 1
+    got = ctx.read_field(0, "RHO_HAT_NEW")
+    tol = 2e-6 if precision == gp.GP_MIXED else 1e-13
+    assert rel_l2(got, ref[:, :, :nzh]) <= tol
+    del got
+    ctx.write_field(0, "BY_HAT", ref[:, :, :nzh])
+    ctx.fft_inv()
+    back = ctx.read_field(0, "BY")
+    assert rel_l2(back, osp.inverse(ref)) <= tol
+    ctx.close()

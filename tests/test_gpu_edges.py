@@ -13,12 +13,20 @@ from tests.test_gpu_step import compare_state, setup
 
 pytestmark = pytest.mark.gpu
 
-# (shape, spacing, dt): the smallest grid, and a 1024-long line on each axis
+# (shape, spacing, dt): the smallest grid, a 1024-long line on each axis,
+# and the line lengths of the benchmarked grids that no other case reaches:
+# 64-point x and y lines (the batched runs), 256-point x and y lines and
+# 512-point z lines (the boosted run)
 EDGE_GRIDS = [
     ((8, 8, 8), (1.0, 1.0, 1.0), 1.0),
     ((1024, 8, 16), (0.5, 1.0, 1.0), 0.5),
     ((8, 1024, 16), (1.0, 0.5, 1.0), 0.5),
     ((16, 8, 1024), (1.0, 1.0, 0.5), 0.5),
+    ((64, 8, 16), (1.0, 1.0, 1.0), 1.0),
+    ((8, 64, 16), (1.0, 1.0, 1.0), 1.0),
+    ((256, 8, 16), (1.0, 1.0, 1.0), 1.0),
+    ((8, 256, 16), (1.0, 1.0, 1.0), 1.0),
+    ((16, 8, 512), (1.0, 1.0, 1.0), 1.0),
 ]
 
 

@@ -183,3 +183,67 @@ def test_nci_pair_gpu(gpu_lib):
     assert np.max(Wg) <= 6.0 * Wg[0]
     assert Ws[-1] >= 30.0 * Ws[0]
     assert Ws[-1] >= 10.0 * Wg[-1]
+
+
+@pytest.mark.parametrize("precision,tol_u,tol_f", [(gp.GP_FP64, 1e-12, 1e-12),
+                                                   (gp.GP_MIXED, 1e-6, 1e-5)])
+def test_laser_start_half_push_c3_lite(gpu_lib, precision, tol_u, tol_f):
+    """The laser start as the boosted run uses it: fields set and projected,
+    then the Boris half push u^0 -> u^{1/2} (gp_half_push) against the
+    oracle's half push, then two whole steps from there."""
+    from workload import laser_fields
+
+    cfg = get_config("c3_lite")
+    ctx, parts, inp = setup(cfg, precision)
+    sim = oracle_sim(cfg)
+    lf = laser_fields(cfg)
+    E0 = tuple(a.astype(np.float32).astype(np.float64) for a in lf[0])
+    B0 = tuple(a.astype(np.float32).astype(np.float64) for a in lf[1])
+    ctx.set_fields(0, E0, B0, project_transverse=True)
+    st = sim.initial_state(inp["x"], inp["u"], E0, B0, project_transverse=True)
+    ctx.half_push()
+    st = sim.half_push(st)
+    from tests.sampled import momentum_bar
+
+    ids = parts.id_array()
+    assert np.max(np.abs(st.u - inp["u"])) > 1e-2      # the pulse kicks the particles
+    # per particle: a rounding of the stored momentum plus that of the kick
+    bars = (1e-13, 1e-10) if precision == gp.GP_FP64 else (2e-6, 1e-5)
+    assert momentum_bar(parts.momenta(), st.u[ids], inp["u"][ids], *bars) <= 1.0
+    assert rel_l2(parts.momenta(), st.u[ids]) <= tol_u
+    ctx.run(2)
+    for _ in range(2):
+        st = sim.step(st)
+    compare_state(ctx, parts, st, cfg, tol_f * 2, 1e-9 if precision == gp.GP_FP64 else 5e-6)
+    ctx.close()
+
+
+@pytest.mark.parametrize("precision", [gp.GP_FP64, gp.GP_MIXED])
+def test_field_pointer_views_the_library_arrays(gpu_lib, precision):
+    """gp_field_ptr: a torch view of a real array and of a spectrum reads
+    what gp_read_field copies, a write through the view is what the library
+    then reads, and the rho^ roles swap at the update."""
+    import torch
+
+    cfg = get_config("c2_lite").with_(u_th=0.2)
+    ctx, parts, _ = setup(cfg, precision)
+    ctx.run(2)
+    ctx.synchronize()
+    for name in ("EX", "BZ", "RHO", "EY_HAT", "RHO_HAT_OLD", "COEF3"):
+        t = ctx.field_tensor(0, name)
+        assert np.array_equal(t.cpu().numpy(), ctx.read_field(0, name)), name
+    ex = ctx.field_tensor(0, "EX")
+    ex.mul_(2.0)
+    torch.cuda.synchronize()
+    assert np.array_equal(ctx.read_field(0, "EX"), ex.cpu().numpy())
+    old = ctx.field_ptr(0, "RHO_HAT_OLD")
+    new = ctx.field_ptr(0, "RHO_HAT_NEW")
+    assert old != new
+    ctx.deposit()
+    ctx.fft_fwd()
+    ctx.galilean_psatd_update()
+    assert ctx.field_ptr(0, "RHO_HAT_OLD") == new
+    assert ctx.field_ptr(0, "RHO_HAT_NEW") == old
+    with pytest.raises(gp.GalpicError):
+        ctx.field_ptr(1, "EX")
+    ctx.close()

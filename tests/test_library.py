@@ -58,3 +58,36 @@ def test_product_package_does_not_import_the_oracle():
                 assert not re.search(r"\boracle\b", src.replace("no fallback", "")) or \
                     "import oracle" not in src, f
                 assert "import oracle" not in src and "from oracle" not in src, f
+
+
+PASSAGES = ("the transformed equations", "the update display", "the deposition paragraph",
+            "the simulation parameters")
+CITED_CALLS = ("gp_init_grid", "gp_set_v_gal", "gp_bind_particles", "gp_deposit",
+               "gp_fft_fwd", "gp_galilean_psatd_update", "gp_fft_inv", "gp_gather_push",
+               "gp_gather_push_deposit", "gp_step", "gp_run", "gp_step_graph",
+               "gp_half_push", "gp_field_ptr")
+
+
+def test_hot_path_calls_cite_a_passage():
+    """Every call of the step (and the field accessor) names, in the comment
+    just above its declaration, the passage of the paper that defines it,
+    from the list of passages the header's preamble explains."""
+    text = open(HEADER).read()
+    preamble = text[:text.index("#ifndef GALPIC_H")]
+    for p in PASSAGES:
+        assert f'"{p}"' in preamble, p
+    for call in CITED_CALLS:
+        m = re.search(r"/\*((?:(?!\*/).)*)\*/\s*(?:gp_status\s+[a-z_0-9]+\([^;]*;\s*)*gp_status\s+"
+                      + call + r"\(", text, flags=re.S)
+        assert m, call
+        comment = " ".join(re.sub(r"\n\s*\*", " ", m.group(1)).split())
+        assert "Paper:" in comment, call
+        cited = comment[comment.index("Paper:"):]
+        assert any(p in cited for p in PASSAGES), (call, cited[:80])
+
+
+def test_field_pointer_accessor_declared():
+    assert "gp_field_ptr" in declared_functions()
+    text = open(HEADER).read()
+    assert re.search(r"gp_status\s+gp_field_ptr\(gp_ctx \*ctx, int run, int which, void \*\*dev_ptr\)",
+                     text)

@@ -301,3 +301,38 @@ def test_max_galilean_phase_on_named_workloads():
     for cfg in CONFIGS.values():
         ph = co.max_galilean_phase(cfg.shape, cfg.spacing, cfg.v_gal(), cfg.dt)
         assert ph < 2 * np.pi * (1 - 1e-6)
+
+
+def test_max_galilean_phase_hand_value():
+    """Hand-computed largest Galilean phase: on a 16x16x64 grid with unit
+    spacing, the largest non-Nyquist k_z is 2 pi 31 / 64, so with v_gal =
+    (0, 0, -beta), beta = sqrt(1 - 1/gamma^2) at gamma = 10, and dt = 1 the
+    phase is beta 2 pi 31 / 64 = 3.0281625... (a dropped Nyquist exclusion
+    gives beta pi, a dropped 2 pi gives 0.48...)."""
+    beta = np.sqrt(1.0 - 1.0 / 100.0)
+    got = co.max_galilean_phase((16, 16, 64), (1.0, 1.0, 1.0), (0.0, 0.0, -beta), 1.0)
+    assert abs(got - 3.0281625596149095) <= 1e-13
+    # half the time step halves it; twice the spacing along z halves it
+    assert abs(co.max_galilean_phase((16, 16, 64), (1.0, 1.0, 1.0), (0.0, 0.0, -beta), 0.5)
+               - 0.5 * 3.0281625596149095) <= 1e-13
+    assert abs(co.max_galilean_phase((16, 16, 64), (1.0, 1.0, 2.0), (0.0, 0.0, -beta), 1.0)
+               - 0.5 * 3.0281625596149095) <= 1e-13
+
+
+def test_max_galilean_phase_brute_force():
+    """The largest |k.v_gal| dt over every mode of a small oblique case,
+    enumerated one by one from numpy's FFT frequencies with the Nyquist
+    planes left out, equals the oracle's per-axis sum."""
+    shape, spacing = (8, 6, 10), (1.0, 0.7, 1.3)
+    v, dt = (0.3, -0.2, 0.5), 0.9
+    best = 0.0
+    f = [2 * np.pi * np.fft.fftfreq(n, d) for n, d in zip(shape, spacing)]
+    for i in range(shape[0]):
+        for j in range(shape[1]):
+            for k in range(shape[2]):
+                if i == shape[0] // 2 or j == shape[1] // 2 or k == shape[2] // 2:
+                    continue
+                ph = abs(f[0][i] * v[0] + f[1][j] * v[1] + f[2][k] * v[2]) * dt
+                best = max(best, ph)
+    got = co.max_galilean_phase(shape, spacing, v, dt)
+    assert abs(got - best) <= 1e-14 * best

@@ -104,3 +104,53 @@ def test_fft_sign_convention_is_caught(monkeypatch):
     from tests import test_oracle_spectral as ts
 
     _fails(ts.test_forward_matches_direct_dft)
+
+
+def test_half_push_with_full_step_is_caught(monkeypatch):
+    """The laser start pushed through dt instead of dt / 2."""
+    from oracle import pic
+    from tests import test_oracle_step as tst
+
+    def wrong(self, state):
+        g, s = self.grid, self.species
+        F = pt.gather(list(state.E) + list(state.B), state.x, g.shape, g.spacing, g.order)
+        state.u = pt.boris_push(state.u, F[:3].T, F[3:].T, s.q, s.m, g.dt, self.c)
+        return state
+
+    monkeypatch.setattr(pic.Simulation, "half_push", wrong)
+    _fails(tst.test_half_push_uniform_electric_field, 3)
+    _fails(tst.test_half_push_uniform_magnetic_field)
+
+
+def test_field_energy_without_half_is_caught(monkeypatch):
+    from oracle import diagnostics as dg
+    from tests import test_oracle_step as tst
+
+    orig = dg.field_energy
+
+    def wrong(E, B, cell_volume):
+        we, wb = orig(E, B, cell_volume)
+        return 2 * we, 2 * wb
+
+    monkeypatch.setattr(dg, "field_energy", wrong)
+    _fails(tst.test_field_energy_closed_form)
+
+
+def test_field_energy_without_cell_volume_is_caught(monkeypatch):
+    from oracle import diagnostics as dg
+    from tests import test_oracle_step as tst
+
+    orig = dg.field_energy
+    monkeypatch.setattr(dg, "field_energy", lambda E, B, cell_volume: orig(E, B, 1.0))
+    _fails(tst.test_field_energy_closed_form)
+
+
+def test_galilean_phase_with_nyquist_is_caught(monkeypatch):
+    """The largest phase taken at the Nyquist index n / 2 instead of n / 2 - 1."""
+    def wrong(shape, spacing, v_gal, dt):
+        return sum(abs(v) * 2 * np.pi * (n // 2) / (n * d)
+                   for n, d, v in zip(shape, spacing, v_gal)) * dt
+
+    monkeypatch.setattr(co, "max_galilean_phase", wrong)
+    _fails(tc.test_max_galilean_phase_hand_value)
+    _fails(tc.test_max_galilean_phase_brute_force)

@@ -119,3 +119,93 @@ def test_transverse_projection():
         np.testing.assert_allclose(st.B[a], FT[a], atol=1e-12 * scale)
     div = sum(kk[a] * np.fft.fftn(st.E[a]) for a in range(3))
     assert np.abs(div).max() <= 1e-11 * scale * np.prod(shape)
+
+
+def _state_with_fields(x, u, E, B):
+    """A state whose real-space E, B are given directly (the half push only
+    reads those, the positions and the momenta)."""
+    z = np.zeros(1)
+    return pic.State(x=np.array(x, float), u=np.array(u, float), E_hat=(z, z, z),
+                     B_hat=(z, z, z), rho_hat=z, E=tuple(E), B=tuple(B))
+
+
+@pytest.mark.parametrize("order", [1, 3])
+def test_half_push_uniform_electric_field(order):
+    """The laser start u^0 -> u^{1/2} in a uniform E and no B adds exactly
+    q E dt / (2 m) (Boris with B = 0 is two kicks of q E dt / (4 m));
+    a full dt in its place would double it."""
+    cfg = get_config("c1_cic_fp64").with_(shape=(8, 8, 16), order=order, dt=0.8)
+    sim = make_sim(cfg)
+    rng = np.random.default_rng(11)
+    x = rng.random((30, 3)) * np.array(cfg.shape)
+    u = rng.standard_normal((30, 3))
+    Ev = np.array([0.3, -1.2, 0.7])
+    E = [np.full(cfg.shape, Ev[a]) for a in range(3)]
+    B = [np.zeros(cfg.shape)] * 3
+    st = sim.half_push(_state_with_fields(x, u, E, B))
+    np.testing.assert_allclose(st.u, u + cfg.q * Ev[None, :] * cfg.dt / (2 * cfg.m),
+                               rtol=0, atol=1e-14)
+
+
+def test_half_push_uniform_magnetic_field():
+    """In a uniform B along z the half push keeps |u| and u_z and turns the
+    transverse momentum by 2 atan(|q| B (dt/2) / (2 m gamma)), an electron
+    counter-clockwise about +z."""
+    cfg = get_config("c1_cic_fp64").with_(shape=(8, 8, 16), order=3, dt=1.1)
+    sim = make_sim(cfg)
+    x = np.array([[1.2, 3.4, 5.6], [7.9, 0.1, 15.5]])
+    u = np.array([[2.0, -1.0, 0.5], [-0.3, 4.0, -9.0]])
+    Bz = 1.7
+    E = [np.zeros(cfg.shape)] * 3
+    B = [np.zeros(cfg.shape), np.zeros(cfg.shape), np.full(cfg.shape, Bz)]
+    st = sim.half_push(_state_with_fields(x, u, E, B))
+    gamma = np.sqrt(1 + np.sum(u * u, axis=1))
+    angle = np.arctan2(st.u[:, 1], st.u[:, 0]) - np.arctan2(u[:, 1], u[:, 0])
+    angle = np.mod(angle + np.pi, 2 * np.pi) - np.pi
+    expect = 2 * np.arctan(abs(cfg.q) * Bz * (0.5 * cfg.dt) / (2 * cfg.m * gamma))
+    np.testing.assert_allclose(angle, expect, rtol=0, atol=1e-14)
+    np.testing.assert_allclose(np.linalg.norm(st.u, axis=1), np.linalg.norm(u, axis=1),
+                               rtol=1e-15)
+    assert np.array_equal(st.u[:, 2], u[:, 2])
+
+
+@pytest.mark.parametrize("order", [1, 3])
+def test_half_push_reads_fields_at_the_particle(order):
+    """E_x growing linearly along x (node values a + b i) is reproduced
+    exactly by both shapes away from the periodic seam, so each particle's
+    kick is q (a + b x / dx) dt / (2 m): the half push samples the fields at
+    the particle's own position."""
+    cfg = get_config("c1_cic_fp64").with_(shape=(16, 8, 8), spacing=(0.5, 1.0, 1.0),
+                                          order=order, dt=0.6)
+    sim = make_sim(cfg)
+    a, b = 0.4, -0.05
+    ex = a + b * np.arange(16, dtype=float)[:, None, None] * np.ones(cfg.shape)
+    rng = np.random.default_rng(12)
+    x = np.stack([rng.uniform(2.0, 5.5, 40), rng.uniform(0, 8, 40), rng.uniform(0, 8, 40)], 1)
+    u = np.zeros((40, 3))
+    E = [ex, np.zeros(cfg.shape), np.zeros(cfg.shape)]
+    B = [np.zeros(cfg.shape)] * 3
+    st = sim.half_push(_state_with_fields(x, u, E, B))
+    expect = cfg.q * (a + b * x[:, 0] / 0.5) * cfg.dt / (2 * cfg.m)
+    np.testing.assert_allclose(st.u[:, 0], expect, rtol=0, atol=1e-14)
+    assert np.all(st.u[:, 1:] == 0.0)
+
+
+def test_field_energy_closed_form():
+    """W = 1/2 sum (|E|^2 + |B|^2) dV for single Fourier modes: over a
+    periodic grid sum cos^2(2 pi m i / N) = N / 2 for 0 < m < N / 2, while
+    a uniform component sums to N; so with E = (A cos, A' sin, 0) and B =
+    (0, 0, C), W_E = dV N (A^2 + A'^2) / 4 and W_B = dV N C^2 / 2
+    (anisotropic spacing, so a missing cell volume is caught)."""
+    shape, spacing = (8, 6, 10), (0.5, 1.5, 2.0)
+    dV = 0.5 * 1.5 * 2.0
+    N = 8 * 6 * 10
+    i, j, k = np.meshgrid(*[np.arange(n) for n in shape], indexing="ij")
+    A, A2, C = 1.3, -0.7, 0.25
+    ph = 2 * np.pi * (2 * i / 8 + 1 * j / 6 + 3 * k / 10)
+    ph2 = 2 * np.pi * (3 * i / 8 - 2 * k / 10)
+    E = (A * np.cos(ph), A2 * np.sin(ph2), np.zeros(shape))
+    B = (np.zeros(shape), np.zeros(shape), np.full(shape, C))
+    we, wb = dg.field_energy(E, B, dV)
+    assert abs(we - dV * N * (A * A + A2 * A2) / 4) <= 1e-13 * we
+    assert abs(wb - dV * N * C * C / 2) <= 1e-13 * wb
