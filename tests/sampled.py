@@ -204,3 +204,36 @@ def update_reference(cfg, spectra, idx):
     J = tuple(take("J" + c + "_HAT") for c in "XYZ")
     return osp.galilean_psatd_update(E, B, J, take("RHO_HAT_OLD"), take("RHO_HAT_NEW"), k,
                                      coef, held_at(idx, cfg.shape))
+
+
+def update_scale(cfg, spectra, idx):
+    """Per sampled mode, the sum of the magnitudes of the terms of the
+    update (|c||input| over every term, with |k| for the curls and the
+    charge terms): the size against which the float rounding of inputs and
+    coefficients is measured, since cancellation can make the result far
+    smaller than its terms."""
+    from oracle import coefficients as oco
+
+    k = half_k_at(idx, cfg.shape, cfg.spacing)
+    kmag = np.sqrt(k[0] ** 2 + k[1] ** 2 + k[2] ** 2)
+    coef = oco.galilean_psatd_coefficients(k, cfg.v_gal(), cfg.dt)
+    take = lambda n: np.abs(np.asarray(spectra[n])[idx].astype(np.complex128))
+    E = np.sqrt(sum(take("E" + c + "_HAT") ** 2 for c in "XYZ"))
+    B = np.sqrt(sum(take("B" + c + "_HAT") ** 2 for c in "XYZ"))
+    J = np.sqrt(sum(take("J" + c + "_HAT") ** 2 for c in "XYZ"))
+    a = lambda key: np.abs(coef[key])
+    return ((E + B) * (a("c_EE") + a("s") * kmag) + J * (a("c_BJ") * kmag + a("c_EJ"))
+            + kmag * (a("c_R1") * take("RHO_HAT_NEW") + a("c_R0") * take("RHO_HAT_OLD")))
+
+
+def check_update(ctx, run, cfg, spectra, idx, tol):
+    """E^, B^ after the update at the sampled modes against the oracle's
+    update of the library's inputs, each component within tol of the
+    update's term scale (L2 over the modes)."""
+    En, Bn = update_reference(cfg, spectra, idx)
+    scale = float(np.linalg.norm(update_scale(cfg, spectra, idx)))
+    for a, c in enumerate("XYZ"):
+        for name, ref in (("E" + c + "_HAT", En[a]), ("B" + c + "_HAT", Bn[a])):
+            got = ctx.read_field(run, name)[idx].astype(np.complex128)
+            err = float(np.linalg.norm(got - ref))
+            assert err <= tol * scale, (run, name, err / scale)

@@ -127,14 +127,14 @@ def test_batched_stages_match_oracle(gpu_lib, c5_inputs, precision):
     # update at sampled modes
     ctx.galilean_psatd_update()
     ctx.synchronize()
-    utol = 1e-6 if precision == gp.GP_MIXED else 1e-12
+    # against the update's term scale: float inputs and complex64 coefficients
+    # carry 6e-8 of each term, and the result can be far smaller than its
+    # terms (B_z of a drifting plasma)
+    utol = 1e-6 if precision == gp.GP_MIXED else 1e-13
     for r in PICK:
         cfg = RUNS[r]
         idx = sm.sample_modes(cfg.shape, 6000, 60 + r)
-        En, Bn = sm.update_reference(cfg, spectra[r], idx)
-        for a, c in enumerate("XYZ"):
-            assert rel_l2(ctx.read_field(r, "E" + c + "_HAT")[idx], En[a]) <= utol, (r, c)
-            assert rel_l2(ctx.read_field(r, "B" + c + "_HAT")[idx], Bn[a]) <= utol, (r, c)
+        sm.check_update(ctx, r, cfg, spectra[r], idx, utol)
     # inverse transform of the library's E^, B^
     ctx.fft_inv()
     ctx.synchronize()

@@ -85,6 +85,25 @@ def test_nci_pair_galilean_quiet_standard_grows():
     assert Ws[-1] >= 10.0 * Wg[-1]
 
 
+@pytest.mark.slow
+def test_nci_pair_over_400_steps():
+    """The pair run eight times longer (the extension of the calibration
+    the 50-step test is cut from).  The standard run's fast growth
+    (e-folding ~11 steps over steps 10-50) saturates near 60 W(1) by step
+    50 and then grows slowly, passing 100 W(1) at step ~230, while the
+    Galilean run stays within the plasma oscillation of its seeded noise
+    (period 2 pi gamma^1.5 ~ 200 steps, peaks ~4-5 W(1)).  Over 400 steps:
+    Galilean max W <= 6 W(1); standard W(400) >= 100 W(1); the standard
+    run's smallest W over steps 200-400 is at least 10x the Galilean
+    run's largest."""
+    cfg = get_config("c1_cic_fp64")
+    Wg = energy_history(cfg, 400)
+    Ws = energy_history(cfg.with_(galilean=False), 400)
+    assert np.max(Wg) <= 6.0 * Wg[0]
+    assert Ws[-1] >= 100.0 * Ws[0]
+    assert np.min(Ws[199:]) >= 10.0 * np.max(Wg)
+
+
 def test_transverse_projection():
     """The laser start removes the part of E^0, B^0 along k: a field built
     as a curl (transverse) plus a gradient (longitudinal) comes back as the
