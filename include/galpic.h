@@ -178,7 +178,8 @@ gp_status gp_init_grid(const gp_grid_desc *runs, int n_runs, void *hip_stream,
  * 2 pi (1 - 1e-6). */
 gp_status gp_set_v_gal(gp_ctx *ctx, int run, double vx, double vy, double vz);
 
-/* Option, off by default: before each update replace the longitudinal part
+/* Option, off by default (not with the slab solve of gp_set_local_slabs,
+ * GP_ERR_STATE): before each update replace the longitudinal part
  * of J^ of every run so that the Galilean continuity equation of the
  * transformed equations, integrated over the step with J constant
  * (rho^{n+1} = theta^2 rho^n + F k.J, F = (1 - theta^2) / (k.v_gal), -> -i dt
@@ -255,6 +256,44 @@ gp_status gp_run(gp_ctx *ctx, const gp_particles *p, int nsteps);
  * paragraph (the same cycle as gp_run).  The context stream must not be
  * the null stream. */
 gp_status gp_step_graph(gp_ctx *ctx, const gp_particles *p, int nsteps);
+
+/* Option, off by default: the field solve of every run on z-slabs with
+ * local transforms and guard cells.  The paper's closing paragraph names
+ * domain decomposition with local transforms over subdomains padded by
+ * guard cells, which finite-order solvers make possible, as future work; it
+ * does not print the procedure.  Reading taken here (one device; the guard
+ * exchange between neighbouring slabs is a copy out of the run's grids):
+ *  - the grid is cut into n_slabs slabs of ns = nz / n_slabs planes; slab s
+ *    owns planes s ns .. s ns + ns - 1 and transforms the window of planes
+ *    s ns - guard .. s ns + ns + guard - 1 (periodic) as its own periodic
+ *    grid of nw = ns + 2 guard planes;
+ *  - the state is the real E, B; each field cycle takes the windows of E, B
+ *    and of J, rho^{n+1} (less their grid means: the co-moving ions that
+ *    hold the global solve's k = 0 mode at zero), holds the windows' Nyquist
+ *    planes of the sources at zero and nothing else, advances every local
+ *    mode with the Galilean-PSATD update on the window's grid (the run's
+ *    stencil orders; at [k] = 0 the update is E' = E - dt J, B' = B), with
+ *    rho^n the slab's previous rho^{n+1} window, and writes the windows'
+ *    owned planes of the new E, B back into the run's E, B (the guard
+ *    planes are dropped and read again from the neighbours next cycle);
+ *  - gp_fft_fwd, gp_galilean_psatd_update and gp_fft_inv then run these
+ *    three parts (windows and forward transforms; the slabs' update; inverse
+ *    transforms and owned planes), and the step drivers use them; the run's
+ *    own spectral E^, B^, rho^ are not kept up to date (gp_read_field of
+ *    them returns old values).
+ * A window as long as the grid (nw = nz) reproduces the global solve; a
+ * shorter one differs from it by the part of the one-step propagator that
+ * reaches past the guard planes.
+ *   n_slabs  0: back to the global solve (its spectral state is rebuilt from
+ *            the real E, B and rho); else nz must be a multiple of it;
+ *   guard    planes on each side: nz / n_slabs + 2 guard must be a power of
+ *            two in [8, nz].
+ * Every run needs a finite-order stencil along z (gp_grid_desc.stencil[2]
+ * in [2, 64]); the current correction must be off (GP_ERR_STATE).  Requires real E, B current; with particles bound, rho^n of
+ * the slabs is taken from the runs' current rho (the last deposit).
+ * Allocates the slabs' grids (like a context of n_runs * n_slabs runs of
+ * nx x ny x nw).  Errors: GP_ERR_ARG, GP_ERR_STATE, GP_ERR_OOM. */
+gp_status gp_set_local_slabs(gp_ctx *ctx, int n_slabs, int guard);
 
 /* Lab-frame snapshots of a boosted run (back-transformed diagnostics): the
  * paper reports its boosted-frame results in the lab frame through an
@@ -368,7 +407,7 @@ gp_status gp_last_graph_ms(gp_ctx *ctx, double *ms);
  * gp_stage_times returns, per stage, the summed milliseconds and the number
  * of recorded launches, then clears them (synchronising).  Graph replays
  * are not recorded. */
-#define GP_N_STAGES 13
+#define GP_N_STAGES 15
 gp_status gp_stage_timing(gp_ctx *ctx, int enable);
 gp_status gp_stage_times(gp_ctx *ctx, double ms[GP_N_STAGES], int count[GP_N_STAGES]);
 const char *gp_stage_name(int stage);

@@ -30,6 +30,7 @@ import numpy as np
 from . import particles as pt
 from . import spectral as sp
 from .coefficients import galilean_psatd_coefficients
+from .local import SlabSolver
 
 
 @dataclass
@@ -73,7 +74,7 @@ class Simulation:
     """Holds the grid, species, v_gal and the per-mode coefficients."""
 
     def __init__(self, grid, species, v_gal, c=sp.C_LIGHT, eps0=sp.EPS0,
-                 current_correction=False, stencil=(0, 0, 0)):
+                 current_correction=False, stencil=(0, 0, 0), slabs=None):
         self.grid = grid
         self.species = species
         self.v_gal = np.asarray(v_gal, dtype=np.float64)
@@ -88,6 +89,13 @@ class Simulation:
         self.k = sp.wavevectors(grid.shape, grid.spacing, self.stencil)
         self.mask = sp.held_zero_mask(grid.shape)
         self.coef = galilean_psatd_coefficients(self.k, self.v_gal, grid.dt, c, eps0)
+        # optional: the field solve on z-slabs with local transforms and
+        # guard cells, slabs = (n_slabs, guard) (see ``local``); the state
+        # is then the real-space E, B
+        self.slab = None
+        if slabs is not None:
+            self.slab = SlabSolver(grid.shape, grid.spacing, grid.dt, self.v_gal, self.stencil,
+                                   slabs[0], slabs[1], c, eps0)
 
     # -- grid sources -----------------------------------------------------
     def deposit_charge(self, x):
@@ -123,7 +131,10 @@ class Simulation:
         if project_transverse:
             E_hat = self._transverse(E_hat)
             B_hat = self._transverse(B_hat)
-        rho_hat = self.to_spectral_source(self.deposit_charge(x))
+        rho0 = self.deposit_charge(x)
+        rho_hat = self.to_spectral_source(rho0)
+        if self.slab is not None:
+            self.slab.start(rho0)
         E_real = tuple(sp.inverse(a) for a in E_hat)
         B_real = tuple(sp.inverse(a) for a in B_hat)
         return State(x=np.array(x, dtype=np.float64), u=np.array(u, dtype=np.float64),
@@ -154,6 +165,12 @@ class Simulation:
         rho_new = self.deposit_charge(x_new)
         J_hat = tuple(self.to_spectral_source(J[a]) for a in range(3))
         rho_new_hat = self.to_spectral_source(rho_new)
+        if self.slab is not None:
+            E, B = self.slab.step(state.E, state.B, J, rho_new)
+            F = pt.gather(list(E) + list(B), x_new, g.shape, g.spacing, g.order)
+            u_new = pt.boris_push(state.u, F[:3].T, F[3:].T, s.q, s.m, g.dt, self.c)
+            return State(x=x_new, u=u_new, E_hat=None, B_hat=None, rho_hat=rho_new_hat,
+                         E=E, B=B, J_hat=J_hat, rho_new_hat=rho_new_hat, step=state.step + 1)
         if self.current_correction:
             J_hat = sp.galilean_current_correction(J_hat, state.rho_hat, rho_new_hat, self.k,
                                                    self.v_gal, g.dt, self.mask)

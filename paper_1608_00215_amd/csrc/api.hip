@@ -60,13 +60,13 @@ int ilog2(int n) {
 // Kernel stages of a step (names: gp_stage_name).
 enum {
   kStZero = 0, kStSort, kStDeposit, kStFused, kStFwdZ, kStFwdY, kStFwdX, kStUpdate, kStInvX,
-  kStInvY, kStInvZ, kStGather, kStBtd, kNStages
+  kStInvY, kStInvZ, kStGather, kStBtd, kStSlab, kStSlabEB, kNStages
 };
 static_assert(kNStages == GP_N_STAGES, "stage count");
 const char *const kStageNames[kNStages] = {
     "zero_sources", "sort",      "deposit",   "fused_push_deposit", "fft_fwd_z", "fft_fwd_y",
     "fft_fwd_x",    "update",    "fft_inv_x", "fft_inv_y",          "fft_inv_z", "gather_push",
-    "btd"};
+    "btd",          "slab_copy", "slab_fft_fwd_eb"};
 
 enum { kReal = 10, kSpec = 11 };
 // real[] slots: 0-2 E, 3-5 B, 6-8 J, 9 rho
@@ -171,6 +171,19 @@ struct gp_ctx {
   std::vector<StageRec> stage_recs;
   Tables tab;
   bool current_correction = false;
+  // slab field solve (gp_set_local_slabs): the slabs' local grids are the
+  // runs of a context of their own, slab s of run r at r * n_slabs + s
+  gp_ctx *slab = nullptr;
+  gp_ctx *timing_parent = nullptr;  // a slab context records its stages there
+  int n_slabs = 0;
+  int guard = 0;
+  int src_mask = kMaskHeld;  // x-pass mask of the sources' forward transform
+  bool no_hold = false;      // the update advances every mode
+  std::vector<void *> slab_allocs;
+  void *slab_copy = nullptr;  // SlabCopy<T>[runs * n_slabs]
+  void *slab_sum = nullptr;   // SlabSum<T>[runs]
+  double *slab_sums = nullptr;
+  int64_t slab_max_cells = 0, slab_max_win = 0, slab_max_owned = 0;
 };
 
 namespace {
@@ -306,21 +319,24 @@ GridPtrs<T> grid_ptrs(const Run &r) {
 
 // Records device events around one stage when timing is on.
 struct Stamp {
-  gp_ctx *c;
+  gp_ctx *c;  // the context whose record list takes the stage
+  hipStream_t stream;
   StageRec rec{};
   bool on;
-  Stamp(gp_ctx *ctx, int stage) : c(ctx), on(ctx->stage_timing) {
+  Stamp(gp_ctx *ctx, int stage)
+      : c(ctx->timing_parent ? ctx->timing_parent : ctx), stream(ctx->stream),
+        on(c->stage_timing) {
     if (!on) return;
     rec.stage = stage;
     if (hipEventCreate(&rec.a) != hipSuccess || hipEventCreate(&rec.b) != hipSuccess) {
       on = false;
       return;
     }
-    (void)hipEventRecord(rec.a, c->stream);
+    (void)hipEventRecord(rec.a, stream);
   }
   ~Stamp() {
     if (!on) return;
-    (void)hipEventRecord(rec.b, c->stream);
+    (void)hipEventRecord(rec.b, stream);
     c->stage_recs.push_back(rec);
   }
 };
@@ -460,6 +476,7 @@ void fill_update_scalars(gp_ctx *c) {
       for (int a = 0; a < 3; ++a) u->vgal[a] = r.g.vgal[a];
       u->dt = r.g.dt;
       u->correct = c->current_correction ? 1 : 0;
+      u->no_hold = c->no_hold ? 1 : 0;
     }
   }
 }
@@ -559,19 +576,19 @@ gp_status upload_tables(gp_ctx *c) {
 // count runs) through a pair of tables.
 template <typename T>
 void fft_forward(gp_ctx *c, int tab_z, int tab_yx, int nf, int pos, int count,
-                 const RunGeom &g) {
+                 const RunGeom &g, int mask = kMaskHeld) {
   const Cx<T> *tw = static_cast<const Cx<T> *>(c->tw);
   launch_r2c_z<T>(fs_tab(c, tab_z, pos), count, nf, g, tw, c->stream);
-  launch_c2c<T>(fs_tab(c, tab_yx, pos), count, nf, g, 1, false, false, tw, c->stream);
-  launch_c2c<T>(fs_tab(c, tab_yx, pos), count, nf, g, 0, false, true, tw, c->stream);
+  launch_c2c<T>(fs_tab(c, tab_yx, pos), count, nf, g, 1, false, kMaskNone, tw, c->stream);
+  launch_c2c<T>(fs_tab(c, tab_yx, pos), count, nf, g, 0, false, mask, tw, c->stream);
 }
 
 // Inverse 3D FFT of E^, B^ into real E, B (via the scratch spectra).
 template <typename T>
 void fft_inverse(gp_ctx *c, int pos, int count, const RunGeom &g) {
   const Cx<T> *tw = static_cast<const Cx<T> *>(c->tw);
-  launch_c2c<T>(fs_tab(c, kTabInvX, pos), count, 6, g, 0, true, false, tw, c->stream);
-  launch_c2c<T>(fs_tab(c, kTabInvY, pos), count, 6, g, 1, true, false, tw, c->stream);
+  launch_c2c<T>(fs_tab(c, kTabInvX, pos), count, 6, g, 0, true, kMaskNone, tw, c->stream);
+  launch_c2c<T>(fs_tab(c, kTabInvY, pos), count, 6, g, 1, true, kMaskNone, tw, c->stream);
   launch_c2r_z<T>(fs_tab(c, kTabInvZ, pos), count, 6, g, tw, c->stream);
 }
 
@@ -605,8 +622,68 @@ void enqueue_sources(gp_ctx *c, int mode) {
 // all runs rotate their rho buffers together
 int rho_parity(const gp_ctx *c) { return c->runs[0].rho_old - 9; }
 
+// rho^n in slot 9 + par for every run of c and of its slab context
+void set_rho_parity(gp_ctx *c, int par) {
+  for (auto &r : c->runs) r.rho_old = 9 + par;
+  if (c->slab)
+    for (auto &r : c->slab->runs) r.rho_old = 9 + par;
+}
+
+template <typename T>
+const SlabCopy<T> *slab_copy_tab(gp_ctx *c) {
+  return static_cast<const SlabCopy<T> *>(c->slab_copy);
+}
+template <typename T>
+const SlabSum<T> *slab_sum_tab(gp_ctx *c) {
+  return static_cast<const SlabSum<T> *>(c->slab_sum);
+}
+
+// Slab solve: the grid sums of J and rho, then the windows of fields
+// f0 .. f0 + nf - 1 into the slabs (J and rho less their means).
+template <typename T>
+void slab_windows(gp_ctx *c, int f0, int nf) {
+  Stamp s(c, kStSlab);
+  launch_zero(c->slab_sums, 4 * c->runs.size() * sizeof(double), c->stream);
+  launch_slab_sums<T>(slab_sum_tab<T>(c), int(c->runs.size()), c->slab_max_cells, c->stream);
+  launch_slab_window<T>(slab_copy_tab<T>(c), int(c->slab->runs.size()), f0, nf,
+                        c->slab_max_win, c->stream);
+}
+
+// Slab solve: rho^n of every slab from the runs' current real rho.
+template <typename T>
+void slab_init_rho(gp_ctx *c) {
+  gp_ctx *sc = c->slab;
+  slab_windows<T>(c, 9, 1);
+  const int par = rho_parity(sc);
+  for (const Class &k : sc->tab.classes)
+    fft_forward<T>(sc, kTabRhoZ0 + par, kTabRhoYX0 + par, 1, k.first, k.count, k.g,
+                   sc->src_mask);
+}
+
+template <typename T>
+void enqueue_fft_fwd(gp_ctx *c);
+
+// Slab solve, forward half: windows of E, B, J, rho, and their transforms on
+// the slabs' local grids (E, B with nothing held, the sources with their
+// Nyquist planes held).
+template <typename T>
+void slab_forward(gp_ctx *c) {
+  gp_ctx *sc = c->slab;
+  slab_windows<T>(c, 0, 10);
+  {
+    Stamp s(c, kStSlabEB);
+    for (const Class &k : sc->tab.classes)
+      fft_forward<T>(sc, kTabEBZ, kTabEBYX, 6, k.first, k.count, k.g, kMaskNone);
+  }
+  enqueue_fft_fwd<T>(sc);
+}
+
 template <typename T>
 void enqueue_fft_fwd(gp_ctx *c) {
+  if (c->slab) {
+    slab_forward<T>(c);
+    return;
+  }
   const Cx<T> *tw = static_cast<const Cx<T> *>(c->tw);
   const int par = rho_parity(c);
   {
@@ -617,19 +694,24 @@ void enqueue_fft_fwd(gp_ctx *c) {
   {
     Stamp s(c, kStFwdY);
     for (const Class &k : c->tab.classes)
-      launch_c2c<T>(fs_tab(c, kTabFwdYX0 + par, k.first), k.count, 4, k.g, 1, false, false, tw,
+      launch_c2c<T>(fs_tab(c, kTabFwdYX0 + par, k.first), k.count, 4, k.g, 1, false, kMaskNone, tw,
                     c->stream);
   }
   {
     Stamp s(c, kStFwdX);
     for (const Class &k : c->tab.classes)
-      launch_c2c<T>(fs_tab(c, kTabFwdYX0 + par, k.first), k.count, 4, k.g, 0, false, true, tw,
+      launch_c2c<T>(fs_tab(c, kTabFwdYX0 + par, k.first), k.count, 4, k.g, 0, false, c->src_mask, tw,
                     c->stream);
   }
 }
 
 template <typename T>
 void enqueue_update(gp_ctx *c) {
+  if (c->slab) {  // the slabs' update; the run's rho roles turn with theirs
+    enqueue_update<T>(c->slab);
+    for (auto &r : c->runs) r.rho_old = r.rho_old == 9 ? 10 : 9;
+    return;
+  }
   Stamp s(c, kStUpdate);
   const int par = rho_parity(c);
   for (const Class &k : c->tab.classes)
@@ -639,17 +721,24 @@ void enqueue_update(gp_ctx *c) {
 
 template <typename T>
 void enqueue_fft_inv(gp_ctx *c) {
+  if (c->slab) {  // the slabs' inverse, then their owned planes into E, B
+    enqueue_fft_inv<T>(c->slab);
+    Stamp s(c, kStSlab);
+    launch_slab_interior<T>(slab_copy_tab<T>(c), int(c->slab->runs.size()), c->slab_max_owned,
+                            c->stream);
+    return;
+  }
   const Cx<T> *tw = static_cast<const Cx<T> *>(c->tw);
   {
     Stamp s(c, kStInvX);
     for (const Class &k : c->tab.classes)
-      launch_c2c<T>(fs_tab(c, kTabInvX, k.first), k.count, 6, k.g, 0, true, false, tw,
+      launch_c2c<T>(fs_tab(c, kTabInvX, k.first), k.count, 6, k.g, 0, true, kMaskNone, tw,
                     c->stream);
   }
   {
     Stamp s(c, kStInvY);
     for (const Class &k : c->tab.classes)
-      launch_c2c<T>(fs_tab(c, kTabInvY, k.first), k.count, 6, k.g, 1, true, false, tw,
+      launch_c2c<T>(fs_tab(c, kTabInvY, k.first), k.count, 6, k.g, 1, true, kMaskNone, tw,
                     c->stream);
   }
   {
@@ -882,17 +971,68 @@ gp_status build_graphs(gp_ctx *c) {
   for (size_t i = 0; i < c->runs.size(); ++i) saved[i] = c->runs[i].rho_old;
   gp_status st = capture(c, &c->g_first, body_first<T>);
   for (int k = 0; k < 2 && st == GP_OK; ++k) {
-    for (auto &r : c->runs) r.rho_old = 9 + k;
+    set_rho_parity(c, k);
     st = capture(c, &c->g_mid[k], body_mid<T>);
     if (st == GP_OK) {
-      for (auto &r : c->runs) r.rho_old = 9 + k;
+      set_rho_parity(c, k);
       st = capture(c, &c->g_last[k], body_last<T>);
     }
   }
   for (size_t i = 0; i < c->runs.size(); ++i) c->runs[i].rho_old = saved[i];
+  if (c->slab) set_rho_parity(c->slab, saved[0] - 9);
   c->stage_timing = timing;
   if (st != GP_OK) drop_graphs(c);
   return st;
+}
+
+// Device tables of the slab solve: one SlabSum per run, one SlabCopy per
+// slab (run-major), and the sums they share.
+template <typename T>
+gp_status build_slab_tables(gp_ctx *c) {
+  const int n = int(c->runs.size());
+  const int S = c->n_slabs;
+  std::vector<SlabSum<T>> sums(n);
+  std::vector<SlabCopy<T>> jobs(size_t(n) * S);
+  void *d = nullptr;
+  GP_TRY(dev_alloc(c->slab_allocs, size_t(4 * n) * sizeof(double), &d));
+  c->slab_sums = static_cast<double *>(d);
+  c->slab_max_cells = c->slab_max_win = c->slab_max_owned = 0;
+  for (int i = 0; i < n; ++i) {
+    const Run &r = c->runs[i];
+    for (int q = 0; q < 4; ++q) sums[i].src[q] = R<T>(r, 6 + q);
+    sums[i].out = c->slab_sums + 4 * i;
+    sums[i].ncell = r.g.ncell;
+    const int ns = r.g.nz / S;
+    const int nw = ns + 2 * c->guard;
+    const int nxy = r.g.nx * r.g.ny;
+    c->slab_max_cells = std::max(c->slab_max_cells, r.g.ncell);
+    c->slab_max_win = std::max(c->slab_max_win, int64_t(nxy) * nw);
+    c->slab_max_owned = std::max(c->slab_max_owned, int64_t(nxy) * ns);
+    for (int sl = 0; sl < S; ++sl) {
+      const Run &w = c->slab->runs[size_t(i) * S + sl];
+      SlabCopy<T> &jb = jobs[size_t(i) * S + sl];
+      for (int f = 0; f < 10; ++f) {
+        jb.glob[f] = R<T>(r, f);
+        jb.win[f] = R<T>(w, f);
+      }
+      jb.sums = c->slab_sums + 4 * i;
+      jb.nxy = nxy;
+      jb.nz = r.g.nz;
+      jb.nw = nw;
+      jb.first = sl * ns - c->guard;
+      jb.ns = ns;
+      jb.guard = c->guard;
+      jb.inv_ncell = 1.0 / double(r.g.ncell);
+    }
+  }
+  GP_TRY(dev_alloc(c->slab_allocs, sums.size() * sizeof(SlabSum<T>), &c->slab_sum));
+  GP_TRY(dev_alloc(c->slab_allocs, jobs.size() * sizeof(SlabCopy<T>), &c->slab_copy));
+  GP_HIP(hipMemcpyAsync(c->slab_sum, sums.data(), sums.size() * sizeof(SlabSum<T>),
+                        hipMemcpyHostToDevice, c->stream));
+  GP_HIP(hipMemcpyAsync(c->slab_copy, jobs.data(), jobs.size() * sizeof(SlabCopy<T>),
+                        hipMemcpyHostToDevice, c->stream));
+  GP_HIP(hipStreamSynchronize(c->stream));
+  return GP_OK;
 }
 
 void mark_step_done(gp_ctx *c) {
@@ -962,6 +1102,8 @@ gp_status gp_destroy(gp_ctx *c) {
     (void)hipEventDestroy(rec.b);
   }
   for (auto &r : c->runs) free_sort(r);
+  if (c->slab) gp_destroy(c->slab);
+  for (void *p : c->slab_allocs) (void)hipFree(p);
   for (void *p : c->allocs) (void)hipFree(p);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
@@ -1126,12 +1268,17 @@ gp_status gp_set_v_gal(gp_ctx *c, int run, double vx, double vy, double vz) {
     }
     GP_TRY(upload_tables(c));
   }
+  if (c->slab)
+    for (int s = 0; s < c->n_slabs; ++s)
+      GP_TRY(gp_set_v_gal(c->slab, run * c->n_slabs + s, vx, vy, vz));
   return GP_OK;
 }
 
 gp_status gp_set_current_correction(gp_ctx *c, int enable) {
   GP_TRY(check_ctx(c));
   if (enable != 0 && enable != 1) return fail(GP_ERR_ARG, "enable must be 0 or 1");
+  if (enable && c->slab)
+    return fail(GP_ERR_STATE, "the slab solve does not take the current correction");
   c->current_correction = enable != 0;
   drop_graphs(c);
   if (c->precision == GP_FP64)
@@ -1139,6 +1286,109 @@ gp_status gp_set_current_correction(gp_ctx *c, int enable) {
   else
     fill_update_scalars<float>(c);
   GP_TRY(upload_tables(c));
+  return GP_OK;
+}
+
+gp_status gp_set_local_slabs(gp_ctx *c, int n_slabs, int guard) {
+  GP_TRY(check_ctx(c));
+  if (c->timing_parent) return fail(GP_ERR_ARG, "a slab context cannot be split again");
+  if (n_slabs < 0 || guard < 0) return fail(GP_ERR_ARG, "n_slabs and guard must be >= 0");
+  if (n_slabs > 0 && c->current_correction)
+    return fail(GP_ERR_STATE, "the slab solve does not take the current correction");
+  for (auto &r : c->runs)
+    if (!r.eb_real_ready)
+      return fail(GP_ERR_STATE, "the real E, B must be current (run gp_fft_inv first)");
+  if (n_slabs > 0) {
+    for (size_t i = 0; i < c->runs.size(); ++i) {
+      const Run &r = c->runs[i];
+      const std::string who = "run " + std::to_string(i) + ": ";
+      if (r.stencil[2] == 0)
+        return fail(GP_ERR_ARG, who + "local transforms need a finite-order stencil along z");
+      if (r.g.nz % n_slabs != 0)
+        return fail(GP_ERR_ARG, who + "nz must be a multiple of n_slabs");
+      const int nw = r.g.nz / n_slabs + 2 * guard;
+      if (nw < 8 || nw > r.g.nz || (nw & (nw - 1)) != 0)
+        return fail(GP_ERR_ARG, who + "nz / n_slabs + 2 guard must be a power of two in "
+                                      "[8, nz]");
+    }
+  }
+  drop_graphs(c);
+  GP_HIP(hipStreamSynchronize(c->stream));
+  if (c->slab) {  // back to the global solve first
+    gp_destroy(c->slab);
+    c->slab = nullptr;
+    for (void *p : c->slab_allocs) (void)hipFree(p);
+    c->slab_allocs.clear();
+    c->slab_copy = c->slab_sum = nullptr;
+    c->slab_sums = nullptr;
+    c->n_slabs = c->guard = 0;
+    // the global solve's state from the real E, B and rho
+    GP_TRY(dispatch(c, [&](auto t) {
+      using T = decltype(t);
+      const int par = rho_parity(c);
+      for (const Class &k : c->tab.classes) {
+        fft_forward<T>(c, kTabEBZ, kTabEBYX, 6, k.first, k.count, k.g);
+        fft_forward<T>(c, kTabRhoZ0 + par, kTabRhoYX0 + par, 1, k.first, k.count, k.g);
+      }
+    }));
+    GP_HIP(hipStreamSynchronize(c->stream));
+  }
+  for (auto &r : c->runs) {
+    r.src_real_ready = false;
+    r.src_spec_ready = false;
+  }
+  if (n_slabs == 0) return GP_OK;
+  std::vector<gp_grid_desc> descs;
+  for (const Run &r : c->runs)
+    for (int s = 0; s < n_slabs; ++s) {
+      gp_grid_desc d{};
+      d.nx = r.g.nx;
+      d.ny = r.g.ny;
+      d.nz = r.g.nz / n_slabs + 2 * guard;
+      d.dx = r.g.dx;
+      d.dy = r.g.dy;
+      d.dz = r.g.dz;
+      d.dt = r.g.dt;
+      d.shape_order = c->order;
+      d.precision = c->precision;
+      for (int a = 0; a < 3; ++a) d.stencil[a] = r.stencil[a];
+      descs.push_back(d);
+    }
+  gp_ctx *sc = nullptr;
+  GP_TRY(gp_init_grid(descs.data(), int(descs.size()), c->stream, &sc));
+  sc->timing_parent = c;
+  sc->src_mask = kMaskNyquist;
+  sc->no_hold = true;
+  c->slab = sc;
+  c->n_slabs = n_slabs;
+  c->guard = guard;
+  auto undo = [&](gp_status st) {
+    std::string keep = g_err;
+    gp_destroy(sc);
+    c->slab = nullptr;
+    for (void *p : c->slab_allocs) (void)hipFree(p);
+    c->slab_allocs.clear();
+    c->n_slabs = c->guard = 0;
+    g_err = keep;
+    return st;
+  };
+  for (size_t i = 0; i < c->runs.size(); ++i)
+    for (int s = 0; s < n_slabs; ++s) {
+      const double *v = c->runs[i].g.vgal;
+      gp_status st = gp_set_v_gal(sc, int(i) * n_slabs + s, v[0], v[1], v[2]);
+      if (st) return undo(st);
+    }
+  {
+    gp_status st = c->precision == GP_FP64 ? build_slab_tables<double>(c)
+                                           : build_slab_tables<float>(c);
+    if (st) return undo(st);
+  }
+  set_rho_parity(c, rho_parity(c));
+  gp_status st = dispatch(c, [&](auto t) {
+    using T = decltype(t);
+    slab_init_rho<T>(c);
+  });
+  if (st) return undo(st);
   return GP_OK;
 }
 
@@ -1252,6 +1502,7 @@ gp_status gp_bind_particles(gp_ctx *c, const gp_particles *p) {
     const int par = rho_parity(c);
     for (const Class &k : c->tab.classes)
       fft_forward<T>(c, kTabRhoZ0 + par, kTabRhoYX0 + par, 1, k.first, k.count, k.g);
+    if (c->slab) slab_init_rho<T>(c);
   }));
   for (auto &r : c->runs) {
     r.src_real_ready = false;
@@ -1273,8 +1524,11 @@ gp_status gp_deposit(gp_ctx *c, const gp_particles *p) {
 
 gp_status gp_fft_fwd(gp_ctx *c) {
   GP_TRY(check_ctx(c));
-  for (auto &r : c->runs)
+  for (auto &r : c->runs) {
     if (!r.src_real_ready) return fail(GP_ERR_STATE, "gp_fft_fwd needs a deposit first");
+    if (c->slab && !r.eb_real_ready)
+      return fail(GP_ERR_STATE, "the slab solve transforms the real E, B: run gp_fft_inv first");
+  }
   GP_TRY(dispatch(c, [&](auto t) {
     using T = decltype(t);
     enqueue_fft_fwd<T>(c);
@@ -1384,7 +1638,7 @@ gp_status gp_step_graph(gp_ctx *c, const gp_particles *p, int nsteps) {
   par ^= 1;
   GP_HIP(hipEventRecord(c->ev1, c->stream));
   c->timed = true;
-  for (auto &r : c->runs) r.rho_old = 9 + par;
+  set_rho_parity(c, par);
   mark_step_done(c);
   return GP_OK;
 }

@@ -270,7 +270,8 @@ struct StridedGeom {
   int col_tiles;        // ceil(ncols / CW)
   int64_t row_stride;   // distance between consecutive line elements
   int64_t outer_stride; // distance between consecutive outer indices
-  // held-mode mask (forward x pass only): row = ix, outer = iy, col = iz
+  // held-mode mask (forward x pass only; kMask*): row = ix, outer = iy,
+  // col = iz
   int mask;
   int half_row, half_outer, half_col;
 };
@@ -309,7 +310,7 @@ __global__ __launch_bounds__(kThreads) void k_c2c_strided(const FieldSet *__rest
     Cx<T> v = lds[j * S + c];
     if (sg.mask) {
       const bool held = j == sg.half_row || outer == sg.half_outer || col == sg.half_col ||
-                        (j == 0 && outer == 0 && col == 0);
+                        (sg.mask == kMaskHeld && j == 0 && outer == 0 && col == 0);
       if (held) v = cx(T(0), T(0));
     }
     out[base + j * sg.row_stride + c] = v;
@@ -391,12 +392,12 @@ void launch_c2r_z(const FieldSet *sets, int nsets, int nf, const RunGeom &g, con
 
 template <typename T>
 void launch_c2c(const FieldSet *sets, int nsets, int nf, const RunGeom &g, int axis,
-                bool inverse, bool mask_held, const Cx<T> *tw, hipStream_t s) {
+                bool inverse, int mask, const Cx<T> *tw, hipStream_t s) {
   constexpr int CW = TileCols<T>::value;
   StridedGeom sg;
   sg.ncols = g.nzh;
   sg.col_tiles = (g.nzh + CW - 1) / CW;
-  sg.mask = mask_held ? 1 : 0;
+  sg.mask = mask;
   int logl, n_outer;
   if (axis == 1) {  // y lines: outer = x
     sg.row_stride = g.nzh;
@@ -481,9 +482,9 @@ template void launch_c2r_z<float>(const FieldSet *, int, int, const RunGeom &, c
                                   hipStream_t);
 template void launch_c2r_z<double>(const FieldSet *, int, int, const RunGeom &,
                                    const Cx<double> *, hipStream_t);
-template void launch_c2c<float>(const FieldSet *, int, int, const RunGeom &, int, bool, bool,
+template void launch_c2c<float>(const FieldSet *, int, int, const RunGeom &, int, bool, int,
                                 const Cx<float> *, hipStream_t);
-template void launch_c2c<double>(const FieldSet *, int, int, const RunGeom &, int, bool, bool,
+template void launch_c2c<double>(const FieldSet *, int, int, const RunGeom &, int, bool, int,
                                  const Cx<double> *, hipStream_t);
 
 }  // namespace galpic

@@ -30,10 +30,12 @@ template <typename T>
 void launch_r2c_z(const FieldSet *sets, int nsets, int nf, const RunGeom &g, const Cx<T> *tw,
                   hipStream_t s);
 // Complex transform along y (axis 1) or x (axis 0) of nf half spectra.
-// mask_held: write zero on the k = 0 mode and every Nyquist plane.
+// mask: kMaskNone; kMaskHeld writes zero on the k = 0 mode and every Nyquist
+// plane; kMaskNyquist on the Nyquist planes only.
+enum { kMaskNone = 0, kMaskHeld = 1, kMaskNyquist = 2 };
 template <typename T>
 void launch_c2c(const FieldSet *sets, int nsets, int nf, const RunGeom &g, int axis,
-                bool inverse, bool mask_held, const Cx<T> *tw, hipStream_t s);
+                bool inverse, int mask, const Cx<T> *tw, hipStream_t s);
 // Inverse complex-to-real transform along z with the 1/(nx ny nz) scale.
 template <typename T>
 void launch_c2r_z(const FieldSet *sets, int nsets, int nf, const RunGeom &g, const Cx<T> *tw,
@@ -70,7 +72,9 @@ struct UpdatePtrs {
   double vgal[3];  // the run's v_gal and dt, for the current correction
   double dt;
   int correct;     // nonzero: correct J before the update (see update.hip)
-  int pad;
+  int no_hold;     // nonzero: advance every mode (the slab solve's local
+                   // grids); zero: k = 0 and the Nyquist planes are written
+                   // as zero
 };
 // The update of the nsets runs (all of grid shape g) of the device table.
 template <typename T>
@@ -123,6 +127,37 @@ void launch_btd_particles(const BtdJob<T> *jobs, int njobs, int64_t max_n, hipSt
 template <typename T>
 void launch_sum_squares(const T *a, const T *b, const T *c, int64_t n, double *out,
                         hipStream_t s);
+
+// ---- slab field solve (slab.hip) ------------------------------------------
+// Sums over the grid of J_x, J_y, J_z and rho of one run.
+template <typename T>
+struct SlabSum {
+  const T *src[4];
+  double *out;     // 4 sums, cleared by the caller
+  int64_t ncell;
+};
+// One slab's window of a run's real grids: window plane j of slab run
+// (nx x ny x nw) is global plane (first + j) mod nz; owned planes are
+// window planes guard .. guard + ns - 1.
+template <typename T>
+struct SlabCopy {
+  T *glob[10];          // the run's real E, B, J, rho
+  T *win[10];           // the slab run's real arrays
+  const double *sums;   // the run's SlabSum output (J, rho), mean = sum / ncell
+  int nxy, nz, nw, first, ns, guard;
+  double inv_ncell;
+};
+template <typename T>
+void launch_slab_sums(const SlabSum<T> *sums, int nruns, int64_t max_cells, hipStream_t s);
+// Windows of fields f0 .. f0 + nf - 1 (0-5 E, B; 6-8 J; 9 rho) into every
+// slab of the table; J and rho lose their means.
+template <typename T>
+void launch_slab_window(const SlabCopy<T> *jobs, int njobs, int f0, int nf, int64_t max_win,
+                        hipStream_t s);
+// Owned planes of the slabs' E, B back into the runs' E, B.
+template <typename T>
+void launch_slab_interior(const SlabCopy<T> *jobs, int njobs, int64_t max_owned,
+                          hipStream_t s);
 
 // ---- particles (particles.hip) ----------------------------------------------
 template <typename T>

@@ -9,7 +9,9 @@
 //
 // k comes from the run's per-axis wavenumber tables (the exact k, or the
 // symbol [k] of a finite-order stencil).  Modes on a Nyquist plane and
-// k = 0 are written as zero.  HBM-bound: 17 complex values per mode move
+// k = 0 are written as zero, except in the slab solve's local grids, which
+// advance every mode (at [k] = 0 the coefficients' limits give E' = E - dt J,
+// B' = B).  HBM-bound: 17 complex values per mode move
 // (136 B in float, 272 B in double) plus the 6 coefficients.
 #include "kernels.hpp"
 
@@ -45,8 +47,8 @@ __global__ __launch_bounds__(256) void k_update(RunGeom g, const UpdatePtrs<T> *
   const int iz = int(idx % g.nzh);
   const int iy = int((idx / g.nzh) % g.ny);
   const int ix = int(idx / (int64_t(g.nzh) * g.ny));
-  const bool held = ix == g.nx / 2 || iy == g.ny / 2 || iz == g.nz / 2 ||
-                    (ix == 0 && iy == 0 && iz == 0);
+  const bool held = !p.no_hold && (ix == g.nx / 2 || iy == g.ny / 2 || iz == g.nz / 2 ||
+                                    (ix == 0 && iy == 0 && iz == 0));
   if (held) {
     const Cx<T> z = cx(T(0), T(0));
 #pragma unroll

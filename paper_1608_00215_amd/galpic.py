@@ -25,7 +25,8 @@ FIELDS = ["EX", "EY", "EZ", "BX", "BY", "BZ", "JX", "JY", "JZ", "RHO",
 FIELD = {name: i for i, name in enumerate(FIELDS)}
 
 #: every symbol the header declares
-EXPORTS = ["gp_init_grid", "gp_set_v_gal", "gp_set_current_correction", "gp_bind_particles", "gp_deposit", "gp_fft_fwd",
+EXPORTS = ["gp_init_grid", "gp_set_v_gal", "gp_set_current_correction", "gp_set_local_slabs",
+           "gp_bind_particles", "gp_deposit", "gp_fft_fwd",
            "gp_galilean_psatd_update", "gp_fft_inv", "gp_gather_push",
            "gp_gather_push_deposit", "gp_step",
            "gp_step_graph", "gp_set_fields", "gp_half_push", "gp_read_field",
@@ -45,7 +46,7 @@ QC_FIELDS = ["ER", "ET", "EZ", "BR", "BT", "BZ", "JR", "JT", "JZ", "RHO",
 QC_FIELD = {name: i for i, name in enumerate(QC_FIELDS)}
 QC_STAGES = ["z_fwd", "hankel_fwd", "update", "hankel_bwd", "z_inv", "deposit",
              "gather_push"]
-GP_N_STAGES = 13
+GP_N_STAGES = 15
 
 
 class GridDesc(ctypes.Structure):
@@ -102,6 +103,7 @@ def load(path=LIB_PATH):
         "gp_init_grid": [ctypes.POINTER(GridDesc), i32, vp, ctypes.POINTER(vp)],
         "gp_set_v_gal": [vp, i32, dbl, dbl, dbl],
         "gp_set_current_correction": [vp, i32],
+        "gp_set_local_slabs": [vp, i32, i32],
         "gp_bind_particles": [vp, vp],
         "gp_deposit": [vp, vp],
         "gp_fft_fwd": [vp],
@@ -292,6 +294,11 @@ class Context:
 
     def set_current_correction(self, enable):
         self._call("gp_set_current_correction", 1 if enable else 0)
+
+    def set_local_slabs(self, n_slabs, guard):
+        """Field solve on z-slabs with local transforms and guard cells
+        (gp_set_local_slabs); n_slabs = 0 returns to the global solve."""
+        self._call("gp_set_local_slabs", int(n_slabs), int(guard))
 
     def bind_particles(self, parts):
         import torch

@@ -154,3 +154,22 @@ def test_galilean_phase_with_nyquist_is_caught(monkeypatch):
     monkeypatch.setattr(co, "max_galilean_phase", wrong)
     _fails(tc.test_max_galilean_phase_hand_value)
     _fails(tc.test_max_galilean_phase_brute_force)
+
+
+def test_slab_window_off_by_one_is_caught(monkeypatch):
+    from oracle import local as olc
+    from tests import test_oracle_local as tl
+
+    orig = olc.slab_planes
+    monkeypatch.setattr(olc, "slab_planes",
+                        lambda nz, n, g: [np.mod(p + 1, nz) for p in orig(nz, n, g)])
+    _fails(tl.test_full_window_equals_global_solve, 4, 12)
+
+
+def test_slab_sources_keeping_their_mean_is_caught(monkeypatch):
+    from oracle import local as olc
+    from tests import test_oracle_local as tl
+
+    orig = olc.SlabSolver._source
+    monkeypatch.setattr(olc.SlabSolver, "_source", lambda self, f, s, mean: orig(self, f, s, 0.0))
+    _fails(tl.test_full_window_equals_global_solve, 2, 8)
