@@ -58,6 +58,10 @@ def stage_bytes(cfg, precision_fp64):
         "fft_inv_z": 6 * (nk * cb + nc * rb),
         "gather_push": npart * (pos + 3 * rb + 3 * rb) + 6 * nc * rb,
         "btd": 0,                               # a few planes per snapshot and step
+        # the slab solve: windows and owned planes (two stamps of unequal
+        # size per step) and the windows' E, B transforms; reported as times
+        "slab_copy": 0,
+        "slab_fft_fwd_eb": 0,
     }
 
 
@@ -92,7 +96,7 @@ def btd_snapshot_times(c, nsnap, t_mid):
 
 
 def run_gpu(cfg, precision, steps, warmup, inputs, tile=(0, 0, 0), resort_div=0, btd=0,
-            btd_cap=0, correction=False, late_at=0, late_n=20):
+            btd_cap=0, correction=False, late_at=0, late_n=20, slabs=None):
     """Time one run (cfg, inputs) or a batch of runs (lists of both)."""
     import torch
 
@@ -118,6 +122,8 @@ def run_gpu(cfg, precision, steps, warmup, inputs, tile=(0, 0, 0), resort_div=0,
             ctx.set_fields(r, lf[0], lf[1], project_transverse=True)
     if any(c.laser is not None for c in cfgs):
         ctx.half_push()
+    if slabs is not None:
+        ctx.set_local_slabs(*slabs)
     if btd > 0:
         # lab-frame snapshots of the first run, recorded on the fly; their
         # planes are reached in the middle of the timed steps
@@ -699,6 +705,11 @@ def main():
                          "axis (0: spectral, the default)")
     ap.add_argument("--current-correction", action="store_true",
                     help="field solve with the Galilean current correction")
+    ap.add_argument("--slabs", type=int, default=0, metavar="S",
+                    help="field solve on S z-slabs with local transforms and guard cells "
+                         "(needs --stencil; see --guard)")
+    ap.add_argument("--guard", type=int, default=0, metavar="G",
+                    help="with --slabs: guard planes on each side of a slab")
     ap.add_argument("--qc", default=None, choices=sorted(QC_WORKLOADS),
                     help="instead, time the quasi-cylindrical (azimuthal-mode) field solve "
                          "on the named grid and print its own line")
@@ -766,15 +777,16 @@ def main():
                   "tuning_s": round(time.perf_counter() - t0, 1),
                   "candidates_ms_per_step": {f"{k[0][0]}x{k[0][1]}x{k[0][2]}/n{k[1]}": round(v, 4)
                                              for k, v in res.items()}}
+    slabs = (args.slabs, args.guard) if args.slabs > 0 else None
     mixed = run_gpu(run_arg, gp.GP_MIXED, args.steps, args.warmup, inputs, btd=args.btd,
                     btd_cap=args.btd_particles, correction=args.current_correction,
-                    late_at=args.late_at, **setting)
+                    late_at=args.late_at, slabs=slabs, **setting)
     print(f"[bench] mixed: {mixed['wall_s'] / args.steps * 1e3:.3f} ms/step", file=sys.stderr,
           flush=True)
     fp64 = None
     if not args.no_fp64:
         fp64 = run_gpu(run_arg, gp.GP_FP64, args.steps, args.warmup, inputs,
-                       correction=args.current_correction, late_at=args.late_at)
+                       correction=args.current_correction, late_at=args.late_at, slabs=slabs)
         print(f"[bench] fp64: {fp64['wall_s'] / args.steps * 1e3:.3f} ms/step",
               file=sys.stderr, flush=True)
     del inputs
@@ -822,6 +834,7 @@ def main():
             "precision": "mixed",
             "stencil": list(cfg.stencil) if not isinstance(cfg, BatchView) else None,
             "current_correction": args.current_correction,
+            "slabs": None if slabs is None else {"n_slabs": slabs[0], "guard": slabs[1]},
         },
         "grid_updates_per_s": cfg.n_cells * args.steps / mixed["wall_s"],
         "graph_ms_per_step": mixed["graph_ms_per_step"],
