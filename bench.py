@@ -438,7 +438,7 @@ def run_qc(name, precision, steps, warmup):
 
 
 def qc_column_inputs(w):
-    """Seeded electron column: 8 particles per (r, z) cell inside rp, r drawn
+    """Seeded electron column: w["ppc"] particles per (r, z) cell inside rp, r drawn
     with density proportional to r, angle and z uniform; cold drift at
     gamma along -z.  Returns x, u (n, 3) and the weight of density 1."""
     rng = np.random.Generator(np.random.PCG64(7002))
