@@ -397,6 +397,21 @@ gp_status gp_field_ptr(gp_ctx *ctx, int run, int which, void **dev_ptr);
  * real fields, reduced in double on the device (synchronising). */
 gp_status gp_field_energy(gp_ctx *ctx, int run, double *we, double *wb);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * quantity of gp_field_energy, out[0] = W_E, out[1] = W_B of one run's real
+ * E, B, reduced in double, written to out (device memory, 2 doubles, the
+ * caller's) asynchronously on the context's stream (no synchronisation, so
+ * it can be captured in a graph).  It allocates nothing: the per-workgroup
+ * partial sums go to a file-scope device array of the library (8192 slots
+ * of two doubles, 128 KiB per device, held until the process ends); every
+ * slot it reads is written by the same call, so nothing needs clearing, and
+ * the result does not depend on scheduling.  All calls on one device share
+ * that array: calls that may overlap on one device (other streams, other
+ * threads) race and must be ordered by the caller.  Errors: GP_ERR_ARG (bad
+ * run, NULL out, a run of more than 2^26 = 67,108,864 cells). */
+gp_status gp_field_energy_noalloc(gp_ctx *ctx, int run, double *out);
+
 /* Device time of the last gp_step_graph replay in milliseconds (HIP
  * events on the context stream; synchronising). */
 gp_status gp_last_graph_ms(gp_ctx *ctx, double *ms);

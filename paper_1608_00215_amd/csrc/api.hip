@@ -184,6 +184,7 @@ struct gp_ctx {
   void *slab_sum = nullptr;   // SlabSum<T>[runs]
   double *slab_sums = nullptr;
   int64_t slab_max_cells = 0, slab_max_win = 0, slab_max_owned = 0;
+  int device = 0;  // the device current at gp_init_grid
 };
 
 namespace {
@@ -1140,6 +1141,14 @@ gp_status gp_init_grid(const gp_grid_desc *runs, int n_runs, void *hip_stream, g
   }
   if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess)
     return bail(fail(GP_ERR_HIP, "hipEventCreate failed"));
+  if (hipGetDevice(&c->device) != hipSuccess)
+    return bail(fail(GP_ERR_HIP, "hipGetDevice failed"));
+  {
+    const hipError_t e = noalloc_prepare();
+    if (e != hipSuccess)
+      return bail(fail(GP_ERR_HIP, std::string("hipGetSymbolAddress of the energy scratch: ") +
+                                       hipGetErrorString(e)));
+  }
   c->runs.resize(n_runs);
   for (int i = 0; i < n_runs; ++i) {
     const gp_grid_desc &d = runs[i];
@@ -1751,6 +1760,25 @@ gp_status gp_field_energy(gp_ctx *c, int run, double *we, double *wb) {
   *we = 0.5 * dv * h[0];
   *wb = 0.5 * dv * h[1];
   return GP_OK;
+}
+
+gp_status gp_field_energy_noalloc(gp_ctx *c, int run, double *out) {
+  GP_TRY(check_run(c, run));
+  if (!out) return fail(GP_ERR_ARG, "out is NULL");
+  const Run &r = c->runs[run];
+  if (r.g.ncell > noalloc_max_cells())
+    return fail(GP_ERR_ARG, "gp_field_energy_noalloc takes at most " +
+                                std::to_string(noalloc_max_cells()) + " cells; the run has " +
+                                std::to_string(r.g.ncell));
+  double *slots = noalloc_scratch(c->device);
+  if (!slots) return fail(GP_ERR_STATE, "no energy scratch on the context's device");
+  const double dv = r.g.dx * r.g.dy * r.g.dz;
+  return dispatch(c, [&](auto t) {
+    using T = decltype(t);
+    const T *E[3] = {R<T>(r, 0), R<T>(r, 1), R<T>(r, 2)};
+    const T *B[3] = {R<T>(r, 3), R<T>(r, 4), R<T>(r, 5)};
+    launch_energy_noalloc<T>(E, B, r.g.ncell, dv, slots, out, c->stream);
+  });
 }
 
 }  // extern "C"

@@ -159,6 +159,18 @@ template <typename T>
 void launch_slab_interior(const SlabCopy<T> *jobs, int njobs, int64_t max_owned,
                           hipStream_t s);
 
+// ---- field energy without allocation (noalloc.hip) ---------------------------
+// Look up, once per device (the current one), the device address of the
+// file-scope array the no-allocation entry point uses; cells it can take.
+hipError_t noalloc_prepare();
+double *noalloc_scratch(int device);
+int64_t noalloc_max_cells();
+// W_E, W_B (times dv / 2) of one run's real E, B into out[0..1] (device),
+// through slots (the array above), on stream s; nothing allocated.
+template <typename T>
+void launch_energy_noalloc(const T *const E[3], const T *const B[3], int64_t ncell, double dv,
+                           double *slots, double *out, hipStream_t s);
+
 // ---- particles (particles.hip) ----------------------------------------------
 template <typename T>
 struct GridPtrs {

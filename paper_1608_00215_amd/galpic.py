@@ -30,7 +30,7 @@ EXPORTS = ["gp_init_grid", "gp_set_v_gal", "gp_set_current_correction", "gp_set_
            "gp_galilean_psatd_update", "gp_fft_inv", "gp_gather_push",
            "gp_gather_push_deposit", "gp_step",
            "gp_step_graph", "gp_set_fields", "gp_half_push", "gp_read_field",
-           "gp_write_field", "gp_field_ptr", "gp_field_energy", "gp_last_graph_ms", "gp_synchronize",
+           "gp_write_field", "gp_field_ptr", "gp_field_energy", "gp_field_energy_noalloc", "gp_last_graph_ms", "gp_synchronize",
            "gp_stage_timing", "gp_stage_times", "gp_stage_name", "gp_sort_count",
            "gp_run", "gp_destroy", "gp_last_error", "gp_btd_configure", "gp_btd_record",
            "gp_btd_particles", "gp_qc_init", "gp_qc_set_v_gal", "gp_qc_write", "gp_qc_read",
@@ -119,6 +119,7 @@ def load(path=LIB_PATH):
         "gp_write_field": [vp, i32, i32, vp],
         "gp_field_ptr": [vp, i32, i32, ctypes.POINTER(vp)],
         "gp_field_energy": [vp, i32, ctypes.POINTER(dbl), ctypes.POINTER(dbl)],
+        "gp_field_energy_noalloc": [vp, i32, vp],
         "gp_last_graph_ms": [vp, ctypes.POINTER(dbl)],
         "gp_synchronize": [vp],
         "gp_stage_timing": [vp, i32],
@@ -480,6 +481,11 @@ class Context:
         t = torch.as_tensor(_Iface(), device="cuda")
         assert t.element_size() == elem and t.dtype == tdt
         return t.view(shape)
+
+    def field_energy_noalloc(self, run, out_ptr):
+        """gp_field_energy_noalloc: W_E, W_B into the device buffer at
+        out_ptr (2 doubles), asynchronously, allocating nothing."""
+        self._call("gp_field_energy_noalloc", int(run), out_ptr)
 
     def field_energy(self, run=0):
         we, wb = ctypes.c_double(), ctypes.c_double()
