@@ -62,6 +62,11 @@ def stage_bytes(cfg, precision_fp64):
         # size per step) and the windows' E, B transforms; reported as times
         "slab_copy": 0,
         "slab_fft_fwd_eb": 0,
+        # region buffer (flush 2): every tile's region of J, rho read once
+        # (8^3 tiles, region (8 + shape width - 1 + 2)^3), J and rho read
+        # and written
+        "region_reduce": (nc // 512) * 4 * (8 + (3 if cfg.order == 3 else 1) + 2) ** 3 * rb
+        + 8 * nc * rb,
     }
 
 
@@ -96,7 +101,7 @@ def btd_snapshot_times(c, nsnap, t_mid):
 
 
 def run_gpu(cfg, precision, steps, warmup, inputs, tile=(0, 0, 0), resort_div=0, btd=0,
-            btd_cap=0, correction=False, late_at=0, late_n=20, slabs=None):
+            btd_cap=0, correction=False, late_at=0, late_n=20, slabs=None, flush=0):
     """Time one run (cfg, inputs) or a batch of runs (lists of both)."""
     import torch
 
@@ -107,7 +112,7 @@ def run_gpu(cfg, precision, steps, warmup, inputs, tile=(0, 0, 0), resort_div=0,
     inps = inputs if isinstance(inputs, list) else [inputs]
     grids = [gp.grid_from_config(c, precision,
                                  tile=tuple(min(tile[a], c.shape[a]) for a in range(3)),
-                                 resort_div=resort_div) for c in cfgs]
+                                 resort_div=resort_div, flush=flush) for c in cfgs]
     ctx = gp.Context(grids)
     for r, c in enumerate(cfgs):
         ctx.set_v_gal(r, c.v_gal())
@@ -710,6 +715,9 @@ def main():
                          "(needs --stencil; see --guard)")
     ap.add_argument("--guard", type=int, default=0, metavar="G",
                     help="with --slabs: guard planes on each side of a slab")
+    ap.add_argument("--flush", type=int, default=0, choices=(0, 1, 2),
+                    help="how deposition tiles add their regions: 1 (and 0, the default) "
+                         "atomics, 2 region buffer and per-node sum")
     ap.add_argument("--qc", default=None, choices=sorted(QC_WORKLOADS),
                     help="instead, time the quasi-cylindrical (azimuthal-mode) field solve "
                          "on the named grid and print its own line")
@@ -780,13 +788,14 @@ def main():
     slabs = (args.slabs, args.guard) if args.slabs > 0 else None
     mixed = run_gpu(run_arg, gp.GP_MIXED, args.steps, args.warmup, inputs, btd=args.btd,
                     btd_cap=args.btd_particles, correction=args.current_correction,
-                    late_at=args.late_at, slabs=slabs, **setting)
+                    late_at=args.late_at, slabs=slabs, flush=args.flush, **setting)
     print(f"[bench] mixed: {mixed['wall_s'] / args.steps * 1e3:.3f} ms/step", file=sys.stderr,
           flush=True)
     fp64 = None
     if not args.no_fp64:
         fp64 = run_gpu(run_arg, gp.GP_FP64, args.steps, args.warmup, inputs,
-                       correction=args.current_correction, late_at=args.late_at, slabs=slabs)
+                       correction=args.current_correction, late_at=args.late_at, slabs=slabs,
+                       flush=args.flush)
         print(f"[bench] fp64: {fp64['wall_s'] / args.steps * 1e3:.3f} ms/step",
               file=sys.stderr, flush=True)
     del inputs

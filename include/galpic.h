@@ -126,7 +126,13 @@ enum {
  *               and at most the grid (default 8, or the grid if smaller);
  *   resort_div  re-sort the particles by tile when more than n / resort_div
  *               of them used the global path since the last decision
- *               (default 64; at least 1). */
+ *               (default 64; at least 1);
+ *   flush       how a deposition tile adds its node region (the tile, the
+ *               shape's support and the drift margin, summed in LDS) into
+ *               J and rho: 1 (and 0, the default) float atomics into the
+ *               grids; 2 plain stores into a region buffer (tiles x 4 x
+ *               region values, allocated at binding), summed node by node
+ *               by a second kernel (stage "region_reduce"). */
 typedef struct {
   int nx, ny, nz;
   double dx, dy, dz, dt;
@@ -135,6 +141,7 @@ typedef struct {
   int tile[3];
   int resort_div;
   int stencil[3];
+  int flush;
 } gp_grid_desc;
 
 /* One run's macro-particles (one species, uniform weights).
@@ -422,7 +429,7 @@ gp_status gp_last_graph_ms(gp_ctx *ctx, double *ms);
  * gp_stage_times returns, per stage, the summed milliseconds and the number
  * of recorded launches, then clears them (synchronising).  Graph replays
  * are not recorded. */
-#define GP_N_STAGES 15
+#define GP_N_STAGES 16
 gp_status gp_stage_timing(gp_ctx *ctx, int enable);
 gp_status gp_stage_times(gp_ctx *ctx, double ms[GP_N_STAGES], int count[GP_N_STAGES]);
 const char *gp_stage_name(int stage);

@@ -60,13 +60,13 @@ int ilog2(int n) {
 // Kernel stages of a step (names: gp_stage_name).
 enum {
   kStZero = 0, kStSort, kStDeposit, kStFused, kStFwdZ, kStFwdY, kStFwdX, kStUpdate, kStInvX,
-  kStInvY, kStInvZ, kStGather, kStBtd, kStSlab, kStSlabEB, kNStages
+  kStInvY, kStInvZ, kStGather, kStBtd, kStSlab, kStSlabEB, kStReduce, kNStages
 };
 static_assert(kNStages == GP_N_STAGES, "stage count");
 const char *const kStageNames[kNStages] = {
     "zero_sources", "sort",      "deposit",   "fused_push_deposit", "fft_fwd_z", "fft_fwd_y",
     "fft_fwd_x",    "update",    "fft_inv_x", "fft_inv_y",          "fft_inv_z", "gather_push",
-    "btd",          "slab_copy", "slab_fft_fwd_eb"};
+    "btd",          "slab_copy", "slab_fft_fwd_eb", "region_reduce"};
 
 enum { kReal = 10, kSpec = 11 };
 // real[] slots: 0-2 E, 3-5 B, 6-8 J, 9 rho
@@ -84,6 +84,8 @@ struct Run {
   void *kt = nullptr;           // the same in the run's real type (kd for FP64)
   int rho_old = 9;              // spec slot holding rho^n; the other holds rho^{n+1}
   int resort_div = 64;          // re-sort when > n / resort_div particles went global
+  int flush = 1;                // 1: tile regions by float atomics; 2: region buffer
+  void *regbuf = nullptr;       // flush 2: tiles x 4 x region values (freed with the sort)
   PartPtrs parts{};
   bool bound = false;
   SortBufs sb{};
@@ -238,6 +240,7 @@ gp_status validate_desc(const gp_grid_desc &d, int i) {
     if (d.tile[a] != 0 && (!is_pow2(d.tile[a]) || d.tile[a] > 8 || d.tile[a] > n[a]))
       return fail(GP_ERR_ARG, w + "tile sizes must be 0 or powers of two <= min(8, grid)");
   if (d.resort_div < 0) return fail(GP_ERR_ARG, w + "resort_div must be >= 0");
+  if (d.flush < 0 || d.flush > 2) return fail(GP_ERR_ARG, w + "flush must be 0, 1 or 2");
   for (int a = 0; a < 3; ++a)
     if (d.stencil[a] != 0 && (d.stencil[a] < 2 || d.stencil[a] > 64 || d.stencil[a] % 2))
       return fail(GP_ERR_ARG, w + "stencil orders must be 0 or even in [2, 64]");
@@ -499,12 +502,14 @@ void fill_jobs(gp_ctx *c) {
     j->gr = grid_ptrs<T>(r);
     j->sb = r.sb;
     j->block0 = b.nblocks;
+    j->regbuf = static_cast<T *>(r.regbuf);
     j->resort_threshold = int(r.parts.n / r.resort_div);
     b.nblocks += r.tg.n_tiles;
     if (r.parts.n > b.max_n) b.max_n = r.parts.n;
     const int64_t cells = int64_t(r.tg.n_tiles) << r.tg.lcpt;
     if (cells > b.max_cells) b.max_cells = cells;
     if (r.tg.n_tiles > b.max_tiles) b.max_tiles = r.tg.n_tiles;
+    if (r.regbuf) b.any_regbuf = 1;
     for (int m = 0; m < 4; ++m) {
       const size_t l = particle_lds_bytes<T>(m, r.tg);
       if (l > b.lds[m]) b.lds[m] = l;
@@ -616,6 +621,10 @@ void enqueue_sources(gp_ctx *c, int mode) {
   {
     Stamp s(c, mode == kPartFused ? kStFused : kStDeposit);
     launch_particles<T>(mode, job_tab<T>(c), c->tab.batch, 1.0, c->stream);
+  }
+  if (c->tab.batch.any_regbuf) {
+    Stamp s(c, kStReduce);
+    launch_region_reduce<T>(job_tab<T>(c), c->tab.batch, c->stream);
   }
   enqueue_btd_particles<T>(c);
 }
@@ -922,6 +931,12 @@ gp_status alloc_sort(gp_ctx *c, Run &r) {
     GP_TRY(dev_alloc(r.sort_allocs, n * sizeof(int64_t), &p));
     r.sb.tmp[ncol] = p;
   }
+  r.regbuf = nullptr;
+  if (r.flush == 2) {
+    GP_TRY(dev_alloc(r.sort_allocs,
+                     size_t(r.tg.n_tiles) * 4 * size_t(r.tg.region) * c->real_size, &p));
+    r.regbuf = p;
+  }
   // a sort is forced at the first decision; the tile table starts empty
   const int init[4] = {0, 0, 0, 1};
   GP_HIP(hipMemcpyAsync(r.sb.state, init, sizeof(init), hipMemcpyHostToDevice, c->stream));
@@ -1171,6 +1186,10 @@ gp_status gp_init_grid(const gp_grid_desc *runs, int n_runs, void *hip_stream, g
     g.nmode = int64_t(d.nx) * d.ny * g.nzh;
     r.tg = make_tile_geom(g, c->real_size, d.tile);
     r.resort_div = d.resort_div > 0 ? d.resort_div : 64;
+    // region buffer only when asked for: measured, its per-node sum costs
+    // more than the atomics it saves (256x256x512: 12.44 + 1.53 ms against
+    // 13.47 ms per fused pass)
+    r.flush = d.flush == 2 ? 2 : 1;
     for (int a = 0; a < 3; ++a) r.stencil[a] = d.stencil[a];
     {
       gp_status st = upload_wavenumbers(c, r);

@@ -218,6 +218,8 @@ struct PartJob {
   SortBufs sb;
   int block0;            // first workgroup of the run in a launch with one workgroup per tile
   int resort_threshold;  // re-sort when more particles than this used the global path
+  T *regbuf;             // null: tiles add their regions by atomics; else the deposit
+                         // and fused passes store them here ([tile][J_x J_y J_z rho][region])
 };
 
 // What the launchers need to know about a table of PartJobs.
@@ -229,6 +231,7 @@ struct PartBatch {
   int64_t max_cells;  // most cells in one run
   int max_tiles;      // most tiles in one run
   size_t lds[4];      // dynamic LDS of the particle kernel per mode: the most of any run
+  int any_regbuf;     // some run stores its tile regions in a region buffer
 };
 
 // Sort the particles of each run by tile when flagged (state[3] forces it;
@@ -246,6 +249,11 @@ enum { kPartRho = 0, kPartDeposit = 1, kPartFused = 2, kPartPush = 3 };
 template <typename T>
 void launch_particles(int mode, const PartJob<T> *jobs, const PartBatch &b, double dt_factor,
                       hipStream_t s);
+// After a deposit or fused pass: for every run with a region buffer, add the
+// regions that hold each node into J and rho (which hold the global-path
+// contributions of the pass).
+template <typename T>
+void launch_region_reduce(const PartJob<T> *jobs, const PartBatch &b, hipStream_t s);
 // Dynamic LDS bytes of the particle kernel of a mode for one run's tiles.
 template <typename T>
 size_t particle_lds_bytes(int mode, const TileGeom &tg);

@@ -892,15 +892,150 @@ __global__ __launch_bounds__(NT) void k_quad(const PartJob<typename L::T> *__res
   }
   if constexpr (kDeposit) {
     __syncthreads();
-    T *dst[4] = {gr.J[0], gr.J[1], gr.J[2], gr.rho};
-    const int q_first = MODE == kModeRho ? 3 : 0;
-    for (int r = tid; r < R; r += NT) {
-      const int64_t node = region_node(r, rg, tg, g);
-      for (int q = q_first; q < 4; ++q) {
-        const T vq = T(acc[q * R + r]);
-        if (vq != T(0)) unsafeAtomicAdd(dst[q] + node, vq);
+    T *buf = MODE == kModeRho ? nullptr : load_const(&jp->regbuf);
+    if (buf) {
+      // plain stores of the whole region (zeros included) into the tile's
+      // slot of the region buffer; k_region_reduce adds the slots per node
+      T *__restrict__ slot = global_ptr(buf) + size_t(tile) * 4 * size_t(R);
+      for (int i = tid; i < 4 * R; i += NT) slot[i] = T(acc[i]);
+    } else {
+      T *dst[4] = {gr.J[0], gr.J[1], gr.J[2], gr.rho};
+      const int q_first = MODE == kModeRho ? 3 : 0;
+      for (int r = tid; r < R; r += NT) {
+        const int64_t node = region_node(r, rg, tg, g);
+        for (int q = q_first; q < 4; ++q) {
+          const T vq = T(acc[q * R + r]);
+          if (vq != T(0)) unsafeAtomicAdd(dst[q] + node, vq);
+        }
       }
     }
+  }
+}
+
+// ---- region buffer reduction --------------------------------------------------
+// Tile t's region starts at node t * t_a + FIRST - margin along axis a and
+// spans e_a nodes (periodic; a node appears twice when e_a exceeds the grid).
+// The (tile, region index) pairs that hold node i along one axis: at most
+// kPairs (e_a <= 8 + 3 + 2 and t_a >= 1 give at most 13 on a grid of 8).
+constexpr int kPairs = 16;
+
+__device__ __forceinline__ int axis_pairs(int i, int n, int ta, int nt, int e, int off,
+                                          int *tiles, int *locs) {
+  int cnt = 0;
+  auto add = [&](int t) {
+    int l = (i - (t * ta + off)) % n;
+    if (l < 0) l += n;
+    for (; l < e && cnt < kPairs; l += n) {
+      tiles[cnt] = t;
+      locs[cnt] = l;
+      ++cnt;
+    }
+  };
+  const int span = (e + ta - 1) / ta;  // candidate tiles below the one holding i - off
+  if (nt <= span + 1) {
+    for (int t = 0; t < nt; ++t) add(t);
+  } else {
+    int t0 = (i - off) >= 0 ? (i - off) / ta : -((ta - 1 - (i - off)) / ta);
+    for (int k = 0; k <= span; ++k) add(((t0 - k) % nt + nt) % nt);
+  }
+  return cnt;
+}
+
+// Workgroup row blockIdx.y = run; grid-stride over its nodes.  Adds to J and
+// rho (zeroed before the pass, holding the global-path contributions).
+template <typename T, int ORDER>
+__global__ __launch_bounds__(256) void k_region_reduce(const PartJob<T> *__restrict__ jobs) {
+  using CJob = __attribute__((address_space(4))) const PartJob<T>;
+  const PartJob<T> *jp = jobs + blockIdx.y;
+  T *raw = load_const(&jp->regbuf);
+  if (!raw) return;
+  const T *__restrict__ buf = global_ptr(raw);
+  const RunGeom g = load_const(&jp->g);
+  const TileGeom tg = load_const(&jp->tg);
+  GridPtrs<T> gr = load_const(&jp->gr);
+  globalize(gr);
+  (void)sizeof(CJob);
+  const int off = Shape<ORDER, T>::FIRST - tg.margin;
+  const size_t R = size_t(tg.region);
+  const int n[3] = {g.nx, g.ny, g.nz};
+  // usual geometry (regions at most two tiles long, three or more tiles per
+  // axis): each axis gives the tile holding i - off and, if the region
+  // reaches that far, the one before it
+  bool two = true;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) two = two && tg.e[a] <= 2 * tg.t[a] && tg.nt[a] >= 3;
+  if (two) {
+    for (int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; c < g.ncell;
+         c += int64_t(gridDim.x) * blockDim.x) {
+      const int i[3] = {int(c >> (g.lz + g.ly)), int((c >> g.lz) & (g.ny - 1)),
+                        int(c & (g.nz - 1))};
+      int t0[3], t1[3], l0[3];
+      bool has1[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const int v = (i[a] - off + n[a]) & (n[a] - 1);  // i - off, periodic
+        t0[a] = v >> tg.lt[a];
+        l0[a] = v & (tg.t[a] - 1);
+        t1[a] = t0[a] == 0 ? tg.nt[a] - 1 : t0[a] - 1;
+        has1[a] = l0[a] + tg.t[a] < tg.e[a];
+      }
+      T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0);
+#pragma unroll
+      for (int x = 0; x < 2; ++x) {
+        if (x && !has1[0]) continue;
+        const int tx = x ? t1[0] : t0[0];
+        const int lx = l0[0] + (x ? tg.t[0] : 0);
+#pragma unroll
+        for (int y = 0; y < 2; ++y) {
+          if (y && !has1[1]) continue;
+          const int txy = tx * tg.nt[1] + (y ? t1[1] : t0[1]);
+          const int lxy = lx * tg.e[1] + l0[1] + (y ? tg.t[1] : 0);
+#pragma unroll
+          for (int z = 0; z < 2; ++z) {
+            if (z && !has1[2]) continue;
+            const size_t tile = size_t(txy) * tg.nt[2] + (z ? t1[2] : t0[2]);
+            const size_t base =
+                tile * 4 * R + size_t(lxy) * tg.e[2] + l0[2] + (z ? tg.t[2] : 0);
+            s0 += buf[base];
+            s1 += buf[base + R];
+            s2 += buf[base + 2 * R];
+            s3 += buf[base + 3 * R];
+          }
+        }
+      }
+      gr.J[0][c] += s0;
+      gr.J[1][c] += s1;
+      gr.J[2][c] += s2;
+      gr.rho[c] += s3;
+    }
+    return;
+  }
+  for (int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; c < g.ncell;
+       c += int64_t(gridDim.x) * blockDim.x) {
+    const int i[3] = {int(c >> (g.lz + g.ly)), int((c >> g.lz) & (g.ny - 1)),
+                      int(c & (g.nz - 1))};
+    int tl[3][kPairs], ll[3][kPairs], cnt[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+      cnt[a] = axis_pairs(i[a], n[a], tg.t[a], tg.nt[a], tg.e[a], off, tl[a], ll[a]);
+    T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0);
+    for (int x = 0; x < cnt[0]; ++x)
+      for (int y = 0; y < cnt[1]; ++y) {
+        const int txy = tl[0][x] * tg.nt[1] + tl[1][y];
+        const int lxy = ll[0][x] * tg.e[1] + ll[1][y];
+        for (int z = 0; z < cnt[2]; ++z) {
+          const size_t tile = size_t(txy) * tg.nt[2] + tl[2][z];
+          const size_t base = tile * 4 * R + size_t(lxy) * tg.e[2] + ll[2][z];
+          s0 += buf[base];
+          s1 += buf[base + R];
+          s2 += buf[base + 2 * R];
+          s3 += buf[base + 3 * R];
+        }
+      }
+    gr.J[0][c] += s0;
+    gr.J[1][c] += s1;
+    gr.J[2][c] += s2;
+    gr.rho[c] += s3;
   }
 }
 
@@ -1227,6 +1362,18 @@ void launch_particles(int mode, const PartJob<T> *jobs, const PartBatch &b, doub
 }
 
 template <typename T>
+void launch_region_reduce(const PartJob<T> *jobs, const PartBatch &b, hipStream_t s) {
+  if (b.njobs <= 0 || !b.any_regbuf) return;
+  const unsigned blocks = std::min(stride_blocks(b.max_cells), std::max(64u, 8192u / unsigned(b.njobs)));
+  if (b.order == 1)
+    hipLaunchKernelGGL((k_region_reduce<T, 1>), dim3(blocks, unsigned(b.njobs)), dim3(256), 0, s,
+                       jobs);
+  else
+    hipLaunchKernelGGL((k_region_reduce<T, 3>), dim3(blocks, unsigned(b.njobs)), dim3(256), 0, s,
+                       jobs);
+}
+
+template <typename T>
 size_t particle_lds_bytes(int mode, const TileGeom &tg) {
   using A = typename LayoutOf<T>::acc;
   const bool gather = mode == kPartFused || mode == kPartPush;
@@ -1245,6 +1392,9 @@ template void launch_particles<float>(int, const PartJob<float> *, const PartBat
                                       hipStream_t);
 template void launch_particles<double>(int, const PartJob<double> *, const PartBatch &, double,
                                        hipStream_t);
+template void launch_region_reduce<float>(const PartJob<float> *, const PartBatch &, hipStream_t);
+template void launch_region_reduce<double>(const PartJob<double> *, const PartBatch &,
+                                           hipStream_t);
 template size_t particle_lds_bytes<float>(int, const TileGeom &);
 template size_t particle_lds_bytes<double>(int, const TileGeom &);
 

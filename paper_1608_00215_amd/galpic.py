@@ -46,7 +46,7 @@ QC_FIELDS = ["ER", "ET", "EZ", "BR", "BT", "BZ", "JR", "JT", "JZ", "RHO",
 QC_FIELD = {name: i for i, name in enumerate(QC_FIELDS)}
 QC_STAGES = ["z_fwd", "hankel_fwd", "update", "hankel_bwd", "z_inv", "deposit",
              "gather_push"]
-GP_N_STAGES = 15
+GP_N_STAGES = 16
 
 
 class GridDesc(ctypes.Structure):
@@ -54,7 +54,8 @@ class GridDesc(ctypes.Structure):
                 ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", ctypes.c_double),
                 ("dt", ctypes.c_double), ("shape_order", ctypes.c_int),
                 ("precision", ctypes.c_int), ("tile", ctypes.c_int * 3),
-                ("resort_div", ctypes.c_int), ("stencil", ctypes.c_int * 3)]
+                ("resort_div", ctypes.c_int), ("stencil", ctypes.c_int * 3),
+                ("flush", ctypes.c_int)]
 
 
 class QcParticlesC(ctypes.Structure):
@@ -263,7 +264,7 @@ class Context:
             stencil = (ctypes.c_int * 3)(*g.get("stencil", (0, 0, 0)))
             arr[i] = GridDesc(g["nx"], g["ny"], g["nz"], g.get("dx", 1.0), g.get("dy", 1.0),
                               g.get("dz", 1.0), g["dt"], g["order"], g["precision"], tile,
-                              g.get("resort_div", 0), stencil)
+                              g.get("resort_div", 0), stencil, g.get("flush", 0))
         self.grids = grids
         self.precision = grids[0]["precision"]
         self.real = np.float64 if self.precision == GP_FP64 else np.float32
@@ -493,16 +494,16 @@ class Context:
         return we.value, wb.value
 
 
-def grid_from_config(cfg, precision=None, tile=(0, 0, 0), resort_div=0):
-    """Grid descriptor dict of a workload.RunConfig (tile, resort_div: the
-    tuning knobs of gp_grid_desc, 0 = default; the stencil orders of the
-    field solve come from the config)."""
+def grid_from_config(cfg, precision=None, tile=(0, 0, 0), resort_div=0, flush=0):
+    """Grid descriptor dict of a workload.RunConfig (tile, resort_div,
+    flush: the tuning knobs of gp_grid_desc, 0 = default; the stencil orders
+    of the field solve come from the config)."""
     prec = precision if precision is not None else (
         GP_FP64 if cfg.precision == "fp64" else GP_MIXED)
     return {"nx": cfg.shape[0], "ny": cfg.shape[1], "nz": cfg.shape[2],
             "dx": cfg.spacing[0], "dy": cfg.spacing[1], "dz": cfg.spacing[2],
             "dt": cfg.dt, "order": cfg.order, "precision": prec,
-            "tile": tuple(tile), "resort_div": int(resort_div),
+            "tile": tuple(tile), "resort_div": int(resort_div), "flush": int(flush),
             "stencil": tuple(int(p) for p in cfg.stencil)}
 
 

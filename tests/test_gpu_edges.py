@@ -144,15 +144,19 @@ def test_empty_run_next_to_a_full_one(gpu_lib):
     single.close()
 
 
-@pytest.mark.parametrize("shape,tile", [((8, 8, 8), (0, 0, 0)), ((16, 16, 32), (8, 2, 4))])
-def test_mixed_cubic_steps_small_grid_and_tiles(gpu_lib, shape, tile):
+@pytest.mark.parametrize("flush", [1, 2])
+@pytest.mark.parametrize("shape,tile", [((8, 8, 8), (0, 0, 0)), ((16, 16, 32), (8, 2, 4)),
+                                        ((32, 16, 64), (8, 8, 8)), ((8, 32, 16), (1, 4, 2))])
+def test_mixed_cubic_steps_small_grid_and_tiles(gpu_lib, shape, tile, flush):
     """Mixed precision, cubic shape, drift margin: on a grid smaller than a
-    tile's node region (every region holds some nodes twice) and with thin
-    tiles (up to four tiles' regions hold a node along an axis), three
-    steps match the FP64 oracle."""
+    tile's node region (every region holds some nodes twice), with thin
+    tiles (up to four tiles' regions hold a node along an axis; one-cell
+    tiles: six), and with the usual 8^3 tiles, three steps match the FP64
+    oracle, with the tile regions added by atomics (flush 1) and through the
+    region buffer and its per-node sum (flush 2)."""
     cfg = get_config("c2_lite").with_(shape=shape, u_th=0.2)
     inp = particles_for(cfg)
-    ctx = gp.Context([gp.grid_from_config(cfg, gp.GP_MIXED, tile=tile)])
+    ctx = gp.Context([gp.grid_from_config(cfg, gp.GP_MIXED, tile=tile, flush=flush)])
     ctx.set_v_gal(0, cfg.v_gal())
     parts = gp.particles_from_inputs(inp, cfg, gp.GP_MIXED)
     ctx.bind_particles([parts])

@@ -12,9 +12,9 @@ from tests.gpu_common import oracle_sim, rel_l2
 pytestmark = pytest.mark.gpu
 
 
-def setup(cfg, precision, inp=None):
+def setup(cfg, precision, inp=None, flush=0):
     inp = particles_for(cfg) if inp is None else inp
-    ctx = gp.Context([gp.grid_from_config(cfg, precision)])
+    ctx = gp.Context([gp.grid_from_config(cfg, precision, flush=flush)])
     ctx.set_v_gal(0, cfg.v_gal())
     parts = gp.particles_from_inputs(inp, cfg, precision)
     ctx.bind_particles([parts])
@@ -38,12 +38,14 @@ def compare_state(ctx, parts, st, cfg, tol_f, tol_p):
     return errs
 
 
-@pytest.mark.parametrize("galilean,steps,tol", [(True, 50, 1e-10), (False, 20, 1e-8)])
-def test_c1_history_fp64(gpu_lib, galilean, steps, tol):
+@pytest.mark.parametrize("galilean,steps,tol,flush", [(True, 50, 1e-10, 0), (False, 20, 1e-8, 0),
+                                                     (False, 20, 1e-8, 2)])
+def test_c1_history_fp64(gpu_lib, galilean, steps, tol, flush):
     """16x16x64 FP64 CIC drifting plasma: every step's field energy and the
-    final fields and particles match the oracle."""
+    final fields and particles match the oracle (the standard run also with
+    the tile regions summed through the region buffer, flush 2)."""
     cfg = get_config("c1_cic_fp64").with_(galilean=galilean)
-    ctx, parts, inp = setup(cfg, gp.GP_FP64)
+    ctx, parts, inp = setup(cfg, gp.GP_FP64, flush=flush)
     sim = oracle_sim(cfg)
     st = sim.initial_state(inp["x"], inp["u"])
     for n in range(steps):
