@@ -708,21 +708,36 @@ __device__ __forceinline__ int bucket_of(const PartPtrs &p, int64_t k, const Run
   return in ? b : tg.nb;
 }
 
-// exclusive scan of v[0 .. n) into out[0 .. n], n <= 2 * NT
+// exclusive scan of v[0 .. n) into out[0 .. n], n <= 2 * NT: each thread
+// takes a pair, waves scan their pair sums with lane shuffles, one wave
+// scans the wave totals (tmp[0 .. NT/64)), three barriers in all
 template <int NT>
 __device__ __forceinline__ void scan2(const int *v, int *out, int n, int *tmp) {
+  static_assert(NT % 64 == 0 && NT / 64 <= 64, "whole waves, at most 64");
   const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
   const int a = 2 * tid < n ? v[2 * tid] : 0;
   const int b = 2 * tid + 1 < n ? v[2 * tid + 1] : 0;
-  tmp[tid] = a + b;
-  __syncthreads();
-  for (int off = 1; off < NT; off <<= 1) {
-    const int add = tid >= off ? tmp[tid - off] : 0;
-    __syncthreads();
-    tmp[tid] += add;
-    __syncthreads();
+  int x = a + b;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int y = __shfl_up(x, off, 64);
+    if (lane >= off) x += y;
   }
-  const int excl = tmp[tid] - a - b;
+  if (lane == 63) tmp[wave] = x;
+  __syncthreads();
+  if (wave == 0) {
+    int t = lane < NT / 64 ? tmp[lane] : 0;
+#pragma unroll
+    for (int off = 1; off < NT / 64; off <<= 1) {
+      const int y = __shfl_up(t, off, 64);
+      if (lane >= off) t += y;
+    }
+    if (lane < NT / 64) tmp[lane] = t;
+  }
+  __syncthreads();
+  const int excl = x + (wave ? tmp[wave - 1] : 0) - a - b;
   if (2 * tid <= n) out[2 * tid] = excl;
   if (2 * tid + 1 <= n) out[2 * tid + 1] = excl + a;
   __syncthreads();
