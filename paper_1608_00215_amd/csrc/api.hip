@@ -1150,8 +1150,9 @@ gp_status gp_init_grid(const gp_grid_desc *runs, int n_runs, void *hip_stream, g
   if (hip_stream) {
     c->stream = static_cast<hipStream_t>(hip_stream);
   } else {
-    if (hipStreamCreate(&c->stream) != hipSuccess)
-      return bail(fail(GP_ERR_HIP, "hipStreamCreate failed"));
+    const hipError_t e = hipStreamCreate(&c->stream);
+    if (e != hipSuccess)
+      return bail(fail(GP_ERR_HIP, std::string("hipStreamCreate: ") + hipGetErrorString(e)));
     c->own_stream = true;
   }
   if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess)

@@ -98,6 +98,11 @@ def load(path=LIB_PATH):
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with "
                            "`python -m paper_1608_00215_amd.build` (no CPU fallback exists)")
+    # torch first: its HIP runtime then also serves the library (the same
+    # soname), so the process holds one runtime and torch's streams and
+    # allocations are the library's
+    import torch  # noqa: F401
+
     lib = ctypes.CDLL(path)
     vp, i32, dbl = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
     sig = {

@@ -43,3 +43,25 @@ def test_bad_tile_rejected(gpu_lib):
     cfg = get_config("c2_lite")
     with pytest.raises(gp.GalpicError):
         gp.Context([gp.grid_from_config(cfg, gp.GP_MIXED, tile=(3, 8, 8))])
+
+
+@pytest.mark.parametrize("tile", [(4, 4, 8), (8, 4, 4), (4, 4, 4)])
+def test_mixed_steps_with_small_tiles(gpu_lib, tile):
+    """Small tiles in mixed precision (smaller regions, bucket blocks and
+    lists than the default): three steps of a hot cubic plasma against the
+    oracle, to the same bars as the default tiles."""
+    from tests.test_gpu_step import compare_state
+
+    cfg = get_config("c2_lite").with_(u_th=0.2)
+    inp = particles_for(cfg)
+    ctx = gp.Context([gp.grid_from_config(cfg, gp.GP_MIXED, tile=tile)])
+    ctx.set_v_gal(0, cfg.v_gal())
+    parts = gp.particles_from_inputs(inp, cfg, gp.GP_MIXED)
+    ctx.bind_particles([parts])
+    sim = oracle_sim(cfg)
+    st = sim.initial_state(inp["x"], inp["u"])
+    ctx.run(3)
+    for _ in range(3):
+        st = sim.step(st)
+    compare_state(ctx, parts, st, cfg, 2e-5, 5e-6)
+    ctx.close()
