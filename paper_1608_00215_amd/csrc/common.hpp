@@ -79,4 +79,16 @@ __device__ __forceinline__ P *global_ptr(P *p) {
   return (P *)(G *)(uintptr_t)p;
 }
 
+// gfx950 deals the workgroups of a launch out to its 8 XCDs in turn (the
+// linear workgroup w to XCD w mod 8), and every XCD has an L2 of its own.
+// Numbering the logical work so that each XCD takes one contiguous range of
+// it keeps neighbouring tiles, whose reads and writes share cache lines, in
+// one L2.  A bijection of [0, total).
+constexpr unsigned kXcds = 8;
+__device__ __forceinline__ unsigned xcd_contiguous(unsigned w, unsigned total) {
+  const unsigned q = total / kXcds, r = total % kXcds;
+  const unsigned x = w % kXcds, slot = w / kXcds;
+  return x * q + (x < r ? x : r) + slot;
+}
+
 }  // namespace galpic

@@ -181,6 +181,53 @@ struct TileFFT {
 
 constexpr int kThreads = 256;
 
+// Items per thread whose global loads (or LDS reads) are issued together
+// before any of their results is used: a rolled loop would wait for each
+// load in turn, one memory latency per item.
+template <typename T>
+struct Chunk {
+  static constexpr int value = sizeof(T) == 4 ? 16 : 8;
+};
+
+// Items it = tid, tid + kThreads, ... < ITEMS of a tile: get(it) for a chunk
+// of them, then put(it, value) for the same chunk.  Moves a tile from
+// global memory into LDS (get loads) or out of it (get reads LDS).
+template <typename T, int ITEMS, class Get, class Put>
+__device__ __forceinline__ void tile_items(int tid, Get get, Put put) {
+  constexpr int PER = (ITEMS + kThreads - 1) / kThreads;
+  constexpr int CH = PER < Chunk<T>::value ? PER : Chunk<T>::value;
+  // every item of every chunk exists: no bound checks
+  constexpr bool kExact = ITEMS % kThreads == 0 && PER % CH == 0;
+  for (int p0 = 0; p0 < PER; p0 += CH) {
+    Cx<T> v[CH];
+#pragma unroll
+    for (int q = 0; q < CH; ++q) {
+      const int it = tid + (p0 + q) * kThreads;
+      if (kExact || it < ITEMS) v[q] = get(it);
+    }
+#pragma unroll
+    for (int q = 0; q < CH; ++q) {
+      const int it = tid + (p0 + q) * kThreads;
+      if (kExact || it < ITEMS) put(it, v[q]);
+    }
+  }
+}
+
+// The workgroup's (x, y) in the launch grid, renumbered so that each XCD
+// takes a contiguous range of tiles: neighbouring column tiles of the y and
+// x passes share the cache lines at their edges (rows of nz/2 + 1 complex
+// values are not line-aligned), which one L2 then fetches once.  (The z
+// passes, whose tiles are whole contiguous lines, keep the plain order:
+// measured no faster renumbered.)
+struct Tile {
+  unsigned x, y;
+};
+__device__ __forceinline__ Tile tile_xcd() {
+  const unsigned w = blockIdx.x + blockIdx.y * gridDim.x;
+  const unsigned l = xcd_contiguous(w, gridDim.x * gridDim.y);
+  return Tile{l % gridDim.x, l / gridDim.x};
+}
+
 // ---- z pass, forward: real lines -> half spectra ---------------------------
 template <typename T, int LOGM>
 __global__ __launch_bounds__(kThreads) void k_r2c_z(const FieldSet *__restrict__ sets, int nf,
@@ -197,29 +244,32 @@ __global__ __launch_bounds__(kThreads) void k_r2c_z(const FieldSet *__restrict__
   Cx<T> *__restrict__ out = static_cast<Cx<T> *>(global_ptr(fs.out[f]));
   const int64_t line0 = int64_t(blockIdx.x) * CW;
   const int tid = threadIdx.x;
-  for (int it = tid; it < CW * M; it += kThreads) {
-    const int j = it % M;
-    const int c = it / M;
-    const int64_t line = line0 + c;
-    Cx<T> v = cx(T(0), T(0));
-    if (line < nlines) v = in[line * M + j];
-    lds[j * S + c] = v;
-  }
+  tile_items<T, CW * M>(
+      tid,
+      [&](int it) {
+        const int64_t line = line0 + it / M;
+        return line < nlines ? in[line * M + it % M] : cx(T(0), T(0));
+      },
+      [&](int it, Cx<T> v) { lds[(it % M) * S + it / M] = v; });
   __syncthreads();
   TileFFT<T, LOGM, CW, kThreads, S>::run(lds, tw, tid, false);
-  for (int it = tid; it < CW * NZH; it += kThreads) {
-    const int k = it % NZH;
-    const int c = it / NZH;
-    const int64_t line = line0 + c;
-    if (line >= nlines) continue;
-    const Cx<T> zk = lds[(k & (M - 1)) * S + c];
-    const Cx<T> zm = conj(lds[((M - k) & (M - 1)) * S + c]);
-    const Cx<T> even = T(0.5) * (zk + zm);
-    const Cx<T> d = zk - zm;
-    const Cx<T> odd = cx(T(0.5) * d.im, T(-0.5) * d.re);  // (zk - zm) / (2i)
-    const Cx<T> w = twiddle(tw, k, LOGM + 1, false);       // exp(-2 pi i k / nz)
-    out[line * NZH + k] = even + w * odd;
-  }
+  tile_items<T, CW * NZH>(
+      tid,
+      [&](int it) {
+        const int k = it % NZH;
+        const int c = it / NZH;
+        const Cx<T> zk = lds[(k & (M - 1)) * S + c];
+        const Cx<T> zm = conj(lds[((M - k) & (M - 1)) * S + c]);
+        const Cx<T> even = T(0.5) * (zk + zm);
+        const Cx<T> d = zk - zm;
+        const Cx<T> odd = cx(T(0.5) * d.im, T(-0.5) * d.re);  // (zk - zm) / (2i)
+        const Cx<T> w = twiddle(tw, k, LOGM + 1, false);       // exp(-2 pi i k / nz)
+        return even + w * odd;
+      },
+      [&](int it, Cx<T> v) {
+        const int64_t line = line0 + it / NZH;
+        if (line < nlines) out[line * NZH + it % NZH] = v;
+      });
 }
 
 // ---- z pass, inverse: half spectra -> real lines, scaled -------------------
@@ -238,30 +288,39 @@ __global__ __launch_bounds__(kThreads) void k_c2r_z(const FieldSet *__restrict__
   Cx<T> *__restrict__ out = static_cast<Cx<T> *>(global_ptr(fs.out[f]));
   const int64_t line0 = int64_t(blockIdx.x) * CW;
   const int tid = threadIdx.x;
-  for (int it = tid; it < CW * M; it += kThreads) {
-    const int k = it % M;
-    const int c = it / M;
-    const int64_t line = line0 + c;
-    Cx<T> z = cx(T(0), T(0));
-    if (line < nlines) {
-      const Cx<T> xk = in[line * NZH + k];
-      const Cx<T> xm = conj(in[line * NZH + (M - k)]);
-      const Cx<T> even = xk + xm;
-      const Cx<T> odd = (xk - xm) * twiddle(tw, k, LOGM + 1, true);
-      z = even + mul_i(odd);
-    }
-    lds[k * S + c] = z;
-  }
+  tile_items<T, CW * M>(
+      tid,
+      [&](int it) {
+        const int k = it % M;
+        const int64_t line = line0 + it / M;
+        // loads from a valid line in every case (no branch around them, so
+        // a chunk's loads are all in flight together); a line past the
+        // last gives zero
+        const int64_t ln = line < nlines ? line : nlines - 1;
+        Cx<T> xk = in[ln * NZH + k];
+        Cx<T> xm = conj(in[ln * NZH + (M - k)]);
+        if (k == 0) {
+          // the k_z = 0 and Nyquist values of a real field are real after
+          // the x and y passes: keeping their real parts takes the
+          // Hermitian part of the spectrum (as a real inverse transform
+          // does), whatever rounding left in the other part
+          xk.im = T(0);
+          xm.im = T(0);
+        }
+        const Cx<T> even = xk + xm;
+        const Cx<T> odd = (xk - xm) * twiddle(tw, k, LOGM + 1, true);
+        const Cx<T> z = even + mul_i(odd);
+        return line < nlines ? z : cx(T(0), T(0));
+      },
+      [&](int it, Cx<T> v) { lds[(it % M) * S + it / M] = v; });
   __syncthreads();
   TileFFT<T, LOGM, CW, kThreads, S>::run(lds, tw, tid, true);
-  for (int it = tid; it < CW * M; it += kThreads) {
-    const int j = it % M;
-    const int c = it / M;
-    const int64_t line = line0 + c;
-    if (line >= nlines) continue;
-    const Cx<T> z = lds[j * S + c];
-    out[line * M + j] = cx(scale * z.re, scale * z.im);
-  }
+  tile_items<T, CW * M>(
+      tid, [&](int it) { return lds[(it % M) * S + it / M]; },
+      [&](int it, Cx<T> z) {
+        const int64_t line = line0 + it / M;
+        if (line < nlines) out[line * M + it % M] = cx(scale * z.re, scale * z.im);
+      });
 }
 
 // ---- y / x passes: complex transforms along a strided axis -----------------
@@ -285,36 +344,38 @@ __global__ __launch_bounds__(kThreads) void k_c2c_strided(const FieldSet *__rest
   constexpr int S = CW + 1;
   constexpr int L = 1 << LOGL;
   __shared__ Cx<T> lds[L * S];
-  const FieldSet &fs = sets[blockIdx.y / nf];
-  const int f = blockIdx.y % nf;
+  const Tile wg = tile_xcd();
+  const FieldSet &fs = sets[wg.y / nf];
+  const int f = wg.y % nf;
   const Cx<T> *__restrict__ in = static_cast<const Cx<T> *>(global_ptr(fs.in[f]));
   Cx<T> *__restrict__ out = static_cast<Cx<T> *>(global_ptr(fs.out[f]));
-  const int outer = blockIdx.x / sg.col_tiles;
-  const int col0 = (blockIdx.x % sg.col_tiles) * CW;
+  const int outer = wg.x / sg.col_tiles;
+  const int col0 = (wg.x % sg.col_tiles) * CW;
   const int64_t base = int64_t(outer) * sg.outer_stride + col0;
   const int tid = threadIdx.x;
-  for (int it = tid; it < CW * L; it += kThreads) {
-    const int c = it % CW;
-    const int j = it / CW;
-    Cx<T> v = cx(T(0), T(0));
-    if (col0 + c < sg.ncols) v = in[base + j * sg.row_stride + c];
-    lds[j * S + c] = v;
-  }
+  tile_items<T, CW * L>(
+      tid,
+      [&](int it) {
+        const int c = it % CW;
+        return col0 + c < sg.ncols ? in[base + (it / CW) * sg.row_stride + c] : cx(T(0), T(0));
+      },
+      [&](int it, Cx<T> v) { lds[(it / CW) * S + it % CW] = v; });
   __syncthreads();
   TileFFT<T, LOGL, CW, kThreads, S>::run(lds, tw, tid, inverse != 0);
-  for (int it = tid; it < CW * L; it += kThreads) {
-    const int c = it % CW;
-    const int j = it / CW;
-    const int col = col0 + c;
-    if (col >= sg.ncols) continue;
-    Cx<T> v = lds[j * S + c];
-    if (sg.mask) {
-      const bool held = j == sg.half_row || outer == sg.half_outer || col == sg.half_col ||
-                        (sg.mask == kMaskHeld && j == 0 && outer == 0 && col == 0);
-      if (held) v = cx(T(0), T(0));
-    }
-    out[base + j * sg.row_stride + c] = v;
-  }
+  tile_items<T, CW * L>(
+      tid, [&](int it) { return lds[(it / CW) * S + it % CW]; },
+      [&](int it, Cx<T> v) {
+        const int c = it % CW;
+        const int j = it / CW;
+        const int col = col0 + c;
+        if (col >= sg.ncols) return;
+        if (sg.mask) {
+          const bool held = j == sg.half_row || outer == sg.half_outer || col == sg.half_col ||
+                            (sg.mask == kMaskHeld && j == 0 && outer == 0 && col == 0);
+          if (held) v = cx(T(0), T(0));
+        }
+        out[base + j * sg.row_stride + c] = v;
+      });
 }
 
 // Workgroup row blockIdx.y = set * nf + field: one launch transforms nf
