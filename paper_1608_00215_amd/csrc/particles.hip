@@ -980,48 +980,56 @@ __global__ __launch_bounds__(256) void k_region_reduce(const PartJob<T> *__restr
 #pragma unroll
   for (int a = 0; a < 3; ++a) two = two && tg.e[a] <= 2 * tg.t[a] && tg.nt[a] >= 3;
   if (two) {
-    for (int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; c < g.ncell;
-         c += int64_t(gridDim.x) * blockDim.x) {
-      const int i[3] = {int(c >> (g.lz + g.ly)), int((c >> g.lz) & (g.ny - 1)),
-                        int(c & (g.nz - 1))};
-      int t0[3], t1[3], l0[3];
+    // one workgroup per tile (numbered XCD-contiguously, so that tiles that
+    // are neighbours along z share an L2): the nodes of the tile's own
+    // block, each the sum of the slots of the tile and of the tiles before
+    // it whose regions reach the node
+    const unsigned tile = xcd_contiguous(blockIdx.x, gridDim.x);
+    if (tile >= unsigned(tg.n_tiles)) return;
+    const int tt[3] = {int(tile) / (tg.nt[2] * tg.nt[1]), (int(tile) / tg.nt[2]) % tg.nt[1],
+                       int(tile) % tg.nt[2]};
+    for (int w = threadIdx.x; w < (1 << tg.lcpt); w += blockDim.x) {
+      const int l0[3] = {w >> (tg.lt[2] + tg.lt[1]), (w >> tg.lt[2]) & (tg.t[1] - 1),
+                         w & (tg.t[2] - 1)};
+      int i[3], t1[3];
       bool has1[3];
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
-        const int v = (i[a] - off + n[a]) & (n[a] - 1);  // i - off, periodic
-        t0[a] = v >> tg.lt[a];
-        l0[a] = v & (tg.t[a] - 1);
-        t1[a] = t0[a] == 0 ? tg.nt[a] - 1 : t0[a] - 1;
+        i[a] = (tt[a] * tg.t[a] + off + l0[a] + n[a]) & (n[a] - 1);
+        t1[a] = tt[a] == 0 ? tg.nt[a] - 1 : tt[a] - 1;
         has1[a] = l0[a] + tg.t[a] < tg.e[a];
       }
-      T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0);
+      const int64_t c = (int64_t(i[0]) * g.ny + i[1]) * g.nz + i[2];
+      // all eight (tile, index) combinations load unconditionally, so that
+      // their 32 loads are in flight together: one whose second tile along
+      // some axis does not reach the node reads the first tile's slot again
+      // and adds nothing
+      T v[8][4];
+      bool use[8];
 #pragma unroll
-      for (int x = 0; x < 2; ++x) {
-        if (x && !has1[0]) continue;
-        const int tx = x ? t1[0] : t0[0];
-        const int lx = l0[0] + (x ? tg.t[0] : 0);
+      for (int k = 0; k < 8; ++k) {
+        const bool sx = (k >> 2) && has1[0], sy = ((k >> 1) & 1) && has1[1],
+                   sz = (k & 1) && has1[2];
+        use[k] = ((k >> 2) == int(sx)) && (((k >> 1) & 1) == int(sy)) && ((k & 1) == int(sz));
+        const int txy = (sx ? t1[0] : tt[0]) * tg.nt[1] + (sy ? t1[1] : tt[1]);
+        const int lxy = (l0[0] + (sx ? tg.t[0] : 0)) * tg.e[1] + l0[1] + (sy ? tg.t[1] : 0);
+        const size_t tl = size_t(txy) * tg.nt[2] + (sz ? t1[2] : tt[2]);
+        const size_t base = tl * 4 * R + size_t(lxy) * tg.e[2] + l0[2] + (sz ? tg.t[2] : 0);
 #pragma unroll
-        for (int y = 0; y < 2; ++y) {
-          if (y && !has1[1]) continue;
-          const int txy = tx * tg.nt[1] + (y ? t1[1] : t0[1]);
-          const int lxy = lx * tg.e[1] + l0[1] + (y ? tg.t[1] : 0);
-#pragma unroll
-          for (int z = 0; z < 2; ++z) {
-            if (z && !has1[2]) continue;
-            const size_t tile = size_t(txy) * tg.nt[2] + (z ? t1[2] : t0[2]);
-            const size_t base =
-                tile * 4 * R + size_t(lxy) * tg.e[2] + l0[2] + (z ? tg.t[2] : 0);
-            s0 += buf[base];
-            s1 += buf[base + R];
-            s2 += buf[base + 2 * R];
-            s3 += buf[base + 3 * R];
-          }
-        }
+        for (int q = 0; q < 4; ++q) v[k][q] = buf[base + q * R];
       }
-      gr.J[0][c] += s0;
-      gr.J[1][c] += s1;
-      gr.J[2][c] += s2;
-      gr.rho[c] += s3;
+      // the grids' own values (global-path deposits), all read before the
+      // first store so that the reads need not wait for it
+      const T old[4] = {gr.J[0][c], gr.J[1][c], gr.J[2][c], gr.rho[c]};
+      T sum[4] = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) sum[q] += use[k] ? v[k][q] : T(0);
+      gr.J[0][c] = old[0] + sum[0];
+      gr.J[1][c] = old[1] + sum[1];
+      gr.J[2][c] = old[2] + sum[2];
+      gr.rho[c] = old[3] + sum[3];
     }
     return;
   }
@@ -1379,7 +1387,9 @@ void launch_particles(int mode, const PartJob<T> *jobs, const PartBatch &b, doub
 template <typename T>
 void launch_region_reduce(const PartJob<T> *jobs, const PartBatch &b, hipStream_t s) {
   if (b.njobs <= 0 || !b.any_regbuf) return;
-  const unsigned blocks = std::min(stride_blocks(b.max_cells), std::max(64u, 8192u / unsigned(b.njobs)));
+  // one workgroup per tile on the usual geometry; the general path strides
+  // over the nodes with the same grid
+  const unsigned blocks = unsigned(std::max(1, b.max_tiles));
   if (b.order == 1)
     hipLaunchKernelGGL((k_region_reduce<T, 1>), dim3(blocks, unsigned(b.njobs)), dim3(256), 0, s,
                        jobs);

@@ -146,12 +146,14 @@ def test_empty_run_next_to_a_full_one(gpu_lib):
 
 @pytest.mark.parametrize("flush", [1, 2])
 @pytest.mark.parametrize("shape,tile", [((8, 8, 8), (0, 0, 0)), ((16, 16, 32), (8, 2, 4)),
-                                        ((32, 16, 64), (8, 8, 8)), ((8, 32, 16), (1, 4, 2))])
+                                        ((32, 16, 64), (8, 8, 8)), ((8, 32, 16), (1, 4, 2)),
+                                        ((32, 32, 32), (8, 8, 8))])
 def test_mixed_cubic_steps_small_grid_and_tiles(gpu_lib, shape, tile, flush):
     """Mixed precision, cubic shape, drift margin: on a grid smaller than a
     tile's node region (every region holds some nodes twice), with thin
     tiles (up to four tiles' regions hold a node along an axis; one-cell
-    tiles: six), and with the usual 8^3 tiles, three steps match the FP64
+    tiles: six), and with the usual 8^3 tiles (at 32^3 at least three tiles
+    per axis, the per-tile path of the region sum), three steps match the FP64
     oracle, with the tile regions added by atomics (flush 1) and through the
     region buffer and its per-node sum (flush 2)."""
     cfg = get_config("c2_lite").with_(shape=shape, u_th=0.2)
