@@ -1,7 +1,9 @@
 // Copies of the slab field solve: windows of a run's real grids into its
 // slabs' local grids (owned planes plus guard planes on each side, periodic
 // in z), the grid sums whose means the sources lose, and the owned planes
-// of the slabs' new E, B back into the run's grids.
+// of the slabs' new E, B back into the run's grids.  Each thread of the
+// copies takes kUnroll elements a grid stride apart per round and issues
+// their loads before any store, so that their latencies overlap.
 //
 // The paper names domain decomposition with local transforms over
 // subdomains padded by guard cells, made possible by finite-order solvers,
@@ -13,6 +15,8 @@
 namespace galpic {
 namespace {
 
+constexpr int kUnroll = 4;
+
 // Workgroup row blockIdx.y = run * 4 + quantity.
 template <typename T>
 __global__ __launch_bounds__(256) void k_slab_sums(const SlabSum<T> *__restrict__ sums) {
@@ -20,9 +24,15 @@ __global__ __launch_bounds__(256) void k_slab_sums(const SlabSum<T> *__restrict_
   const int q = blockIdx.y & 3;
   const T *__restrict__ src = global_ptr(sm.src[q]);
   double acc = 0.0;
-  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < sm.ncell;
-       i += int64_t(gridDim.x) * blockDim.x)
-    acc += double(src[i]);
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t i0 = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i0 < sm.ncell;
+       i0 += kUnroll * stride) {
+    T v[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) v[u] = i0 + u * stride < sm.ncell ? src[i0 + u * stride] : T(0);
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) acc += double(v[u]);
+  }
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
   if ((threadIdx.x & 63) == 0) atomicAdd(global_ptr(sm.out) + q, acc);
 }
@@ -37,12 +47,21 @@ __global__ __launch_bounds__(256) void k_slab_window(const SlabCopy<T> *__restri
   T *__restrict__ dst = global_ptr(jb.win[f]);
   const T mean = f >= 6 ? T(global_ptr(jb.sums)[f - 6] * jb.inv_ncell) : T(0);
   const int64_t n = int64_t(jb.nxy) * jb.nw;
-  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n;
-       e += int64_t(gridDim.x) * blockDim.x) {
-    const int64_t xy = e / jb.nw;
-    const int j = int(e - xy * jb.nw);
-    const int z = (jb.first + j) & (jb.nz - 1);
-    dst[e] = src[xy * jb.nz + z] - mean;
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t e0 = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e0 < n;
+       e0 += kUnroll * stride) {
+    T v[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int64_t e = e0 + u * stride;
+      const int64_t xy = e / jb.nw;
+      const int j = int(e - xy * jb.nw);
+      const int z = (jb.first + j) & (jb.nz - 1);
+      v[u] = e < n ? src[xy * jb.nz + z] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u)
+      if (e0 + u * stride < n) dst[e0 + u * stride] = v[u] - mean;
   }
 }
 
@@ -55,11 +74,25 @@ __global__ __launch_bounds__(256) void k_slab_interior(const SlabCopy<T> *__rest
   T *__restrict__ dst = global_ptr(jb.glob[f]);
   const int64_t n = int64_t(jb.nxy) * jb.ns;
   const int own0 = jb.first + jb.guard;  // global plane of owned plane 0 (in [0, nz))
-  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n;
-       e += int64_t(gridDim.x) * blockDim.x) {
-    const int64_t xy = e / jb.ns;
-    const int i = int(e - xy * jb.ns);
-    dst[xy * jb.nz + own0 + i] = src[xy * jb.nw + jb.guard + i];
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t e0 = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e0 < n;
+       e0 += kUnroll * stride) {
+    T v[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int64_t e = e0 + u * stride;
+      const int64_t xy = e / jb.ns;
+      const int i = int(e - xy * jb.ns);
+      v[u] = e < n ? src[xy * jb.nw + jb.guard + i] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int64_t e = e0 + u * stride;
+      if (e < n) {
+        const int64_t xy = e / jb.ns;
+        dst[xy * jb.nz + own0 + int(e - xy * jb.ns)] = v[u];
+      }
+    }
   }
 }
 
