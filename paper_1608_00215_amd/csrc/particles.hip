@@ -35,6 +35,11 @@ namespace galpic {
 namespace {
 
 constexpr int kNT = 512;          // threads per workgroup of the per-tile sort scan
+// per thread and round of the particle kernel's set-up: region nodes staged
+// (three cover the 13^3 region of an 8^3 cubic tile at 768 threads) and
+// particles bucketed
+constexpr int kStageNodes = 3;
+constexpr int kListParts = 4;
 constexpr size_t kLdsBytes = 160 * 1024;  // LDS of one workgroup on gfx950
 // threads per tile workgroup of the particle kernel, one workgroup per CU
 // (its LDS): the fused float kernel needs 167 registers per lane, so 768
@@ -793,11 +798,27 @@ __global__ __launch_bounds__(NT) void k_quad(const PartJob<typename L::T> *__res
   const T qw = T(p.q * p.w / (g.dx * g.dy * g.dz));
   const int tid = threadIdx.x;
   if constexpr (kGather) {
+    // kStageNodes nodes per thread and round, all their loads issued
+    // before the first LDS store (one memory latency per round; the
+    // workgroup is alone on its CU and nothing hides it); a node past the
+    // region loads the last node again and stores nothing
     const T *src[6] = {gr.E[0], gr.E[1], gr.E[2], gr.B[0], gr.B[1], gr.B[2]};
-    for (int r = tid; r < R; r += NT) {
-      const int64_t node = region_node(r, rg, tg, g);
+    for (int r0 = tid; r0 < R; r0 += kStageNodes * NT) {
+      T v[kStageNodes][6];
 #pragma unroll
-      for (int q = 0; q < 6; ++q) fld[q * R + r] = src[q][node];
+      for (int u = 0; u < kStageNodes; ++u) {
+        const int64_t node = region_node(min(r0 + u * NT, R - 1), rg, tg, g);
+#pragma unroll
+        for (int q = 0; q < 6; ++q) v[u][q] = src[q][node];
+      }
+#pragma unroll
+      for (int u = 0; u < kStageNodes; ++u) {
+        const int r = r0 + u * NT;
+        if (r < R) {
+#pragma unroll
+          for (int q = 0; q < 6; ++q) fld[q * R + r] = v[u][q];
+        }
+      }
     }
   }
   if constexpr (kDeposit) {
@@ -819,8 +840,16 @@ __global__ __launch_bounds__(NT) void k_quad(const PartJob<typename L::T> *__res
   if (listed) {
     for (int b = tid; b <= tg.nb; b += NT) tl.fill[b] = 0;
     __syncthreads();
-    for (int i = tid; i < count; i += NT)
-      atomicAdd(&tl.fill[bucket_of<L>(p, tbase + i, g, tg, org)], 1);
+    // kListParts particles per thread and round, their loads together
+    for (int i0 = tid; i0 < count; i0 += kListParts * NT) {
+      int bk[kListParts];
+#pragma unroll
+      for (int u = 0; u < kListParts; ++u)
+        bk[u] = bucket_of<L>(p, tbase + min(i0 + u * NT, count - 1), g, tg, org);
+#pragma unroll
+      for (int u = 0; u < kListParts; ++u)
+        if (i0 + u * NT < count) atomicAdd(&tl.fill[bk[u]], 1);
+    }
     __syncthreads();
     scan2<NT>(tl.fill, tl.off, tg.nb + 1, scan_tmp);
     for (int b = tid; b <= tg.nb; b += NT) tl.fill[b] = (tl.fill[b] + 3) >> 2;
@@ -828,13 +857,23 @@ __global__ __launch_bounds__(NT) void k_quad(const PartJob<typename L::T> *__res
     scan2<NT>(tl.fill, tl.job, tg.nb + 1, scan_tmp);
     for (int b = tid; b <= tg.nb; b += NT) tl.fill[b] = tl.off[b];
     __syncthreads();
-    for (int i = tid; i < count; i += NT) {
-      const int b = bucket_of<L>(p, tbase + i, g, tg, org);
-      const int pos = atomicAdd(&tl.fill[b], 1);
-      tl.list[pos] = static_cast<unsigned short>(i);
-      const int r = pos - tl.off[b];
-      if ((r & 3) == 0)  // first particle of a job
-        tl.jobs[tl.job[b] + (r >> 2)] = pos | (min(4, tl.off[b + 1] - pos) << 24);
+    for (int i0 = tid; i0 < count; i0 += kListParts * NT) {
+      int bk[kListParts];
+#pragma unroll
+      for (int u = 0; u < kListParts; ++u)
+        bk[u] = bucket_of<L>(p, tbase + min(i0 + u * NT, count - 1), g, tg, org);
+#pragma unroll
+      for (int u = 0; u < kListParts; ++u) {
+        const int i = i0 + u * NT;
+        if (i < count) {
+          const int b = bk[u];
+          const int pos = atomicAdd(&tl.fill[b], 1);
+          tl.list[pos] = static_cast<unsigned short>(i);
+          const int r = pos - tl.off[b];
+          if ((r & 3) == 0)  // first particle of a job
+            tl.jobs[tl.job[b] + (r >> 2)] = pos | (min(4, tl.off[b + 1] - pos) << 24);
+        }
+      }
     }
     nwork = tl.job[tg.nb + 1];
   } else {
