@@ -417,6 +417,9 @@ def run_qc(name, precision, steps, warmup):
         rho_bg[0] = qc_ion_profile(w)[None, :]
         zero = np.zeros(shp, dtype=complex)
         ctx.set_background(rho_bg, zero, zero, -beta * rho_bg)
+        # re-sort along z when more than n/256 particles had a deposit node
+        # outside their chunk's window (the binding order decays over a run)
+        ctx.set_resort(256)
         ctx.bind_particles(-1.0, 1.0, qw_w, *parts)
         ctx.electrostatic_fields()
         advance = ctx.particle_step

@@ -564,6 +564,20 @@ gp_status gp_qc_bind_particles(gp_qc_ctx *ctx, const gp_qc_particles *p);
 gp_status gp_qc_electrostatic_fields(gp_qc_ctx *ctx);
 gp_status gp_qc_particle_step(gp_qc_ctx *ctx, int nsteps);
 
+/* Re-sort of the bound particles along z during gp_qc_particle_step.  The
+ * deposit takes chunks of consecutive particles, each with an LDS window of
+ * a few z planes; as the particles move the binding order decays and more
+ * of their nodes fall outside the window (global atomics instead).  The
+ * deposit counts the particles that had such a node; before the next
+ * deposit, when more than n / div of them were counted since the last
+ * decision, the particles are sorted along z again on the device (a
+ * counting sort by z cell of all six arrays together, in the caller's
+ * arrays; their order within a cell is not kept, and with no particle ids
+ * the caller can no longer match particles across steps, hence opt-in).
+ * The decision is taken on the device; its time is part of the deposit
+ * stage.  div = 0 (the default): never.  Errors: GP_ERR_ARG (div < 0). */
+gp_status gp_qc_set_resort(gp_qc_ctx *ctx, int div);
+
 /* With timing on, every launch records HIP events on the context stream,
  * by stage: 0 z transforms forward, 1 Hankel transforms forward, 2 mode
  * update, 3 Hankel transforms backward, 4 z transforms inverse, 5 particle

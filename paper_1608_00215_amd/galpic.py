@@ -38,7 +38,7 @@ EXPORTS = ["gp_init_grid", "gp_set_v_gal", "gp_set_current_correction", "gp_set_
            "gp_qc_fields_inv", "gp_qc_step", "gp_qc_synchronize", "gp_qc_destroy",
            "gp_qc_wavenumbers", "gp_qc_hankel_matrix", "gp_qc_stage_timing",
            "gp_qc_stage_times", "gp_qc_set_background", "gp_qc_bind_particles",
-           "gp_qc_electrostatic_fields", "gp_qc_particle_step"]
+           "gp_qc_electrostatic_fields", "gp_qc_particle_step", "gp_qc_set_resort"]
 QC_FIELDS = ["ER", "ET", "EZ", "BR", "BT", "BZ", "JR", "JT", "JZ", "RHO",
              "E_PLUS", "E_MINUS", "E_Z_HAT", "B_PLUS", "B_MINUS", "B_Z_HAT",
              "J_PLUS", "J_MINUS", "J_Z_HAT", "RHO_HAT_OLD", "RHO_HAT_NEW",
@@ -154,6 +154,7 @@ def load(path=LIB_PATH):
         "gp_qc_bind_particles": [vp, ctypes.POINTER(QcParticlesC)],
         "gp_qc_electrostatic_fields": [vp],
         "gp_qc_particle_step": [vp, i32],
+        "gp_qc_set_resort": [vp, i32],
         "gp_qc_stage_times": [vp, vp, vp],
         "gp_qc_hankel_matrix": [i32, i32, i32, dbl, i32, vp],
     }
@@ -635,6 +636,11 @@ class QcContext:
 
     def particle_step(self, nsteps=1):
         self._call("gp_qc_particle_step", int(nsteps))
+
+    def set_resort(self, div):
+        """Re-sort the particles along z when more than n / div of them had
+        a deposit node outside their chunk's window (0: never)."""
+        self._call("gp_qc_set_resort", int(div))
 
     def stage_timing(self, enable=True):
         self._call("gp_qc_stage_timing", int(bool(enable)))

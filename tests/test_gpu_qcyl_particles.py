@@ -473,3 +473,56 @@ def test_column_workload_sampled(gpu_lib, precision, order):
     assert err <= c_u * np.max(np.abs(u0)) + c_du * np.max(np.abs(du_ref)), \
         (err, np.max(np.abs(du_ref)))
     ctx.close()
+
+
+@pytest.mark.parametrize("precision", [gp.GP_FP64, gp.GP_MIXED])
+def test_resort_along_z_keeps_the_history(gpu_lib, precision):
+    """The device re-sort along z (gp_qc_set_resort) reorders the particles
+    between steps and changes nothing else: ten steps of the cubic column
+    with a re-sort before every deposit (a threshold of zero particles)
+    match the oracle's steps in binding order (fields per mode; positions
+    and momenta as multisets, each coordinate sorted), and the particles
+    have been reordered against a run without re-sorts."""
+    nz, nr, nm, dz, dr, dt = 32, 12, 2, 1.0, 1.0, 1.0
+    gamma = 5.0
+    uz = np.float32(-np.sqrt(gamma * gamma - 1.0))
+    vz = float(uz / np.sqrt(1.0 + uz * uz))
+    rp = 8.0
+    rng = np.random.default_rng(405)
+    x0, u0 = _column(rng, 5000, rp, nz * dz, precision, gamma, u_th=0.05)
+    w = np.pi * rp * rp * nz * dz / len(x0)
+    bg = cy.uniform_cylinder_background(1.0, rp, vz, nm, nr, dr, nz, dz, 3)
+    rho_bg, J_bg = _bg_arrays(bg, nm)
+    runs = []
+    for div in (1 << 30, 0):
+        ctx = gp.QcContext(nz, nr, nm, dz, dr, dt, precision, shape_order=3)
+        ctx.set_v_gal(vz)
+        ctx.set_background(rho_bg, *J_bg)
+        ctx.set_resort(div)
+        parts = _gpu_particles(x0, u0, precision)
+        ctx.bind_particles(-1.0, 1.0, w, *parts)
+        xb, ub = _particles_back(parts)
+        ctx.electrostatic_fields()
+        ctx.particle_step(10)
+        ctx.synchronize()
+        runs.append((ctx, parts, xb, ub))
+    sim = cy.CylindricalPIC(nz, nr, nm, dz, dr, dt, -1.0, 1.0, w, vz, background=bg, order=3)
+    st = sim.initial_state(runs[0][2], runs[0][3], electrostatic=True)
+    for _ in range(10):
+        st = sim.step(st)
+    tol = 1e-10 if precision == gp.GP_FP64 else 1e-4
+    ctx, parts = runs[0][0], runs[0][1]
+    for names, F in ((("ER", "ET", "EZ"), st["E"]), (("BR", "BT", "BZ"), st["B"])):
+        for m in range(nm):
+            got = np.stack([ctx.read(nme)[m] for nme in names])
+            ref = np.stack([F[m][a] for a in range(3)])
+            assert rel_l2(got, ref) <= tol, (names, m)
+    xg, ug = _particles_back(parts)
+    for a in range(3):
+        assert np.max(np.abs(np.sort(xg[:, a]) - np.sort(st["x"][:, a]))) <= tol * 10 * nz * dz
+        assert np.max(np.abs(np.sort(ug[:, a]) - np.sort(st["u"][:, a]))) <= \
+            tol * 10 * np.max(np.abs(st["u"]))
+    x_plain, _ = _particles_back(runs[1][1])
+    assert not np.array_equal(xg, x_plain)   # reordered
+    for r in runs:
+        r[0].close()
