@@ -568,7 +568,7 @@ gp_status gp_qc_particle_step(gp_qc_ctx *ctx, int nsteps);
  * deposit takes chunks of consecutive particles, each with an LDS window of
  * a few z planes; as the particles move the binding order decays and more
  * of their nodes fall outside the window (global atomics instead).  The
- * deposit counts the particles that had such a node; before the next
+ * deposit counts the particles that had such a node; before every 16th
  * deposit, when more than n / div of them were counted since the last
  * decision, the particles are sorted along z again on the device (a
  * counting sort by z cell of all six arrays together, in the caller's

@@ -719,6 +719,7 @@ __global__ __launch_bounds__(kQcDepThreads) void k_qc_move_deposit_tiled(QcPart<
 constexpr int kQcSortThreads = 256;
 constexpr int kQcSortPer = 8;  // particles per thread of the count and scatter
 constexpr int kQcMaxNz = 1024;
+constexpr int kQcResortEvery = 16;
 
 __global__ void k_qcz_decide(int *ctl, int64_t n, int div) {
   const int64_t out = ctl[0];
@@ -1163,6 +1164,7 @@ struct gp_qc_ctx {
   void *zs_tmp = nullptr;
   int64_t zs_cap = 0;
   int resort_div = 0;
+  int64_t zs_steps = 0;  // particle steps since binding
 };
 
 namespace {
@@ -1626,7 +1628,10 @@ void launch_move_deposit(gp_qc_ctx *c, int move) {
   src.jz = static_cast<T *>(c->real[8]);
   src.rho = static_cast<T *>(c->real[9]);
   QStamp stamp(c, 5);
-  if (move) launch_zsort<T>(c);
+  // the decision every kQcResortEvery steps (its five launches cost more
+  // than the check saves when taken every step; the order decays over
+  // hundreds of steps)
+  if (move && c->resort_div > 0 && ++c->zs_steps % kQcResortEvery == 0) launch_zsort<T>(c);
   if (c->order == 3)
     launch_move_deposit_o<T, 3>(c, src, move);
   else
@@ -1900,6 +1905,7 @@ gp_status gp_qc_bind_particles(gp_qc_ctx *c, const gp_qc_particles *p) {
   c->part = *p;
   c->bound = true;
   c->dep_per = 0;  // chosen again for the new particle count
+  c->zs_steps = 0;
   if (!c->zs_ctl) {
     void *ctl = nullptr;
     QTRY(qalloc(c, size_t(2 + 2 * kQcMaxNz) * sizeof(int), &ctl));

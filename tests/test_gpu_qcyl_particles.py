@@ -478,11 +478,11 @@ def test_column_workload_sampled(gpu_lib, precision, order):
 @pytest.mark.parametrize("precision", [gp.GP_FP64, gp.GP_MIXED])
 def test_resort_along_z_keeps_the_history(gpu_lib, precision):
     """The device re-sort along z (gp_qc_set_resort) reorders the particles
-    between steps and changes nothing else: ten steps of the cubic column
-    with a re-sort before every deposit (a threshold of zero particles)
-    match the oracle's steps in binding order (fields per mode; positions
-    and momenta as multisets, each coordinate sorted), and the particles
-    have been reordered against a run without re-sorts."""
+    between steps and changes nothing else: twenty steps of the cubic
+    column with the threshold at zero particles (so a re-sort at the 16th
+    deposit) match the oracle's steps in binding order (fields per mode;
+    positions and momenta as multisets, each coordinate sorted), and the
+    particles have been reordered against a run without re-sorts."""
     nz, nr, nm, dz, dr, dt = 32, 12, 2, 1.0, 1.0, 1.0
     gamma = 5.0
     uz = np.float32(-np.sqrt(gamma * gamma - 1.0))
@@ -503,12 +503,12 @@ def test_resort_along_z_keeps_the_history(gpu_lib, precision):
         ctx.bind_particles(-1.0, 1.0, w, *parts)
         xb, ub = _particles_back(parts)
         ctx.electrostatic_fields()
-        ctx.particle_step(10)
+        ctx.particle_step(20)
         ctx.synchronize()
         runs.append((ctx, parts, xb, ub))
     sim = cy.CylindricalPIC(nz, nr, nm, dz, dr, dt, -1.0, 1.0, w, vz, background=bg, order=3)
     st = sim.initial_state(runs[0][2], runs[0][3], electrostatic=True)
-    for _ in range(10):
+    for _ in range(20):
         st = sim.step(st)
     tol = 1e-10 if precision == gp.GP_FP64 else 1e-4
     ctx, parts = runs[0][0], runs[0][1]
