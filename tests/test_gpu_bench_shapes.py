@@ -7,7 +7,8 @@ on outputs the oracle computes one by one from the library's own inputs:
   and for a hot one whose particles cross cells and tiles;
 * the 256 x 256 x 512 boosted run with its laser: the laser start (Boris
   half push through dt/2), the moves and deposit, the update on sampled
-  modes and the gather-push, in both precisions;
+  modes and the gather-push, in both precisions; and the fused pass after
+  two whole steps, as the benchmark runs it;
 * full-size forward and inverse transforms of that grid (256- and 512-point
   lines, the instantiations the boosted run uses).
 """
@@ -117,6 +118,54 @@ def test_fused_pass_c2_sampled(gpu_lib, c2_inputs, case, pre):
     rho = ctx.read_field(0, "RHO").astype(np.float64)
     total = cfg.n_particles * cfg.q * cfg.w
     assert abs(rho.sum() - total) <= 1e-6 * abs(total)
+    ctx.close()
+
+
+@pytest.mark.parametrize("precision", [gp.GP_MIXED, gp.GP_FP64])
+def test_fused_pass_c3_sampled(gpu_lib, c3_inputs, precision):
+    """The boosted run as the benchmark times it: laser start (fields set
+    and projected, the Boris half push), two whole steps (gp_run), one more
+    deposit and field cycle, then one fused pass (gp_gather_push_deposit,
+    the benchmark's dominant kernel at this shape and launch): sampled
+    momenta (half of them inside the pulse) and positions, and J and rho on
+    node windows inside and outside the pulse, against the oracle's gather,
+    Boris push, moves and deposit from the state and fields the pass
+    started from."""
+    cfg = C3
+    ctx, parts = _ctx(cfg, precision, c3_inputs)
+    lf = laser_fields(cfg)
+    ctx.set_fields(0, lf[0], lf[1], project_transverse=True)
+    ctx.half_push()
+    ctx.run(2)
+    ctx.deposit()
+    _field_cycle(ctx)
+    ctx.synchronize()
+    F = sm.read_fields(ctx, 0)
+    rng = np.random.Generator(np.random.PCG64(54))
+    nx, ny, nz = cfg.shape
+    ix = rng.integers(nx // 2 - 16, nx // 2 + 16, 10000)
+    iy = rng.integers(ny // 2 - 16, ny // 2 + 16, 10000)
+    iz = rng.integers(nz // 4 - 40, nz // 4 + 40, 10000)
+    inside = ((ix * ny + iy) * nz + iz) * cfg.ppc + rng.integers(0, cfg.ppc, 10000)
+    pick = np.unique(np.concatenate([inside, rng.choice(cfg.n_particles, 10000,
+                                                        replace=False)]))
+    x0, u0 = sm.state_of(parts, cfg, pick)
+    corners = [(126, 126, 126), (0, 0, 0), (255, 200, 511)]
+    before = {}
+    for corner in corners:
+        lo, hi = sm.window_sources(cfg, corner)
+        ids = sm.ids_near(parts, cfg, lo, hi)
+        xw, uw = sm.state_of(parts, cfg, ids)
+        un, _, _, _ = sm.oracle_pass(cfg, xw, uw, F)
+        before[corner] = (xw, un)
+    ctx.gather_push_deposit()
+    ctx.synchronize()
+    x1, u1 = sm.state_of(parts, cfg, pick)
+    un, _, _, xn = sm.oracle_pass(cfg, x0, u0, F)
+    assert np.max(np.linalg.norm(un - u0, axis=1)) > 1e-3   # the pulse kicks them
+    assert sm.momentum_bar(u1, un, u0, *BARS[precision]) <= 1.0
+    assert sm.periodic_max_diff(x1, xn, cfg) <= XTOL[precision]
+    _check_windows(ctx, cfg, corners, before, FTOL[precision])
     ctx.close()
 
 
