@@ -28,6 +28,7 @@
 // stores an int32 linear cell index and float offsets in [0, 1), so that a
 // particle static on the Galilean grid keeps its position exactly.
 #include <algorithm>
+#include <type_traits>
 
 #include "kernels.hpp"
 
@@ -465,18 +466,21 @@ __device__ __forceinline__ int64_t region_node(int r, const Region &rg, const Ti
 
 enum { kModeRho = 0, kModeDeposit = 1, kModeFused = 2, kModePush = 3 };
 
-// ---- quads -----------------------------------------------------------------
-// Lanes 4k .. 4k+3 of a wave form a quad.  A quad takes up to four
-// particles of one cell at a time, one per lane.  While the four share a
-// cell they share its N^3 node block, and lane m works on a quarter of the
-// block (its N*N/4 (x, y) node rows) for all four particles: the gather
-// reads every node of the block once per quad instead of once per particle,
-// and the deposit adds the four particles' contributions to a node in
-// registers before one LDS atomic.  In slot s (0 .. 3) lane m handles the
-// particle of lane (m - s) mod 4; weights, values and partial sums move
-// between lanes by DPP rotations inside the quad (no LDS traffic).  A quad
-// whose particles do not share a block inside the tile's region falls back
-// to one particle per lane.
+// ---- quads and pairs ------------------------------------------------------------
+// Lanes 4k .. 4k+3 of a wave form a quad.  A group of G lanes (G = 4: the
+// quad; G = 2: lanes 4k, 4k+1 or 4k+2, 4k+3) takes up to G particles of one
+// cell at a time, one per lane.  While they share a cell they share its N^3
+// node block, and lane m of the group works on a G-th of the block (its
+// N*N/G (x, y) node rows) for all of the group's particles: the gather reads
+// every node of the block once per group instead of once per particle, and
+// the deposit adds the group's contributions to a node in registers before
+// one LDS atomic.  In slot s (0 .. G-1) lane m handles the particle of lane
+// (m - s) mod G; weights, values and partial sums move between lanes by DPP
+// permutations inside the quad (no LDS traffic).  A group whose particles
+// do not share a block inside the tile's region falls back to one particle
+// per lane.  Quads take a cell's particles four at a time; a remainder of
+// one or two particles goes to a pair, so that two such remainders fill one
+// quad's lanes.
 
 template <int CTRL>
 __device__ __forceinline__ int dpp_int(int v) {
@@ -492,114 +496,146 @@ __device__ __forceinline__ double dpp_val(double v) {
   const int hi = __double2hiint(v);
   return __hiloint2double(dpp_int<CTRL>(hi), dpp_int<CTRL>(lo));
 }
-// quad_perm controls: lane m reads lane (m - s) mod 4 ...
-template <typename V>
+// quad_perm controls: lane m reads lane (m - s) mod G ...
+template <int G, typename V>
 __device__ __forceinline__ V from_minus(V v, int s) {
-  switch (s) {
-    case 0: return v;
-    case 1: return dpp_val<0x93>(v);  // [3,0,1,2]
-    case 2: return dpp_val<0x4E>(v);  // [2,3,0,1]
-    default: return dpp_val<0x39>(v);  // [1,2,3,0]
+  if constexpr (G == 2) {
+    return s == 0 ? v : dpp_val<0xB1>(v);  // [1,0,3,2]
+  } else {
+    switch (s) {
+      case 0: return v;
+      case 1: return dpp_val<0x93>(v);  // [3,0,1,2]
+      case 2: return dpp_val<0x4E>(v);  // [2,3,0,1]
+      default: return dpp_val<0x39>(v);  // [1,2,3,0]
+    }
   }
 }
-// ... or lane (m + s) mod 4
-template <typename V>
+// ... or lane (m + s) mod G
+template <int G, typename V>
 __device__ __forceinline__ V from_plus(V v, int s) {
-  switch (s) {
-    case 0: return v;
-    case 1: return dpp_val<0x39>(v);
-    case 2: return dpp_val<0x4E>(v);
-    default: return dpp_val<0x93>(v);
+  if constexpr (G == 2) {
+    return s == 0 ? v : dpp_val<0xB1>(v);
+  } else {
+    switch (s) {
+      case 0: return v;
+      case 1: return dpp_val<0x39>(v);
+      case 2: return dpp_val<0x4E>(v);
+      default: return dpp_val<0x93>(v);
+    }
   }
 }
-__device__ __forceinline__ int lane0_int(int v) { return dpp_int<0x00>(v); }
-__device__ __forceinline__ bool quad_all(bool b) {
+// the group's first lane's value, and whether b holds on every lane of it
+template <int G>
+__device__ __forceinline__ int lead_int(int v) {
+  return G == 2 ? dpp_int<0xA0>(v) : dpp_int<0x00>(v);  // [0,0,2,2] or [0,0,0,0]
+}
+template <int G>
+__device__ __forceinline__ bool group_all(bool b) {
   int v = b ? 1 : 0;
   v &= dpp_int<0xB1>(v);  // [1,0,3,2]
-  v &= dpp_int<0x4E>(v);
+  if constexpr (G == 4) v &= dpp_int<0x4E>(v);
   return v != 0;
 }
 
-// The quad shares one node block when every lane's block starts at the same
-// region-local node and lies inside the region.
-template <int ORDER, typename T>
-__device__ __forceinline__ bool quad_block(const CellPos<T> &c, const Region &rg,
-                                           const TileGeom &tg, const RunGeom &g, int hb[3]) {
+// The group shares one node block when every lane's block starts at the
+// same region-local node and lies inside the region.
+template <int ORDER, typename T, int G>
+__device__ __forceinline__ bool group_block(const CellPos<T> &c, const Region &rg,
+                                            const TileGeom &tg, const RunGeom &g, int hb[3]) {
   const bool in = region_base<ORDER, T>(c, rg, tg, g, hb);
   const int key = (hb[0] * tg.e[1] + hb[1]) * tg.e[2] + hb[2];
-  return quad_all(in && key == lane0_int(key));
+  return group_all<G>(in && key == lead_int<G>(key));
 }
 
-// Weights of the quad's particles for lane m's rows: slot s holds the
-// particle of lane (m - s) mod 4 with wxy[s][r] = wx(a) wy(b) for row r
+// Weights of the group's particles for lane m's rows: slot s holds the
+// particle of lane (m - s) mod G with wxy[s][r] = wx(a) wy(b) for row r
 // (row m*ROWS + r of the block, a = row / N, b = row % N) and wz[s][e].
-template <int ORDER, typename T>
-struct QuadWeights {
+template <int ORDER, typename T, int G>
+struct GroupWeights {
   using Sh = Shape<ORDER, T>;
   static constexpr int N = Sh::N;
-  static constexpr int ROWS = N * N / 4;
-  T wxy[4][ROWS];
-  T wz[4][N];
+  static constexpr int ROWS = N * N / G;
+  T wxy[G][ROWS];
+  T wz[G][N];
+  // w[i] by selects on the bits of i (a chain of equality tests can be
+  // folded into a private-memory table lookup)
+  __device__ __forceinline__ static T pick(const T (&w)[N], int i) {
+    const T lo = (i & 1) ? w[1] : w[0];
+    if constexpr (N == 2) {
+      return lo;
+    } else {
+      const T hi = (i & 1) ? w[3] : w[2];
+      return (i & 2) ? hi : lo;
+    }
+  }
   __device__ __forceinline__ void build(const T o[3], int m) {
     T wx[N], wy[N], wzo[N];
     Sh::weights(o[0], wx);
     Sh::weights(o[1], wy);
     Sh::weights(o[2], wzo);
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      // this lane's particle goes to slot s of lane (m + s) mod 4: send
+    for (int s = 0; s < G; ++s) {
+      // this lane's particle goes to slot s of lane (m + s) mod G: send
       // that lane's row weights
-      const int dst = (m + s) & 3;
+      const int dst = (m + s) & (G - 1);
       T send[ROWS];
-      if constexpr (N == 4) {
-        const T wxa = dst == 0 ? wx[0] : dst == 1 ? wx[1] : dst == 2 ? wx[2] : wx[3];
+      if constexpr (ROWS % N == 0) {
+        // rows dst*ROWS .. +ROWS-1 cover ROWS/N values of a, all of b
 #pragma unroll
-        for (int r = 0; r < ROWS; ++r) send[r] = wxa * wy[r];
+        for (int ia = 0; ia < ROWS / N; ++ia) {
+          const T wxa = pick(wx, dst * (ROWS / N) + ia);
+#pragma unroll
+          for (int b = 0; b < N; ++b) send[ia * N + b] = wxa * wy[b];
+        }
       } else {
-        send[0] = ((dst >> 1) ? wx[1] : wx[0]) * ((dst & 1) ? wy[1] : wy[0]);
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r) {
+          const int row = dst * ROWS + r;
+          send[r] = pick(wx, row / N) * pick(wy, row % N);
+        }
       }
 #pragma unroll
-      for (int r = 0; r < ROWS; ++r) wxy[s][r] = from_minus(send[r], s);
+      for (int r = 0; r < ROWS; ++r) wxy[s][r] = from_minus<G>(send[r], s);
 #pragma unroll
-      for (int e = 0; e < N; ++e) wz[s][e] = from_minus(wzo[e], s);
+      for (int e = 0; e < N; ++e) wz[s][e] = from_minus<G>(wzo[e], s);
     }
   }
 };
 
 // region-local index of the first node of lane m's row r in the block hb
-template <int ORDER>
-__device__ __forceinline__ int quad_row(const int hb[3], int m, int r, const TileGeom &tg) {
+template <int ORDER, int G>
+__device__ __forceinline__ int group_row(const int hb[3], int m, int r, const TileGeom &tg) {
   constexpr int N = ORDER == 1 ? 2 : 4;
-  constexpr int ROWS = N * N / 4;
+  constexpr int ROWS = N * N / G;
   const int row = m * ROWS + r;
   return ((hb[0] + row / N) * tg.e[1] + (hb[1] + row % N)) * tg.e[2] + hb[2];
 }
 
-// E and B of the quad's four particles from the shared block; every lane
-// gets its own particle's six values.
-template <int ORDER, typename T>
-__device__ __forceinline__ void gather_quad(const int hb[3], const T o[3], int m,
-                                            const TileGeom &tg, const T *fld, T F[6]) {
-  using QW = QuadWeights<ORDER, T>;
-  constexpr int N = QW::N;
-  QW w;
+// E and B of the group's particles from the shared block; every lane gets
+// its own particle's six values.
+template <int ORDER, typename T, int G>
+__device__ __forceinline__ void gather_group(const int hb[3], const T o[3], int m,
+                                             const TileGeom &tg, const T *fld, T F[6]) {
+  using GW = GroupWeights<ORDER, T, G>;
+  constexpr int N = GW::N;
+  GW w;
   w.build(o, m);
   const int R = tg.region;
-  T P[4][6];
+  T P[G][6];
 #pragma unroll
-  for (int s = 0; s < 4; ++s)
+  for (int s = 0; s < G; ++s)
 #pragma unroll
     for (int q = 0; q < 6; ++q) P[s][q] = T(0);
 #pragma unroll
-  for (int r = 0; r < QW::ROWS; ++r) {
-    const T *row = fld + quad_row<ORDER>(hb, m, r, tg);
+  for (int r = 0; r < GW::ROWS; ++r) {
+    const T *row = fld + group_row<ORDER, G>(hb, m, r, tg);
 #pragma unroll
     for (int q = 0; q < 6; ++q) {
       T f[N];
 #pragma unroll
       for (int e = 0; e < N; ++e) f[e] = row[q * R + e];
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
+      for (int s = 0; s < G; ++s) {
         T acc = P[s][q];
 #pragma unroll
         for (int e = 0; e < N; ++e) acc += (w.wxy[s][r] * w.wz[s][e]) * f[e];
@@ -607,41 +643,41 @@ __device__ __forceinline__ void gather_quad(const int hb[3], const T o[3], int m
       }
     }
   }
-  // the particle of lane m sits in slot s of lane (m + s) mod 4
+  // the particle of lane m sits in slot s of lane (m + s) mod G
 #pragma unroll
   for (int q = 0; q < 6; ++q) {
     T v = P[0][q];
 #pragma unroll
-    for (int s = 1; s < 4; ++s) v += from_plus(P[s][q], s);
+    for (int s = 1; s < G; ++s) v += from_plus<G>(P[s][q], s);
     F[q] = v;
   }
 }
 
-// Deposit NQ values per particle (val, zero for an idle lane) of the quad's
-// four particles into the shared block hb of LDS accumulators q0 ..
-template <int ORDER, typename T, typename A, int NQ>
-__device__ __forceinline__ void deposit_quad(const int hb[3], const T o[3], const T val[NQ],
-                                             int m, const TileGeom &tg, A *acc, int q0) {
-  using QW = QuadWeights<ORDER, T>;
-  constexpr int N = QW::N;
-  QW w;
+// Deposit NQ values per particle (val, zero for an idle lane) of the
+// group's particles into the shared block hb of LDS accumulators q0 ..
+template <int ORDER, typename T, typename A, int NQ, int G>
+__device__ __forceinline__ void deposit_group(const int hb[3], const T o[3], const T val[NQ],
+                                              int m, const TileGeom &tg, A *acc, int q0) {
+  using GW = GroupWeights<ORDER, T, G>;
+  constexpr int N = GW::N;
+  GW w;
   w.build(o, m);
-  T vs[4][NQ];
+  T vs[G][NQ];
 #pragma unroll
-  for (int s = 0; s < 4; ++s)
+  for (int s = 0; s < G; ++s)
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) vs[s][q] = from_minus(val[q], s);
+    for (int q = 0; q < NQ; ++q) vs[s][q] = from_minus<G>(val[q], s);
   const int R = tg.region;
 #pragma unroll
-  for (int r = 0; r < QW::ROWS; ++r) {
-    const int row = quad_row<ORDER>(hb, m, r, tg);
+  for (int r = 0; r < GW::ROWS; ++r) {
+    const int row = group_row<ORDER, G>(hb, m, r, tg);
 #pragma unroll
     for (int e = 0; e < N; ++e) {
       T sum[NQ];
 #pragma unroll
       for (int q = 0; q < NQ; ++q) sum[q] = T(0);
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
+      for (int s = 0; s < G; ++s) {
         const T we = w.wxy[s][r] * w.wz[s][e];
 #pragma unroll
         for (int q = 0; q < NQ; ++q) sum[q] += we * vs[s][q];
@@ -654,19 +690,19 @@ __device__ __forceinline__ void deposit_quad(const int hb[3], const T o[3], cons
   }
 }
 
-// Deposit of NQ values at position c: the quad's shared block if it has
+// Deposit of NQ values at position c: the group's shared block if it has
 // one, else one particle per lane (an idle lane deposits nothing).
-template <int ORDER, typename T, typename A, int NQ>
+template <int ORDER, typename T, typename A, int NQ, int G>
 __device__ __forceinline__ void deposit_at(const CellPos<T> &c, const T val[NQ], bool act,
                                            int m, const Region &rg, const TileGeom &tg,
                                            const RunGeom &g, A *acc, int q0, T *const *dst,
                                            int *fallback) {
   int hb[3];
-  if (quad_block<ORDER, T>(c, rg, tg, g, hb)) {
+  if (group_block<ORDER, T, G>(c, rg, tg, g, hb)) {
     T v[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) v[q] = act ? val[q] : T(0);
-    deposit_quad<ORDER, T, A, NQ>(hb, c.o, v, m, tg, acc, q0);
+    deposit_group<ORDER, T, A, NQ, G>(hb, c.o, v, m, tg, acc, q0);
   } else if (act) {
     Support<ORDER, T> s;
     support_of<ORDER, T>(c, rg, tg, g, s);
@@ -680,12 +716,15 @@ __device__ __forceinline__ void deposit_at(const CellPos<T> &c, const T val[NQ],
 // indices), so the quads find four particles of one cell however far the
 // particles have moved inside the region since the last global sort.
 // Buckets are the cells of the tile plus the drift margin, and one bucket
-// for particles beyond it.  Quads take jobs of up to four particles of one
-// bucket.  A tile with more particles than the list holds is processed in
-// memory order instead.
+// for particles beyond it.  A bucket of c particles gives c / 4 quad jobs
+// of four, one more quad job of three when c mod 4 = 3, and a pair job of
+// one or two when c mod 4 is 1 or 2.  The quad jobs come first in the job
+// table, then the pair jobs; a quad takes either one quad job or two pair
+// jobs.  A tile with more particles than the list holds is processed in
+// memory order instead, by quads only.
 struct TileLists {
   int *off;    // nb + 2: first list entry of each bucket
-  int *job;    // nb + 2: first job of each bucket
+  int *job;    // nb + 2: first quad job | first pair job << 16 of each bucket
   int *fill;   // nb + 1: counts, then fill pointers
   unsigned short *list;  // cap tile-local particle indices
   int *jobs;   // cap / 4 + nb + 2: first list entry | size << 24 of each job
@@ -836,7 +875,8 @@ __global__ __launch_bounds__(NT) void k_quad(const PartJob<typename L::T> *__res
     org[1] = (ty * tg.t[1] - tg.margin) & (g.ny - 1);
     org[2] = (tz * tg.t[2] - tg.margin) & (g.nz - 1);
   }
-  int nwork;  // jobs of up to four particles in this tile
+  int nquad;  // quad jobs (up to four particles) in this tile
+  int npair;  // pair jobs (one or two particles), after the quad jobs
   if (listed) {
     for (int b = tid; b <= tg.nb; b += NT) tl.fill[b] = 0;
     __syncthreads();
@@ -851,12 +891,32 @@ __global__ __launch_bounds__(NT) void k_quad(const PartJob<typename L::T> *__res
         if (i0 + u * NT < count) atomicAdd(&tl.fill[bk[u]], 1);
     }
     __syncthreads();
+    // Job table order: the first quad job of every bucket, then the second
+    // ones, then the rest, then the pair jobs.  Neighbouring jobs then come
+    // from different cells, so that the quads of a wave do not send the
+    // same LDS addresses to one atomic instruction.  Per bucket of c
+    // particles (nq quad jobs), two packed scans give the offsets:
+    //   off: c (bits 0-14, c <= cap <= 2^14) | max(nq - 2, 0) << 15
+    //   job: [nq >= 1] | [nq >= 2] << 10 | [c mod 4 in {1, 2}] << 20
+    // (nb + 1 <= 1001 buckets fit 10 bits; the third and later quad jobs,
+    // fewer than cap / 4, fit 12; both sums stay below 2^31).
+    for (int b = tid; b <= tg.nb; b += NT) {
+      const int c = tl.fill[b];
+      const int rem = c & 3;
+      const int nq = (c >> 2) + (rem == 3);
+      tl.fill[b] = c | max(nq - 2, 0) << 15;
+      tl.job[b] = int(nq >= 1) | int(nq >= 2) << 10 | int(rem == 1 || rem == 2) << 20;
+    }
+    __syncthreads();
     scan2<NT>(tl.fill, tl.off, tg.nb + 1, scan_tmp);
-    for (int b = tid; b <= tg.nb; b += NT) tl.fill[b] = (tl.fill[b] + 3) >> 2;
+    scan2<NT>(tl.job, tl.job, tg.nb + 1, scan_tmp);
+    for (int b = tid; b <= tg.nb; b += NT) tl.fill[b] = tl.off[b] & 0x7FFF;
     __syncthreads();
-    scan2<NT>(tl.fill, tl.job, tg.nb + 1, scan_tmp);
-    for (int b = tid; b <= tg.nb; b += NT) tl.fill[b] = tl.off[b];
-    __syncthreads();
+    const unsigned tot_a = unsigned(tl.off[tg.nb + 1]), tot_b = unsigned(tl.job[tg.nb + 1]);
+    const int start1 = int(tot_b & 0x3FF);                       // second quad jobs
+    const int start_rest = start1 + int((tot_b >> 10) & 0x3FF);  // third and later
+    nquad = start_rest + int(tot_a >> 15);
+    npair = int(tot_b >> 20);
     for (int i0 = tid; i0 < count; i0 += kListParts * NT) {
       int bk[kListParts];
 #pragma unroll
@@ -869,33 +929,40 @@ __global__ __launch_bounds__(NT) void k_quad(const PartJob<typename L::T> *__res
           const int b = bk[u];
           const int pos = atomicAdd(&tl.fill[b], 1);
           tl.list[pos] = static_cast<unsigned short>(i);
-          const int r = pos - tl.off[b];
-          if ((r & 3) == 0)  // first particle of a job
-            tl.jobs[tl.job[b] + (r >> 2)] = pos | (min(4, tl.off[b + 1] - pos) << 24);
+          const unsigned oa = unsigned(tl.off[b]);
+          const int first = int(oa & 0x7FFF);
+          const int c = (tl.off[b + 1] & 0x7FFF) - first;
+          const int r = pos - first;
+          const int full = c & ~3;
+          // the first particle of a job writes its entry
+          if ((r & 3) == 0 && r < c && (r < full || c - full == 3)) {
+            const unsigned ob = unsigned(tl.job[b]);
+            const int k = r >> 2;
+            const int at = k == 0   ? int(ob & 0x3FF)
+                           : k == 1 ? start1 + int((ob >> 10) & 0x3FF)
+                                    : start_rest + int(oa >> 15) + (k - 2);
+            tl.jobs[at] = pos | min(4, c - r) << 24;
+          } else if (r == full) {
+            tl.jobs[nquad + int(unsigned(tl.job[b]) >> 20)] = pos | (c - full) << 24;
+          }
         }
       }
     }
-    nwork = tl.job[tg.nb + 1];
   } else {
-    nwork = (count + 3) >> 2;
+    nquad = (count + 3) >> 2;
+    npair = 0;
   }
   __syncthreads();
 
   T *jdst[3] = {gr.J[0], gr.J[1], gr.J[2]};
   T *rdst[1] = {gr.rho};
-  const int m = tid & 3;
-  for (int j = tid >> 2; j < nwork; j += NT / 4) {
-    int first, n;  // list position (or tile index) of the job's first particle; its size
-    if (listed) {
-      const int e = tl.jobs[j];
-      first = e & 0xFFFFFF;
-      n = e >> 24;
-    } else {
-      first = 4 * j;
-      n = min(4, count - first);
-    }
-    // an idle lane (past the job's last particle) mirrors lane 0: it takes
-    // the same path through the quad code and stores nothing
+  // One job of group size G: list position (or tile index) of its first
+  // particle and its size n (0 .. G).  An idle lane (past the job's last
+  // particle) mirrors the group's first lane: it takes the same path
+  // through the group code and stores nothing.
+  auto run_job = [&](auto gsize, int first, int n) {
+    constexpr int G = decltype(gsize)::value;
+    const int m = tid & (G - 1);
     const bool act = m < n;
     const int pos = first + (act ? m : 0);
     const int64_t k = tbase + (listed ? int(tl.list[pos]) : pos);
@@ -910,8 +977,8 @@ __global__ __launch_bounds__(NT) void k_quad(const PartJob<typename L::T> *__res
       const CellPos<T> c0 = L::cell(st, g);
       T F[6];
       int hb[3];
-      if (quad_block<ORDER, T>(c0, rg, tg, g, hb)) {
-        gather_quad<ORDER, T>(hb, c0.o, m, tg, fld, F);
+      if (group_block<ORDER, T, G>(c0, rg, tg, g, hb)) {
+        gather_group<ORDER, T, G>(hb, c0.o, m, tg, fld, F);
       } else {
         Support<ORDER, T> s;
         support_of<ORDER, T>(c0, rg, tg, g, s);
@@ -921,7 +988,7 @@ __global__ __launch_bounds__(NT) void k_quad(const PartJob<typename L::T> *__res
     }
     if constexpr (MODE == kModeRho) {
       const T val[1] = {qw};
-      deposit_at<ORDER, T, A, 1>(L::cell(st, g), val, act, m, rg, tg, g, acc, 3, rdst, state);
+      deposit_at<ORDER, T, A, 1, G>(L::cell(st, g), val, act, m, rg, tg, g, acc, 3, rdst, state);
     }
     if constexpr (kMove) {
       // v - v_gal is a difference of nearly equal numbers for the drifting
@@ -930,10 +997,10 @@ __global__ __launch_bounds__(NT) void k_quad(const PartJob<typename L::T> *__res
       const T v[3] = {u[0] / gamma, u[1] / gamma, u[2] / gamma};
       L::half_move(st, v, g);
       const T jv[3] = {qw * v[0], qw * v[1], qw * v[2]};
-      deposit_at<ORDER, T, A, 3>(L::cell(st, g), jv, act, m, rg, tg, g, acc, 0, jdst, state);
+      deposit_at<ORDER, T, A, 3, G>(L::cell(st, g), jv, act, m, rg, tg, g, acc, 0, jdst, state);
       L::half_move(st, v, g);
       const T val[1] = {qw};
-      deposit_at<ORDER, T, A, 1>(L::cell(st, g), val, act, m, rg, tg, g, acc, 3, rdst, state);
+      deposit_at<ORDER, T, A, 1, G>(L::cell(st, g), val, act, m, rg, tg, g, acc, 3, rdst, state);
     }
     if (act) {
       if constexpr (kMove) store_state<L>(p, k, st, g);
@@ -943,6 +1010,32 @@ __global__ __launch_bounds__(NT) void k_quad(const PartJob<typename L::T> *__res
         static_cast<T *>(p.uz)[k] = u[2];
       }
     }
+  };
+  // work unit w < nquad: quad job w; w >= nquad: pair jobs 2 (w - nquad)
+  // and the next (lanes 0, 1 and 2, 3 of the quad).  Quad q takes units q,
+  // q + NT/4, ...; the units of a wave are consecutive, so at most one wave
+  // meets both kinds.  Two loops keep the two kinds' loop-invariant values
+  // from being live together.
+  const int nwork = nquad + ((npair + 1) >> 1);
+  int w = tid >> 2;
+  for (; w < nquad; w += NT / 4) {
+    int first, n;
+    if (listed) {
+      const int e = tl.jobs[w];
+      first = e & 0xFFFFFF;
+      n = e >> 24;
+    } else {
+      first = 4 * w;
+      n = min(4, count - first);
+    }
+    run_job(std::integral_constant<int, 4>{}, first, n);
+  }
+  for (; w < nwork; w += NT / 4) {
+    // the second pair of an odd count's last unit is idle: it mirrors the
+    // first pair's job with no particle
+    const int pj = 2 * (w - nquad) + ((tid >> 1) & 1);
+    const int e = tl.jobs[nquad + min(pj, npair - 1)];
+    run_job(std::integral_constant<int, 2>{}, e & 0xFFFFFF, pj < npair ? e >> 24 : 0);
   }
   if constexpr (kDeposit) {
     __syncthreads();
