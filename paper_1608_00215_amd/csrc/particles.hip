@@ -668,20 +668,26 @@ __device__ __forceinline__ void deposit_group(const int hb[3], const T o[3], con
 #pragma unroll
     for (int q = 0; q < NQ; ++q) vs[s][q] = from_minus<G>(val[q], s);
   const int R = tg.region;
+  // the z weight goes into the values once per node plane e, the row
+  // weight per node: G * NQ multiplies per plane instead of one weight
+  // product per node and slot
 #pragma unroll
-  for (int r = 0; r < GW::ROWS; ++r) {
-    const int row = group_row<ORDER, G>(hb, m, r, tg);
+  for (int e = 0; e < N; ++e) {
+    T vz[G][NQ];
 #pragma unroll
-    for (int e = 0; e < N; ++e) {
+    for (int s = 0; s < G; ++s)
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) vz[s][q] = w.wz[s][e] * vs[s][q];
+#pragma unroll
+    for (int r = 0; r < GW::ROWS; ++r) {
+      const int row = group_row<ORDER, G>(hb, m, r, tg);
       T sum[NQ];
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) sum[q] = T(0);
+      for (int q = 0; q < NQ; ++q) sum[q] = w.wxy[0][r] * vz[0][q];
 #pragma unroll
-      for (int s = 0; s < G; ++s) {
-        const T we = w.wxy[s][r] * w.wz[s][e];
+      for (int s = 1; s < G; ++s)
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) sum[q] += we * vs[s][q];
-      }
+        for (int q = 0; q < NQ; ++q) sum[q] += w.wxy[s][r] * vz[s][q];
 #pragma unroll
       for (int q = 0; q < NQ; ++q)
         __hip_atomic_fetch_add(acc + size_t(q0 + q) * R + row + e, A(sum[q]), __ATOMIC_RELAXED,
