@@ -821,6 +821,8 @@ __global__ __launch_bounds__(NT) void k_quad(const PartJob<typename L::T> *__res
   constexpr bool kGather = MODE == kModeFused || MODE == kModePush;
   constexpr bool kDeposit = MODE != kModePush;
   constexpr bool kMove = MODE == kModeFused || MODE == kModeDeposit;
+  // pair jobs and the job table by rounds (float particles only)
+  constexpr bool kSpread = sizeof(T) == 4;
   static_assert(2 * NT >= 1024, "bucket scan covers up to 2 NT buckets");
   extern __shared__ __align__(16) unsigned char smem[];
   // accumulators first (8-byte aligned when A is double), then the fields,
@@ -897,21 +899,28 @@ __global__ __launch_bounds__(NT) void k_quad(const PartJob<typename L::T> *__res
         if (i0 + u * NT < count) atomicAdd(&tl.fill[bk[u]], 1);
     }
     __syncthreads();
-    // Job table order: the first quad job of every bucket, then the second
-    // ones, then the rest, then the pair jobs.  Neighbouring jobs then come
-    // from different cells, so that the quads of a wave do not send the
-    // same LDS addresses to one atomic instruction.  Per bucket of c
-    // particles (nq quad jobs), two packed scans give the offsets:
+    // Float particles: the job table holds the first quad job of every
+    // bucket, then the second ones, then the rest, then the pair jobs.
+    // Neighbouring jobs then come from different cells, so that the quads
+    // of a wave do not send the same LDS addresses to one atomic
+    // instruction.  Per bucket of c particles (nq quad jobs), two packed
+    // scans give the offsets:
     //   off: c (bits 0-14, c <= cap <= 2^14) | max(nq - 2, 0) << 15
     //   job: [nq >= 1] | [nq >= 2] << 10 | [c mod 4 in {1, 2}] << 20
     // (nb + 1 <= 1001 buckets fit 10 bits; the third and later quad jobs,
-    // fewer than cap / 4, fit 12; both sums stay below 2^31).
+    // fewer than cap / 4, fit 12; both sums stay below 2^31).  FP64
+    // particles (two waves per SIMD) measured slower with both, and keep
+    // quad jobs only, each bucket's in a row: off holds c, job holds nq.
     for (int b = tid; b <= tg.nb; b += NT) {
       const int c = tl.fill[b];
       const int rem = c & 3;
-      const int nq = (c >> 2) + (rem == 3);
-      tl.fill[b] = c | max(nq - 2, 0) << 15;
-      tl.job[b] = int(nq >= 1) | int(nq >= 2) << 10 | int(rem == 1 || rem == 2) << 20;
+      if constexpr (kSpread) {
+        const int nq = (c >> 2) + (rem == 3);
+        tl.fill[b] = c | max(nq - 2, 0) << 15;
+        tl.job[b] = int(nq >= 1) | int(nq >= 2) << 10 | int(rem == 1 || rem == 2) << 20;
+      } else {
+        tl.job[b] = (c + 3) >> 2;
+      }
     }
     __syncthreads();
     scan2<NT>(tl.fill, tl.off, tg.nb + 1, scan_tmp);
@@ -921,8 +930,8 @@ __global__ __launch_bounds__(NT) void k_quad(const PartJob<typename L::T> *__res
     const unsigned tot_a = unsigned(tl.off[tg.nb + 1]), tot_b = unsigned(tl.job[tg.nb + 1]);
     const int start1 = int(tot_b & 0x3FF);                       // second quad jobs
     const int start_rest = start1 + int((tot_b >> 10) & 0x3FF);  // third and later
-    nquad = start_rest + int(tot_a >> 15);
-    npair = int(tot_b >> 20);
+    nquad = kSpread ? start_rest + int(tot_a >> 15) : int(tot_b);
+    npair = kSpread ? int(tot_b >> 20) : 0;
     for (int i0 = tid; i0 < count; i0 += kListParts * NT) {
       int bk[kListParts];
 #pragma unroll
@@ -941,7 +950,9 @@ __global__ __launch_bounds__(NT) void k_quad(const PartJob<typename L::T> *__res
           const int r = pos - first;
           const int full = c & ~3;
           // the first particle of a job writes its entry
-          if ((r & 3) == 0 && r < c && (r < full || c - full == 3)) {
+          if (!kSpread) {
+            if ((r & 3) == 0) tl.jobs[tl.job[b] + (r >> 2)] = pos | min(4, c - r) << 24;
+          } else if ((r & 3) == 0 && r < c && (r < full || c - full == 3)) {
             const unsigned ob = unsigned(tl.job[b]);
             const int k = r >> 2;
             const int at = k == 0   ? int(ob & 0x3FF)
@@ -1036,12 +1047,14 @@ __global__ __launch_bounds__(NT) void k_quad(const PartJob<typename L::T> *__res
     }
     run_job(std::integral_constant<int, 4>{}, first, n);
   }
-  for (; w < nwork; w += NT / 4) {
-    // the second pair of an odd count's last unit is idle: it mirrors the
-    // first pair's job with no particle
-    const int pj = 2 * (w - nquad) + ((tid >> 1) & 1);
-    const int e = tl.jobs[nquad + min(pj, npair - 1)];
-    run_job(std::integral_constant<int, 2>{}, e & 0xFFFFFF, pj < npair ? e >> 24 : 0);
+  if constexpr (kSpread) {
+    for (; w < nwork; w += NT / 4) {
+      // the second pair of an odd count's last unit is idle: it mirrors
+      // the first pair's job with no particle
+      const int pj = 2 * (w - nquad) + ((tid >> 1) & 1);
+      const int e = tl.jobs[nquad + min(pj, npair - 1)];
+      run_job(std::integral_constant<int, 2>{}, e & 0xFFFFFF, pj < npair ? e >> 24 : 0);
+    }
   }
   if constexpr (kDeposit) {
     __syncthreads();
