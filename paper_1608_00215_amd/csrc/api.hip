@@ -493,6 +493,7 @@ void fill_jobs(gp_ctx *c) {
   b = PartBatch{};
   b.order = c->order;
   b.njobs = int(c->runs.size());
+  b.fixed_geom = c->order == 3 ? 1 : 0;
   for (size_t i = 0; i < c->runs.size(); ++i) {
     const Run &r = c->runs[i];
     PartJob<T> *j = host_at<PartJob<T>>(c, t.jobs, int(i));
@@ -510,6 +511,7 @@ void fill_jobs(gp_ctx *c) {
     if (cells > b.max_cells) b.max_cells = cells;
     if (r.tg.n_tiles > b.max_tiles) b.max_tiles = r.tg.n_tiles;
     if (r.regbuf) b.any_regbuf = 1;
+    if (!default_cubic_tiles(r.tg, sizeof(T))) b.fixed_geom = 0;
     for (int m = 0; m < 4; ++m) {
       const size_t l = particle_lds_bytes<T>(m, r.tg);
       if (l > b.lds[m]) b.lds[m] = l;

@@ -189,7 +189,8 @@ struct TileGeom {
   int margin;    // cells beyond the tile still covered by its node region
   int lcpt;      // log2 of cells per tile
   int n_tiles;
-  int region;    // nodes in the region
+  int sx;        // x stride of the region's node slots: e[1] e[2] + pad
+  int region;    // node slots of one region quantity: e[0] sx
   int nb;        // buckets (cells of the bucket block); bucket nb: beyond it
   int cap;       // particles the per-tile bucket list holds
 };
@@ -232,7 +233,11 @@ struct PartBatch {
   int max_tiles;      // most tiles in one run
   size_t lds[4];      // dynamic LDS of the particle kernel per mode: the most of any run
   int any_regbuf;     // some run stores its tile regions in a region buffer
+  int fixed_geom;     // every run has the default cubic tile geometry
 };
+// True when tg is the default cubic 8x8x8 tile geometry for real_size (the
+// particle kernel then has it as compile-time constants).
+bool default_cubic_tiles(const TileGeom &tg, size_t real_size);
 
 // Sort the particles of each run by tile when flagged (state[3] forces it;
 // otherwise when more than n/64 particles used the global fallback since the

@@ -376,7 +376,7 @@ __device__ __forceinline__ void deposit(const CellPos<T> &c, const Support<ORDER
 #pragma unroll
       for (int b = 0; b < Sh::N; ++b) {
         const T wab = s.w[0][a] * s.w[1][b];
-        const int row = ((s.base[0] + a) * tg.e[1] + (s.base[1] + b)) * tg.e[2] + s.base[2];
+        const int row = (s.base[0] + a) * tg.sx + (s.base[1] + b) * tg.e[2] + s.base[2];
 #pragma unroll
         for (int e = 0; e < Sh::N; ++e) {
           const T w = wab * s.w[2][e];
@@ -421,7 +421,7 @@ __device__ __forceinline__ void gather(const CellPos<T> &c, const Support<ORDER,
 #pragma unroll
       for (int b = 0; b < Sh::N; ++b) {
         const T wab = s.w[0][a] * s.w[1][b];
-        const int row = ((s.base[0] + a) * tg.e[1] + (s.base[1] + b)) * tg.e[2] + s.base[2];
+        const int row = (s.base[0] + a) * tg.sx + (s.base[1] + b) * tg.e[2] + s.base[2];
 #pragma unroll
         for (int e = 0; e < Sh::N; ++e) {
           const T w = wab * s.w[2][e];
@@ -452,12 +452,15 @@ __device__ __forceinline__ void gather(const CellPos<T> &c, const Support<ORDER,
   }
 }
 
-// region slot -> global node index
+// region slot -> global node index (a pad slot at the end of an x plane
+// maps to a node of the plane's last row; nothing is deposited there, and
+// what is staged there is never read)
 __device__ __forceinline__ int64_t region_node(int r, const Region &rg, const TileGeom &tg,
                                                const RunGeom &g) {
-  const int az = r % tg.e[2];
-  const int ay = (r / tg.e[2]) % tg.e[1];
-  const int ax = r / (tg.e[2] * tg.e[1]);
+  const int ax = r / tg.sx;
+  const int rem = r - ax * tg.sx;
+  const int ay = min(rem / tg.e[2], tg.e[1] - 1);
+  const int az = rem % tg.e[2];
   const int ix = (rg.org[0] + ax) & (g.nx - 1);
   const int iy = (rg.org[1] + ay) & (g.ny - 1);
   const int iz = (rg.org[2] + az) & (g.nz - 1);
@@ -543,7 +546,7 @@ template <int ORDER, typename T, int G>
 __device__ __forceinline__ bool group_block(const CellPos<T> &c, const Region &rg,
                                             const TileGeom &tg, const RunGeom &g, int hb[3]) {
   const bool in = region_base<ORDER, T>(c, rg, tg, g, hb);
-  const int key = (hb[0] * tg.e[1] + hb[1]) * tg.e[2] + hb[2];
+  const int key = hb[0] * tg.sx + hb[1] * tg.e[2] + hb[2];
   return group_all<G>(in && key == lead_int<G>(key));
 }
 
@@ -608,7 +611,7 @@ __device__ __forceinline__ int group_row(const int hb[3], int m, int r, const Ti
   constexpr int N = ORDER == 1 ? 2 : 4;
   constexpr int ROWS = N * N / G;
   const int row = m * ROWS + r;
-  return ((hb[0] + row / N) * tg.e[1] + (hb[1] + row % N)) * tg.e[2] + hb[2];
+  return (hb[0] + row / N) * tg.sx + (hb[1] + row % N) * tg.e[2] + hb[2];
 }
 
 // E and B of the group's particles from the shared block; every lane gets
@@ -620,7 +623,7 @@ __device__ __forceinline__ void gather_group(const int hb[3], const T o[3], int 
   constexpr int N = GW::N;
   GW w;
   w.build(o, m);
-  const int R = tg.region;
+  const int R = __builtin_amdgcn_readfirstlane(tg.region);
   T P[G][6];
 #pragma unroll
   for (int s = 0; s < G; ++s)
@@ -667,7 +670,7 @@ __device__ __forceinline__ void deposit_group(const int hb[3], const T o[3], con
   for (int s = 0; s < G; ++s)
 #pragma unroll
     for (int q = 0; q < NQ; ++q) vs[s][q] = from_minus<G>(val[q], s);
-  const int R = tg.region;
+  const int R = __builtin_amdgcn_readfirstlane(tg.region);
   // the z weight goes into the values once per node plane e, the row
   // weight per node: G * NQ multiplies per plane instead of one weight
   // product per node and slot
@@ -793,13 +796,48 @@ __device__ __forceinline__ void scan2(const int *v, int *out, int n, int *tmp) {
   __syncthreads();
 }
 
+// The default cubic tile geometry (8x8x8 cells; float: one cell of drift
+// margin, 13^3 nodes; double: no margin, 11^3 nodes; x planes padded to
+// 172 or 124 slots), written over the grid-independent fields of tg.  A
+// kernel built for it folds every region index to constants, which keeps
+// the fused float kernel within 168 registers.
+template <typename T>
+struct DefaultCubicTiles {
+  static constexpr int kMargin = sizeof(T) == 4 ? 1 : 0;
+  static constexpr int kE = 8 + 3 + 2 * kMargin;
+  static constexpr int kCe = 8 + 2 * kMargin;
+  static constexpr int kSx = kE * kE + (12 - (kE * kE) % 8) % 8;
+  __host__ __device__ static void write(TileGeom &tg) {
+    for (int a = 0; a < 3; ++a) {
+      tg.t[a] = 8;
+      tg.lt[a] = 3;
+      tg.e[a] = kE;
+      tg.ce[a] = kCe;
+    }
+    tg.margin = kMargin;
+    tg.lcpt = 9;
+    tg.sx = kSx;
+    tg.region = kE * kSx;
+    tg.nb = kCe * kCe * kCe;
+  }
+  static bool matches(const TileGeom &tg) {
+    TileGeom d = tg;
+    write(d);
+    for (int a = 0; a < 3; ++a)
+      if (d.t[a] != tg.t[a] || d.lt[a] != tg.lt[a] || d.e[a] != tg.e[a] || d.ce[a] != tg.ce[a])
+        return false;
+    return d.margin == tg.margin && d.lcpt == tg.lcpt && d.sx == tg.sx &&
+           d.region == tg.region && d.nb == tg.nb;
+  }
+};
+
 // One workgroup of NT threads per tile.  Modes:
 //  rho:     rho at the current positions (no move)
 //  deposit: move dt/2, J; move dt/2, rho; positions written
 //  fused:   gather at the current positions and push u through dt, then as
 //           deposit with the new u (one pass over the particles per step)
 //  push:    gather and push u through the time step h was built for
-template <class L, int ORDER, int MODE, typename A, int NT>
+template <class L, int ORDER, int MODE, typename A, int NT, bool FIX>
 __global__ __launch_bounds__(NT) void k_quad(const PartJob<typename L::T> *__restrict__ jobs,
                                              int njobs, double dt_factor) {
   using T = typename L::T;
@@ -809,7 +847,8 @@ __global__ __launch_bounds__(NT) void k_quad(const PartJob<typename L::T> *__res
   CJob *cjobs = (CJob *)jobs;
   const PartJob<T> *jp = jobs + job_of_block(cjobs, njobs, blockIdx.x);
   const RunGeom g = load_const(&jp->g);
-  const TileGeom tg = load_const(&jp->tg);
+  TileGeom tg = load_const(&jp->tg);
+  if constexpr (FIX) DefaultCubicTiles<typename L::T>::write(tg);  // the same values, as constants
   PartPtrs p = load_const(&jp->p);
   globalize(p);
   GridPtrs<T> gr = load_const(&jp->gr);
@@ -827,7 +866,7 @@ __global__ __launch_bounds__(NT) void k_quad(const PartJob<typename L::T> *__res
   extern __shared__ __align__(16) unsigned char smem[];
   // accumulators first (8-byte aligned when A is double), then the fields,
   // then the bucket lists
-  const int R = tg.region;
+  const int R = __builtin_amdgcn_readfirstlane(tg.region);
   A *acc = reinterpret_cast<A *>(smem);  // 4 * region
   unsigned char *after_acc = smem + (kDeposit ? 4 * sizeof(A) * R : 0);
   T *fld = reinterpret_cast<T *>(after_acc);
@@ -1163,9 +1202,9 @@ __global__ __launch_bounds__(256) void k_region_reduce(const PartJob<T> *__restr
                    sz = (k & 1) && has1[2];
         use[k] = ((k >> 2) == int(sx)) && (((k >> 1) & 1) == int(sy)) && ((k & 1) == int(sz));
         const int txy = (sx ? t1[0] : tt[0]) * tg.nt[1] + (sy ? t1[1] : tt[1]);
-        const int lxy = (l0[0] + (sx ? tg.t[0] : 0)) * tg.e[1] + l0[1] + (sy ? tg.t[1] : 0);
+        const int lxy = (l0[0] + (sx ? tg.t[0] : 0)) * tg.sx + (l0[1] + (sy ? tg.t[1] : 0)) * tg.e[2];
         const size_t tl = size_t(txy) * tg.nt[2] + (sz ? t1[2] : tt[2]);
-        const size_t base = tl * 4 * R + size_t(lxy) * tg.e[2] + l0[2] + (sz ? tg.t[2] : 0);
+        const size_t base = tl * 4 * R + size_t(lxy) + l0[2] + (sz ? tg.t[2] : 0);
 #pragma unroll
         for (int q = 0; q < 4; ++q) v[k][q] = buf[base + q * R];
       }
@@ -1196,10 +1235,10 @@ __global__ __launch_bounds__(256) void k_region_reduce(const PartJob<T> *__restr
     for (int x = 0; x < cnt[0]; ++x)
       for (int y = 0; y < cnt[1]; ++y) {
         const int txy = tl[0][x] * tg.nt[1] + tl[1][y];
-        const int lxy = ll[0][x] * tg.e[1] + ll[1][y];
+        const int lxy = ll[0][x] * tg.sx + ll[1][y] * tg.e[2];
         for (int z = 0; z < cnt[2]; ++z) {
           const size_t tile = size_t(txy) * tg.nt[2] + tl[2][z];
-          const size_t base = tile * 4 * R + size_t(lxy) * tg.e[2] + ll[2][z];
+          const size_t base = tile * 4 * R + size_t(lxy) + ll[2][z];
           s0 += buf[base];
           s1 += buf[base + R];
           s2 += buf[base + 2 * R];
@@ -1418,19 +1457,19 @@ unsigned stride_blocks(int64_t n) {
   return unsigned(b);
 }
 
-template <class L, int ORDER, int MODE, typename A>
+template <class L, int ORDER, int MODE, typename A, bool FIX>
 void launch_tile_kernel(const PartJob<typename L::T> *jobs, const PartBatch &b, double dt_factor,
                         hipStream_t s) {
   using T = typename L::T;
   constexpr int NT = quad_threads(sizeof(T));
   static bool attr_set = false;  // allow dynamic LDS above 64 KiB (gfx950: 160 KiB)
   if (!attr_set) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_quad<L, ORDER, MODE, A, NT>),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_quad<L, ORDER, MODE, A, NT, FIX>),
                               hipFuncAttributeMaxDynamicSharedMemorySize,
                               int(kLdsBytes - scan_bytes(sizeof(T))));
     attr_set = true;
   }
-  hipLaunchKernelGGL((k_quad<L, ORDER, MODE, A, NT>), dim3(unsigned(b.nblocks)), dim3(NT),
+  hipLaunchKernelGGL((k_quad<L, ORDER, MODE, A, NT, FIX>), dim3(unsigned(b.nblocks)), dim3(NT),
                      b.lds[MODE], s, jobs, b.njobs, dt_factor);
 }
 
@@ -1438,9 +1477,11 @@ template <class L, int MODE, typename A>
 void launch_tile_order(int order, const PartJob<typename L::T> *jobs, const PartBatch &b,
                        double dt_factor, hipStream_t s) {
   if (order == 1)
-    launch_tile_kernel<L, 1, MODE, A>(jobs, b, dt_factor, s);
+    launch_tile_kernel<L, 1, MODE, A, false>(jobs, b, dt_factor, s);
+  else if (b.fixed_geom)
+    launch_tile_kernel<L, 3, MODE, A, true>(jobs, b, dt_factor, s);
   else
-    launch_tile_kernel<L, 3, MODE, A>(jobs, b, dt_factor, s);
+    launch_tile_kernel<L, 3, MODE, A, false>(jobs, b, dt_factor, s);
 }
 
 template <typename T>
@@ -1480,14 +1521,19 @@ TileGeom make_tile_geom(const RunGeom &g, size_t real_size, const int tile[3]) {
   // (3 bytes per particle)
   auto fixed = [&](int margin, TileGeom &t) {
     t.margin = margin;
-    t.region = 1;
     t.nb = 1;
     for (int a = 0; a < 3; ++a) {
       t.e[a] = t.t[a] + halo + 2 * margin;
       t.ce[a] = t.t[a] + 2 * margin;
-      t.region *= t.e[a];
       t.nb *= t.ce[a];
     }
+    // x planes padded to 4 mod 8 slots: the quads' four lanes sit one x
+    // plane apart, and with 169 slots per plane (13 x 13) their 64-bit LDS
+    // atomics met in the same banks (measured: 16.5 against 10.8 cycles
+    // per wave instruction with eight waves, 172 slots)
+    const int plane = t.e[1] * t.e[2];
+    t.sx = plane + ((12 - plane % 8) % 8);
+    t.region = t.e[0] * t.sx;
     return size_t(t.region) * (6 * real_size + 4 * sizeof(double)) + scan_bytes(real_size);
   };
   // one cell of drift margin when the lists still hold 4096 particles
@@ -1497,6 +1543,11 @@ TileGeom make_tile_geom(const RunGeom &g, size_t real_size, const int tile[3]) {
   while (used + list_bytes(tg.nb, cap) > kLdsBytes) cap -= 64;
   tg.cap = cap;
   return tg;
+}
+
+bool default_cubic_tiles(const TileGeom &tg, size_t real_size) {
+  return real_size == sizeof(float) ? DefaultCubicTiles<float>::matches(tg)
+                                    : DefaultCubicTiles<double>::matches(tg);
 }
 
 template <typename T>
