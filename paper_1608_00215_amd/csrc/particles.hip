@@ -40,7 +40,8 @@ constexpr int kNT = 512;          // threads per workgroup of the per-tile sort 
 // (three cover the 13^3 region of an 8^3 cubic tile at 768 threads) and
 // particles bucketed
 constexpr int kStageNodes = 3;
-constexpr int kListParts = 4;
+constexpr int kListParts = 4;       // particles per thread and round, FP64
+constexpr int kListPartsFloat = 6;  // float: one round holds 4608 particles
 constexpr size_t kLdsBytes = 160 * 1024;  // LDS of one workgroup on gfx950
 // threads per tile workgroup of the particle kernel, one workgroup per CU
 // (its LDS): the fused float kernel needs 167 registers per lane, so 768
@@ -883,6 +884,42 @@ __global__ __launch_bounds__(NT) void k_quad(const PartJob<typename L::T> *__res
   const Region rg = region_of(tile, tg, g, Sh::FIRST);
   const T qw = T(p.q * p.w / (g.dx * g.dy * g.dz));
   const int tid = threadIdx.x;
+  const int64_t tbase = start[tile];
+  const int count = start[tile + 1] - start[tile];
+  const bool listed = count <= tg.cap;
+  int org[3];  // first cell of the bucket block (tile start - margin)
+  {
+    const int tz = tile % tg.nt[2];
+    const int ty = (tile / tg.nt[2]) % tg.nt[1];
+    const int tx = tile / (tg.nt[2] * tg.nt[1]);
+    org[0] = (tx * tg.t[0] - tg.margin) & (g.nx - 1);
+    org[1] = (ty * tg.t[1] - tg.margin) & (g.ny - 1);
+    org[2] = (tz * tg.t[2] - tg.margin) & (g.nz - 1);
+  }
+  int nquad;  // quad jobs (up to four particles) in this tile
+  int npair;  // pair jobs (one or two particles), after the quad jobs
+  // First pass over the tile's particles: bucket counts.  A tile that fits
+  // one round keeps its buckets in registers for the placement pass, which
+  // then loads nothing (the E, B staging below runs between the two).
+  constexpr int kParts = sizeof(T) == 4 ? kListPartsFloat : kListParts;
+  const bool one_round = count <= kParts * NT;
+  int kept[kParts];
+  if (listed) {
+    for (int b = tid; b <= tg.nb; b += NT) tl.fill[b] = 0;
+    __syncthreads();
+    // kParts particles per thread and round, their loads together
+    for (int i0 = tid; i0 < count; i0 += kParts * NT) {
+      int bk[kParts];
+#pragma unroll
+      for (int u = 0; u < kParts; ++u)
+        bk[u] = bucket_of<L>(p, tbase + min(i0 + u * NT, count - 1), g, tg, org);
+#pragma unroll
+      for (int u = 0; u < kParts; ++u) {
+        if (i0 + u * NT < count) atomicAdd(&tl.fill[bk[u]], 1);
+        kept[u] = bk[u];
+      }
+    }
+  }
   if constexpr (kGather) {
     // kStageNodes nodes per thread and round, all their loads issued
     // before the first LDS store (one memory latency per round; the
@@ -910,33 +947,7 @@ __global__ __launch_bounds__(NT) void k_quad(const PartJob<typename L::T> *__res
   if constexpr (kDeposit) {
     for (int r = tid; r < 4 * R; r += NT) acc[r] = A(0);
   }
-  const int64_t tbase = start[tile];
-  const int count = start[tile + 1] - start[tile];
-  const bool listed = count <= tg.cap;
-  int org[3];  // first cell of the bucket block (tile start - margin)
-  {
-    const int tz = tile % tg.nt[2];
-    const int ty = (tile / tg.nt[2]) % tg.nt[1];
-    const int tx = tile / (tg.nt[2] * tg.nt[1]);
-    org[0] = (tx * tg.t[0] - tg.margin) & (g.nx - 1);
-    org[1] = (ty * tg.t[1] - tg.margin) & (g.ny - 1);
-    org[2] = (tz * tg.t[2] - tg.margin) & (g.nz - 1);
-  }
-  int nquad;  // quad jobs (up to four particles) in this tile
-  int npair;  // pair jobs (one or two particles), after the quad jobs
   if (listed) {
-    for (int b = tid; b <= tg.nb; b += NT) tl.fill[b] = 0;
-    __syncthreads();
-    // kListParts particles per thread and round, their loads together
-    for (int i0 = tid; i0 < count; i0 += kListParts * NT) {
-      int bk[kListParts];
-#pragma unroll
-      for (int u = 0; u < kListParts; ++u)
-        bk[u] = bucket_of<L>(p, tbase + min(i0 + u * NT, count - 1), g, tg, org);
-#pragma unroll
-      for (int u = 0; u < kListParts; ++u)
-        if (i0 + u * NT < count) atomicAdd(&tl.fill[bk[u]], 1);
-    }
     __syncthreads();
     // Float particles: the job table holds the first quad job of every
     // bucket, then the second ones, then the rest, then the pair jobs.
@@ -971,13 +982,14 @@ __global__ __launch_bounds__(NT) void k_quad(const PartJob<typename L::T> *__res
     const int start_rest = start1 + int((tot_b >> 10) & 0x3FF);  // third and later
     nquad = kSpread ? start_rest + int(tot_a >> 15) : int(tot_b);
     npair = kSpread ? int(tot_b >> 20) : 0;
-    for (int i0 = tid; i0 < count; i0 += kListParts * NT) {
-      int bk[kListParts];
+    for (int i0 = tid; i0 < count; i0 += kParts * NT) {
+      int bk[kParts];
 #pragma unroll
-      for (int u = 0; u < kListParts; ++u)
-        bk[u] = bucket_of<L>(p, tbase + min(i0 + u * NT, count - 1), g, tg, org);
+      for (int u = 0; u < kParts; ++u)
+        bk[u] = one_round ? kept[u]
+                          : bucket_of<L>(p, tbase + min(i0 + u * NT, count - 1), g, tg, org);
 #pragma unroll
-      for (int u = 0; u < kListParts; ++u) {
+      for (int u = 0; u < kParts; ++u) {
         const int i = i0 + u * NT;
         if (i < count) {
           const int b = bk[u];
