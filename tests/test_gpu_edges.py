@@ -169,3 +169,28 @@ def test_mixed_cubic_steps_small_grid_and_tiles(gpu_lib, shape, tile, flush):
         st = sim.step(st)
     compare_state(ctx, parts, st, cfg, 2e-5, 5e-6)
     ctx.close()
+
+
+@pytest.mark.parametrize("precision,ppc,shape,tol_f,tol_p", [
+    (gp.GP_MIXED, 10, (16, 16, 16), 2e-5, 5e-6),
+    (gp.GP_MIXED, 16, (16, 16, 16), 2e-5, 5e-6),
+    (gp.GP_FP64, 10, (16, 16, 16), 1e-10, 1e-9),
+    (gp.GP_FP64, 32, (8, 8, 16), 1e-10, 1e-9),
+])
+def test_dense_tiles_fused_steps(gpu_lib, precision, ppc, shape, tol_f, tol_p):
+    """Tiles denser than the bucket passes' one round or the tile lists'
+    capacity, through the fused pass (three steps of gp_run: deposit, two
+    fused launches, push) against three oracle steps.  Mixed: 5,120 particles
+    per 8^3 tile (two rounds of six per thread; the buckets are read again
+    for the placement) and 8,192 (past the list capacity: jobs in memory
+    order).  FP64: 5,120 (three rounds of four) and 16,384 (past its
+    capacity)."""
+    cfg = get_config("c2_lite").with_(shape=shape, ppc=ppc, u_th=0.2)
+    ctx, parts, inp = setup(cfg, precision)
+    sim = oracle_sim(cfg)
+    st = sim.initial_state(inp["x"], inp["u"])
+    ctx.run(3)
+    for _ in range(3):
+        st = sim.step(st)
+    compare_state(ctx, parts, st, cfg, tol_f, tol_p)
+    ctx.close()
