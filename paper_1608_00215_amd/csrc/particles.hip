@@ -762,38 +762,57 @@ __device__ __forceinline__ int bucket_of(const PartPtrs &p, int64_t k, const Run
   return in ? b : tg.nb;
 }
 
-// exclusive scan of v[0 .. n) into out[0 .. n], n <= 2 * NT: each thread
-// takes a pair, waves scan their pair sums with lane shuffles, one wave
-// scans the wave totals (tmp[0 .. NT/64)), three barriers in all
-template <int NT>
-__device__ __forceinline__ void scan2(const int *v, int *out, int n, int *tmp) {
-  static_assert(NT % 64 == 0 && NT / 64 <= 64, "whole waves, at most 64");
+// Two exclusive scans at once (n < 2 NT): pack(i) gives the two values of entry i
+// (i < n; zero past it), their prefix sums go to out_a[0 .. n] and
+// out_b[0 .. n].  Each thread takes a pair of entries, waves scan their
+// pair sums with lane shuffles, one wave scans the wave totals of both
+// (lanes 0.. and 32..; tmp[0 .. 2 NT/64)), three barriers in all.
+template <int NT, class Pack>
+__device__ __forceinline__ void scan_pair(int n, Pack pack, int *out_a, int *out_b, int *tmp) {
+  constexpr int W = NT / 64;
+  static_assert(NT % 64 == 0 && W <= 32, "whole waves, at most 32");
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int a = 2 * tid < n ? v[2 * tid] : 0;
-  const int b = 2 * tid + 1 < n ? v[2 * tid + 1] : 0;
-  int x = a + b;
+  int a0 = 0, b0 = 0, a1 = 0, b1 = 0;
+  if (2 * tid < n) pack(2 * tid, a0, b0);
+  if (2 * tid + 1 < n) pack(2 * tid + 1, a1, b1);
+  int xa = a0 + a1, xb = b0 + b1;
 #pragma unroll
   for (int off = 1; off < 64; off <<= 1) {
-    const int y = __shfl_up(x, off, 64);
-    if (lane >= off) x += y;
+    const int ya = __shfl_up(xa, off, 64);
+    const int yb = __shfl_up(xb, off, 64);
+    if (lane >= off) {
+      xa += ya;
+      xb += yb;
+    }
   }
-  if (lane == 63) tmp[wave] = x;
+  if (lane == 63) {
+    tmp[wave] = xa;
+    tmp[W + wave] = xb;
+  }
   __syncthreads();
   if (wave == 0) {
-    int t = lane < NT / 64 ? tmp[lane] : 0;
+    const int half = lane >> 5, k = lane & 31;
+    int t = k < W ? tmp[half * W + k] : 0;
 #pragma unroll
-    for (int off = 1; off < NT / 64; off <<= 1) {
-      const int y = __shfl_up(t, off, 64);
-      if (lane >= off) t += y;
+    for (int off = 1; off < W; off <<= 1) {
+      const int y = __shfl_up(t, off, 32);
+      if (k >= off) t += y;
     }
-    if (lane < NT / 64) tmp[lane] = t;
+    if (k < W) tmp[half * W + k] = t;
   }
   __syncthreads();
-  const int excl = x + (wave ? tmp[wave - 1] : 0) - a - b;
-  if (2 * tid <= n) out[2 * tid] = excl;
-  if (2 * tid + 1 <= n) out[2 * tid + 1] = excl + a;
+  const int ea = xa + (wave ? tmp[wave - 1] : 0) - a0 - a1;
+  const int eb = xb + (wave ? tmp[W + wave - 1] : 0) - b0 - b1;
+  if (2 * tid <= n) {
+    out_a[2 * tid] = ea;
+    out_b[2 * tid] = eb;
+  }
+  if (2 * tid + 1 <= n) {
+    out_a[2 * tid + 1] = ea + a0;
+    out_b[2 * tid + 1] = eb + b0;
+  }
   __syncthreads();
 }
 
@@ -954,27 +973,28 @@ __global__ __launch_bounds__(NT) void k_quad(const PartJob<typename L::T> *__res
     // Neighbouring jobs then come from different cells, so that the quads
     // of a wave do not send the same LDS addresses to one atomic
     // instruction.  Per bucket of c particles (nq quad jobs), two packed
-    // scans give the offsets:
+    // scans (run together) give the offsets:
     //   off: c (bits 0-14, c <= cap <= 2^14) | max(nq - 2, 0) << 15
     //   job: [nq >= 1] | [nq >= 2] << 10 | [c mod 4 in {1, 2}] << 20
     // (nb + 1 <= 1001 buckets fit 10 bits; the third and later quad jobs,
     // fewer than cap / 4, fit 12; both sums stay below 2^31).  FP64
     // particles (two waves per SIMD) measured slower with both, and keep
     // quad jobs only, each bucket's in a row: off holds c, job holds nq.
-    for (int b = tid; b <= tg.nb; b += NT) {
-      const int c = tl.fill[b];
-      const int rem = c & 3;
-      if constexpr (kSpread) {
-        const int nq = (c >> 2) + (rem == 3);
-        tl.fill[b] = c | max(nq - 2, 0) << 15;
-        tl.job[b] = int(nq >= 1) | int(nq >= 2) << 10 | int(rem == 1 || rem == 2) << 20;
-      } else {
-        tl.job[b] = (c + 3) >> 2;
-      }
-    }
-    __syncthreads();
-    scan2<NT>(tl.fill, tl.off, tg.nb + 1, scan_tmp);
-    scan2<NT>(tl.job, tl.job, tg.nb + 1, scan_tmp);
+    scan_pair<NT>(
+        tg.nb + 1,
+        [&](int b, int &va, int &vb) {
+          const int c = tl.fill[b];
+          const int rem = c & 3;
+          if constexpr (kSpread) {
+            const int nq = (c >> 2) + (rem == 3);
+            va = c | max(nq - 2, 0) << 15;
+            vb = int(nq >= 1) | int(nq >= 2) << 10 | int(rem == 1 || rem == 2) << 20;
+          } else {
+            va = c;
+            vb = (c + 3) >> 2;
+          }
+        },
+        tl.off, tl.job, scan_tmp);
     for (int b = tid; b <= tg.nb; b += NT) tl.fill[b] = tl.off[b] & 0x7FFF;
     __syncthreads();
     const unsigned tot_a = unsigned(tl.off[tg.nb + 1]), tot_b = unsigned(tl.job[tg.nb + 1]);
