@@ -762,13 +762,14 @@ __device__ __forceinline__ int bucket_of(const PartPtrs &p, int64_t k, const Run
   return in ? b : tg.nb;
 }
 
-// Two exclusive scans at once (n < 2 NT): pack(i) gives the two values of entry i
-// (i < n; zero past it), their prefix sums go to out_a[0 .. n] and
-// out_b[0 .. n].  Each thread takes a pair of entries, waves scan their
-// pair sums with lane shuffles, one wave scans the wave totals of both
-// (lanes 0.. and 32..; tmp[0 .. 2 NT/64)), three barriers in all.
-template <int NT, class Pack>
-__device__ __forceinline__ void scan_pair(int n, Pack pack, int *out_a, int *out_b, int *tmp) {
+// Two exclusive scans at once (n < 2 NT): pack(i) gives the two values of
+// entry i (i < n; zero past it), and store(i, a, b) receives the two prefix
+// sums of every i in [0, n].  Each thread takes a pair of entries, waves
+// scan their pair sums with lane shuffles, one wave scans the wave totals
+// of both (lanes 0.. and 32..; tmp[0 .. 2 NT/64)), three barriers in all;
+// pack runs before the first and store after the second.
+template <int NT, class Pack, class Store>
+__device__ __forceinline__ void scan_pair(int n, Pack pack, Store store, int *tmp) {
   constexpr int W = NT / 64;
   static_assert(NT % 64 == 0 && W <= 32, "whole waves, at most 32");
   const int tid = threadIdx.x;
@@ -805,14 +806,8 @@ __device__ __forceinline__ void scan_pair(int n, Pack pack, int *out_a, int *out
   __syncthreads();
   const int ea = xa + (wave ? tmp[wave - 1] : 0) - a0 - a1;
   const int eb = xb + (wave ? tmp[W + wave - 1] : 0) - b0 - b1;
-  if (2 * tid <= n) {
-    out_a[2 * tid] = ea;
-    out_b[2 * tid] = eb;
-  }
-  if (2 * tid + 1 <= n) {
-    out_a[2 * tid + 1] = ea + a0;
-    out_b[2 * tid + 1] = eb + b0;
-  }
+  if (2 * tid <= n) store(2 * tid, ea, eb);
+  if (2 * tid + 1 <= n) store(2 * tid + 1, ea + a0, eb + b0);
   __syncthreads();
 }
 
@@ -994,9 +989,12 @@ __global__ __launch_bounds__(NT) void k_quad(const PartJob<typename L::T> *__res
             vb = (c + 3) >> 2;
           }
         },
-        tl.off, tl.job, scan_tmp);
-    for (int b = tid; b <= tg.nb; b += NT) tl.fill[b] = tl.off[b] & 0x7FFF;
-    __syncthreads();
+        [&](int b, int va, int vb) {
+          tl.off[b] = va;
+          tl.job[b] = vb;
+          tl.fill[b] = va & 0x7FFF;  // the placement pass's fill pointers
+        },
+        scan_tmp);
     const unsigned tot_a = unsigned(tl.off[tg.nb + 1]), tot_b = unsigned(tl.job[tg.nb + 1]);
     const int start1 = int(tot_b & 0x3FF);                       // second quad jobs
     const int start_rest = start1 + int((tot_b >> 10) & 0x3FF);  // third and later
