@@ -14,8 +14,9 @@
 // the shape's halo and a drift margin) of E and B in LDS for the gather,
 // orders its particles by current cell in LDS, accumulates J and rho in
 // LDS, and adds the region into the global grid once at the end.  Groups of
-// four lanes (quads) take four particles of one cell at a time and share
-// that cell's node block between them (see the quad section).  In mixed
+// four lanes (quads) take four particles of one cell at a time, pairs of
+// lanes a cell's remainder of one or two, and share that cell's node block
+// between them (see the section on quads and pairs).  In mixed
 // precision the per-tile sums are carried in double (no-return LDS
 // atomics): the float roundings of a deposited value are those of the
 // contributions of a quad's particles and their sum, and the final
@@ -37,17 +38,18 @@ namespace {
 
 constexpr int kNT = 512;          // threads per workgroup of the per-tile sort scan
 // per thread and round of the particle kernel's set-up: region nodes staged
-// (three cover the 13^3 region of an 8^3 cubic tile at 768 threads) and
-// particles bucketed
+// (three cover the 13^3 region of an 8^3 cubic tile, 13 x 172 slots with
+// its padded x planes, at 768 threads) and particles bucketed
 constexpr int kStageNodes = 3;
 constexpr int kListParts = 4;       // particles per thread and round, FP64
 constexpr int kListPartsFloat = 6;  // float: one round holds 4608 particles
 constexpr size_t kLdsBytes = 160 * 1024;  // LDS of one workgroup on gfx950
 // threads per tile workgroup of the particle kernel, one workgroup per CU
-// (its LDS): the fused float kernel needs 167 registers per lane, so 768
-// threads (3 waves per SIMD, at most 168 registers) fit without spilling
-// and hide LDS latency better than 512 (5 % faster steps); the double one
-// needs ~240 and stays at 512; 1024 threads would cap them at 128 and spill
+// (its LDS): the fused float kernel needs about 160 registers per lane, so
+// 768 threads (3 waves per SIMD, at most 168 registers) fit without
+// spilling and hide LDS latency better than 512 (5 % faster steps); the
+// double one needs ~234 and stays at 512; 1024 threads would cap them at
+// 128 and spill
 constexpr int quad_threads(size_t real_size) { return real_size == 4 ? 768 : 512; }
 // static bucket-scan buffer of that workgroup
 constexpr size_t scan_bytes(size_t real_size) { return quad_threads(real_size) * sizeof(int); }
