@@ -914,9 +914,36 @@ __global__ __launch_bounds__(NT) void k_quad(const PartJob<typename L::T> *__res
   }
   int nquad;  // quad jobs (up to four particles) in this tile
   int npair;  // pair jobs (one or two particles), after the quad jobs
+  // E and B of the region: kStageNodes nodes per thread and round, all
+  // their loads issued before the first LDS store (one memory latency per
+  // round; a node past the region loads the last node again and stores
+  // nothing).  The first round's loads are issued before the bucket count
+  // pass below and stored after it, so that the two passes' memory
+  // latencies overlap.
+  const T *src[6] = {gr.E[0], gr.E[1], gr.E[2], gr.B[0], gr.B[1], gr.B[2]};
+  T v[kStageNodes][6];
+  auto stage_load = [&](int r0) {
+#pragma unroll
+    for (int u = 0; u < kStageNodes; ++u) {
+      const int64_t node = region_node(min(r0 + u * NT, R - 1), rg, tg, g);
+#pragma unroll
+      for (int q = 0; q < 6; ++q) v[u][q] = src[q][node];
+    }
+  };
+  auto stage_store = [&](int r0) {
+#pragma unroll
+    for (int u = 0; u < kStageNodes; ++u) {
+      const int r = r0 + u * NT;
+      if (r < R) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) fld[q * R + r] = v[u][q];
+      }
+    }
+  };
+  if constexpr (kGather) stage_load(tid);
   // First pass over the tile's particles: bucket counts.  A tile that fits
   // one round keeps its buckets in registers for the placement pass, which
-  // then loads nothing (the E, B staging below runs between the two).
+  // then loads nothing.
   constexpr int kParts = sizeof(T) == 4 ? kListPartsFloat : kListParts;
   const bool one_round = count <= kParts * NT;
   int kept[kParts];
@@ -937,27 +964,10 @@ __global__ __launch_bounds__(NT) void k_quad(const PartJob<typename L::T> *__res
     }
   }
   if constexpr (kGather) {
-    // kStageNodes nodes per thread and round, all their loads issued
-    // before the first LDS store (one memory latency per round; the
-    // workgroup is alone on its CU and nothing hides it); a node past the
-    // region loads the last node again and stores nothing
-    const T *src[6] = {gr.E[0], gr.E[1], gr.E[2], gr.B[0], gr.B[1], gr.B[2]};
-    for (int r0 = tid; r0 < R; r0 += kStageNodes * NT) {
-      T v[kStageNodes][6];
-#pragma unroll
-      for (int u = 0; u < kStageNodes; ++u) {
-        const int64_t node = region_node(min(r0 + u * NT, R - 1), rg, tg, g);
-#pragma unroll
-        for (int q = 0; q < 6; ++q) v[u][q] = src[q][node];
-      }
-#pragma unroll
-      for (int u = 0; u < kStageNodes; ++u) {
-        const int r = r0 + u * NT;
-        if (r < R) {
-#pragma unroll
-          for (int q = 0; q < 6; ++q) fld[q * R + r] = v[u][q];
-        }
-      }
+    stage_store(tid);
+    for (int r0 = tid + kStageNodes * NT; r0 < R; r0 += kStageNodes * NT) {
+      stage_load(r0);
+      stage_store(r0);
     }
   }
   if constexpr (kDeposit) {
