@@ -575,7 +575,10 @@ gp_status gp_qc_particle_step(gp_qc_ctx *ctx, int nsteps);
  * arrays; their order within a cell is not kept, and with no particle ids
  * the caller can no longer match particles across steps, hence opt-in).
  * The decision is taken on the device; its time is part of the deposit
- * stage.  div = 0 (the default): never.  Errors: GP_ERR_ARG (div < 0). */
+ * stage.  div = 0 (the default): never.  Errors: GP_ERR_ARG (div < 0).
+ * No passage of the paper defines it: it changes the order in which the
+ * deposit visits the particles (the deposited sums up to rounding), not
+ * the method. */
 gp_status gp_qc_set_resort(gp_qc_ctx *ctx, int div);
 
 /* With timing on, every launch records HIP events on the context stream,
