@@ -1342,13 +1342,41 @@ __global__ void k_sort_count(const PartJob<typename L::T> *__restrict__ jobs) {
   globalize(job.p);
   globalize(job.sb);
   if (!job.sb.state[1]) return;
-  for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < job.p.n;
-       k += int64_t(gridDim.x) * blockDim.x) {
-    const typename L::State st = load_state<L>(job.p, k, job.g);
-    const auto c = L::cell(st, job.g);
-    const int cell = tile_major_cell(c.i, job.tg);
-    job.sb.key[k] = cell;
-    job.sb.rank[k] = atomicAdd(job.sb.cell_count + cell, 1);
+  // A wave takes 64 consecutive particles per round (the round's start is
+  // the same for all its lanes, so the loop and the shuffles stay
+  // wave-uniform).  The particles are mostly in cell order already, so a
+  // run of lanes with one cell takes its ranks with one atomic on the
+  // cell's counter, made by the run's first lane, instead of one atomic per
+  // particle on a contended counter.
+  const int lane = int(threadIdx.x) & 63;
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t k0 = int64_t(blockIdx.x) * blockDim.x + (int(threadIdx.x) & ~63); k0 < job.p.n;
+       k0 += stride) {
+    const int64_t k = k0 + lane;
+    const bool in = k < job.p.n;  // the lanes past the end are a suffix of the wave
+    int cell = -1;
+    if (in) {
+      const typename L::State st = load_state<L>(job.p, k, job.g);
+      const auto c = L::cell(st, job.g);
+      cell = tile_major_cell(c.i, job.tg);
+    }
+    const int prev = __shfl_up(cell, 1, 64);
+    const bool head = in && (lane == 0 || prev != cell);
+    const uint64_t heads = __ballot(head);
+    const uint64_t ends = heads | ~__ballot(in);  // a run ends where another starts or at the end
+    const uint64_t upto = (2ull << lane) - 1;     // lanes 0 .. lane (all ones for lane 63)
+    int base = 0;
+    if (head) {
+      const uint64_t later = ends & ~upto;
+      const int next = later ? __builtin_ctzll(later) : 64;
+      base = atomicAdd(job.sb.cell_count + cell, next - lane);
+    }
+    const int first = in ? 63 - __builtin_clzll(heads & upto) : lane;
+    base = __shfl(base, first, 64);
+    if (in) {
+      job.sb.key[k] = cell;
+      job.sb.rank[k] = base + (lane - first);
+    }
   }
 }
 
@@ -1450,15 +1478,30 @@ __device__ __forceinline__ Columns columns_of(const PartJob<T> &job) {
   return c;
 }
 
+// All loads before the stores, over the fixed maximum of 8 columns: with
+// constant indices the column pointers stay in registers (a loop over the
+// run-time count indexed the table in scratch memory, and waited for each
+// load in turn).
 __device__ __forceinline__ void copy_columns(const Columns &cols, bool to_scratch, int64_t src,
                                              int64_t dst) {
-  for (int c = 0; c < cols.n; ++c) {
-    const void *from = global_ptr(to_scratch ? cols.a[c] : cols.b[c]);
-    void *to = global_ptr(to_scratch ? cols.b[c] : cols.a[c]);
-    if (cols.size[c] == 8)
-      static_cast<int64_t *>(to)[dst] = static_cast<const int64_t *>(from)[src];
-    else
-      static_cast<int *>(to)[dst] = static_cast<const int *>(from)[src];
+  int64_t v[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    if (c < cols.n) {
+      const void *from = global_ptr(to_scratch ? cols.a[c] : cols.b[c]);
+      v[c] = cols.size[c] == 8 ? static_cast<const int64_t *>(from)[src]
+                               : int64_t(static_cast<const int *>(from)[src]);
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    if (c < cols.n) {
+      void *to = global_ptr(to_scratch ? cols.b[c] : cols.a[c]);
+      if (cols.size[c] == 8)
+        static_cast<int64_t *>(to)[dst] = v[c];
+      else
+        static_cast<int *>(to)[dst] = int(v[c]);
+    }
   }
 }
 
