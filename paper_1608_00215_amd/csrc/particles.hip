@@ -110,6 +110,16 @@ struct LayoutAbs {
     s.x[2] = static_cast<const double *>(p.z)[k];
     return s;
   }
+  // what the bucket pass reads of a particle (its position) and the cell
+  using Key = State;
+  __device__ __forceinline__ static Key load_key(const PartPtrs &p, int64_t k) {
+    return load(p, k);
+  }
+  __device__ __forceinline__ static void key_cell(const Key &s, const RunGeom &g, int i[3]) {
+    const CellPos<double> c = cell(s, g);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) i[a] = c.i[a];
+  }
   __device__ __forceinline__ static void store(const PartPtrs &p, int64_t k, const State &s) {
     static_cast<double *>(p.x)[k] = s.x[0];
     static_cast<double *>(p.y)[k] = s.x[1];
@@ -156,6 +166,14 @@ struct LayoutCell {
     s.o[1] = static_cast<const float *>(p.oy)[k];
     s.o[2] = static_cast<const float *>(p.oz)[k];
     return s;
+  }
+  // what the bucket pass reads of a particle (its cell word) and the cell
+  using Key = int;
+  __device__ __forceinline__ static Key load_key(const PartPtrs &p, int64_t k) {
+    return static_cast<const int *>(p.x)[k];
+  }
+  __device__ __forceinline__ static void key_cell(Key w, const RunGeom &g, int i[3]) {
+    decode_cell(w, g, i);
   }
   __device__ __forceinline__ static void store(const PartPtrs &p, int64_t k, const State &s,
                                                const RunGeom &g) {
@@ -749,19 +767,26 @@ __host__ __device__ constexpr size_t list_bytes(int nb, int cap) {
 }
 
 template <class L>
-__device__ __forceinline__ int bucket_of(const PartPtrs &p, int64_t k, const RunGeom &g,
-                                         const TileGeom &tg, const int org[3]) {
-  const auto c = L::cell(load_state<L>(p, k, g), g);
+__device__ __forceinline__ int bucket_of_key(const typename L::Key &key, const RunGeom &g,
+                                             const TileGeom &tg, const int org[3]) {
+  int i[3];
+  L::key_cell(key, g, i);
   const int n[3] = {g.nx, g.ny, g.nz};
   int b = 0;
   bool in = true;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    const int rel = (c.i[a] - org[a]) & (n[a] - 1);
+    const int rel = (i[a] - org[a]) & (n[a] - 1);
     in = in && rel < tg.ce[a];
     b = b * tg.ce[a] + rel;
   }
   return in ? b : tg.nb;
+}
+
+template <class L>
+__device__ __forceinline__ int bucket_of(const PartPtrs &p, int64_t k, const RunGeom &g,
+                                         const TileGeom &tg, const int org[3]) {
+  return bucket_of_key<L>(L::load_key(p, k), g, tg, org);
 }
 
 // Two exclusive scans at once (n < 2 NT): pack(i) gives the two values of
@@ -917,9 +942,10 @@ __global__ __launch_bounds__(NT) void k_quad(const PartJob<typename L::T> *__res
   // E and B of the region: kStageNodes nodes per thread and round, all
   // their loads issued before the first LDS store (one memory latency per
   // round; a node past the region loads the last node again and stores
-  // nothing).  The first round's loads are issued before the bucket count
-  // pass below and stored after it, so that the two passes' memory
-  // latencies overlap.
+  // nothing).  The first round's loads go out between the loads of the
+  // bucket count pass's first round and their use, and are stored after
+  // the pass: the counts wait for the particles' cells only, and the
+  // staging latency overlaps the counts.
   const T *src[6] = {gr.E[0], gr.E[1], gr.E[2], gr.B[0], gr.B[1], gr.B[2]};
   T v[kStageNodes][6];
   auto stage_load = [&](int r0) {
@@ -940,27 +966,38 @@ __global__ __launch_bounds__(NT) void k_quad(const PartJob<typename L::T> *__res
       }
     }
   };
-  if constexpr (kGather) stage_load(tid);
-  // First pass over the tile's particles: bucket counts.  A tile that fits
-  // one round keeps its buckets in registers for the placement pass, which
-  // then loads nothing.
+  // First pass over the tile's particles: bucket counts, kParts particles
+  // per thread and round, their loads together.  A tile that fits one
+  // round keeps its buckets in registers for the placement pass, which then
+  // loads nothing.
   constexpr int kParts = sizeof(T) == 4 ? kListPartsFloat : kListParts;
   const bool one_round = count <= kParts * NT;
+  const bool counted = listed && count > 0;
   int kept[kParts];
   if (listed) {
     for (int b = tid; b <= tg.nb; b += NT) tl.fill[b] = 0;
-    __syncthreads();
-    // kParts particles per thread and round, their loads together
-    for (int i0 = tid; i0 < count; i0 += kParts * NT) {
+  }
+  __syncthreads();
+  typename L::Key key0[kParts];  // the first round's keys (a lane past the end reloads the last)
+  if (counted) {
+#pragma unroll
+    for (int u = 0; u < kParts; ++u) key0[u] = L::load_key(p, tbase + min(tid + u * NT, count - 1));
+  }
+  if constexpr (kGather) stage_load(tid);
+  if (counted) {
+#pragma unroll
+    for (int u = 0; u < kParts; ++u) {
+      kept[u] = bucket_of_key<L>(key0[u], g, tg, org);
+      if (tid + u * NT < count) atomicAdd(&tl.fill[kept[u]], 1);
+    }
+    for (int i0 = tid + kParts * NT; i0 < count; i0 += kParts * NT) {
       int bk[kParts];
 #pragma unroll
       for (int u = 0; u < kParts; ++u)
         bk[u] = bucket_of<L>(p, tbase + min(i0 + u * NT, count - 1), g, tg, org);
 #pragma unroll
-      for (int u = 0; u < kParts; ++u) {
+      for (int u = 0; u < kParts; ++u)
         if (i0 + u * NT < count) atomicAdd(&tl.fill[bk[u]], 1);
-        kept[u] = bk[u];
-      }
     }
   }
   if constexpr (kGather) {
