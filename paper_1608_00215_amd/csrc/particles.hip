@@ -904,6 +904,11 @@ __global__ __launch_bounds__(NT) void k_quad(const PartJob<typename L::T> *__res
   constexpr bool kMove = MODE == kModeFused || MODE == kModeDeposit;
   // pair jobs and the job table by rounds (float particles only)
   constexpr bool kSpread = sizeof(T) == 4;
+  // float particles: the staged E and B go to LDS after the bucket scans
+  // and the placement pass instead of after the count pass (FP64, whose
+  // tiles more often take several rounds of the count pass, measured
+  // slower so)
+  constexpr bool kLateStore = sizeof(T) == 4;
   static_assert(2 * NT >= 1024, "bucket scan covers up to 2 NT buckets");
   extern __shared__ __align__(16) unsigned char smem[];
   // accumulators first (8-byte aligned when A is double), then the fields,
@@ -943,9 +948,10 @@ __global__ __launch_bounds__(NT) void k_quad(const PartJob<typename L::T> *__res
   // their loads issued before the first LDS store (one memory latency per
   // round; a node past the region loads the last node again and stores
   // nothing).  The first round's loads go out between the loads of the
-  // bucket count pass's first round and their use, and are stored after
-  // the pass: the counts wait for the particles' cells only, and the
-  // staging latency overlaps the counts.
+  // bucket count pass's first round and their use (loads complete in
+  // issue order, so the counts wait for the particles' cells only), and
+  // are stored after the pass (FP64) or after the scans and the placement
+  // pass (float), so that the staging latency overlaps that work.
   const T *src[6] = {gr.E[0], gr.E[1], gr.E[2], gr.B[0], gr.B[1], gr.B[2]};
   T v[kStageNodes][6];
   auto stage_load = [&](int r0) {
@@ -983,13 +989,7 @@ __global__ __launch_bounds__(NT) void k_quad(const PartJob<typename L::T> *__res
 #pragma unroll
     for (int u = 0; u < kParts; ++u) key0[u] = L::load_key(p, tbase + min(tid + u * NT, count - 1));
   }
-  if constexpr (kGather) stage_load(tid);
-  if (counted) {
-#pragma unroll
-    for (int u = 0; u < kParts; ++u) {
-      kept[u] = bucket_of_key<L>(key0[u], g, tg, org);
-      if (tid + u * NT < count) atomicAdd(&tl.fill[kept[u]], 1);
-    }
+  auto later_rounds = [&] {
     for (int i0 = tid + kParts * NT; i0 < count; i0 += kParts * NT) {
       int bk[kParts];
 #pragma unroll
@@ -999,13 +999,39 @@ __global__ __launch_bounds__(NT) void k_quad(const PartJob<typename L::T> *__res
       for (int u = 0; u < kParts; ++u)
         if (i0 + u * NT < count) atomicAdd(&tl.fill[bk[u]], 1);
     }
-  }
-  if constexpr (kGather) {
+  };
+  auto first_round_counts = [&] {
+#pragma unroll
+    for (int u = 0; u < kParts; ++u) {
+      kept[u] = bucket_of_key<L>(key0[u], g, tg, org);
+      if (tid + u * NT < count) atomicAdd(&tl.fill[kept[u]], 1);
+    }
+  };
+  auto stage_rest = [&] {
     stage_store(tid);
     for (int r0 = tid + kStageNodes * NT; r0 < R; r0 += kStageNodes * NT) {
       stage_load(r0);
       stage_store(r0);
     }
+  };
+  if constexpr (kLateStore) {
+    // The later rounds go before the staging loads: the compiler waits for
+    // every outstanding load where a loop that loads ends, and the staging
+    // loads then stay in flight through the scans and the placement pass.
+    if (counted && !one_round) {
+      later_rounds();
+      if constexpr (kGather) stage_load(tid);
+    } else {
+      if constexpr (kGather) stage_load(tid);
+    }
+    if (counted) first_round_counts();
+  } else {
+    if constexpr (kGather) stage_load(tid);
+    if (counted) {
+      first_round_counts();
+      later_rounds();
+    }
+    if constexpr (kGather) stage_rest();
   }
   if constexpr (kDeposit) {
     for (int r = tid; r < 4 * R; r += NT) acc[r] = A(0);
@@ -1087,6 +1113,7 @@ __global__ __launch_bounds__(NT) void k_quad(const PartJob<typename L::T> *__res
     nquad = (count + 3) >> 2;
     npair = 0;
   }
+  if constexpr (kGather && kLateStore) stage_rest();
   __syncthreads();
 
   T *jdst[3] = {gr.J[0], gr.J[1], gr.J[2]};
