@@ -194,3 +194,25 @@ def test_dense_tiles_fused_steps(gpu_lib, precision, ppc, shape, tol_f, tol_p):
         st = sim.step(st)
     compare_state(ctx, parts, st, cfg, tol_f, tol_p)
     ctx.close()
+
+
+@pytest.mark.parametrize("precision,tol_f,tol_p", [(gp.GP_MIXED, 2e-5, 5e-6),
+                                                   (gp.GP_FP64, 1e-10, 1e-9)])
+def test_half_filled_grid_fused_steps(gpu_lib, precision, tol_f, tol_p):
+    """Particles in the lower half of x only (32x16x32 grid, 8 per cell):
+    tiles without particles beside full ones, and tiles whose region holds
+    the particles of a neighbour only, through the fused pass (three steps
+    of gp_run) against three oracle steps."""
+    cfg = get_config("c2_lite").with_(shape=(32, 16, 32), u_th=0.2)
+    full = particles_for(cfg)
+    keep = full["x"][:, 0] < 0.5 * cfg.shape[0] * cfg.spacing[0]
+    inp = {k: (v[keep] if isinstance(v, np.ndarray) else v) for k, v in full.items()}
+    inp["n"] = int(np.count_nonzero(keep))
+    ctx, parts, inp = setup(cfg, precision, inp)
+    sim = oracle_sim(cfg)
+    st = sim.initial_state(inp["x"], inp["u"])
+    ctx.run(3)
+    for _ in range(3):
+        st = sim.step(st)
+    compare_state(ctx, parts, st, cfg, tol_f, tol_p)
+    ctx.close()
